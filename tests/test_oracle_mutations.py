@@ -1,0 +1,93 @@
+"""Planted mistakes in the oracle (on the CPU): each plausible slip - a
+dropped term, a wrong sign, index or factor, a transposed operand - must make
+at least one of the independent pins fail."""
+import numpy as np
+import pytest
+
+import oracle.fredec_ref as R
+import tests.test_oracle as P
+
+PINS = [
+    P.test_scan_m0_matches_scipy_lombscargle_plain_workload,
+    P.test_scan_fft_special_case,
+    P.test_golden_dft_worked_example,
+    lambda: P.test_lsq_matches_lstsq(3, 2),
+    lambda: P.test_scan_base_matches_lstsq(2),
+    P.test_scan_invariances,
+    lambda: P.test_gradient_matches_central_differences(2),
+    P.test_gn_converges_to_truth_on_noiseless_data,
+    P.test_phase3_multiplicative_table,
+    P.test_tuple_permutation_and_lstsq,
+]
+
+
+def _design_no_2pi(tau, freqs):
+    freqs = np.atleast_1d(np.asarray(freqs, np.float64))
+    cols = [np.ones_like(tau)]
+    for f in freqs:
+        cols += [np.cos(f * tau), np.sin(f * tau)]
+    return np.stack(cols, axis=1)
+
+
+def _design_no_constant(tau, freqs):
+    freqs = np.atleast_1d(np.asarray(freqs, np.float64))
+    cols = [np.zeros_like(tau) + 1e-3 * tau]   # constant column replaced by a slope
+    for f in freqs:
+        ph = R.TWO_PI * f * tau
+        cols += [np.cos(ph), np.sin(ph)]
+    return np.stack(cols, axis=1)
+
+
+def _forward_transposed(L, g):
+    n = L.shape[-1]
+    a = np.zeros(np.broadcast_shapes(L.shape[:-1], np.shape(g)))
+    for i in range(n):
+        a[..., i] = (g[..., i] - np.sum(L[..., :i, i] * a[..., :i], axis=-1)) / L[..., i, i]
+    return a
+
+
+def _jacobian_sign(nrm, freqs, theta):
+    freqs = np.atleast_1d(np.asarray(freqs, np.float64))
+    J = np.empty((nrm.N, freqs.size))
+    for k, f in enumerate(freqs):
+        ph = R.TWO_PI * f * nrm.tau
+        a, b = theta[1 + 2 * k], theta[2 + 2 * k]
+        J[:, k] = R.TWO_PI * nrm.tau * (a * np.sin(ph) + b * np.cos(ph))
+    return J
+
+
+_orig_normalize = R.normalize
+
+
+def _normalize_unweighted_mean(t, x, w):
+    n = _orig_normalize(t, x, w)
+    xbar = float(np.mean(x))
+    d = np.asarray(x) - xbar
+    sx = float(np.sqrt(np.sum(n.wt * d * d)))
+    return R.Normalized(n.tau, d / sx, n.wt, n.tbar, xbar, sx, n.var_t, n.T_eff)
+
+
+MUTATIONS = {
+    "phase without 2 pi": ("design", _design_no_2pi),
+    "dropped constant column": ("design", _design_no_constant),
+    "N_H off by one": ("n_dof", lambda N, n: N - 3 * n),
+    "N_H without the 3 per frequency": ("n_dof", lambda N, n: N - 2 * n - 1),
+    "transposed L in forward substitution": ("forward_subst", _forward_transposed),
+    "wrong sign in the frequency derivative": ("model_jacobian", _jacobian_sign),
+    "unweighted mean of x": ("normalize", _normalize_unweighted_mean),
+    "popcount off by one": ("popcount", lambda m: bin(m).count("1") + (1 if m > 2 else 0)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name, monkeypatch):
+    attr, fn = MUTATIONS[name]
+    monkeypatch.setattr(R, attr, fn)
+    failures = 0
+    for pin in PINS:
+        try:
+            with np.errstate(all="ignore"):
+                pin()
+        except Exception:
+            failures += 1
+    assert failures > 0, f"no pin caught the planted mistake: {name}"
