@@ -1,0 +1,141 @@
+/*
+ * fredec.h - C ABI of the FREDEC multifrequency-periodogram hot path for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: R. V. Baluev, "Detecting multiple periodicities in observational
+ * data with the multifrequency periodogram - II. Frequency Decomposer"
+ * (Astronomy and Computing; arXiv:1309.0100).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Bulk arrays (times, values, weights, outputs, tables) are DEVICE pointers
+ *    owned by the caller.  Small descriptors (offsets, base frequencies, grid
+ *    steps, masks, thresholds) are HOST pointers.  Each argument says which.
+ *    The library never frees or retains caller memory beyond the work it
+ *    enqueues on `stream`; host arrays may be reused as soon as a call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    work is enqueued asynchronously on it; results are valid once the stream
+ *    has reached that point.
+ *  - Scratch memory comes from a caller-provided device `workspace` whose size
+ *    is given by the matching *_workspace query; too small a workspace returns
+ *    FREDEC_ENOMEM before anything is enqueued.
+ *  - Return value: FREDEC_OK (0) or a negative code.  Every check on host
+ *    arguments is made before any work is enqueued.  Conditions that need the
+ *    device data (weights, degenerate series, singular base model) are
+ *    reported per series in `status_out` (one int32 per series, 0 = ok, else
+ *    the negative code), and the outputs of that series are NaN.
+ *  - Per-element numeric conditions are not call errors: they are reported in
+ *    `flags_out` bits (see FREDEC_FLAG_*).
+ *  - A context is bound to one device and is not thread-safe: use one context
+ *    per host thread.  Outputs are always float64 whatever the precision.
+ *  - Time t is in the caller's unit (e.g. days); frequencies are in cycles per
+ *    that unit.  Data are normalised internally as in Sect. 4.1 (eq. idn):
+ *    weights to unit sum, x to zero weighted mean and unit weighted variance,
+ *    t centred.  The statistics do not depend on the units.
+ */
+#ifndef FREDEC_H
+#define FREDEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fredec_ctx fredec_ctx;
+
+/* Internal arithmetic of the trigonometric sums (outputs are float64). */
+enum {
+  FREDEC_FP64 = 0, /* float64 phase, trig and sums */
+  FREDEC_FP32 = 1  /* float64 phase reduction and solves; float32 trig and
+                      MFMA sums with float64 accumulation across sample tiles */
+};
+
+enum {
+  FREDEC_OK = 0,
+  FREDEC_EINVAL = -1,    /* null pointer, bad size, bad precision, bad option */
+  FREDEC_EDOF = -2,      /* N - 3(m+1) - 1 <= 0 (scan) or N - 3n - 1 <= 0 (tuples), Sect. 2 */
+  FREDEC_EWEIGHT = -3,   /* a weight w_i <= 0 or a non-finite t, x or w, Sect. 2 */
+  FREDEC_EDEGEN = -4,    /* zero weighted variance of x or of t */
+  FREDEC_ESINGULAR = -5, /* base normal matrix not positive definite */
+  FREDEC_ENOMEM = -6,    /* workspace too small, or host allocation failed */
+  FREDEC_EDEVICE = -7,   /* HIP runtime error (launch or earlier asynchronous fault) */
+  FREDEC_ENOTSUP = -8    /* size beyond a compiled limit (e.g. m > FREDEC_MAX_BASE) */
+};
+
+/* Element flags (uint8). */
+enum {
+  FREDEC_FLAG_MASKED = 1,     /* |f - f'_k| * T_eff < 0.05 for a base frequency: z := 0 */
+  FREDEC_FLAG_SINGULAR = 2,   /* Cholesky pivot below 1e-13 of its diagonal: z := 0 */
+  FREDEC_FLAG_PERFECT = 4,    /* l <= 0 (perfect fit): z := +inf */
+  FREDEC_FLAG_DEGENERATE = 8, /* tuple with merged frequencies or singular matrix: z := -inf */
+  FREDEC_FLAG_BADSERIES = 128 /* the series failed validation (see status_out): z := NaN */
+};
+
+#define FREDEC_MAX_BASE 24   /* largest base model m of a scan */
+#define FREDEC_MAX_POOL 24   /* largest pool size n for tuples and the cascade */
+
+/* Context --------------------------------------------------------------- */
+int fredec_create(fredec_ctx** ctx, int device);
+void fredec_destroy(fredec_ctx* ctx);
+const char* fredec_strerror(int code);
+int fredec_version(void); /* 100 * major + minor */
+
+/* Timing of the dominant kernel of each call (the trig-sum kernels of a
+ * scan, the Gram kernel of tuples): while enabled, every call records a pair
+ * of HIP events on its stream around those launches.  fredec_profile_read
+ * waits for them and returns the summed elapsed time (ms) and the number of
+ * event pairs since the last read or enable, then resets the count. */
+int fredec_profile(fredec_ctx* ctx, int32_t enable);
+int fredec_profile_read(fredec_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Normalisation (Sect. 4.1, eq. idn; T_eff of Sect. 2) -------------------
+ * Batch of n_series series in CSR form: series s owns samples
+ * [soff[s], soff[s+1]) of t, x, w (device, float64).
+ * Outputs (device, float64, same layout): tau = t - <t>, xt = (x - <x>)/s_x,
+ * wt = w / sum(w).  stats_out (device, [n_series * 6]): <t>, <x>, s_x,
+ * Var(t), T_eff = sqrt(4 pi Var(t)), sum(w).  status_out: per-series status. */
+int fredec_normalize_workspace(int32_t n_series, size_t* bytes);
+int fredec_normalize(fredec_ctx* ctx, void* stream, int32_t n_series, const int64_t* soff_host,
+                     const double* t, const double* x, const double* w,
+                     void* workspace, size_t ws_bytes,
+                     double* tau_out, double* xt_out, double* wt_out, double* stats_out,
+                     int32_t* status_out);
+
+/* Residual periodogram scan (eq. zpowrel with n = 1; Sects. 2, 3, 5) -----
+ * For series s with base frequencies f'_1..f'_m (m = boff[s+1]-boff[s] <=
+ * FREDEC_MAX_BASE, host base_f[boff[s]..]) and grid f_j = (j+1) * df[s],
+ * j = 0..F[s]-1, computes
+ *     z_j = (N - 3m - 4)/2 * ln( l_m(f') / l_{m+1}(f', f_j) )
+ * where l is the least-squares chi^2 minimum of the normalised data for the
+ * model "constant + sinusoids" (eq. Hn).  z of series s is written to
+ * z_out[goff_s + j] with goff_s = F[0] + ... + F[s-1] (device, float64);
+ * flags_out (device uint8, same layout, nullable); l_base_out (device,
+ * [n_series], nullable) receives l_m; status_out (device int32 [n_series],
+ * nullable).  soff, boff, base_f, df and F are host arrays.
+ * Errors: EINVAL (null/size/precision), EDOF (N - 3m - 4 <= 0 for a series),
+ * ENOTSUP (m > FREDEC_MAX_BASE), ENOMEM (workspace). */
+int fredec_scan_workspace(int32_t n_series, const int64_t* soff_host, const int64_t* boff_host,
+                          const int64_t* F_host, int32_t precision, size_t* bytes);
+int fredec_scan(fredec_ctx* ctx, void* stream, int32_t n_series,
+                const double* t, const double* x, const double* w, const int64_t* soff_host,
+                const double* base_f_host, const int64_t* boff_host,
+                const double* df_host, const int64_t* F_host,
+                int32_t precision, void* workspace, size_t ws_bytes,
+                double* z_out, uint8_t* flags_out, double* l_base_out, int32_t* status_out);
+
+/* The same statistic for one series at an explicit list of grid indices
+ * (device int64 idx[n_idx], each in [0, F)), always in float64.  Used to
+ * re-score reduced-precision peaks.  z_out/flags_out: device [n_idx]. */
+int fredec_scan_at_workspace(int64_t N, int32_t m, size_t* bytes);
+int fredec_scan_at(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w,
+                   int64_t N, const double* base_f_host, int32_t m, double df,
+                   const int64_t* idx, int64_t n_idx, void* workspace, size_t ws_bytes,
+                   double* z_out, uint8_t* flags_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FREDEC_H */

@@ -1,0 +1,408 @@
+// C ABI of libfredec: argument checks, workspace layout, uploads of the small
+// per-series descriptors and kernel launches.  See include/fredec.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fredec_internal.h"
+#include "fredec_api_internal.h"
+
+using namespace fredec;
+
+struct fredec_ctx {
+  int device = 0;
+  int n_cu = 0;
+  void* staging = nullptr;  // pinned host buffer for descriptor uploads
+  size_t staging_bytes = 0;
+  hipEvent_t staging_done = nullptr;
+  bool staging_pending = false;
+  // optional timing of the dominant kernel of each call (HIP events)
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+  size_t prof_used = 0;
+};
+
+namespace fredec {
+
+DeviceGuard::DeviceGuard(int dev) {
+  if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+  if (prev_ != dev) (void)hipSetDevice(dev);
+}
+DeviceGuard::~DeviceGuard() {
+  if (prev_ >= 0) (void)hipSetDevice(prev_);
+}
+
+// Copy `bytes` of host data to device memory `dst` on `st` through the
+// context's pinned staging buffer.
+int upload(fredec_ctx* ctx, hipStream_t st, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return FREDEC_OK;
+  if (ctx->staging_pending) {
+    if (hipEventSynchronize(ctx->staging_done) != hipSuccess) return FREDEC_EDEVICE;
+    ctx->staging_pending = false;
+  }
+  if (bytes > ctx->staging_bytes) {
+    if (ctx->staging) (void)hipHostFree(ctx->staging);
+    ctx->staging = nullptr;
+    ctx->staging_bytes = 0;
+    size_t cap = std::max<size_t>(bytes, 1 << 20);
+    if (hipHostMalloc(&ctx->staging, cap, hipHostMallocDefault) != hipSuccess) return FREDEC_ENOMEM;
+    ctx->staging_bytes = cap;
+  }
+  std::memcpy(ctx->staging, src, bytes);
+  if (hipMemcpyAsync(dst, ctx->staging, bytes, hipMemcpyHostToDevice, st) != hipSuccess) return FREDEC_EDEVICE;
+  if (hipEventRecord(ctx->staging_done, st) != hipSuccess) return FREDEC_EDEVICE;
+  ctx->staging_pending = true;
+  return FREDEC_OK;
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
+
+ProfScope::ProfScope(fredec_ctx* ctx, hipStream_t st) : ctx_(ctx), st_(st) {
+  if (!ctx_->profiling) return;
+  if (ctx_->prof_used == ctx_->prof_events.size()) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+    ctx_->prof_events.push_back({a, b});
+  }
+  idx_ = static_cast<long>(ctx_->prof_used++);
+  (void)hipEventRecord(ctx_->prof_events[idx_].first, st_);
+}
+ProfScope::~ProfScope() {
+  if (idx_ >= 0) (void)hipEventRecord(ctx_->prof_events[idx_].second, st_);
+}
+
+}  // namespace fredec
+
+namespace {
+
+struct ScanLayout {
+  size_t off_sin = 0, off_hdr = 0, off_work = 0, off_tau = 0, off_xt = 0, off_wt = 0, off_rec = 0, off_phi = 0;
+  size_t total = 0;
+  int64_t Ntot = 0, rec_total = 0, phi_total = 0, n_work = 0;
+};
+
+// Checks the host descriptors of a scan batch and computes the workspace layout.
+int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, const int64_t* F, int32_t precision,
+                ScanLayout& L) {
+  if (n_series <= 0 || !soff || !boff || !F) return FREDEC_EINVAL;
+  if (precision != FREDEC_FP64 && precision != FREDEC_FP32) return FREDEC_EINVAL;
+  if (soff[0] < 0 || boff[0] < 0) return FREDEC_EINVAL;
+  for (int32_t s = 0; s < n_series; ++s) {
+    const int64_t N = soff[s + 1] - soff[s];
+    const int64_t m = boff[s + 1] - boff[s];
+    if (N <= 0 || m < 0 || F[s] <= 0) return FREDEC_EINVAL;
+    if (m > MAXM) return FREDEC_ENOTSUP;
+    if (N - 3 * m - 4 <= 0) return FREDEC_EDOF;
+    const int KP = static_cast<int>(2 * m + 2);
+    const int64_t tile = static_cast<int64_t>(BLOCK) * scan_freqs_per_thread(KP);
+    L.n_work += (F[s] + tile - 1) / tile;
+    L.Ntot += N;
+    L.rec_total += N * rec_stride(KP);
+    L.phi_total += N * KP;
+  }
+  size_t off = 0;
+  L.off_sin = off;
+  off = align_up(off + sizeof(SeriesIn) * n_series);
+  L.off_hdr = off;
+  off = align_up(off + sizeof(SeriesHdr) * n_series);
+  L.off_work = off;
+  off = align_up(off + sizeof(ScanWork) * L.n_work);
+  L.off_tau = off;
+  off = align_up(off + sizeof(double) * L.Ntot);
+  L.off_xt = off;
+  off = align_up(off + sizeof(double) * L.Ntot);
+  L.off_wt = off;
+  off = align_up(off + sizeof(double) * L.Ntot);
+  L.off_rec = off;
+  off = align_up(off + sizeof(double) * L.rec_total);
+  L.off_phi = off;
+  off = align_up(off + sizeof(double) * L.phi_total);
+  L.total = off;
+  return FREDEC_OK;
+}
+
+template <typename T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+}  // namespace
+
+extern "C" {
+
+int fredec_version(void) { return 100; }
+
+const char* fredec_strerror(int code) {
+  switch (code) {
+    case FREDEC_OK: return "ok";
+    case FREDEC_EINVAL: return "invalid argument";
+    case FREDEC_EDOF: return "too few samples for the model (N - 3n - 1 <= 0)";
+    case FREDEC_EWEIGHT: return "non-positive weight or non-finite input";
+    case FREDEC_EDEGEN: return "degenerate series (zero variance of x or t)";
+    case FREDEC_ESINGULAR: return "singular base model";
+    case FREDEC_ENOMEM: return "workspace too small or allocation failure";
+    case FREDEC_EDEVICE: return "HIP runtime error";
+    case FREDEC_ENOTSUP: return "size beyond a compiled limit";
+    default: return "unknown error";
+  }
+}
+
+int fredec_create(fredec_ctx** out, int device) {
+  if (!out) return FREDEC_EINVAL;
+  *out = nullptr;
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev) return FREDEC_EDEVICE;
+  fredec_ctx* ctx = new (std::nothrow) fredec_ctx();
+  if (!ctx) return FREDEC_ENOMEM;
+  ctx->device = device;
+  DeviceGuard g(device);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming) != hipSuccess) {
+    delete ctx;
+    return FREDEC_EDEVICE;
+  }
+  ctx->n_cu = prop.multiProcessorCount;
+  *out = ctx;
+  return FREDEC_OK;
+}
+
+int fredec_profile(fredec_ctx* ctx, int32_t enable) {
+  if (!ctx) return FREDEC_EINVAL;
+  ctx->profiling = enable != 0;
+  ctx->prof_used = 0;
+  return FREDEC_OK;
+}
+
+int fredec_profile_read(fredec_ctx* ctx, double* total_ms, int64_t* launches) {
+  if (!ctx || !total_ms || !launches) return FREDEC_EINVAL;
+  DeviceGuard g(ctx->device);
+  double sum = 0.0;
+  for (size_t k = 0; k < ctx->prof_used; ++k) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(ctx->prof_events[k].second) != hipSuccess ||
+        hipEventElapsedTime(&ms, ctx->prof_events[k].first, ctx->prof_events[k].second) != hipSuccess)
+      return FREDEC_EDEVICE;
+    sum += ms;
+  }
+  *total_ms = sum;
+  *launches = static_cast<int64_t>(ctx->prof_used);
+  ctx->prof_used = 0;
+  return FREDEC_OK;
+}
+
+void fredec_destroy(fredec_ctx* ctx) {
+  if (!ctx) return;
+  DeviceGuard g(ctx->device);
+  for (auto& e : ctx->prof_events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  if (ctx->staging_pending) (void)hipEventSynchronize(ctx->staging_done);
+  if (ctx->staging) (void)hipHostFree(ctx->staging);
+  if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
+  delete ctx;
+}
+
+// ------------------------------------------------------------ normalisation
+int fredec_normalize_workspace(int32_t n_series, size_t* bytes) {
+  if (!bytes || n_series <= 0) return FREDEC_EINVAL;
+  *bytes = align_up(sizeof(SeriesIn) * n_series) + align_up(sizeof(SeriesHdr) * n_series);
+  return FREDEC_OK;
+}
+
+int fredec_normalize(fredec_ctx* ctx, void* stream, int32_t n_series, const int64_t* soff, const double* t,
+                     const double* x, const double* w, void* ws, size_t ws_bytes, double* tau_out, double* xt_out,
+                     double* wt_out, double* stats_out, int32_t* status_out) {
+  if (!soff || !t || !x || !w || !tau_out || !xt_out || !wt_out || n_series <= 0) return FREDEC_EINVAL;
+  if (soff[0] < 0) return FREDEC_EINVAL;
+  for (int32_t s = 0; s < n_series; ++s)
+    if (soff[s + 1] - soff[s] <= 0) return FREDEC_EINVAL;
+  size_t need = 0;
+  fredec_normalize_workspace(n_series, &need);
+  if (!ws || ws_bytes < need) return FREDEC_ENOMEM;
+  if (!ctx) return FREDEC_EINVAL;
+  std::vector<SeriesIn> sin(n_series);
+  std::memset(sin.data(), 0, sizeof(SeriesIn) * n_series);
+  for (int32_t s = 0; s < n_series; ++s) {
+    sin[s].soff = soff[s];
+    sin[s].N = soff[s + 1] - soff[s];
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SeriesIn* d_sin = at<SeriesIn>(ws, 0);
+  SeriesHdr* d_hdr = at<SeriesHdr>(ws, align_up(sizeof(SeriesIn) * n_series));
+  int rc = upload(ctx, st, d_sin, sin.data(), sizeof(SeriesIn) * n_series);
+  if (rc) return rc;
+  // the prep kernel writes the normalised series at the caller's offsets
+  if (launch_prep(st, n_series, d_sin, d_hdr, t, x, w, tau_out, xt_out, wt_out, nullptr, nullptr, 0) != hipSuccess)
+    return FREDEC_EDEVICE;
+  if (launch_copy_stats(st, n_series, d_hdr, d_sin, nullptr, status_out, stats_out) != hipSuccess)
+    return FREDEC_EDEVICE;
+  return FREDEC_OK;
+}
+
+// ------------------------------------------------------------ scan
+int fredec_scan_workspace(int32_t n_series, const int64_t* soff, const int64_t* boff, const int64_t* F,
+                          int32_t precision, size_t* bytes) {
+  if (!bytes) return FREDEC_EINVAL;
+  ScanLayout L;
+  int rc = scan_layout(n_series, soff, boff, F, precision, L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return FREDEC_OK;
+}
+
+int fredec_scan(fredec_ctx* ctx, void* stream, int32_t n_series, const double* t, const double* x, const double* w,
+                const int64_t* soff, const double* base_f, const int64_t* boff, const double* df, const int64_t* F,
+                int32_t precision, void* ws, size_t ws_bytes, double* z_out, uint8_t* flags_out, double* l_base_out,
+                int32_t* status_out) {
+  // host-side checks first (they need no device), the context last
+  if (!t || !x || !w || !df || !z_out) return FREDEC_EINVAL;
+  ScanLayout L;
+  int rc = scan_layout(n_series, soff, boff, F, precision, L);
+  if (rc) return rc;
+  if (boff[n_series] > boff[0] && !base_f) return FREDEC_EINVAL;
+  if (precision == FREDEC_FP32) return FREDEC_ENOTSUP;
+  if (!ws || ws_bytes < L.total) return FREDEC_ENOMEM;
+
+  std::vector<SeriesIn> sin(n_series);
+  std::memset(sin.data(), 0, sizeof(SeriesIn) * n_series);
+  int64_t goff = 0, rec_off = 0, phi_off = 0;
+  for (int32_t s = 0; s < n_series; ++s) {
+    SeriesIn& d = sin[s];
+    d.soff = soff[s];
+    d.N = soff[s + 1] - soff[s];
+    d.goff = goff;
+    d.F = F[s];
+    d.df = df[s];
+    if (!std::isfinite(df[s]) || df[s] == 0.0) return FREDEC_EINVAL;
+    d.rot_step = static_cast<double>(BLOCK) * df[s];
+    d.m = static_cast<int32_t>(boff[s + 1] - boff[s]);
+    d.KP = 2 * d.m + 2;
+    for (int k = 0; k < d.m; ++k) {
+      d.base_f[k] = base_f[boff[s] - boff[0] + k];
+      if (!std::isfinite(d.base_f[k])) return FREDEC_EINVAL;
+    }
+    d.rec_off = rec_off;
+    d.phi_off = phi_off;
+    goff += F[s];
+    rec_off += d.N * rec_stride(d.KP);
+    phi_off += d.N * d.KP;
+  }
+  // Work list: tiles grouped by KP (one kernel instance per group), longest
+  // series first inside a group.
+  std::vector<int32_t> order(n_series);
+  for (int32_t s = 0; s < n_series; ++s) order[s] = s;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    if (sin[a].KP != sin[b].KP) return sin[a].KP < sin[b].KP;
+    return sin[a].N > sin[b].N;
+  });
+  std::vector<ScanWork> work;
+  work.reserve(L.n_work);
+  std::vector<std::pair<int, std::pair<int64_t, int64_t>>> groups;  // KP -> [begin, end)
+  for (int32_t s : order) {
+    const int KP = sin[s].KP;
+    const int64_t tile = static_cast<int64_t>(BLOCK) * scan_freqs_per_thread(KP);
+    if (groups.empty() || groups.back().first != KP) groups.push_back({KP, {(int64_t)work.size(), 0}});
+    for (int64_t j0 = 0; j0 < sin[s].F; j0 += tile) work.push_back(ScanWork{s, 0, j0});
+    groups.back().second.second = static_cast<int64_t>(work.size());
+  }
+
+  if (!ctx) return FREDEC_EINVAL;
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SeriesIn* d_sin = at<SeriesIn>(ws, L.off_sin);
+  SeriesHdr* d_hdr = at<SeriesHdr>(ws, L.off_hdr);
+  ScanWork* d_work = at<ScanWork>(ws, L.off_work);
+  double* d_tau = at<double>(ws, L.off_tau);
+  double* d_xt = at<double>(ws, L.off_xt);
+  double* d_wt = at<double>(ws, L.off_wt);
+  double* d_rec = at<double>(ws, L.off_rec);
+  double* d_phi = at<double>(ws, L.off_phi);
+  if ((rc = upload(ctx, st, d_sin, sin.data(), sizeof(SeriesIn) * n_series))) return rc;
+  if ((rc = upload(ctx, st, d_work, work.data(), sizeof(ScanWork) * work.size()))) return rc;
+  const double* t0 = t;
+  const double* x0 = x;
+  const double* w0 = w;
+  // soff is absolute into t/x/w; the normalised arrays use the same indexing
+  // relative to soff[0].
+  const int64_t base_off = soff[0];
+  if (launch_prep(st, n_series, d_sin, d_hdr, t0, x0, w0, d_tau - base_off, d_xt - base_off, d_wt - base_off, d_rec,
+                  d_phi, 1) != hipSuccess)
+    return FREDEC_EDEVICE;
+  ProfScope prof(ctx, st);
+  for (auto& gr : groups) {
+    const int64_t b = gr.second.first, e = gr.second.second;
+    if (launch_scan_f64(st, gr.first, static_cast<int>(e - b), d_work + b, d_sin, d_hdr, d_rec, z_out, flags_out) !=
+        hipSuccess)
+      return FREDEC_EDEVICE;
+  }
+  if (launch_copy_stats(st, n_series, d_hdr, d_sin, l_base_out, status_out, nullptr) != hipSuccess)
+    return FREDEC_EDEVICE;
+  return FREDEC_OK;
+}
+
+int fredec_scan_at_workspace(int64_t N, int32_t m, size_t* bytes) {
+  if (!bytes || N <= 0 || m < 0) return FREDEC_EINVAL;
+  if (m > MAXM) return FREDEC_ENOTSUP;
+  const int KP = 2 * m + 2;
+  *bytes = align_up(sizeof(SeriesIn)) + align_up(sizeof(SeriesHdr)) + 3 * align_up(sizeof(double) * N) +
+           align_up(sizeof(double) * N * rec_stride(KP)) + align_up(sizeof(double) * N * KP);
+  return FREDEC_OK;
+}
+
+int fredec_scan_at(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                   const double* base_f, int32_t m, double df, const int64_t* idx, int64_t n_idx, void* ws,
+                   size_t ws_bytes, double* z_out, uint8_t* flags_out) {
+  if (!t || !x || !w || !z_out || N <= 0 || m < 0 || n_idx < 0) return FREDEC_EINVAL;
+  if (n_idx > 0 && !idx) return FREDEC_EINVAL;
+  if (m > 0 && !base_f) return FREDEC_EINVAL;
+  if (!std::isfinite(df) || df == 0.0) return FREDEC_EINVAL;
+  if (m > MAXM) return FREDEC_ENOTSUP;
+  if (N - 3 * static_cast<int64_t>(m) - 4 <= 0) return FREDEC_EDOF;
+  size_t need = 0;
+  fredec_scan_at_workspace(N, m, &need);
+  if (!ws || ws_bytes < need) return FREDEC_ENOMEM;
+  SeriesIn si;
+  std::memset(&si, 0, sizeof(si));
+  si.N = N;
+  si.F = 1;
+  si.df = df;
+  si.rot_step = static_cast<double>(BLOCK) * df;
+  si.m = m;
+  si.KP = 2 * m + 2;
+  for (int k = 0; k < m; ++k) {
+    if (!std::isfinite(base_f[k])) return FREDEC_EINVAL;
+    si.base_f[k] = base_f[k];
+  }
+  if (!ctx) return FREDEC_EINVAL;
+  if (n_idx == 0) return FREDEC_OK;
+  size_t off = 0;
+  SeriesIn* d_sin = at<SeriesIn>(ws, off);
+  off += align_up(sizeof(SeriesIn));
+  SeriesHdr* d_hdr = at<SeriesHdr>(ws, off);
+  off += align_up(sizeof(SeriesHdr));
+  double* d_tau = at<double>(ws, off);
+  off += align_up(sizeof(double) * N);
+  double* d_xt = at<double>(ws, off);
+  off += align_up(sizeof(double) * N);
+  double* d_wt = at<double>(ws, off);
+  off += align_up(sizeof(double) * N);
+  double* d_rec = at<double>(ws, off);
+  off += align_up(sizeof(double) * N * rec_stride(si.KP));
+  double* d_phi = at<double>(ws, off);
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = upload(ctx, st, d_sin, &si, sizeof(si));
+  if (rc) return rc;
+  if (launch_prep(st, 1, d_sin, d_hdr, t, x, w, d_tau, d_xt, d_wt, d_rec, d_phi, 1) != hipSuccess)
+    return FREDEC_EDEVICE;
+  if (launch_scan_at_f64(st, si.KP, d_sin, d_hdr, d_rec, idx, n_idx, z_out, flags_out) != hipSuccess)
+    return FREDEC_EDEVICE;
+  return FREDEC_OK;
+}
+
+}  // extern "C"

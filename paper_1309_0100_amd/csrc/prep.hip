@@ -1,0 +1,213 @@
+// Normalisation (Sect. 4.1, eq. idn) and base-model precomputation for the
+// residual scan (eq. zpowrel): one workgroup per series.
+#include "fredec_internal.h"
+
+namespace fredec {
+
+namespace {
+
+constexpr int GRAM_CHUNK = 8;  // Gram entries accumulated per pass
+
+__global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict__ sin_, SeriesHdr* __restrict__ hdr,
+                                                     const double* __restrict__ t, const double* __restrict__ x,
+                                                     const double* __restrict__ w, double* __restrict__ tau,
+                                                     double* __restrict__ xt, double* __restrict__ wt,
+                                                     double* __restrict__ rec, double* __restrict__ phi, int with_base) {
+  __shared__ double sh[GRAM_CHUNK * BLOCK];
+  __shared__ double gram[MAXKP * (MAXKP + 1) / 2];
+  const int tid = threadIdx.x;
+  const SeriesIn& si = sin_[blockIdx.x];
+  SeriesHdr& h = hdr[blockIdx.x];
+  const int64_t N = si.N;
+  const double* ts = t + si.soff;
+  const double* xs = x + si.soff;
+  const double* ws = w + si.soff;
+  double* taus = tau + si.soff;
+  double* xts = xt + si.soff;
+  double* wts = wt + si.soff;
+
+  // pass 1: sum of weights and input validity (Sect. 2: w_i > 0)
+  double v1[2] = {0.0, 0.0};
+  for (int64_t i = tid; i < N; i += BLOCK) {
+    const double wi = ws[i], ti = ts[i], xi = xs[i];
+    v1[0] += wi;
+    const bool ok = (wi > 0.0) && isfinite(wi) && isfinite(ti) && isfinite(xi);
+    v1[1] += ok ? 0.0 : 1.0;
+  }
+  block_sum(v1, sh);
+  int status = 0;
+  if (v1[1] != 0.0 || !(v1[0] > 0.0) || !isfinite(v1[0])) status = FREDEC_EWEIGHT;
+  const double W = v1[0];
+
+  // pass 2: weighted means of t and x
+  double v2[2] = {0.0, 0.0};
+  for (int64_t i = tid; i < N; i += BLOCK) {
+    const double wi = ws[i] / W;
+    v2[0] += wi * ts[i];
+    v2[1] += wi * xs[i];
+  }
+  block_sum(v2, sh);
+  const double tbar = v2[0], xbar = v2[1];
+
+  // pass 3: second moments
+  double v3[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = tid; i < N; i += BLOCK) {
+    const double wi = ws[i] / W;
+    const double ta = ts[i] - tbar, d = xs[i] - xbar;
+    v3[0] += wi * ta * ta;
+    v3[1] += wi * d * d;
+    v3[2] += wi * xs[i] * xs[i];
+    v3[3] += wi * ts[i] * ts[i];
+  }
+  block_sum(v3, sh);
+  const double var_t = v3[0], sx2 = v3[1];
+  if (status == 0 && (sx2 <= 1e-28 * v3[2] || var_t <= 1e-28 * v3[3])) status = FREDEC_EDEGEN;
+  const double sx = sqrt(sx2);
+  const double T_eff = sqrt(4.0 * M_PI * var_t);
+
+  // pass 4: normalised series and, for scans, the base records
+  const int KP = si.KP;
+  const int m = si.m;
+  const int P = rec_stride(KP);
+  for (int64_t i = tid; i < N; i += BLOCK) {
+    const double wi = ws[i] / W;
+    const double ta = ts[i] - tbar;
+    const double xi = (xs[i] - xbar) / sx;
+    taus[i] = ta;
+    xts[i] = xi;
+    wts[i] = wi;
+    if (with_base) {
+      double* q = rec + si.rec_off + i * P;
+      double* ph = phi + si.phi_off + i * KP;
+      double rs, rc;
+      sincos_rev(si.rot_step * ta, rs, rc);
+      q[0] = ta;
+      q[1] = rc;
+      q[2] = rs;
+      ph[0] = 1.0;
+      q[3] = wi;
+      for (int k = 0; k < m; ++k) {
+        double s, c;
+        sincos_rev(si.base_f[k] * ta, s, c);
+        ph[1 + 2 * k] = c;
+        ph[2 + 2 * k] = s;
+        q[4 + 2 * k] = wi * c;
+        q[5 + 2 * k] = wi * s;
+      }
+      ph[KP - 1] = xi;
+      q[3 + KP - 1] = wi * xi;
+    }
+  }
+  __syncthreads();
+
+  if (with_base) {
+    // Gram of the columns (1, cos f'_k, sin f'_k, x~): base normal matrix A,
+    // right-hand side g_b (last row) and D = <x~^2> (last diagonal entry).
+    const int n_ent = KP * (KP + 1) / 2;
+    const double* phs = phi + si.phi_off;
+    for (int e0 = 0; e0 < n_ent; e0 += GRAM_CHUNK) {
+      double acc[GRAM_CHUNK];
+      int ka[GRAM_CHUNK], la[GRAM_CHUNK];
+#pragma unroll
+      for (int c = 0; c < GRAM_CHUNK; ++c) {
+        acc[c] = 0.0;
+        int e = e0 + c;
+        if (e >= n_ent) e = n_ent - 1;
+        int k = 0;
+        while ((k + 1) * (k + 2) / 2 <= e) ++k;
+        ka[c] = k;
+        la[c] = e - k * (k + 1) / 2;
+      }
+      for (int64_t i = tid; i < N; i += BLOCK) {
+        const double* ph = phs + i * KP;
+        const double wi = wts[i];
+#pragma unroll
+        for (int c = 0; c < GRAM_CHUNK; ++c) acc[c] += wi * ph[ka[c]] * ph[la[c]];
+      }
+      block_sum(acc, sh);
+      if (tid == 0) {
+        for (int c = 0; c < GRAM_CHUNK && e0 + c < n_ent; ++c) gram[e0 + c] = acc[c];
+      }
+    }
+    __syncthreads();
+  }
+
+  if (tid == 0) {
+    h.T_eff = T_eff;
+    h.stats[0] = tbar;
+    h.stats[1] = xbar;
+    h.stats[2] = sx;
+    h.stats[3] = var_t;
+    h.stats[4] = T_eff;
+    h.stats[5] = W;
+    h.NH = static_cast<double>(N - 3 * m - 4);
+    if (with_base) {
+      // Cholesky A = L L^T (Sect. 3), a_b = L^{-1} g_b, l_m = D - a_b.a_b
+      const int K = KP - 1;
+      for (int j = 0; j < K && status == 0; ++j) {
+        double d = gram[j * (j + 1) / 2 + j];
+        for (int k = 0; k < j; ++k) d -= h.L[j * (j + 1) / 2 + k] * h.L[j * (j + 1) / 2 + k];
+        if (!(d > PIVOT_TOL * gram[j * (j + 1) / 2 + j])) {
+          status = FREDEC_ESINGULAR;
+          break;
+        }
+        const double ljj = sqrt(d);
+        h.L[j * (j + 1) / 2 + j] = ljj;
+        h.inv_diag[j] = 1.0 / ljj;
+        for (int i = j + 1; i < K; ++i) {
+          double v = gram[i * (i + 1) / 2 + j];
+          for (int k = 0; k < j; ++k) v -= h.L[i * (i + 1) / 2 + k] * h.L[j * (j + 1) / 2 + k];
+          h.L[i * (i + 1) / 2 + j] = v / ljj;
+        }
+      }
+      double lm = 0.0;
+      if (status == 0) {
+        const double* gb = gram + K * (K + 1) / 2;  // row K: <x~ phi_k>, then D
+        double aa = 0.0;
+        for (int i = 0; i < K; ++i) {
+          double v = gb[i];
+          for (int k = 0; k < i; ++k) v -= h.L[i * (i + 1) / 2 + k] * h.a_b[k];
+          h.a_b[i] = v * h.inv_diag[i];
+          aa += h.a_b[i] * h.a_b[i];
+        }
+        h.D = gb[K];
+        lm = gb[K] - aa;
+      }
+      h.l_m = lm;
+    }
+    if (status == 0 && with_base && N - 3 * m - 4 <= 0) status = FREDEC_EDOF;
+    h.status = status;
+  }
+}
+
+__global__ void copy_stats_kernel(int n_series, const SeriesHdr* __restrict__ hdr, double* __restrict__ l_base,
+                                  int32_t* __restrict__ status, double* __restrict__ stats) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_series) return;
+  const SeriesHdr& h = hdr[s];
+  if (l_base) l_base[s] = h.status == 0 ? h.l_m : __builtin_nan("");
+  if (status) status[s] = h.status;
+  if (stats) {
+    for (int k = 0; k < 6; ++k) stats[6 * s + k] = h.stats[k];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_prep(hipStream_t st, int n_series, const SeriesIn* sin, SeriesHdr* hdr, const double* t,
+                       const double* x, const double* w, double* tau, double* xt, double* wt, double* rec,
+                       double* phi, int with_base) {
+  if (n_series <= 0) return hipSuccess;
+  prep_kernel<<<n_series, BLOCK, 0, st>>>(sin, hdr, t, x, w, tau, xt, wt, rec, phi, with_base);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_stats(hipStream_t st, int n_series, const SeriesHdr* hdr, const SeriesIn* sin,
+                             double* l_base, int32_t* status, double* stats) {
+  (void)sin;
+  if (n_series <= 0 || (!l_base && !status && !stats)) return hipSuccess;
+  copy_stats_kernel<<<(n_series + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(n_series, hdr, l_base, status, stats);
+  return hipGetLastError();
+}
+
+}  // namespace fredec

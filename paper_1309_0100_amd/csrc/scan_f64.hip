@@ -1,0 +1,264 @@
+// Residual periodogram scan in float64 (eq. zpowrel with n = 1, Sects. 3, 5).
+//
+// Layout: one lane owns R grid frequencies f_{j0+t+256r}, r = 0..R-1, and
+// walks over all samples of its series.  The per-sample record
+// [tau, cos(2 pi s tau), sin(2 pi s tau), w~ phi_0 .. w~ phi_{KP-1}] (s = 256 df,
+// phi = 1, cos f'_k tau, sin f'_k tau, x~) is the same for every lane, so it is
+// read with scalar loads and used as a scalar operand: no LDS and no
+// cross-lane reduction is needed.  cos/sin of the first frequency come from
+// the float64 phase reduction; the other R-1 follow by rotation with the
+// record's (cos, sin)(2 pi s tau).  Per frequency the lane accumulates
+//   B_c[k] = <phi_k cos>, B_s[k] = <phi_k sin> (k < K), <x~ cos>, <x~ sin>,
+//   <cos^2>, <cos sin>, <sin^2>
+// and the epilogue extends the base Cholesky factor by the 2x2 Schur block of
+// the trial column pair (the incremental extension of Sect. 3):
+//   U = L_A^{-1} B, S = C - U^T U, a_psi = L_S^{-1}(g_psi - U^T a_b),
+//   l_{m+1} = l_m - |a_psi|^2,  z = (N - 3m - 4)/2 ln(l_m / l_{m+1}).
+#include "fredec_internal.h"
+
+namespace fredec {
+
+namespace {
+
+constexpr int R_of(int KP) {
+  int r = 112 / (2 * KP + 3);
+  return r < 1 ? 1 : (r > 8 ? 8 : r);
+}
+
+template <int KP>
+__device__ __forceinline__ void scan_epilogue(const double (&acc)[2 * KP + 3], double f, const SeriesIn& si,
+                                              const SeriesHdr& h, double& z, uint8_t& flag) {
+  constexpr int K = KP - 1;
+  double uc[K], us[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double bc = (k == 0) ? acc[0] : acc[3 + 2 * k];
+    double bs = (k == 0) ? acc[1] : acc[4 + 2 * k];
+#pragma unroll
+    for (int j = 0; j < k; ++j) {
+      const double l = h.L[k * (k + 1) / 2 + j];
+      bc = __builtin_fma(-l, uc[j], bc);
+      bs = __builtin_fma(-l, us[j], bs);
+    }
+    uc[k] = bc * h.inv_diag[k];
+    us[k] = bs * h.inv_diag[k];
+  }
+  double cc = acc[2], ss = acc[4];
+  double Scc = cc, Scs = acc[3], Sss = ss;
+  double gc = acc[3 + 2 * K], gs = acc[4 + 2 * K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    Scc = __builtin_fma(-uc[k], uc[k], Scc);
+    Scs = __builtin_fma(-uc[k], us[k], Scs);
+    Sss = __builtin_fma(-us[k], us[k], Sss);
+    gc = __builtin_fma(-uc[k], h.a_b[k], gc);
+    gs = __builtin_fma(-us[k], h.a_b[k], gs);
+  }
+  bool masked = false;
+  for (int k = 0; k < si.m; ++k) masked |= fabs(f - si.base_f[k]) * h.T_eff < MASK_WIDTH;
+  flag = 0;
+  z = 0.0;
+  if (masked) {
+    flag = FREDEC_FLAG_MASKED;
+    return;
+  }
+  bool ok = Scc > PIVOT_TOL * cc;
+  const double l11 = sqrt(ok ? Scc : 1.0);
+  const double l21 = Scs / l11;
+  const double d2 = Sss - l21 * l21;
+  ok = ok && (d2 > PIVOT_TOL * ss);
+  if (!ok) {
+    flag = FREDEC_FLAG_SINGULAR;
+    return;
+  }
+  const double l22 = sqrt(d2);
+  const double a1 = gc / l11;
+  const double a2 = (gs - l21 * a1) / l22;
+  const double l1 = h.l_m - (a1 * a1 + a2 * a2);
+  if (!(l1 > 0.0)) {
+    flag = FREDEC_FLAG_PERFECT;
+    z = __builtin_inf();
+    return;
+  }
+  z = 0.5 * h.NH * log(h.l_m / l1);
+}
+
+template <int KP, int R>
+__global__ __launch_bounds__(BLOCK) void scan_f64_kernel(const ScanWork* __restrict__ work,
+                                                         const SeriesIn* __restrict__ sin_,
+                                                         const SeriesHdr* __restrict__ hdr,
+                                                         const double* __restrict__ rec,
+                                                         double* __restrict__ z_out, uint8_t* __restrict__ flags_out) {
+  constexpr int NS = 2 * KP + 3;
+  constexpr int P = rec_stride(KP);
+  const ScanWork wk = work[blockIdx.x];
+  const SeriesIn& si = sin_[wk.series];
+  const SeriesHdr& h = hdr[wk.series];
+  const int64_t N = si.N;
+  const int64_t F = si.F;
+  const double df = si.df;
+  const int64_t jb = wk.j0 + threadIdx.x;
+  double* zs = z_out + si.goff;
+  uint8_t* fs = flags_out ? flags_out + si.goff : nullptr;
+  if (h.status != 0) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t j = jb + (int64_t)BLOCK * r;
+      if (j < F) {
+        zs[j] = __builtin_nan("");
+        if (fs) fs[j] = FREDEC_FLAG_BADSERIES;
+      }
+    }
+    return;
+  }
+  const double f0 = static_cast<double>(jb + 1) * df;
+  double acc[R][NS];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) acc[r][k] = 0.0;
+
+  const double* __restrict__ q = rec + si.rec_off;
+  for (int64_t i = 0; i < N; ++i, q += P) {
+    double s, c;
+    sincos_rev(f0 * q[0], s, c);
+    const double rc = q[1], rs = q[2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r) {
+        const double cn = __builtin_fma(c, rc, -s * rs);
+        s = __builtin_fma(s, rc, c * rs);
+        c = cn;
+      }
+      const double g0 = q[3];
+      const double tc = g0 * c, tsn = g0 * s;
+      acc[r][0] += tc;
+      acc[r][1] += tsn;
+      acc[r][2] = __builtin_fma(tc, c, acc[r][2]);
+      acc[r][3] = __builtin_fma(tc, s, acc[r][3]);
+      acc[r][4] = __builtin_fma(tsn, s, acc[r][4]);
+#pragma unroll
+      for (int k = 1; k < KP; ++k) {
+        const double g = q[3 + k];
+        acc[r][3 + 2 * k] = __builtin_fma(g, c, acc[r][3 + 2 * k]);
+        acc[r][4 + 2 * k] = __builtin_fma(g, s, acc[r][4 + 2 * k]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t j = jb + (int64_t)BLOCK * r;
+    if (j < F) {
+      double z;
+      uint8_t fl;
+      scan_epilogue<KP>(acc[r], static_cast<double>(j + 1) * df, si, h, z, fl);
+      zs[j] = z;
+      if (fs) fs[j] = fl;
+    }
+  }
+}
+
+// Same statistic at an explicit list of grid indices of one series (R = 1).
+template <int KP>
+__global__ __launch_bounds__(BLOCK) void scan_at_f64_kernel(const SeriesIn* __restrict__ sin_,
+                                                            const SeriesHdr* __restrict__ hdr,
+                                                            const double* __restrict__ rec,
+                                                            const int64_t* __restrict__ idx, int64_t n_idx,
+                                                            double* __restrict__ z_out, uint8_t* __restrict__ flags_out) {
+  constexpr int NS = 2 * KP + 3;
+  constexpr int P = rec_stride(KP);
+  const SeriesIn& si = sin_[0];
+  const SeriesHdr& h = hdr[0];
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+  const int64_t gi = g < n_idx ? g : n_idx - 1;
+  const int64_t j = idx[gi];
+  if (h.status != 0) {
+    if (g < n_idx) {
+      z_out[g] = __builtin_nan("");
+      if (flags_out) flags_out[g] = FREDEC_FLAG_BADSERIES;
+    }
+    return;
+  }
+  const double f = static_cast<double>(j + 1) * si.df;
+  double acc[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+  const double* __restrict__ q = rec + si.rec_off;
+  for (int64_t i = 0; i < si.N; ++i, q += P) {
+    double s, c;
+    sincos_rev(f * q[0], s, c);
+    const double g0 = q[3];
+    const double tc = g0 * c, tsn = g0 * s;
+    acc[0] += tc;
+    acc[1] += tsn;
+    acc[2] = __builtin_fma(tc, c, acc[2]);
+    acc[3] = __builtin_fma(tc, s, acc[3]);
+    acc[4] = __builtin_fma(tsn, s, acc[4]);
+#pragma unroll
+    for (int k = 1; k < KP; ++k) {
+      const double gk = q[3 + k];
+      acc[3 + 2 * k] = __builtin_fma(gk, c, acc[3 + 2 * k]);
+      acc[4 + 2 * k] = __builtin_fma(gk, s, acc[4 + 2 * k]);
+    }
+  }
+  if (g < n_idx) {
+    double z;
+    uint8_t fl;
+    scan_epilogue<KP>(acc, f, si, h, z, fl);
+    z_out[g] = z;
+    if (flags_out) flags_out[g] = fl;
+  }
+}
+
+template <int KP>
+hipError_t launch_kp(hipStream_t st, int n_work, const ScanWork* work, const SeriesIn* sin, const SeriesHdr* hdr,
+                     const double* rec, double* z, uint8_t* flags) {
+  scan_f64_kernel<KP, R_of(KP)><<<n_work, BLOCK, 0, st>>>(work, sin, hdr, rec, z, flags);
+  return hipGetLastError();
+}
+
+template <int KP>
+hipError_t launch_at_kp(hipStream_t st, const SeriesIn* sin, const SeriesHdr* hdr, const double* rec,
+                        const int64_t* idx, int64_t n_idx, double* z, uint8_t* flags) {
+  const int64_t blocks = (n_idx + BLOCK - 1) / BLOCK;
+  scan_at_f64_kernel<KP><<<static_cast<unsigned>(blocks), BLOCK, 0, st>>>(sin, hdr, rec, idx, n_idx, z, flags);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int scan_freqs_per_thread(int KP) { return R_of(KP); }
+
+#define FREDEC_KP_CASES(X) \
+  X(2) X(4) X(6) X(8) X(10) X(12) X(14) X(16) X(18) X(20) X(22) X(24) X(26) \
+  X(28) X(30) X(32) X(34) X(36) X(38) X(40) X(42) X(44) X(46) X(48) X(50)
+
+hipError_t launch_scan_f64(hipStream_t st, int KP, int n_work, const ScanWork* work, const SeriesIn* sin,
+                           const SeriesHdr* hdr, const double* rec, double* z, uint8_t* flags) {
+  if (n_work <= 0) return hipSuccess;
+  switch (KP) {
+#define X(kp) \
+  case kp:    \
+    return launch_kp<kp>(st, n_work, work, sin, hdr, rec, z, flags);
+    FREDEC_KP_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_scan_at_f64(hipStream_t st, int KP, const SeriesIn* sin, const SeriesHdr* hdr, const double* rec,
+                              const int64_t* idx, int64_t n_idx, double* z, uint8_t* flags) {
+  if (n_idx <= 0) return hipSuccess;
+  switch (KP) {
+#define X(kp) \
+  case kp:    \
+    return launch_at_kp<kp>(st, sin, hdr, rec, idx, n_idx, z, flags);
+    FREDEC_KP_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fredec

@@ -1,0 +1,234 @@
+"""Thin Python binding of libfredec (ctypes).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libfredec.so.  torch provides device memory (tensors, workspaces)
+and streams; no torch type crosses the C ABI.  If the library is not built,
+every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfredec.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "fredec.h")
+
+FP64 = 0
+FP32 = 1
+
+OK, EINVAL, EDOF, EWEIGHT, EDEGEN, ESINGULAR, ENOMEM, EDEVICE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7, -8
+FLAG_MASKED, FLAG_SINGULAR, FLAG_PERFECT, FLAG_DEGENERATE, FLAG_BADSERIES = 1, 2, 4, 8, 128
+
+c_i32, c_i64, c_sz, c_p, c_d = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
+c_pp = ctypes.POINTER(ctypes.c_void_p)
+c_szp = ctypes.POINTER(ctypes.c_size_t)
+
+_SIGS = {
+    "fredec_create": (c_i32, [c_pp, ctypes.c_int]),
+    "fredec_destroy": (None, [c_p]),
+    "fredec_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "fredec_version": (ctypes.c_int, []),
+    "fredec_profile": (c_i32, [c_p, c_i32]),
+    "fredec_profile_read": (c_i32, [c_p, ctypes.POINTER(c_d), ctypes.POINTER(c_i64)]),
+    "fredec_normalize_workspace": (c_i32, [c_i32, c_szp]),
+    "fredec_normalize": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_sz, c_p, c_p, c_p, c_p, c_p]),
+    "fredec_scan_workspace": (c_i32, [c_i32, c_p, c_p, c_p, c_i32, c_szp]),
+    "fredec_scan": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_i32, c_p, c_sz,
+                            c_p, c_p, c_p, c_p]),
+    "fredec_scan_at_workspace": (c_i32, [c_i64, c_i32, c_szp]),
+    "fredec_scan_at": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_i32, c_d, c_p, c_i64, c_p, c_sz, c_p, c_p]),
+}
+
+_lib = None
+
+
+class FredecError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = load().fredec_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{where}: {msg} ({code})")
+
+
+def header_functions() -> list[str]:
+    """Names of every function declared in include/fredec.h."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"\b(fredec_[a-z0-9_]+)\s*\(", text)))
+
+
+def load():
+    """Load libfredec.so (built in-tree) and declare its signatures."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1309_0100_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(code: int, where: str):
+    if code != OK:
+        raise FredecError(code, where)
+
+
+def _ptr(a) -> int | None:
+    """Device pointer of a tensor, host pointer of a numpy array, or None."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    assert a.is_contiguous()
+    return a.data_ptr()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(device):
+    torch = _torch()
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Context:
+    """A libfredec context bound to one GPU."""
+
+    def __init__(self, device: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.fredec_create(ctypes.byref(h), device), "fredec_create")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().fredec_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, enable: bool = True):
+        _check(load().fredec_profile(self.handle, int(enable)), "fredec_profile")
+
+    def profile_read(self):
+        """(total ms, event pairs) of the dominant kernels since the last read."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(load().fredec_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(n)), "fredec_profile_read")
+        return ms.value, n.value
+
+    # ------------------------------------------------------------ helpers
+    def _dev(self):
+        return _torch().device("cuda", self.device)
+
+    def _empty(self, n, dtype):
+        return _torch().empty(int(n), dtype=dtype, device=self._dev())
+
+    def _workspace(self, nbytes: int):
+        return _torch().empty(max(int(nbytes), 1), dtype=_torch().uint8, device=self._dev())
+
+    def _f64(self, a):
+        torch = _torch()
+        if isinstance(a, torch.Tensor):
+            assert a.dtype == torch.float64 and a.device.type == "cuda"
+            return a.contiguous()
+        return torch.as_tensor(np.ascontiguousarray(a, np.float64), device=self._dev())
+
+    # ------------------------------------------------------------ API
+    def normalize(self, t, x, w, soff=None):
+        """Normalised series (tau, xt, wt), per-series stats and status."""
+        torch = _torch()
+        t, x, w = self._f64(t), self._f64(x), self._f64(w)
+        soff = np.asarray([0, t.numel()] if soff is None else soff, np.int64)
+        ns = soff.size - 1
+        need = ctypes.c_size_t()
+        _check(load().fredec_normalize_workspace(ns, ctypes.byref(need)), "fredec_normalize_workspace")
+        ws = self._workspace(need.value)
+        tau, xt, wt = (torch.empty_like(t) for _ in range(3))
+        stats = self._empty(6 * ns, torch.float64)
+        status = self._empty(ns, torch.int32)
+        _check(load().fredec_normalize(self.handle, _stream(self.device), ns, _ptr(soff), _ptr(t), _ptr(x), _ptr(w),
+                                       _ptr(ws), need.value, _ptr(tau), _ptr(xt), _ptr(wt), _ptr(stats),
+                                       _ptr(status)), "fredec_normalize")
+        return tau, xt, wt, stats.view(ns, 6), status
+
+    def scan_workspace(self, soff, boff, F, precision=FP64) -> int:
+        soff = np.ascontiguousarray(soff, np.int64)
+        boff = np.ascontiguousarray(boff, np.int64)
+        F = np.ascontiguousarray(F, np.int64)
+        need = ctypes.c_size_t()
+        _check(load().fredec_scan_workspace(soff.size - 1, _ptr(soff), _ptr(boff), _ptr(F), precision,
+                                            ctypes.byref(need)), "fredec_scan_workspace")
+        return need.value
+
+    def scan(self, t, x, w, soff, base_f, boff, df, F, precision=FP64, workspace=None, out=None):
+        """Residual periodogram of a CSR batch of series.  Returns
+        (z, flags, l_base, status) as device tensors; z of series s occupies
+        [sum(F[:s]), sum(F[:s+1]))."""
+        torch = _torch()
+        t, x, w = self._f64(t), self._f64(x), self._f64(w)
+        soff = np.ascontiguousarray(soff, np.int64)
+        boff = np.ascontiguousarray(boff, np.int64)
+        base_f = np.ascontiguousarray(base_f, np.float64)
+        df = np.ascontiguousarray(np.broadcast_to(df, (soff.size - 1,)), np.float64)
+        F = np.ascontiguousarray(np.broadcast_to(F, (soff.size - 1,)), np.int64)
+        ns = soff.size - 1
+        need = self.scan_workspace(soff, boff, F, precision)
+        ws = workspace if workspace is not None and workspace.numel() >= need else self._workspace(need)
+        total = int(F.sum())
+        if out is None:
+            out = (self._empty(total, torch.float64), self._empty(total, torch.uint8),
+                   self._empty(ns, torch.float64), self._empty(ns, torch.int32))
+        z, flags, lbase, status = out
+        _check(load().fredec_scan(self.handle, _stream(self.device), ns, _ptr(t), _ptr(x), _ptr(w), _ptr(soff),
+                                  _ptr(base_f) if base_f.size else None, _ptr(boff), _ptr(df), _ptr(F), precision,
+                                  _ptr(ws), ws.numel(), _ptr(z), _ptr(flags), _ptr(lbase), _ptr(status)),
+               "fredec_scan")
+        return z, flags, lbase, status
+
+    def scan_series(self, t, x, w, base_f, df, F, precision=FP64):
+        """One series: returns (z, flags, l_base, status)."""
+        n = len(t) if not hasattr(t, "numel") else t.numel()
+        base_f = np.atleast_1d(np.asarray(base_f, np.float64))
+        return self.scan(t, x, w, [0, n], base_f, [0, base_f.size], [df], [F], precision)
+
+    def scan_at(self, t, x, w, base_f, df, idx):
+        """float64 statistic of one series at grid indices idx (device int64)."""
+        torch = _torch()
+        t, x, w = self._f64(t), self._f64(x), self._f64(w)
+        base_f = np.ascontiguousarray(np.atleast_1d(base_f), np.float64)
+        idx = idx if isinstance(idx, torch.Tensor) else torch.as_tensor(np.asarray(idx, np.int64), device=self._dev())
+        n_idx = idx.numel()
+        need = ctypes.c_size_t()
+        _check(load().fredec_scan_at_workspace(t.numel(), base_f.size, ctypes.byref(need)), "fredec_scan_at_workspace")
+        ws = self._workspace(need.value)
+        z = self._empty(n_idx, torch.float64)
+        fl = self._empty(n_idx, torch.uint8)
+        _check(load().fredec_scan_at(self.handle, _stream(self.device), _ptr(t), _ptr(x), _ptr(w), t.numel(),
+                                     _ptr(base_f) if base_f.size else None, base_f.size, float(df), _ptr(idx), n_idx,
+                                     _ptr(ws), need.value, _ptr(z), _ptr(fl)), "fredec_scan_at")
+        return z, fl
+
+
+@dataclass
+class ScanOut:
+    z: object
+    flags: object
+    l_base: object
+    status: object

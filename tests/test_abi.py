@@ -1,0 +1,109 @@
+"""The C-ABI library loads on the CPU, exports every symbol the header
+declares, and rejects invalid host arguments before touching a device."""
+import ctypes
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1309_0100_amd import fredec as F
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return F.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = F.header_functions()
+    assert len(names) >= 10
+    out = subprocess.run(["nm", "-D", "--defined-only", F.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        getattr(lib, n)
+
+
+def test_strerror_and_version(lib):
+    assert lib.fredec_version() >= 100
+    for code in range(0, -9, -1):
+        assert lib.fredec_strerror(code)
+    assert b"unknown" in lib.fredec_strerror(-99)
+
+
+def _p(a):
+    return a.ctypes.data
+
+
+def _scan_ws(lib, soff, boff, Fs, prec=0):
+    soff = np.asarray(soff, np.int64)
+    boff = np.asarray(boff, np.int64)
+    Fs = np.asarray(Fs, np.int64)
+    n = ctypes.c_size_t()
+    rc = lib.fredec_scan_workspace(soff.size - 1, _p(soff), _p(boff), _p(Fs), prec, ctypes.byref(n))
+    return rc, n.value
+
+
+def test_scan_workspace_validation(lib):
+    rc, n = _scan_ws(lib, [0, 100], [0, 2], [1000])
+    assert rc == F.OK and n > 0
+    assert _scan_ws(lib, [0, 100, 150], [0, 2, 2], [1000, 10])[0] == F.OK
+    assert _scan_ws(lib, [0, 10], [0, 2], [1000])[0] == F.EDOF          # N - 3m - 4 = 0
+    assert _scan_ws(lib, [0, 100], [0, 25], [1000])[0] == F.ENOTSUP     # m > FREDEC_MAX_BASE
+    assert _scan_ws(lib, [0, 100], [0, 0], [0])[0] == F.EINVAL          # F <= 0
+    assert _scan_ws(lib, [0, 0], [0, 0], [10])[0] == F.EINVAL           # N <= 0
+    assert _scan_ws(lib, [0, 100], [0, 0], [10], prec=7)[0] == F.EINVAL
+    # the workspace grows with F (tiles), N (records) and m (columns)
+    assert _scan_ws(lib, [0, 100], [0, 0], [10 ** 6])[1] > _scan_ws(lib, [0, 100], [0, 0], [10])[1]
+    assert _scan_ws(lib, [0, 1000], [0, 3], [10])[1] > _scan_ws(lib, [0, 1000], [0, 0], [10])[1]
+
+
+def test_scan_rejects_host_errors_without_device(lib):
+    N, Fg = 100, 500
+    soff = np.array([0, N], np.int64)
+    boff = np.array([0, 1], np.int64)
+    base = np.array([0.1])
+    df = np.array([1e-3])
+    Fs = np.array([Fg], np.int64)
+    rc, need = _scan_ws(lib, soff, boff, Fs)
+    dummy = ctypes.c_void_p(16)   # never dereferenced: every call below fails a host check
+
+    def call(ctx=None, soff=soff, boff=boff, base=base, df=df, Fs=Fs, prec=0, ws=dummy, wsb=need, z=dummy):
+        return lib.fredec_scan(ctx, None, soff.size - 1, dummy, dummy, dummy, _p(soff),
+                               _p(base) if base is not None else None, _p(boff), _p(df), _p(Fs), prec,
+                               ws, wsb, z, None, None, None)
+
+    assert call() == F.EINVAL                                   # valid arguments, null context
+    assert call(wsb=need - 1) == F.ENOMEM
+    assert call(ws=None) == F.ENOMEM
+    assert call(z=None) == F.EINVAL
+    assert call(base=None) == F.EINVAL
+    assert call(df=np.array([np.nan])) == F.EINVAL
+    assert call(df=np.array([0.0])) == F.EINVAL
+    assert call(base=np.array([np.inf])) == F.EINVAL
+    assert call(soff=np.array([0, 6], np.int64)) == F.EDOF
+    assert call(prec=3) == F.EINVAL
+
+
+def test_scan_at_and_normalize_validation(lib):
+    d = ctypes.c_void_p(16)
+    n = ctypes.c_size_t()
+    assert lib.fredec_scan_at_workspace(100, 2, ctypes.byref(n)) == F.OK and n.value > 0
+    assert lib.fredec_scan_at_workspace(100, 30, ctypes.byref(n)) == F.ENOTSUP
+    assert lib.fredec_scan_at(None, None, d, d, d, 100, None, 0, 1e-3, d, 10, d, n.value, d, None) == F.EINVAL
+    assert lib.fredec_scan_at(None, None, d, d, d, 6, None, 1, 1e-3, d, 10, d, n.value, d, None) == F.EINVAL
+    base = np.array([0.1])
+    assert lib.fredec_scan_at(None, None, d, d, d, 6, _p(base), 1, 1e-3, d, 10, d, n.value, d, None) == F.EDOF
+    assert lib.fredec_scan_at(None, None, d, d, d, 100, _p(base), 1, 0.0, d, 10, d, n.value, d, None) == F.EINVAL
+    assert lib.fredec_normalize_workspace(0, ctypes.byref(n)) == F.EINVAL
+    soff = np.array([0, 0], np.int64)
+    assert lib.fredec_normalize(None, None, 1, _p(soff), d, d, d, d, 1 << 20, d, d, d, None, None) == F.EINVAL
+
+
+def test_create_without_gpu_reports_device_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert lib.fredec_create(ctypes.byref(h), 0) == F.EDEVICE

@@ -1,0 +1,163 @@
+"""GPU parity of the residual scan (fredec_scan, float64) against the oracle:
+element by element on sizes that span several tiles with a ragged tail, and
+on sampled grid points at the full residual-scan workload size."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1309_0100_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+# float64 bound on err = |z_gpu - z_ref| / max(z_ref, 1)
+TOL64 = 1e-9
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1309_0100_amd import fredec as F
+    return F.Context(0)
+
+
+def zerr(z, zr):
+    return np.abs(z - zr) / np.maximum(np.abs(zr), 1.0)
+
+
+def check_scan(z, fl, ref, tol=TOL64):
+    z = z.cpu().numpy()
+    fl = fl.cpu().numpy()
+    assert np.array_equal(fl, ref.flags), (np.flatnonzero(fl != ref.flags)[:10], fl[fl != ref.flags][:10])
+    good = fl == 0
+    e = zerr(z[good], ref.z[good])
+    assert e.max(initial=0.0) <= tol, (e.max(), np.argmax(e))
+    assert np.all(z[fl == 1] == 0)
+    return e.max(initial=0.0)
+
+
+def test_plain_workload_full_grid(ctx):
+    """Workload 1: N=200, F=10^4, m=0; every grid point."""
+    s = synth.plain()
+    print("case: plain N=200 F=10000 m=0", flush=True)
+    z, fl, lb, st = ctx.scan_series(s.t, s.x, s.w, [], s.df, s.F)
+    ref = O.scan(s.t, s.x, s.w, [], s.df, s.F)
+    check_scan(z, fl, ref)
+    assert int(st.item()) == 0
+    assert abs(float(lb.item()) - ref.l_base) < 1e-14
+    # local maxima (candidate peaks) agree exactly
+    zz = z.cpu().numpy()
+    assert np.array_equal(O.local_maxima(zz, fl.cpu().numpy()), O.local_maxima(ref.z, ref.flags))
+
+
+@pytest.mark.parametrize("m,N,F", [(1, 150, 3001), (2, 300, 5000), (4, 257, 2049), (7, 400, 1500), (12, 300, 700)])
+def test_base_models_ragged(ctx, m, N, F):
+    s = synth.random_series(100 + m, N, span=300.0, n_sin=3)
+    rng = np.random.default_rng(m)
+    base = np.concatenate([s.true_f, rng.uniform(0.01, 1.0, size=max(0, m - 3))])[:m]
+    df = 1.2 / F
+    print(f"case: m={m} N={N} F={F}", flush=True)
+    z, fl, lb, st = ctx.scan_series(s.t, s.x, s.w, base, df, F)
+    ref = O.scan(s.t, s.x, s.w, base, df, F)
+    check_scan(z, fl, ref)
+    assert abs(float(lb.item()) - ref.l_base) < 1e-13
+
+
+def test_batched_csr_uneven(ctx):
+    """Several series of uneven N, m and F in one call (several kernel
+    instances, ragged tiles, F = 1)."""
+    specs = [(80, 0, 1), (300, 3, 4097), (120, 1, 513), (640, 5, 1000), (90, 2, 2), (1000, 0, 3000)]
+    ts, xs, ws, bs, soff, boff, dfs, Fs = [], [], [], [], [0], [0], [], []
+    for k, (N, m, F) in enumerate(specs):
+        s = synth.random_series(200 + k, N, span=50.0 + 40 * k, n_sin=2)
+        base = np.random.default_rng(k).uniform(0.02, 0.5, size=m)
+        ts.append(s.t); xs.append(s.x); ws.append(s.w); bs.append(base)
+        soff.append(soff[-1] + N); boff.append(boff[-1] + m)
+        dfs.append(0.9 / F); Fs.append(F)
+    print("case: batched csr", specs, flush=True)
+    z, fl, lb, st = ctx.scan(np.concatenate(ts), np.concatenate(xs), np.concatenate(ws), soff,
+                             np.concatenate(bs), boff, dfs, Fs)
+    z, fl, lb, st = z.cpu().numpy(), fl.cpu().numpy(), lb.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0)
+    g = 0
+    for k in range(len(specs)):
+        ref = O.scan(ts[k], xs[k], ws[k], bs[k], dfs[k], Fs[k])
+        zz, ff = z[g:g + Fs[k]], fl[g:g + Fs[k]]
+        assert np.array_equal(ff, ref.flags)
+        good = ff == 0
+        assert zerr(zz[good], ref.z[good]).max(initial=0) <= TOL64
+        assert abs(lb[k] - ref.l_base) < 1e-13
+        g += Fs[k]
+
+
+def test_residual_workload_sampled(ctx):
+    """Workload 2 at full size (N=2000, F=10^6, m=4) in the launch
+    configuration the benchmark times; sampled grid points, plus every point
+    within 20 steps of each base frequency (mask edges) and the low end."""
+    s = synth.residual()
+    print("case: residual N=2000 F=1e6 m=4", flush=True)
+    z, fl, lb, st = ctx.scan_series(s.t, s.x, s.w, s.base_f, s.df, s.F)
+    z, fl = z.cpu().numpy(), fl.cpu().numpy()
+    rng = np.random.default_rng(2)
+    idx = [rng.choice(s.F, size=1500, replace=False), np.arange(0, 40), np.arange(s.F - 40, s.F)]
+    for f in s.base_f:
+        j = int(round(f / s.df)) - 1
+        idx.append(np.arange(max(0, j - 20), min(s.F, j + 21)))
+    idx = np.unique(np.concatenate(idx))
+    ref = O.scan(s.t, s.x, s.w, s.base_f, s.df, s.F, idx=idx)
+    assert np.array_equal(fl[idx], ref.flags)
+    good = ref.flags == 0
+    e = zerr(z[idx][good], ref.z[good])
+    assert e.max() <= TOL64, e.max()
+    assert fl.sum() > 0 and np.all(z[fl == 1] == 0)
+
+
+def test_per_series_status_and_outputs(ctx):
+    """Device-side validation: bad weight, degenerate x, singular base."""
+    s = synth.random_series(300, 120, n_sin=1)
+    w_bad = s.w.copy()
+    w_bad[5] = -1.0
+    x_const = np.full_like(s.x, 3.0)
+    t = np.concatenate([s.t, s.t, s.t, s.t])
+    x = np.concatenate([s.x, s.x, x_const, s.x])
+    w = np.concatenate([s.w, w_bad, s.w, s.w])
+    soff = [0, 120, 240, 360, 480]
+    base = np.array([0.1, 0.1, 0.1, 0.2, 0.2])      # series 3 repeats 0.2: singular base
+    boff = [0, 1, 2, 3, 5]
+    z, fl, lb, st = ctx.scan(t, x, w, soff, base, boff, [1e-3] * 4, [500] * 4)
+    st = st.cpu().numpy()
+    assert list(st) == [0, -3, -4, -5]
+    z = z.cpu().numpy().reshape(4, 500)
+    fl = fl.cpu().numpy().reshape(4, 500)
+    assert np.all(np.isfinite(z[0]))
+    for k in (1, 2, 3):
+        assert np.all(np.isnan(z[k])) and np.all(fl[k] == 128)
+
+
+def test_deterministic_bytes(ctx):
+    s = synth.random_series(301, 500, n_sin=2)
+    a = ctx.scan_series(s.t, s.x, s.w, [0.1, 0.3], 2e-4, 9000)[0].cpu().numpy()
+    b = ctx.scan_series(s.t, s.x, s.w, [0.1, 0.3], 2e-4, 9000)[0].cpu().numpy()
+    assert a.tobytes() == b.tobytes()
+
+
+def test_scan_at_matches_scan(ctx):
+    s = synth.random_series(302, 333, n_sin=2)
+    base = [0.05, 0.21]
+    z, fl, _, _ = ctx.scan_series(s.t, s.x, s.w, base, 3e-4, 3000)
+    idx = np.array([0, 1, 17, 255, 256, 257, 2999, 1234], np.int64)
+    za, fa = ctx.scan_at(s.t, s.x, s.w, base, 3e-4, idx)
+    assert np.array_equal(fa.cpu().numpy(), fl.cpu().numpy()[idx])
+    assert zerr(za.cpu().numpy(), z.cpu().numpy()[idx]).max() < 1e-11
+
+
+def test_normalize_matches_oracle(ctx):
+    s = synth.random_series(303, 777, n_sin=2)
+    tau, xt, wt, stats, st = ctx.normalize(s.t, s.x, s.w)
+    n = O.normalize(s.t, s.x, s.w)
+    assert np.allclose(tau.cpu().numpy(), n.tau, rtol=0, atol=1e-12)
+    assert np.allclose(xt.cpu().numpy(), n.xt, rtol=1e-13, atol=1e-13)
+    assert np.allclose(wt.cpu().numpy(), n.wt, rtol=1e-14, atol=0)
+    st6 = stats.cpu().numpy()[0]
+    assert st6[4] == pytest.approx(n.T_eff, rel=1e-13)
+    assert int(st.item()) == 0
