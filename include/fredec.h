@@ -70,6 +70,9 @@ enum {
   FREDEC_FLAG_SINGULAR = 2,   /* Cholesky pivot below 1e-13 of its diagonal: z := 0 */
   FREDEC_FLAG_PERFECT = 4,    /* l <= 0 (perfect fit): z := +inf */
   FREDEC_FLAG_DEGENERATE = 8, /* tuple with merged frequencies or singular matrix: z := -inf */
+  FREDEC_FLAG_RESCORED = 64,  /* FREDEC_FP32 scan: trial columns nearly in the base span (relative
+                                 Schur pivot < 0.5) or a strong peak (l_{m+1} < l_m / 2):
+                                 value recomputed in float64 */
   FREDEC_FLAG_BADSERIES = 128 /* the series failed validation (see status_out): z := NaN */
 };
 
@@ -89,6 +92,15 @@ int fredec_version(void); /* 100 * major + minor */
  * event pairs since the last read or enable, then resets the count. */
 int fredec_profile(fredec_ctx* ctx, int32_t enable);
 int fredec_profile_read(fredec_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Tile shapes chosen by the autotuner (paper_1309_0100_amd/autotune.py).
+ * FREDEC_TILE_SCAN_MFMA: key = column tiles of the float32 MFMA scan operand
+ * (1..4, i.e. ceil((2m+2)/16)), value = 16-frequency tiles per wavefront
+ * (2, 4, 6 or 8 for key 1; 2 or 4 for key 2; 2 for keys 3, 4; 0 = default).
+ * Errors: EINVAL for an unsupported combination.  The workspace size of a
+ * scan does not depend on this setting. */
+enum { FREDEC_TILE_SCAN_MFMA = 1 };
+int fredec_set_tile(fredec_ctx* ctx, int32_t kernel, int32_t key, int32_t value);
 
 /* Normalisation (Sect. 4.1, eq. idn; T_eff of Sect. 2) -------------------
  * Batch of n_series series in CSR form: series s owns samples

@@ -19,6 +19,7 @@ struct fredec_ctx {
   hipEvent_t staging_done = nullptr;
   bool staging_pending = false;
   // optional timing of the dominant kernel of each call (HIP events)
+  int mfma_ft[5] = {0, 0, 0, 0, 0};  // MFMA scan: 16-frequency tiles per wave, by column tiles (0 = default)
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
   size_t prof_used = 0;
@@ -79,9 +80,25 @@ namespace {
 
 struct ScanLayout {
   size_t off_sin = 0, off_hdr = 0, off_work = 0, off_tau = 0, off_xt = 0, off_wt = 0, off_rec = 0, off_phi = 0;
+  size_t off_g32 = 0, off_aux = 0, off_list = 0, off_count = 0;
   size_t total = 0;
-  int64_t Ntot = 0, rec_total = 0, phi_total = 0, n_work = 0;
+  int64_t Ntot = 0, rec_total = 0, phi_total = 0, g32_total = 0, aux_total = 0, n_work = 0, F_total = 0;
+  int max_nt = 1;
 };
+
+constexpr int MFMA_FT_MIN = 2;
+
+// Frequencies per workgroup of the scan kernel used for a series (for the
+// MFMA kernel the smallest tile, which bounds the work list of any setting).
+int64_t scan_tile(int KP, int32_t precision) {
+  if (precision == FREDEC_FP32) return 64 * MFMA_FT_MIN;
+  return static_cast<int64_t>(BLOCK) * scan_freqs_per_thread(KP);
+}
+
+int mfma_ft_for(const fredec_ctx* ctx, int NT) {
+  const int ft = (ctx && NT >= 1 && NT <= 4 && ctx->mfma_ft[NT]) ? ctx->mfma_ft[NT] : mfma_freq_tiles(NT);
+  return ft;
+}
 
 // Checks the host descriptors of a scan batch and computes the workspace layout.
 int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, const int64_t* F, int32_t precision,
@@ -96,29 +113,36 @@ int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, cons
     if (m > MAXM) return FREDEC_ENOTSUP;
     if (N - 3 * m - 4 <= 0) return FREDEC_EDOF;
     const int KP = static_cast<int>(2 * m + 2);
-    const int64_t tile = static_cast<int64_t>(BLOCK) * scan_freqs_per_thread(KP);
+    const int64_t tile = scan_tile(KP, precision);
     L.n_work += (F[s] + tile - 1) / tile;
     L.Ntot += N;
-    L.rec_total += N * rec_stride(KP);
     L.phi_total += N * KP;
+    L.rec_total += N * rec_stride(KP);
+    L.F_total += F[s];
+    if (precision == FREDEC_FP32) {
+      L.g32_total += N * 16 * col_tiles(KP);
+      L.aux_total += N * AUX_STRIDE;
+      L.max_nt = std::max(L.max_nt, col_tiles(KP));
+    }
   }
   size_t off = 0;
-  L.off_sin = off;
-  off = align_up(off + sizeof(SeriesIn) * n_series);
-  L.off_hdr = off;
-  off = align_up(off + sizeof(SeriesHdr) * n_series);
-  L.off_work = off;
-  off = align_up(off + sizeof(ScanWork) * L.n_work);
-  L.off_tau = off;
-  off = align_up(off + sizeof(double) * L.Ntot);
-  L.off_xt = off;
-  off = align_up(off + sizeof(double) * L.Ntot);
-  L.off_wt = off;
-  off = align_up(off + sizeof(double) * L.Ntot);
-  L.off_rec = off;
-  off = align_up(off + sizeof(double) * L.rec_total);
-  L.off_phi = off;
-  off = align_up(off + sizeof(double) * L.phi_total);
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.off_sin = take(sizeof(SeriesIn) * n_series);
+  L.off_hdr = take(sizeof(SeriesHdr) * n_series);
+  L.off_work = take(sizeof(ScanWork) * L.n_work);
+  L.off_tau = take(sizeof(double) * L.Ntot);
+  L.off_xt = take(sizeof(double) * L.Ntot);
+  L.off_wt = take(sizeof(double) * L.Ntot);
+  L.off_rec = take(sizeof(double) * L.rec_total);
+  L.off_phi = take(sizeof(double) * L.phi_total);
+  L.off_g32 = take(sizeof(float) * L.g32_total);
+  L.off_aux = take(sizeof(double) * L.aux_total);
+  L.off_list = take(precision == FREDEC_FP32 ? sizeof(Rescore) * L.F_total : 0);
+  L.off_count = take(sizeof(unsigned long long));
   L.total = off;
   return FREDEC_OK;
 }
@@ -167,6 +191,17 @@ int fredec_create(fredec_ctx** out, int device) {
   ctx->n_cu = prop.multiProcessorCount;
   *out = ctx;
   return FREDEC_OK;
+}
+
+int fredec_set_tile(fredec_ctx* ctx, int32_t kernel, int32_t key, int32_t value) {
+  if (!ctx) return FREDEC_EINVAL;
+  if (kernel == FREDEC_TILE_SCAN_MFMA) {
+    if (key < 1 || key > 4) return FREDEC_EINVAL;
+    if (value != 0 && !mfma_tile_supported(key, value)) return FREDEC_EINVAL;
+    ctx->mfma_ft[key] = value;
+    return FREDEC_OK;
+  }
+  return FREDEC_EINVAL;
 }
 
 int fredec_profile(fredec_ctx* ctx, int32_t enable) {
@@ -237,7 +272,8 @@ int fredec_normalize(fredec_ctx* ctx, void* stream, int32_t n_series, const int6
   int rc = upload(ctx, st, d_sin, sin.data(), sizeof(SeriesIn) * n_series);
   if (rc) return rc;
   // the prep kernel writes the normalised series at the caller's offsets
-  if (launch_prep(st, n_series, d_sin, d_hdr, t, x, w, tau_out, xt_out, wt_out, nullptr, nullptr, 0) != hipSuccess)
+  if (launch_prep(st, n_series, d_sin, d_hdr, t, x, w, tau_out, xt_out, wt_out, nullptr, nullptr, nullptr, nullptr,
+                  0) != hipSuccess)
     return FREDEC_EDEVICE;
   if (launch_copy_stats(st, n_series, d_hdr, d_sin, nullptr, status_out, stats_out) != hipSuccess)
     return FREDEC_EDEVICE;
@@ -265,12 +301,11 @@ int fredec_scan(fredec_ctx* ctx, void* stream, int32_t n_series, const double* t
   int rc = scan_layout(n_series, soff, boff, F, precision, L);
   if (rc) return rc;
   if (boff[n_series] > boff[0] && !base_f) return FREDEC_EINVAL;
-  if (precision == FREDEC_FP32) return FREDEC_ENOTSUP;
   if (!ws || ws_bytes < L.total) return FREDEC_ENOMEM;
 
   std::vector<SeriesIn> sin(n_series);
   std::memset(sin.data(), 0, sizeof(SeriesIn) * n_series);
-  int64_t goff = 0, rec_off = 0, phi_off = 0;
+  int64_t goff = 0, rec_off = 0, phi_off = 0, g32_off = 0, aux_off = 0;
   for (int32_t s = 0; s < n_series; ++s) {
     SeriesIn& d = sin[s];
     d.soff = soff[s];
@@ -280,33 +315,42 @@ int fredec_scan(fredec_ctx* ctx, void* stream, int32_t n_series, const double* t
     d.df = df[s];
     if (!std::isfinite(df[s]) || df[s] == 0.0) return FREDEC_EINVAL;
     d.rot_step = static_cast<double>(BLOCK) * df[s];
+    d.rot_tile = 16.0 * df[s];
     d.m = static_cast<int32_t>(boff[s + 1] - boff[s]);
     d.KP = 2 * d.m + 2;
+    d.NT = col_tiles(d.KP);
     for (int k = 0; k < d.m; ++k) {
       d.base_f[k] = base_f[boff[s] - boff[0] + k];
       if (!std::isfinite(d.base_f[k])) return FREDEC_EINVAL;
     }
     d.rec_off = rec_off;
     d.phi_off = phi_off;
+    d.g32_off = g32_off;
+    d.aux_off = aux_off;
     goff += F[s];
-    rec_off += d.N * rec_stride(d.KP);
     phi_off += d.N * d.KP;
+    rec_off += d.N * rec_stride(d.KP);
+    if (precision == FREDEC_FP32) {
+      g32_off += d.N * 16 * d.NT;
+      aux_off += d.N * AUX_STRIDE;
+    }
   }
-  // Work list: tiles grouped by KP (one kernel instance per group), longest
-  // series first inside a group.
+  // Work list: tiles grouped by kernel instance (KP for float64, column
+  // tiles NT for MFMA), longest series first inside a group.
+  auto key = [&](int32_t s) { return precision == FREDEC_FP64 ? sin[s].KP : sin[s].NT; };
   std::vector<int32_t> order(n_series);
   for (int32_t s = 0; s < n_series; ++s) order[s] = s;
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    if (sin[a].KP != sin[b].KP) return sin[a].KP < sin[b].KP;
+    if (key(a) != key(b)) return key(a) < key(b);
     return sin[a].N > sin[b].N;
   });
   std::vector<ScanWork> work;
   work.reserve(L.n_work);
-  std::vector<std::pair<int, std::pair<int64_t, int64_t>>> groups;  // KP -> [begin, end)
+  std::vector<std::pair<int, std::pair<int64_t, int64_t>>> groups;  // key -> [begin, end)
   for (int32_t s : order) {
-    const int KP = sin[s].KP;
-    const int64_t tile = static_cast<int64_t>(BLOCK) * scan_freqs_per_thread(KP);
-    if (groups.empty() || groups.back().first != KP) groups.push_back({KP, {(int64_t)work.size(), 0}});
+    const int64_t tile = precision == FREDEC_FP32 ? 64 * static_cast<int64_t>(mfma_ft_for(ctx, sin[s].NT))
+                                                  : scan_tile(sin[s].KP, precision);
+    if (groups.empty() || groups.back().first != key(s)) groups.push_back({key(s), {(int64_t)work.size(), 0}});
     for (int64_t j0 = 0; j0 < sin[s].F; j0 += tile) work.push_back(ScanWork{s, 0, j0});
     groups.back().second.second = static_cast<int64_t>(work.size());
   }
@@ -322,24 +366,37 @@ int fredec_scan(fredec_ctx* ctx, void* stream, int32_t n_series, const double* t
   double* d_wt = at<double>(ws, L.off_wt);
   double* d_rec = at<double>(ws, L.off_rec);
   double* d_phi = at<double>(ws, L.off_phi);
+  float* d_g32 = at<float>(ws, L.off_g32);
+  double* d_aux = at<double>(ws, L.off_aux);
+  Rescore* d_list = at<Rescore>(ws, L.off_list);
+  unsigned long long* d_count = at<unsigned long long>(ws, L.off_count);
   if ((rc = upload(ctx, st, d_sin, sin.data(), sizeof(SeriesIn) * n_series))) return rc;
   if ((rc = upload(ctx, st, d_work, work.data(), sizeof(ScanWork) * work.size()))) return rc;
-  const double* t0 = t;
-  const double* x0 = x;
-  const double* w0 = w;
-  // soff is absolute into t/x/w; the normalised arrays use the same indexing
-  // relative to soff[0].
+  // soff is absolute into t/x/w; the normalised copies use the same indexing
+  // shifted by soff[0] (the batch is contiguous).
   const int64_t base_off = soff[0];
-  if (launch_prep(st, n_series, d_sin, d_hdr, t0, x0, w0, d_tau - base_off, d_xt - base_off, d_wt - base_off, d_rec,
-                  d_phi, 1) != hipSuccess)
+  const int flags = PREP_BASE | PREP_REC64 | (precision == FREDEC_FP32 ? PREP_F32 : 0);
+  if (precision == FREDEC_FP32 && launch_zero_u64(st, d_count, 1) != hipSuccess) return FREDEC_EDEVICE;
+  if (launch_prep(st, n_series, d_sin, d_hdr, t, x, w, d_tau - base_off, d_xt - base_off, d_wt - base_off, d_rec,
+                  d_phi, d_g32, d_aux, flags) != hipSuccess)
     return FREDEC_EDEVICE;
-  ProfScope prof(ctx, st);
-  for (auto& gr : groups) {
-    const int64_t b = gr.second.first, e = gr.second.second;
-    if (launch_scan_f64(st, gr.first, static_cast<int>(e - b), d_work + b, d_sin, d_hdr, d_rec, z_out, flags_out) !=
-        hipSuccess)
-      return FREDEC_EDEVICE;
+  {
+    ProfScope prof(ctx, st);
+    for (auto& gr : groups) {
+      const int64_t b = gr.second.first, e = gr.second.second;
+      hipError_t err;
+      if (precision == FREDEC_FP64)
+        err = launch_scan_f64(st, gr.first, static_cast<int>(e - b), d_work + b, d_sin, d_hdr, d_rec, z_out, flags_out);
+      else
+        err = launch_scan_mfma(st, gr.first, mfma_ft_for(ctx, gr.first), static_cast<int>(e - b), d_work + b, d_sin,
+                               d_hdr, d_g32, d_aux, z_out, flags_out, d_list, d_count);
+      if (err != hipSuccess) return FREDEC_EDEVICE;
+    }
   }
+  if (precision == FREDEC_FP32 &&
+      launch_rescore(st, L.max_nt, 4 * std::max(ctx->n_cu, 1), d_sin, d_hdr, d_rec, d_list, d_count, z_out,
+                     flags_out) != hipSuccess)
+    return FREDEC_EDEVICE;
   if (launch_copy_stats(st, n_series, d_hdr, d_sin, l_base_out, status_out, nullptr) != hipSuccess)
     return FREDEC_EDEVICE;
   return FREDEC_OK;
@@ -372,8 +429,10 @@ int fredec_scan_at(fredec_ctx* ctx, void* stream, const double* t, const double*
   si.F = 1;
   si.df = df;
   si.rot_step = static_cast<double>(BLOCK) * df;
+  si.rot_tile = 16.0 * df;
   si.m = m;
   si.KP = 2 * m + 2;
+  si.NT = col_tiles(si.KP);
   for (int k = 0; k < m; ++k) {
     if (!std::isfinite(base_f[k])) return FREDEC_EINVAL;
     si.base_f[k] = base_f[k];
@@ -398,7 +457,8 @@ int fredec_scan_at(fredec_ctx* ctx, void* stream, const double* t, const double*
   hipStream_t st = static_cast<hipStream_t>(stream);
   int rc = upload(ctx, st, d_sin, &si, sizeof(si));
   if (rc) return rc;
-  if (launch_prep(st, 1, d_sin, d_hdr, t, x, w, d_tau, d_xt, d_wt, d_rec, d_phi, 1) != hipSuccess)
+  if (launch_prep(st, 1, d_sin, d_hdr, t, x, w, d_tau, d_xt, d_wt, d_rec, d_phi, nullptr, nullptr,
+                  PREP_BASE | PREP_REC64) != hipSuccess)
     return FREDEC_EDEVICE;
   if (launch_scan_at_f64(st, si.KP, d_sin, d_hdr, d_rec, idx, n_idx, z_out, flags_out) != hipSuccess)
     return FREDEC_EDEVICE;

@@ -16,6 +16,10 @@ constexpr int MAXK = 2 * MAXM + 1;       // base columns 1, cos, sin, ...
 constexpr int MAXKP = MAXK + 1;          // base columns plus the data column
 constexpr double MASK_WIDTH = 0.05;      // |f - f'| T_eff below this is masked
 constexpr double PIVOT_TOL = 1e-13;      // relative Cholesky pivot threshold
+constexpr double RHO_MIN = 0.5;          // reduced-precision scan: re-score in float64 below this
+                                         // relative Schur pivot (trial columns nearly in the base span)
+constexpr double LRATIO_MIN = 0.5;       // ... and where l_{m+1} / l_m falls below this (strong peaks,
+                                         // where l_{m+1} = l_m - |a_psi|^2 cancels)
 
 // Per-series description built on the host and uploaded with each call.
 struct SeriesIn {
@@ -23,12 +27,17 @@ struct SeriesIn {
   int64_t N;        // number of samples
   int64_t goff;     // first output element of this series
   int64_t F;        // grid size
-  int64_t rec_off;  // first double of this series in the record array
-  int64_t phi_off;  // first double of this series in the basis array
+  int64_t rec_off;  // first double of this series in the float64 record array
+  int64_t phi_off;  // first double of this series in the basis scratch array
+  int64_t g32_off;  // first float of this series in the float32 operand array
+  int64_t aux_off;  // first double of this series in the float32 kernel's aux array
   double df;        // grid step: f_j = (j+1) df
-  double rot_step;  // frequency step of the trig recurrence (tile stride * df)
+  double rot_step;  // frequency step of the float64 kernel's recurrence (BLOCK * df)
+  double rot_tile;  // frequency step of the MFMA kernel's recurrence (16 * df)
   int32_t m;        // base frequencies
-  int32_t KP;       // 2m + 2 columns: 1, cos f'_1, sin f'_1, ..., data
+  int32_t KP;       // 2m + 2 columns: orthonormal base columns q_0..q_{2m}, residual r_b
+  int32_t NT;       // 16-column tiles of the MFMA operand (K = KP - 1 base columns)
+  int32_t pad;
   double base_f[MAXM];
 };
 
@@ -38,12 +47,10 @@ struct SeriesHdr {
   double NH;        // N - 3m - 4
   double T_eff;     // sqrt(4 pi Var(t))
   double D;         // <x~^2> (= 1 up to rounding)
+  double W1;        // <1> = sum of the normalised weights (= 1 up to rounding)
   double stats[6];  // <t>, <x>, s_x, Var(t), T_eff, sum(w)
   int32_t status;   // 0 or a negative FREDEC_E* code
   int32_t pad;
-  double inv_diag[MAXK];
-  double a_b[MAXK];                 // L_A^{-1} g_b
-  double L[MAXK * (MAXK + 1) / 2];  // Cholesky factor of the base normal matrix, packed rows
 };
 
 struct ScanWork {
@@ -52,7 +59,19 @@ struct ScanWork {
   int64_t j0;  // first grid index of the tile
 };
 
+// A grid point of the reduced-precision scan to be re-scored in float64.
+struct Rescore {
+  int32_t series;
+  int32_t pad;
+  int64_t j;
+};
+
+// Outputs requested from the preparation kernel.
+enum PrepFlags { PREP_BASE = 1, PREP_REC64 = 2, PREP_F32 = 4 };
+
 __host__ __device__ constexpr int rec_stride(int KP) { return ((KP + 3) + 1) & ~1; }
+constexpr int AUX_STRIDE = 6;  // doubles per sample of the MFMA kernel's aux record
+__host__ __device__ constexpr int col_tiles(int KP) { return (KP - 1 + 15) / 16; }
 
 // ------------------------------------------------------------ device math
 // sin(2 pi y) and cos(2 pi y) for |y| <= 1/8 by their Taylor series in y:
@@ -92,6 +111,72 @@ __device__ __forceinline__ void sincos_rev(double p, double& s, double& c) {
   c = (iq == 1 || iq == 2) ? -cc : cc;
 }
 
+// Final step of one scan frequency: 2x2 Cholesky of the Schur block
+// S = [[Scc, Scs], [Scs, Sss]] (the extension of the base factor by the trial
+// columns cos, sin - Sect. 3), a_psi = L_S^{-1} h, l_{m+1} = l_m - |a_psi|^2,
+// z = (N - 3m - 4)/2 ln(l_m / l_{m+1}) (eq. zpowrel).  Flags as in fredec.h.
+__device__ __forceinline__ void schur_finish(double Scc, double Scs, double Sss, double cc, double ss, double hc,
+                                             double hs, double f, const SeriesIn& si, const SeriesHdr& h,
+                                             double& z, uint8_t& flag, double* lratio = nullptr) {
+  if (lratio) *lratio = 1.0;
+  bool masked = false;
+  for (int k = 0; k < si.m; ++k) masked |= fabs(f - si.base_f[k]) * h.T_eff < MASK_WIDTH;
+  flag = 0;
+  z = 0.0;
+  if (masked) {
+    flag = FREDEC_FLAG_MASKED;
+    return;
+  }
+  bool ok = Scc > PIVOT_TOL * cc;
+  const double l11 = sqrt(ok ? Scc : 1.0);
+  const double l21 = Scs / l11;
+  const double d2 = Sss - l21 * l21;
+  ok = ok && (d2 > PIVOT_TOL * ss);
+  if (!ok) {
+    flag = FREDEC_FLAG_SINGULAR;
+    return;
+  }
+  const double l22 = sqrt(d2);
+  const double a1 = hc / l11;
+  const double a2 = (hs - l21 * a1) / l22;
+  const double l1 = h.l_m - (a1 * a1 + a2 * a2);
+  if (lratio) *lratio = l1 / h.l_m;
+  if (!(l1 > 0.0)) {
+    flag = FREDEC_FLAG_PERFECT;
+    z = __builtin_inf();
+    return;
+  }
+  z = 0.5 * h.NH * log(h.l_m / l1);
+}
+
+// Seed for the reduced-precision scan: float64 phase reduction (as in
+// sincos_rev), then sin/cos(2 pi y) of the reduced |y| <= 1/8 by their Taylor
+// series in float32 (coefficients (2 pi)^n / n!, first omitted terms below
+// 3e-9 and 7e-11), widened to float64.  Error about 1.5 float32 ulp.
+__device__ __forceinline__ void sincos_rev_seed32(double p, double& s, double& c) {
+  const double r = p - __builtin_rint(p);
+  const double q = __builtin_rint(4.0 * r);
+  const float y = static_cast<float>(__builtin_fma(-0.25, q, r));
+  const float y2 = y * y;
+  float sp = 42.058693944897655f;
+  sp = __builtin_fmaf(sp, y2, -76.70585975306139f);
+  sp = __builtin_fmaf(sp, y2, 81.60524927607506f);
+  sp = __builtin_fmaf(sp, y2, -41.34170224039976f);
+  sp = __builtin_fmaf(sp, y2, 6.283185307179586f);
+  sp = sp * y;
+  float cp = -26.4262567833744f;
+  cp = __builtin_fmaf(cp, y2, 60.24464137187666f);
+  cp = __builtin_fmaf(cp, y2, -85.45681720669373f);
+  cp = __builtin_fmaf(cp, y2, 64.9393940226683f);
+  cp = __builtin_fmaf(cp, y2, -19.739208802178716f);
+  cp = __builtin_fmaf(cp, y2, 1.0f);
+  const int iq = static_cast<int>(q) & 3;
+  const float ss = (iq & 1) ? cp : sp;
+  const float cc = (iq & 1) ? sp : cp;
+  s = static_cast<double>((iq & 2) ? -ss : ss);
+  c = static_cast<double>((iq == 1 || iq == 2) ? -cc : cc);
+}
+
 // Deterministic block-wide sum of NV values (fixed tree order).
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
@@ -115,7 +200,18 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
 // ------------------------------------------------------------ launchers
 hipError_t launch_prep(hipStream_t st, int n_series, const SeriesIn* sin, SeriesHdr* hdr,
                        const double* t, const double* x, const double* w,
-                       double* tau, double* xt, double* wt, double* rec, double* phi, int with_base);
+                       double* tau, double* xt, double* wt, double* rec, double* phi,
+                       float* g32, double* aux, int flags);
+hipError_t launch_scan_mfma(hipStream_t st, int NT, int FT, int n_work, const ScanWork* work,
+                            const SeriesIn* sin, const SeriesHdr* hdr, const float* g32,
+                            const double* aux, double* z, uint8_t* flags, Rescore* list,
+                            unsigned long long* count);
+hipError_t launch_rescore(hipStream_t st, int NT, int grid, const SeriesIn* sin, const SeriesHdr* hdr,
+                          const double* rec, const Rescore* list, const unsigned long long* count,
+                          double* z, uint8_t* flags);
+hipError_t launch_zero_u64(hipStream_t st, unsigned long long* p, int n);
+int mfma_freq_tiles(int NT);  // default FT of the MFMA scan kernel (16-frequency tiles per wave)
+bool mfma_tile_supported(int NT, int FT);
 hipError_t launch_scan_f64(hipStream_t st, int KP, int n_work, const ScanWork* work,
                            const SeriesIn* sin, const SeriesHdr* hdr, const double* rec,
                            double* z, uint8_t* flags);

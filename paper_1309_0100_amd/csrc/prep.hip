@@ -1,5 +1,14 @@
 // Normalisation (Sect. 4.1, eq. idn) and base-model precomputation for the
 // residual scan (eq. zpowrel): one workgroup per series.
+//
+// The base model's columns phi = (1, cos 2 pi f'_k t, sin 2 pi f'_k t) are
+// replaced by an orthonormal basis q = L_A^{-1} phi (L_A the Cholesky factor
+// of A = <phi phi^T>, Sect. 3) and the data by the base-model residual
+// r_b = x~ - q . a_b with a_b = L_A^{-1} <x~ phi>.  The statistic is unchanged
+// (the same column space and the same residual), but the scan then needs no
+// triangular solve per frequency and its sums are better conditioned:
+//   U = <q psi>, S = <psi psi^T> - U^T U, h = <r_b psi>,
+//   l_{m+1} = l_m - h^T S^{-1} h,  l_m = D - |a_b|^2,  psi = (cos, sin)(2 pi f t).
 #include "fredec_internal.h"
 
 namespace fredec {
@@ -12,9 +21,14 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict_
                                                      const double* __restrict__ t, const double* __restrict__ x,
                                                      const double* __restrict__ w, double* __restrict__ tau,
                                                      double* __restrict__ xt, double* __restrict__ wt,
-                                                     double* __restrict__ rec, double* __restrict__ phi, int with_base) {
+                                                     double* __restrict__ rec, double* __restrict__ phi,
+                                                     float* __restrict__ g32, double* __restrict__ aux, int flags) {
   __shared__ double sh[GRAM_CHUNK * BLOCK];
   __shared__ double gram[MAXKP * (MAXKP + 1) / 2];
+  __shared__ double Lsh[MAXK * (MAXK + 1) / 2];
+  __shared__ double invd[MAXK];
+  __shared__ double ab[MAXK];
+  __shared__ int status_sh;
   const int tid = threadIdx.x;
   const SeriesIn& si = sin_[blockIdx.x];
   SeriesHdr& h = hdr[blockIdx.x];
@@ -25,6 +39,7 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict_
   double* taus = tau + si.soff;
   double* xts = xt + si.soff;
   double* wts = wt + si.soff;
+  const bool with_base = (flags & PREP_BASE) != 0;
 
   // pass 1: sum of weights and input validity (Sect. 2: w_i > 0)
   double v1[2] = {0.0, 0.0};
@@ -65,10 +80,10 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict_
   const double sx = sqrt(sx2);
   const double T_eff = sqrt(4.0 * M_PI * var_t);
 
-  // pass 4: normalised series and, for scans, the base records
+  // pass 4: normalised series and, for scans, the base columns phi
   const int KP = si.KP;
+  const int K = KP - 1;
   const int m = si.m;
-  const int P = rec_stride(KP);
   for (int64_t i = tid; i < N; i += BLOCK) {
     const double wi = ws[i] / W;
     const double ta = ts[i] - tbar;
@@ -77,62 +92,97 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict_
     xts[i] = xi;
     wts[i] = wi;
     if (with_base) {
-      double* q = rec + si.rec_off + i * P;
       double* ph = phi + si.phi_off + i * KP;
-      double rs, rc;
-      sincos_rev(si.rot_step * ta, rs, rc);
-      q[0] = ta;
-      q[1] = rc;
-      q[2] = rs;
       ph[0] = 1.0;
-      q[3] = wi;
       for (int k = 0; k < m; ++k) {
         double s, c;
         sincos_rev(si.base_f[k] * ta, s, c);
         ph[1 + 2 * k] = c;
         ph[2 + 2 * k] = s;
-        q[4 + 2 * k] = wi * c;
-        q[5 + 2 * k] = wi * s;
       }
       ph[KP - 1] = xi;
-      q[3 + KP - 1] = wi * xi;
+    }
+  }
+  if (!with_base) {
+    if (tid == 0) {
+      h.T_eff = T_eff;
+      h.stats[0] = tbar;
+      h.stats[1] = xbar;
+      h.stats[2] = sx;
+      h.stats[3] = var_t;
+      h.stats[4] = T_eff;
+      h.stats[5] = W;
+      h.status = status;
+    }
+    return;
+  }
+  __syncthreads();
+
+  // Gram of the columns (1, cos f'_k, sin f'_k, x~): base normal matrix A,
+  // right-hand side g_b (last row) and D = <x~^2> (last diagonal entry).
+  const int n_ent = KP * (KP + 1) / 2;
+  const double* phs = phi + si.phi_off;
+  for (int e0 = 0; e0 < n_ent; e0 += GRAM_CHUNK) {
+    double acc[GRAM_CHUNK];
+    int ka[GRAM_CHUNK], la[GRAM_CHUNK];
+#pragma unroll
+    for (int c = 0; c < GRAM_CHUNK; ++c) {
+      acc[c] = 0.0;
+      int e = e0 + c;
+      if (e >= n_ent) e = n_ent - 1;
+      int k = 0;
+      while ((k + 1) * (k + 2) / 2 <= e) ++k;
+      ka[c] = k;
+      la[c] = e - k * (k + 1) / 2;
+    }
+    for (int64_t i = tid; i < N; i += BLOCK) {
+      const double* ph = phs + i * KP;
+      const double wi = wts[i];
+#pragma unroll
+      for (int c = 0; c < GRAM_CHUNK; ++c) acc[c] += wi * ph[ka[c]] * ph[la[c]];
+    }
+    block_sum(acc, sh);
+    if (tid == 0) {
+      for (int c = 0; c < GRAM_CHUNK && e0 + c < n_ent; ++c) gram[e0 + c] = acc[c];
     }
   }
   __syncthreads();
 
-  if (with_base) {
-    // Gram of the columns (1, cos f'_k, sin f'_k, x~): base normal matrix A,
-    // right-hand side g_b (last row) and D = <x~^2> (last diagonal entry).
-    const int n_ent = KP * (KP + 1) / 2;
-    const double* phs = phi + si.phi_off;
-    for (int e0 = 0; e0 < n_ent; e0 += GRAM_CHUNK) {
-      double acc[GRAM_CHUNK];
-      int ka[GRAM_CHUNK], la[GRAM_CHUNK];
-#pragma unroll
-      for (int c = 0; c < GRAM_CHUNK; ++c) {
-        acc[c] = 0.0;
-        int e = e0 + c;
-        if (e >= n_ent) e = n_ent - 1;
-        int k = 0;
-        while ((k + 1) * (k + 2) / 2 <= e) ++k;
-        ka[c] = k;
-        la[c] = e - k * (k + 1) / 2;
+  if (tid == 0) {
+    // Cholesky A = L L^T (Sect. 3), a_b = L^{-1} g_b, l_m = D - a_b.a_b
+    for (int j = 0; j < K && status == 0; ++j) {
+      double d = gram[j * (j + 1) / 2 + j];
+      for (int k = 0; k < j; ++k) d -= Lsh[j * (j + 1) / 2 + k] * Lsh[j * (j + 1) / 2 + k];
+      if (!(d > PIVOT_TOL * gram[j * (j + 1) / 2 + j])) {
+        status = FREDEC_ESINGULAR;
+        break;
       }
-      for (int64_t i = tid; i < N; i += BLOCK) {
-        const double* ph = phs + i * KP;
-        const double wi = wts[i];
-#pragma unroll
-        for (int c = 0; c < GRAM_CHUNK; ++c) acc[c] += wi * ph[ka[c]] * ph[la[c]];
-      }
-      block_sum(acc, sh);
-      if (tid == 0) {
-        for (int c = 0; c < GRAM_CHUNK && e0 + c < n_ent; ++c) gram[e0 + c] = acc[c];
+      const double ljj = sqrt(d);
+      Lsh[j * (j + 1) / 2 + j] = ljj;
+      invd[j] = 1.0 / ljj;
+      for (int i = j + 1; i < K; ++i) {
+        double v = gram[i * (i + 1) / 2 + j];
+        for (int k = 0; k < j; ++k) v -= Lsh[i * (i + 1) / 2 + k] * Lsh[j * (j + 1) / 2 + k];
+        Lsh[i * (i + 1) / 2 + j] = v / ljj;
       }
     }
-    __syncthreads();
-  }
-
-  if (tid == 0) {
+    double lm = 0.0;
+    if (status == 0) {
+      const double* gb = gram + K * (K + 1) / 2;  // row K: <x~ phi_k>, then D
+      double aa = 0.0;
+      for (int i = 0; i < K; ++i) {
+        double v = gb[i];
+        for (int k = 0; k < i; ++k) v -= Lsh[i * (i + 1) / 2 + k] * ab[k];
+        ab[i] = v * invd[i];
+        aa += ab[i] * ab[i];
+      }
+      h.D = gb[K];
+      h.W1 = gram[0];
+      lm = gb[K] - aa;
+    }
+    if (status == 0 && N - 3 * m - 4 <= 0) status = FREDEC_EDOF;
+    h.l_m = lm;
+    h.NH = static_cast<double>(N - 3 * m - 4);
     h.T_eff = T_eff;
     h.stats[0] = tbar;
     h.stats[1] = xbar;
@@ -140,43 +190,52 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict_
     h.stats[3] = var_t;
     h.stats[4] = T_eff;
     h.stats[5] = W;
-    h.NH = static_cast<double>(N - 3 * m - 4);
-    if (with_base) {
-      // Cholesky A = L L^T (Sect. 3), a_b = L^{-1} g_b, l_m = D - a_b.a_b
-      const int K = KP - 1;
-      for (int j = 0; j < K && status == 0; ++j) {
-        double d = gram[j * (j + 1) / 2 + j];
-        for (int k = 0; k < j; ++k) d -= h.L[j * (j + 1) / 2 + k] * h.L[j * (j + 1) / 2 + k];
-        if (!(d > PIVOT_TOL * gram[j * (j + 1) / 2 + j])) {
-          status = FREDEC_ESINGULAR;
-          break;
-        }
-        const double ljj = sqrt(d);
-        h.L[j * (j + 1) / 2 + j] = ljj;
-        h.inv_diag[j] = 1.0 / ljj;
-        for (int i = j + 1; i < K; ++i) {
-          double v = gram[i * (i + 1) / 2 + j];
-          for (int k = 0; k < j; ++k) v -= h.L[i * (i + 1) / 2 + k] * h.L[j * (j + 1) / 2 + k];
-          h.L[i * (i + 1) / 2 + j] = v / ljj;
-        }
-      }
-      double lm = 0.0;
-      if (status == 0) {
-        const double* gb = gram + K * (K + 1) / 2;  // row K: <x~ phi_k>, then D
-        double aa = 0.0;
-        for (int i = 0; i < K; ++i) {
-          double v = gb[i];
-          for (int k = 0; k < i; ++k) v -= h.L[i * (i + 1) / 2 + k] * h.a_b[k];
-          h.a_b[i] = v * h.inv_diag[i];
-          aa += h.a_b[i] * h.a_b[i];
-        }
-        h.D = gb[K];
-        lm = gb[K] - aa;
-      }
-      h.l_m = lm;
-    }
-    if (status == 0 && with_base && N - 3 * m - 4 <= 0) status = FREDEC_EDOF;
     h.status = status;
+    status_sh = status;
+  }
+  __syncthreads();
+  if (status_sh != 0) return;
+
+  // pass 5: orthonormal columns q = L^{-1} phi (in place) and residual r_b;
+  // operand records for the scan kernels
+  const int P = rec_stride(KP);
+  const int G32W = 16 * si.NT;
+  for (int64_t i = tid; i < N; i += BLOCK) {
+    double* ph = phi + si.phi_off + i * KP;
+    const double wi = wts[i];
+    double r = ph[KP - 1];
+    for (int k = 0; k < K; ++k) {
+      double v = ph[k];
+      for (int j = 0; j < k; ++j) v -= Lsh[k * (k + 1) / 2 + j] * ph[j];
+      v *= invd[k];
+      ph[k] = v;
+      r -= v * ab[k];
+    }
+    ph[KP - 1] = r;
+    const double ta = taus[i];
+    if (flags & PREP_REC64) {
+      double* q = rec + si.rec_off + i * P;
+      double rs, rc;
+      sincos_rev(si.rot_step * ta, rs, rc);
+      q[0] = ta;
+      q[1] = rc;
+      q[2] = rs;
+      for (int k = 0; k < KP; ++k) q[3 + k] = wi * ph[k];
+    }
+    if (flags & PREP_F32) {
+      float* g = g32 + si.g32_off + i * G32W;
+      for (int k = 0; k < K; ++k) g[k] = static_cast<float>(wi * ph[k]);
+      for (int k = K; k < G32W; ++k) g[k] = 0.0f;
+      double* a = aux + si.aux_off + i * AUX_STRIDE;
+      double rs, rc;
+      sincos_rev(si.rot_tile * ta, rs, rc);
+      a[0] = ta;
+      a[1] = rc;
+      a[2] = rs;
+      a[3] = wi;
+      a[4] = wi * r;
+      a[5] = 0.0;
+    }
   }
 }
 
@@ -196,9 +255,9 @@ __global__ void copy_stats_kernel(int n_series, const SeriesHdr* __restrict__ hd
 
 hipError_t launch_prep(hipStream_t st, int n_series, const SeriesIn* sin, SeriesHdr* hdr, const double* t,
                        const double* x, const double* w, double* tau, double* xt, double* wt, double* rec,
-                       double* phi, int with_base) {
+                       double* phi, float* g32, double* aux, int flags) {
   if (n_series <= 0) return hipSuccess;
-  prep_kernel<<<n_series, BLOCK, 0, st>>>(sin, hdr, t, x, w, tau, xt, wt, rec, phi, with_base);
+  prep_kernel<<<n_series, BLOCK, 0, st>>>(sin, hdr, t, x, w, tau, xt, wt, rec, phi, g32, aux, flags);
   return hipGetLastError();
 }
 

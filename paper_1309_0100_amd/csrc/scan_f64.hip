@@ -2,18 +2,19 @@
 //
 // Layout: one lane owns R grid frequencies f_{j0+t+256r}, r = 0..R-1, and
 // walks over all samples of its series.  The per-sample record
-// [tau, cos(2 pi s tau), sin(2 pi s tau), w~ phi_0 .. w~ phi_{KP-1}] (s = 256 df,
-// phi = 1, cos f'_k tau, sin f'_k tau, x~) is the same for every lane, so it is
-// read with scalar loads and used as a scalar operand: no LDS and no
-// cross-lane reduction is needed.  cos/sin of the first frequency come from
-// the float64 phase reduction; the other R-1 follow by rotation with the
-// record's (cos, sin)(2 pi s tau).  Per frequency the lane accumulates
-//   B_c[k] = <phi_k cos>, B_s[k] = <phi_k sin> (k < K), <x~ cos>, <x~ sin>,
+// [tau, cos(2 pi s tau), sin(2 pi s tau), w~ q_0 .. w~ q_{K-1}, w~ r_b]
+// (s = 256 df; q the orthonormal base columns, r_b the base residual, both
+// from the preparation kernel) is the same for every lane, so it is read with
+// scalar loads and used as a scalar operand: no LDS and no cross-lane
+// reduction is needed.  cos/sin of the first frequency come from the float64
+// phase reduction; the other R-1 follow by rotation with the record's
+// (cos, sin)(2 pi s tau).  Per frequency the lane accumulates
+//   U_c[k] = <q_k cos>, U_s[k] = <q_k sin>, h = <r_b cos>, <r_b sin>,
 //   <cos^2>, <cos sin>, <sin^2>
 // and the epilogue extends the base Cholesky factor by the 2x2 Schur block of
 // the trial column pair (the incremental extension of Sect. 3):
-//   U = L_A^{-1} B, S = C - U^T U, a_psi = L_S^{-1}(g_psi - U^T a_b),
-//   l_{m+1} = l_m - |a_psi|^2,  z = (N - 3m - 4)/2 ln(l_m / l_{m+1}).
+//   S = C - U^T U, a_psi = L_S^{-1} h, l_{m+1} = l_m - |a_psi|^2,
+//   z = (N - 3m - 4)/2 ln(l_m / l_{m+1}).
 #include "fredec_internal.h"
 
 namespace fredec {
@@ -25,62 +26,27 @@ constexpr int R_of(int KP) {
   return r < 1 ? 1 : (r > 8 ? 8 : r);
 }
 
+// Epilogue of one frequency from its sums (orthonormal base columns q_k,
+// base residual r_b; see the preparation kernel):
+//   acc[0], acc[1]          <q_0 cos>, <q_0 sin>
+//   acc[2], acc[3], acc[4]  <cos^2>, <cos sin>, <sin^2>
+//   acc[3+2k], acc[4+2k]    <q_k cos>, <q_k sin> (k = 1..K-1), then <r_b cos>, <r_b sin> (k = K)
 template <int KP>
 __device__ __forceinline__ void scan_epilogue(const double (&acc)[2 * KP + 3], double f, const SeriesIn& si,
                                               const SeriesHdr& h, double& z, uint8_t& flag) {
   constexpr int K = KP - 1;
-  double uc[K], us[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double bc = (k == 0) ? acc[0] : acc[3 + 2 * k];
-    double bs = (k == 0) ? acc[1] : acc[4 + 2 * k];
-#pragma unroll
-    for (int j = 0; j < k; ++j) {
-      const double l = h.L[k * (k + 1) / 2 + j];
-      bc = __builtin_fma(-l, uc[j], bc);
-      bs = __builtin_fma(-l, us[j], bs);
-    }
-    uc[k] = bc * h.inv_diag[k];
-    us[k] = bs * h.inv_diag[k];
-  }
-  double cc = acc[2], ss = acc[4];
+  const double cc = acc[2], ss = acc[4];
   double Scc = cc, Scs = acc[3], Sss = ss;
-  double gc = acc[3 + 2 * K], gs = acc[4 + 2 * K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    Scc = __builtin_fma(-uc[k], uc[k], Scc);
-    Scs = __builtin_fma(-uc[k], us[k], Scs);
-    Sss = __builtin_fma(-us[k], us[k], Sss);
-    gc = __builtin_fma(-uc[k], h.a_b[k], gc);
-    gs = __builtin_fma(-us[k], h.a_b[k], gs);
+    const double uc = (k == 0) ? acc[0] : acc[3 + 2 * k];
+    const double us = (k == 0) ? acc[1] : acc[4 + 2 * k];
+    Scc = __builtin_fma(-uc, uc, Scc);
+    Scs = __builtin_fma(-uc, us, Scs);
+    Sss = __builtin_fma(-us, us, Sss);
   }
-  bool masked = false;
-  for (int k = 0; k < si.m; ++k) masked |= fabs(f - si.base_f[k]) * h.T_eff < MASK_WIDTH;
-  flag = 0;
-  z = 0.0;
-  if (masked) {
-    flag = FREDEC_FLAG_MASKED;
-    return;
-  }
-  bool ok = Scc > PIVOT_TOL * cc;
-  const double l11 = sqrt(ok ? Scc : 1.0);
-  const double l21 = Scs / l11;
-  const double d2 = Sss - l21 * l21;
-  ok = ok && (d2 > PIVOT_TOL * ss);
-  if (!ok) {
-    flag = FREDEC_FLAG_SINGULAR;
-    return;
-  }
-  const double l22 = sqrt(d2);
-  const double a1 = gc / l11;
-  const double a2 = (gs - l21 * a1) / l22;
-  const double l1 = h.l_m - (a1 * a1 + a2 * a2);
-  if (!(l1 > 0.0)) {
-    flag = FREDEC_FLAG_PERFECT;
-    z = __builtin_inf();
-    return;
-  }
-  z = 0.5 * h.NH * log(h.l_m / l1);
+  const double hc = acc[3 + 2 * K], hs = acc[4 + 2 * K];
+  schur_finish(Scc, Scs, Sss, cc, ss, hc, hs, f, si, h, z, flag);
 }
 
 template <int KP, int R>

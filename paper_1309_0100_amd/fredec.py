@@ -22,6 +22,7 @@ FP64 = 0
 FP32 = 1
 
 OK, EINVAL, EDOF, EWEIGHT, EDEGEN, ESINGULAR, ENOMEM, EDEVICE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7, -8
+TILE_SCAN_MFMA = 1
 FLAG_MASKED, FLAG_SINGULAR, FLAG_PERFECT, FLAG_DEGENERATE, FLAG_BADSERIES = 1, 2, 4, 8, 128
 
 c_i32, c_i64, c_sz, c_p, c_d = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
@@ -33,6 +34,7 @@ _SIGS = {
     "fredec_destroy": (None, [c_p]),
     "fredec_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fredec_version": (ctypes.c_int, []),
+    "fredec_set_tile": (c_i32, [c_p, c_i32, c_i32, c_i32]),
     "fredec_profile": (c_i32, [c_p, c_i32]),
     "fredec_profile_read": (c_i32, [c_p, ctypes.POINTER(c_d), ctypes.POINTER(c_i64)]),
     "fredec_normalize_workspace": (c_i32, [c_i32, c_szp]),
@@ -65,6 +67,10 @@ def load():
     """Load libfredec.so (built in-tree) and declare its signatures."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname as the system
+        # one; loading torch first makes libfredec bind to that single runtime
+        # (two runtimes in one process would not share devices or streams).
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1309_0100_amd.build`")
         lib = ctypes.CDLL(LIB_PATH)
@@ -105,12 +111,15 @@ def _stream(device):
 class Context:
     """A libfredec context bound to one GPU."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tuning: bool = True):
         lib = load()
         h = ctypes.c_void_p()
         _check(lib.fredec_create(ctypes.byref(h), device), "fredec_create")
         self.handle = h
         self.device = device
+        if tuning:
+            from . import autotune
+            autotune.apply(self)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -122,6 +131,9 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_tile(self, kernel: int, key: int, value: int):
+        _check(load().fredec_set_tile(self.handle, kernel, key, value), "fredec_set_tile")
 
     def profile(self, enable: bool = True):
         _check(load().fredec_profile(self.handle, int(enable)), "fredec_profile")

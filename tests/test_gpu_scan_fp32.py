@@ -1,0 +1,118 @@
+"""GPU parity of the reduced-precision residual scan (float32 MFMA sums,
+float64 phase reduction and solves) against the float64 oracle.
+
+Bound (relative error err = |z - z_ref| / max(z_ref, 1)): 1e-6 on every grid
+frequency that the oracle does not flag.  Grid points whose trial columns lie
+nearly in the span of the base model (relative Schur pivot < 0.5: next to a
+base frequency, or f T_eff of order 1 and below) and the tops of strong peaks
+(l_{m+1} < l_m / 2) are re-scored in float64 by the library and carry flag
+bit 6; the rest come from the float32 MFMA sums.
+The masking decision uses float64 frequencies only and must match exactly."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1309_0100_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1309_0100_amd import fredec as F
+    return F.Context(0)
+
+
+def compare(z, fl, ref, tol=TOL32, label=""):
+    z = z.cpu().numpy() if hasattr(z, "cpu") else z
+    fl = fl.cpu().numpy() if hasattr(fl, "cpu") else fl
+    T = ref.T_eff
+    assert np.array_equal(fl & 1, ref.flags & 1), "masking differs"
+    base_fl = fl & ~np.uint8(64)
+    good = (ref.flags == 0) & (base_fl == 0)
+    assert np.array_equal(base_fl, ref.flags), "flags differ"
+    e = np.abs(z - ref.z) / np.maximum(np.abs(ref.z), 1.0)
+    resc = (fl & 64) != 0
+    low = np.abs(ref.freqs) * T < 1.0
+    print(f"{label}: max err {e[good].max(initial=0):.3e} over {good.sum()} points; "
+          f"float32 points {e[good & ~resc].max(initial=0):.3e} ({(good & ~resc).sum()}), "
+          f"re-scored {e[good & resc].max(initial=0):.3e} ({(good & resc).sum()}), "
+          f"f*T_eff<1 {e[good & low].max(initial=0):.3e} ({(good & low).sum()})", flush=True)
+    assert e[good].max(initial=0.0) <= tol
+    return e[good].max(initial=0.0)
+
+
+def test_fp32_residual_workload_sampled(ctx):
+    from paper_1309_0100_amd import fredec as F
+    s = synth.residual()
+    print("case: fp32 residual N=2000 F=1e6 m=4", flush=True)
+    z, fl, lb, st = ctx.scan_series(s.t, s.x, s.w, s.base_f, s.df, s.F, precision=F.FP32)
+    z, fl = z.cpu().numpy(), fl.cpu().numpy()
+    rng = np.random.default_rng(3)
+    idx = [rng.choice(s.F, size=1500, replace=False), np.arange(0, 600, 7)]
+    for f in s.base_f:
+        j = int(round(f / s.df)) - 1
+        idx.append(np.arange(max(0, j - 60), min(s.F, j + 61)))
+    idx = np.unique(np.concatenate(idx))
+    ref = O.scan(s.t, s.x, s.w, s.base_f, s.df, s.F, idx=idx)
+    compare(z[idx], fl[idx], ref, label="residual fp32")
+
+
+@pytest.mark.parametrize("m,N,F", [(0, 500, 3001), (3, 400, 2500), (7, 600, 2049), (8, 700, 1500),
+                                   (12, 500, 1300), (20, 900, 700)])
+def test_fp32_base_models(ctx, m, N, F):
+    from paper_1309_0100_amd import fredec as Fr
+    s = synth.random_series(400 + m, N, span=500.0, n_sin=3)
+    rng = np.random.default_rng(m)
+    base = np.concatenate([s.true_f, rng.uniform(0.01, 0.7, size=max(0, m - 3))])[:m]
+    df = 0.8 / F
+    print(f"case: fp32 m={m} N={N} F={F}", flush=True)
+    z, fl, lb, st = ctx.scan_series(s.t, s.x, s.w, base, df, F, precision=Fr.FP32)
+    ref = O.scan(s.t, s.x, s.w, base, df, F)
+    assert int(st.item()) == 0
+    assert abs(float(lb.item()) - ref.l_base) < 1e-13
+    compare(z, fl, ref, label=f"m={m}")
+
+
+def test_fp32_batched_uneven(ctx):
+    from paper_1309_0100_amd import fredec as Fr
+    specs = [(80, 0, 100), (300, 3, 4097), (120, 1, 513), (640, 9, 1000), (90, 2, 1), (1000, 0, 3000)]
+    ts, xs, ws, bs, soff, boff, dfs, Fs = [], [], [], [], [0], [0], [], []
+    for k, (N, m, F) in enumerate(specs):
+        s = synth.random_series(500 + k, N, span=80.0 + 40 * k, n_sin=2)
+        base = np.random.default_rng(k).uniform(0.02, 0.5, size=m)
+        ts.append(s.t); xs.append(s.x); ws.append(s.w); bs.append(base)
+        soff.append(soff[-1] + N); boff.append(boff[-1] + m)
+        dfs.append(1.1 / F); Fs.append(F)
+    print("case: fp32 batched", specs, flush=True)
+    z, fl, lb, st = ctx.scan(np.concatenate(ts), np.concatenate(xs), np.concatenate(ws), soff,
+                             np.concatenate(bs), boff, dfs, Fs, precision=Fr.FP32)
+    z, fl = z.cpu().numpy(), fl.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    g = 0
+    for k in range(len(specs)):
+        ref = O.scan(ts[k], xs[k], ws[k], bs[k], dfs[k], Fs[k])
+        compare(z[g:g + Fs[k]], fl[g:g + Fs[k]], ref, label=f"series {k}")
+        g += Fs[k]
+
+
+def test_fp32_tile_settings_and_determinism(ctx):
+    """Every tile setting gives the same statistic up to the rounding of the
+    trig recurrence (its depth per frequency depends on the tile), and a
+    repeated call gives identical bytes."""
+    from paper_1309_0100_amd import fredec as Fr
+    s = synth.random_series(600, 700, n_sin=2)
+    outs = []
+    for ft in (2, 4, 8, 0):
+        ctx.set_tile(Fr.TILE_SCAN_MFMA, 1, ft)
+        outs.append(ctx.scan_series(s.t, s.x, s.w, [0.05, 0.3], 2e-4, 5000, precision=Fr.FP32)[0].cpu().numpy())
+    again = ctx.scan_series(s.t, s.x, s.w, [0.05, 0.3], 2e-4, 5000, precision=Fr.FP32)[0].cpu().numpy()
+    assert again.tobytes() == outs[-1].tobytes()
+    for o in outs[:-1]:
+        assert np.max(np.abs(o - outs[-1]) / np.maximum(np.abs(outs[-1]), 1.0)) < TOL32
+    with pytest.raises(Fr.FredecError):
+        ctx.set_tile(Fr.TILE_SCAN_MFMA, 1, 3)
