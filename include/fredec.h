@@ -70,6 +70,7 @@ enum {
   FREDEC_FLAG_SINGULAR = 2,   /* Cholesky pivot below 1e-13 of its diagonal: z := 0 */
   FREDEC_FLAG_PERFECT = 4,    /* l <= 0 (perfect fit): z := +inf */
   FREDEC_FLAG_DEGENERATE = 8, /* tuple with merged frequencies or singular matrix: z := -inf */
+  FREDEC_FLAG_CONVERGED = 16, /* tuple refinement stopped on the step tolerance */
   FREDEC_FLAG_RESCORED = 64,  /* FREDEC_FP32 scan: trial columns nearly in the base span (relative
                                  Schur pivot < 0.5) or a strong peak (l_{m+1} < l_m / 2):
                                  value recomputed in float64 */
@@ -145,6 +146,59 @@ int fredec_scan_at(fredec_ctx* ctx, void* stream, const double* t, const double*
                    int64_t N, const double* base_f_host, int32_t m, double df,
                    const int64_t* idx, int64_t n_idx, void* workspace, size_t ws_bytes,
                    double* z_out, uint8_t* flags_out);
+
+/* Tuple statistics (eq. zpow; Sects. 2, 3, 4.3) --------------------------
+ * One series t, x, w (device, N samples) and a pool of n_pool <= FREDEC_MAX_POOL
+ * frequencies (host pool[n_pool]).  Tuple k is the subset of the pool given by
+ * the bits of masks[k] (host; bit b selects pool[b]); masks == NULL means all
+ * 2^n_pool - 1 subsets in increasing mask order (n_tuples must then equal
+ * 2^n_pool - 1).  For each tuple of n frequencies:
+ *   l = min over theta of <(x~ - mu)^2> for the model of eq. Hn,
+ *   z = (N - 3n - 1)/2 ln(l_0 / l), l_0 the constant-model minimum.
+ * refine_steps = 0 evaluates at the pool frequencies.  refine_steps = R > 0
+ * makes 1 + R float64 least-squares passes per tuple: Gauss-Newton steps on
+ * the frequencies with theta re-solved at each iterate (Sect. 3, eq. lsqf),
+ * each step scaled to max |df| T_eff <= 0.25, a trial point accepted if
+ * l <= l_acc (1 + 1e-12) and otherwise the step halved (at most 5 times in a
+ * row), stopping once max |df| T_eff < 1e-10 (flag FREDEC_FLAG_CONVERGED).
+ * Outputs (device, nullable): l_out[n_tuples], z_out[n_tuples],
+ * f_out[n_tuples * n_pool] (the accepted frequencies of the members at their
+ * pool index, NaN elsewhere), flags_out[n_tuples] (FREDEC_FLAG_DEGENERATE:
+ * two frequencies within 0.05 / T_eff or a singular normal matrix, z = -inf;
+ * FREDEC_FLAG_PERFECT: l <= 0, z = +inf).  The sums are float64 (MFMA) for
+ * both precisions.  Errors: EINVAL, ENOTSUP (n_pool > FREDEC_MAX_POOL),
+ * EDOF (N - 3 n_max - 1 <= 0), ENOMEM. */
+int fredec_tuples_workspace(int64_t N, int32_t n_pool, const uint64_t* masks_host, int64_t n_tuples,
+                            int32_t refine_steps, size_t* bytes);
+int fredec_tuples(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                  const double* pool_host, int32_t n_pool, const uint64_t* masks_host, int64_t n_tuples,
+                  int32_t refine_steps, int32_t precision, void* workspace, size_t ws_bytes,
+                  double* l_out, double* z_out, double* f_out, uint8_t* flags_out);
+
+/* z and its gradient for ragged tuples: tuple k owns the frequencies
+ * f[toff[k] .. toff[k+1]) (f device float64, toff host int64, toff[0] = 0,
+ * 1 <= toff[k+1] - toff[k] <= FREDEC_MAX_POOL).  By the envelope theorem on
+ * l = min_theta chi^2: dz/df_k = (N_H / l) <r J_k>, with r = x~ - Phi theta*
+ * and J_k = d mu / d f_k = 2 pi t (-a_k sin 2 pi f_k t + b_k cos 2 pi f_k t);
+ * h_k = (N_H / l) <J_k^2> is the diagonal Gauss-Newton curvature.  The
+ * adjoint recomputes the trig terms sample by sample (nothing of size N x n
+ * is stored).  Outputs (device, nullable): z_out, l_out, flags_out
+ * [n_tuples]; theta_out [sum(2 n_k + 1)], tuple k at offset 2 toff[k] + k
+ * (c, a_1, b_1, ..., a_n, b_n); dz_df, h_out [toff[n_tuples]]. */
+int fredec_grad_workspace(int64_t N, const int64_t* toff_host, int64_t n_tuples, size_t* bytes);
+int fredec_grad(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                const double* f, const int64_t* toff_host, int64_t n_tuples, int32_t precision,
+                void* workspace, size_t ws_bytes, double* z_out, double* l_out, double* theta_out,
+                double* dz_df, double* h_out, uint8_t* flags_out);
+
+/* Fixed-step preconditioned ascent of z for ragged tuples (workspace as for
+ * fredec_grad): `steps` times f_k += clamp(<r J_k> / <J_k^2>, +-clamp / T_eff),
+ * then a final evaluation.  f (device) is updated in place; outputs as for
+ * fredec_grad. */
+int fredec_ascent(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                  double* f, const int64_t* toff_host, int64_t n_tuples, int32_t steps, double clamp,
+                  int32_t precision, void* workspace, size_t ws_bytes, double* z_out, double* l_out,
+                  uint8_t* flags_out);
 
 #ifdef __cplusplus
 }

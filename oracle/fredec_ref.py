@@ -303,7 +303,7 @@ class Refined:
     f: np.ndarray
     l: float
     z: float
-    converged: bool
+    converged: bool    # the iteration stopped on the step tolerance
     passes: int
     flag: int
 
@@ -330,6 +330,7 @@ def gn_refine(nrm: Normalized, f0, steps: int, clamp: float = 0.25, max_halvings
     f_try = f0.copy()
     halvings = 0
     done = False
+    converged = False      # stopped because the step fell below tol
     passes = 0
     for _ in range(steps + 1):
         if done:
@@ -345,6 +346,7 @@ def gn_refine(nrm: Normalized, f0, steps: int, clamp: float = 0.25, max_halvings
             big = np.max(np.abs(step)) * T
             if not ok or big < tol:
                 done = True
+                converged = ok
                 continue
             if big > clamp:
                 step = step * (clamp / big)
@@ -358,8 +360,8 @@ def gn_refine(nrm: Normalized, f0, steps: int, clamp: float = 0.25, max_halvings
                 continue
         f_try = f_acc + step
     if l_acc <= 0:
-        return Refined(f_acc, l_acc, np.inf, done, passes, FLAG_PERFECT)
-    return Refined(f_acc, l_acc, 0.5 * NH * math.log(l0 / l_acc), done, passes, 0)
+        return Refined(f_acc, l_acc, np.inf, converged, passes, FLAG_PERFECT)
+    return Refined(f_acc, l_acc, 0.5 * NH * math.log(l0 / l_acc), converged, passes, 0)
 
 
 def ascent(nrm: Normalized, f0, steps: int = 20, clamp: float = 0.1):

@@ -11,20 +11,6 @@
 
 using namespace fredec;
 
-struct fredec_ctx {
-  int device = 0;
-  int n_cu = 0;
-  void* staging = nullptr;  // pinned host buffer for descriptor uploads
-  size_t staging_bytes = 0;
-  hipEvent_t staging_done = nullptr;
-  bool staging_pending = false;
-  // optional timing of the dominant kernel of each call (HIP events)
-  int mfma_ft[5] = {0, 0, 0, 0, 0};  // MFMA scan: 16-frequency tiles per wave, by column tiles (0 = default)
-  bool profiling = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
-  size_t prof_used = 0;
-};
-
 namespace fredec {
 
 DeviceGuard::DeviceGuard(int dev) {

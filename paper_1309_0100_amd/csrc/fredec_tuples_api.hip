@@ -1,0 +1,344 @@
+// C ABI of the tuple statistics: fredec_tuples (all subsets of a pool, fixed
+// or refined frequencies), fredec_grad / fredec_adjoint (z and dz/df of
+// ragged tuples) and fredec_ascent (fixed-step preconditioned ascent).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fredec_api_internal.h"
+#include "fredec_tuples_internal.h"
+
+using namespace fredec;
+
+namespace {
+
+template <typename T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+int popcount64(uint64_t v) { return __builtin_popcountll(v); }
+
+// Host-side plan of a tuple batch: descriptors and workspace layout.
+struct TuplePlan {
+  std::vector<TupleDesc> desc;
+  std::vector<int32_t> order;                 // tuple indices sorted by Gram blocks
+  std::vector<std::pair<int, int>> groups;    // (NB, count) in `order`
+  int64_t nf = 0, ngram = 0, nscratch = 0, ntheta = 0;
+  int max_n = 0;
+  size_t off_sin = 0, off_hdr = 0, off_com = 0, off_tau = 0, off_xt = 0, off_wt = 0, off_desc = 0, off_order = 0,
+         off_state = 0, off_ftry = 0, off_facc = 0, off_step = 0, off_theta = 0, off_gram = 0, off_scr = 0,
+         off_g = 0, off_h = 0, off_members = 0, total = 0;
+};
+
+// sizes[k] = number of frequencies of tuple k; gn = whether Gauss-Newton
+// columns are needed (refinement).
+int make_plan(int64_t N, const std::vector<int>& sizes, bool gn, TuplePlan& P) {
+  const int64_t nt = static_cast<int64_t>(sizes.size());
+  if (nt <= 0 || nt > (int64_t(1) << 30)) return FREDEC_EINVAL;
+  P.desc.resize(nt);
+  for (int64_t k = 0; k < nt; ++k) {
+    const int n = sizes[k];
+    if (n < 1) return FREDEC_EINVAL;
+    if (n > MAXPOOL) return FREDEC_ENOTSUP;
+    P.max_n = std::max(P.max_n, n);
+    const int C = gn ? 4 * n + 2 : 2 * n + 2;
+    const int K = 2 * n + 1;
+    TupleDesc& d = P.desc[k];
+    d.n = n;
+    d.nb = (C + 15) / 16;
+    d.foff = P.nf;
+    d.goff = P.ngram;
+    d.soff = P.nscratch;
+    d.thoff = P.ntheta;
+    P.nf += n;
+    P.ngram += static_cast<int64_t>(C) * (C + 1) / 2;
+    P.nscratch += gn ? static_cast<int64_t>(K) * n + n * (n + 1) / 2 + n : 0;
+    P.ntheta += K;
+  }
+  if (N - 3 * static_cast<int64_t>(P.max_n) - 1 <= 0) return FREDEC_EDOF;
+  P.order.resize(nt);
+  for (int64_t k = 0; k < nt; ++k) P.order[k] = static_cast<int32_t>(k);
+  std::stable_sort(P.order.begin(), P.order.end(), [&](int32_t a, int32_t b) { return P.desc[a].nb < P.desc[b].nb; });
+  for (int64_t k = 0; k < nt; ++k) {
+    const int nb = P.desc[P.order[k]].nb;
+    if (P.groups.empty() || P.groups.back().first != nb) P.groups.push_back({nb, 0});
+    P.groups.back().second++;
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  P.off_sin = take(sizeof(SeriesIn));
+  P.off_hdr = take(sizeof(SeriesHdr));
+  P.off_com = take(sizeof(TupleCommon));
+  P.off_tau = take(sizeof(double) * N);
+  P.off_xt = take(sizeof(double) * N);
+  P.off_wt = take(sizeof(double) * N);
+  P.off_desc = take(sizeof(TupleDesc) * nt);
+  P.off_order = take(sizeof(int32_t) * nt);
+  P.off_state = take(sizeof(TupleState) * nt);
+  P.off_ftry = take(sizeof(double) * P.nf);
+  P.off_facc = take(sizeof(double) * P.nf);
+  P.off_step = take(sizeof(double) * P.nf);
+  P.off_theta = take(sizeof(double) * P.ntheta);
+  P.off_gram = take(sizeof(double) * P.ngram);
+  P.off_scr = take(sizeof(double) * P.nscratch);
+  P.off_g = take(sizeof(double) * P.nf);
+  P.off_h = take(sizeof(double) * P.nf);
+  P.off_members = take(P.nf);
+  P.total = off;
+  return FREDEC_OK;
+}
+
+// Device pointers of a planned workspace.
+struct TupleDev {
+  SeriesIn* sin;
+  SeriesHdr* hdr;
+  TupleCommon* com;
+  double *tau, *xt, *wt;
+  TupleDesc* desc;
+  int32_t* order;
+  TupleState* state;
+  double *ftry, *facc, *step, *theta, *gram, *scr, *g, *h;
+  int8_t* members;
+};
+
+TupleDev dev_ptrs(void* ws, const TuplePlan& P) {
+  TupleDev D;
+  D.sin = at<SeriesIn>(ws, P.off_sin);
+  D.hdr = at<SeriesHdr>(ws, P.off_hdr);
+  D.com = at<TupleCommon>(ws, P.off_com);
+  D.tau = at<double>(ws, P.off_tau);
+  D.xt = at<double>(ws, P.off_xt);
+  D.wt = at<double>(ws, P.off_wt);
+  D.desc = at<TupleDesc>(ws, P.off_desc);
+  D.order = at<int32_t>(ws, P.off_order);
+  D.state = at<TupleState>(ws, P.off_state);
+  D.ftry = at<double>(ws, P.off_ftry);
+  D.facc = at<double>(ws, P.off_facc);
+  D.step = at<double>(ws, P.off_step);
+  D.theta = at<double>(ws, P.off_theta);
+  D.gram = at<double>(ws, P.off_gram);
+  D.scr = at<double>(ws, P.off_scr);
+  D.g = at<double>(ws, P.off_g);
+  D.h = at<double>(ws, P.off_h);
+  D.members = at<int8_t>(ws, P.off_members);
+  return D;
+}
+
+// Normalisation of the series and the tuple descriptors on the device.
+int upload_and_normalise(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, const double* t,
+                         const double* x, const double* w, int64_t N) {
+  SeriesIn si;
+  std::memset(&si, 0, sizeof(si));
+  si.N = N;
+  si.F = 1;
+  int rc;
+  if ((rc = upload(ctx, st, D.sin, &si, sizeof(si)))) return rc;
+  if ((rc = upload(ctx, st, D.desc, P.desc.data(), sizeof(TupleDesc) * P.desc.size()))) return rc;
+  if ((rc = upload(ctx, st, D.order, P.order.data(), sizeof(int32_t) * P.order.size()))) return rc;
+  if (launch_prep(st, 1, D.sin, D.hdr, t, x, w, D.tau, D.xt, D.wt, nullptr, nullptr, nullptr, nullptr, 0) !=
+      hipSuccess)
+    return FREDEC_EDEVICE;
+  if (launch_tuple_common(st, D.hdr, N, D.com) != hipSuccess) return FREDEC_EDEVICE;
+  if (launch_tuple_init(st, static_cast<int>(P.desc.size()), D.state) != hipSuccess) return FREDEC_EDEVICE;
+  return FREDEC_OK;
+}
+
+int gram_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, int mode) {
+  ProfScope prof(ctx, st);
+  int64_t base = 0;
+  for (auto& g : P.groups) {
+    if (launch_tuple_gram(st, g.first, D.desc, D.order + base, g.second, D.com, D.tau, D.xt, D.wt, D.ftry, D.state,
+                          D.gram, mode) != hipSuccess)
+      return FREDEC_EDEVICE;
+    base += g.second;
+  }
+  return FREDEC_OK;
+}
+
+// Forward evaluation (and optional Gauss-Newton refinement) of every tuple.
+int run_fit(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, int refine_steps) {
+  const int nt = static_cast<int>(P.desc.size());
+  const int mode = refine_steps > 0 ? TUPLE_GN : TUPLE_FWD;
+  for (int it = 0; it <= refine_steps; ++it) {
+    int rc = gram_pass(ctx, st, P, D, mode);
+    if (rc) return rc;
+    if (launch_tuple_solve(st, D.desc, nt, D.com, D.gram, D.scr, D.ftry, D.facc, D.step, D.theta, D.state, mode,
+                           it == refine_steps ? 1 : 0) != hipSuccess)
+      return FREDEC_EDEVICE;
+  }
+  return FREDEC_OK;
+}
+
+int check_series_args(const double* t, const double* x, const double* w, int64_t N) {
+  if (!t || !x || !w || N <= 0) return FREDEC_EINVAL;
+  return FREDEC_OK;
+}
+
+int sizes_from_toff(const int64_t* toff, int64_t n_tuples, std::vector<int>& sizes) {
+  if (!toff || n_tuples <= 0 || toff[0] != 0) return FREDEC_EINVAL;
+  sizes.resize(n_tuples);
+  for (int64_t k = 0; k < n_tuples; ++k) {
+    const int64_t n = toff[k + 1] - toff[k];
+    if (n < 1) return FREDEC_EINVAL;
+    if (n > MAXPOOL) return FREDEC_ENOTSUP;
+    sizes[k] = static_cast<int>(n);
+  }
+  return FREDEC_OK;
+}
+
+int sizes_from_masks(int32_t n_pool, const uint64_t* masks, int64_t n_tuples, std::vector<int>& sizes) {
+  if (n_pool < 1) return FREDEC_EINVAL;
+  if (n_pool > MAXPOOL) return FREDEC_ENOTSUP;
+  const uint64_t full = (uint64_t(1) << n_pool) - 1;
+  if (!masks && n_tuples != static_cast<int64_t>(full)) return FREDEC_EINVAL;
+  if (n_tuples <= 0) return FREDEC_EINVAL;
+  sizes.resize(n_tuples);
+  for (int64_t k = 0; k < n_tuples; ++k) {
+    const uint64_t m = masks ? masks[k] : static_cast<uint64_t>(k + 1);
+    if (m == 0 || (m & ~full)) return FREDEC_EINVAL;
+    sizes[k] = popcount64(m);
+  }
+  return FREDEC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fredec_tuples_workspace(int64_t N, int32_t n_pool, const uint64_t* masks, int64_t n_tuples, int32_t refine_steps,
+                            size_t* bytes) {
+  if (!bytes || N <= 0 || refine_steps < 0) return FREDEC_EINVAL;
+  std::vector<int> sizes;
+  int rc = sizes_from_masks(n_pool, masks, n_tuples, sizes);
+  if (rc) return rc;
+  TuplePlan P;
+  if ((rc = make_plan(N, sizes, refine_steps > 0, P))) return rc;
+  *bytes = P.total;
+  return FREDEC_OK;
+}
+
+int fredec_tuples(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                  const double* pool, int32_t n_pool, const uint64_t* masks, int64_t n_tuples, int32_t refine_steps,
+                  int32_t precision, void* ws, size_t ws_bytes, double* l_out, double* z_out, double* f_out,
+                  uint8_t* flags_out) {
+  int rc = check_series_args(t, x, w, N);
+  if (rc) return rc;
+  if (!pool || refine_steps < 0) return FREDEC_EINVAL;
+  if (precision != FREDEC_FP64 && precision != FREDEC_FP32) return FREDEC_EINVAL;
+  std::vector<int> sizes;
+  if ((rc = sizes_from_masks(n_pool, masks, n_tuples, sizes))) return rc;
+  for (int k = 0; k < n_pool; ++k)
+    if (!std::isfinite(pool[k])) return FREDEC_EINVAL;
+  TuplePlan P;
+  if ((rc = make_plan(N, sizes, refine_steps > 0, P))) return rc;
+  if (!ws || ws_bytes < P.total) return FREDEC_ENOMEM;
+  if (!ctx) return FREDEC_EINVAL;
+  // starting frequencies and pool indices of the members, in bit order
+  std::vector<double> f0(P.nf);
+  std::vector<int8_t> mem(P.nf);
+  for (int64_t k = 0; k < n_tuples; ++k) {
+    const uint64_t m = masks ? masks[k] : static_cast<uint64_t>(k + 1);
+    int64_t o = P.desc[k].foff;
+    for (int b = 0; b < n_pool; ++b)
+      if (m >> b & 1) {
+        f0[o] = pool[b];
+        mem[o] = static_cast<int8_t>(b);
+        ++o;
+      }
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TupleDev D = dev_ptrs(ws, P);
+  if ((rc = upload_and_normalise(ctx, st, P, D, t, x, w, N))) return rc;
+  if ((rc = upload(ctx, st, D.ftry, f0.data(), sizeof(double) * P.nf))) return rc;
+  if ((rc = upload(ctx, st, D.members, mem.data(), P.nf))) return rc;
+  if ((rc = run_fit(ctx, st, P, D, refine_steps))) return rc;
+  if (launch_tuple_finish(st, D.desc, static_cast<int>(n_tuples), D.com, D.state, D.facc, l_out, z_out, flags_out,
+                          f_out, D.members, n_pool) != hipSuccess)
+    return FREDEC_EDEVICE;
+  return FREDEC_OK;
+}
+
+int fredec_grad_workspace(int64_t N, const int64_t* toff, int64_t n_tuples, size_t* bytes) {
+  if (!bytes || N <= 0) return FREDEC_EINVAL;
+  std::vector<int> sizes;
+  int rc = sizes_from_toff(toff, n_tuples, sizes);
+  if (rc) return rc;
+  TuplePlan P;
+  if ((rc = make_plan(N, sizes, false, P))) return rc;
+  *bytes = P.total;
+  return FREDEC_OK;
+}
+
+int fredec_grad(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                const double* f, const int64_t* toff, int64_t n_tuples, int32_t precision, void* ws, size_t ws_bytes,
+                double* z_out, double* l_out, double* theta_out, double* dz_df, double* h_out, uint8_t* flags_out) {
+  int rc = check_series_args(t, x, w, N);
+  if (rc) return rc;
+  if (!f) return FREDEC_EINVAL;
+  if (precision != FREDEC_FP64 && precision != FREDEC_FP32) return FREDEC_EINVAL;
+  std::vector<int> sizes;
+  if ((rc = sizes_from_toff(toff, n_tuples, sizes))) return rc;
+  TuplePlan P;
+  if ((rc = make_plan(N, sizes, false, P))) return rc;
+  if (!ws || ws_bytes < P.total) return FREDEC_ENOMEM;
+  if (!ctx) return FREDEC_EINVAL;
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TupleDev D = dev_ptrs(ws, P);
+  if ((rc = upload_and_normalise(ctx, st, P, D, t, x, w, N))) return rc;
+  if (launch_copy_f64(st, f, D.ftry, P.nf) != hipSuccess) return FREDEC_EDEVICE;
+  if ((rc = run_fit(ctx, st, P, D, 0))) return rc;
+  const int nt = static_cast<int>(n_tuples);
+  if (launch_tuple_finish(st, D.desc, nt, D.com, D.state, D.facc, l_out, z_out, flags_out, nullptr, nullptr, 0) !=
+      hipSuccess)
+    return FREDEC_EDEVICE;
+  if (theta_out && launch_copy_f64(st, D.theta, theta_out, P.ntheta) != hipSuccess) return FREDEC_EDEVICE;
+  if ((dz_df || h_out) && launch_tuple_adjoint(st, D.desc, nt, D.com, D.tau, D.xt, D.wt, D.ftry, D.theta, D.state,
+                                               dz_df, h_out) != hipSuccess)
+    return FREDEC_EDEVICE;
+  return FREDEC_OK;
+}
+
+int fredec_ascent(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                  double* f, const int64_t* toff, int64_t n_tuples, int32_t steps, double clamp, int32_t precision,
+                  void* ws, size_t ws_bytes, double* z_out, double* l_out, uint8_t* flags_out) {
+  int rc = check_series_args(t, x, w, N);
+  if (rc) return rc;
+  if (!f || steps < 0 || !(clamp > 0.0) || !std::isfinite(clamp)) return FREDEC_EINVAL;
+  if (precision != FREDEC_FP64 && precision != FREDEC_FP32) return FREDEC_EINVAL;
+  std::vector<int> sizes;
+  if ((rc = sizes_from_toff(toff, n_tuples, sizes))) return rc;
+  TuplePlan P;
+  if ((rc = make_plan(N, sizes, false, P))) return rc;
+  if (!ws || ws_bytes < P.total) return FREDEC_ENOMEM;
+  if (!ctx) return FREDEC_EINVAL;
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TupleDev D = dev_ptrs(ws, P);
+  const int nt = static_cast<int>(n_tuples);
+  if ((rc = upload_and_normalise(ctx, st, P, D, t, x, w, N))) return rc;
+  if (launch_copy_f64(st, f, D.ftry, P.nf) != hipSuccess) return FREDEC_EDEVICE;
+  for (int s = 0; s < steps; ++s) {
+    if ((rc = run_fit(ctx, st, P, D, 0))) return rc;
+    if (launch_tuple_adjoint(st, D.desc, nt, D.com, D.tau, D.xt, D.wt, D.ftry, D.theta, D.state, D.g, D.h) !=
+        hipSuccess)
+      return FREDEC_EDEVICE;
+    if (launch_tuple_ascent_update(st, D.desc, nt, D.com, D.g, D.h, D.ftry, clamp, D.state) != hipSuccess)
+      return FREDEC_EDEVICE;
+  }
+  if ((rc = run_fit(ctx, st, P, D, 0))) return rc;
+  if (launch_tuple_finish(st, D.desc, nt, D.com, D.state, D.facc, l_out, z_out, flags_out, nullptr, nullptr, 0) !=
+      hipSuccess)
+    return FREDEC_EDEVICE;
+  if (launch_copy_f64(st, D.ftry, f, P.nf) != hipSuccess) return FREDEC_EDEVICE;
+  return FREDEC_OK;
+}
+
+}  // extern "C"

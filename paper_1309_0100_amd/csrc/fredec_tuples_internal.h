@@ -1,0 +1,59 @@
+// Internal declarations of the tuple kernels.
+#pragma once
+
+#include "fredec_internal.h"
+
+namespace fredec {
+
+constexpr int MAXPOOL = FREDEC_MAX_POOL;
+constexpr int TUPLE_FWD = 0;         // columns 1, cos, sin, x
+constexpr int TUPLE_GN = 1;          // plus t' cos, t' sin
+constexpr double ACCEPT_RTOL = 1e-12;  // a trial point is accepted if l <= l_acc (1 + ACCEPT_RTOL)
+constexpr int MAX_HALVINGS = 5;        // consecutive step halvings before stopping
+constexpr double GN_TOL = 1e-10;       // stop once max |df_k| T_eff falls below this
+constexpr double GN_CLAMP = 0.25;      // largest step max |df_k| T_eff
+
+struct TupleDesc {
+  int64_t foff;   // first frequency of the tuple in the ragged arrays
+  int64_t goff;   // first double of its packed Gram matrix
+  int64_t soff;   // first double of its solve scratch
+  int64_t thoff;  // first double of theta* (2n + 1 values)
+  int32_t n;      // frequencies
+  int32_t nb;     // 16-column blocks of its Gram
+};
+
+struct TupleCommon {
+  int64_t N;
+  double T_eff;
+  double inv_sigma_t;
+  double inv_two_pi_sigma_t;
+};
+
+struct TupleState {
+  double l_acc;     // l at the accepted point (+inf before the first)
+  double l0;        // l of the constant model
+  int32_t halvings;
+  int32_t done;
+  int32_t has_acc;
+  int32_t flags;
+};
+
+hipError_t launch_tuple_gram(hipStream_t st, int NB, const TupleDesc* desc, const int32_t* order, int n_order,
+                             const TupleCommon* com, const double* tau, const double* xt, const double* wt,
+                             const double* ftry, const TupleState* state, double* gram, int mode);
+hipError_t launch_tuple_solve(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
+                              double* gram, double* scratch, double* ftry, double* facc, double* step, double* theta,
+                              TupleState* state, int mode, int last);
+hipError_t launch_tuple_finish(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
+                               const TupleState* state, const double* facc, double* l_out, double* z_out,
+                               uint8_t* flags_out, double* f_out, const int8_t* members, int f_stride);
+hipError_t launch_tuple_adjoint(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
+                                const double* tau, const double* xt, const double* wt, const double* f,
+                                const double* theta, const TupleState* state, double* dzdf, double* hout);
+hipError_t launch_tuple_ascent_update(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
+                                      const double* g, const double* h, double* f, double clamp, TupleState* state);
+hipError_t launch_tuple_init(hipStream_t st, int n_tuples, TupleState* state);
+hipError_t launch_tuple_common(hipStream_t st, const SeriesHdr* hdr, int64_t N, TupleCommon* com);
+hipError_t launch_copy_f64(hipStream_t st, const double* src, double* dst, int64_t n);
+
+}  // namespace fredec

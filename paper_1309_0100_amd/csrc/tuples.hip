@@ -1,0 +1,534 @@
+// Tuple statistics z_n(f_1..f_n) (eq. zpow), their local refinement by
+// Gauss-Newton steps (Sect. 3, eq. lsqf) and the adjoint gradient.
+//
+// tuple_gram_kernel: one wavefront per tuple builds the weighted Gram matrix
+//   G = sum_i w~_i phi(t_i) phi(t_i)^T
+// of on-the-fly generated columns on float64 MFMA (v_mfma_f64_16x16x4_f64):
+//   forward columns  1, cos 2 pi f_k t, sin 2 pi f_k t (k = 1..n), x~
+//   GN columns       the forward ones, then t' cos 2 pi f_k t, t' sin 2 pi f_k t
+//                    (t' = t / sigma_t): the t-weighted averages from which the
+//                    Fisher matrix Q_f of the frequencies follows (eqs. avrg1, avrg2).
+// Each lane of an MFMA step owns one (column, sample) pair; A = column values,
+// B = w~ * column values, so D accumulates the Gram block by block (lower
+// triangle of 16x16 blocks only).
+// tuple_solve_kernel: one thread per tuple, float64: Cholesky of the model
+// block, l, theta*, z, and the Gauss-Newton step with the step control shared
+// with the oracle (clamp, accept/halve, tolerance).
+// tuple_adjoint_kernel: one wavefront per tuple, samples over lanes:
+// recomputes the trig terms, the residual r = x~ - Phi theta* and
+// <r J_k>, <J_k^2> (J_k = d mu / d f_k), reduced with wavefront shuffles.
+#include "fredec_internal.h"
+#include "fredec_tuples_internal.h"
+
+namespace fredec {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// sin(2 pi p) for a phase p in revolutions (float64), by the reduction and
+// polynomials of sincos_rev; cos is obtained as sin(2 pi (p + 1/4)).
+__device__ __forceinline__ double sin_rev(double p) {
+  double s, c;
+  sincos_rev(p, s, c);
+  return s;
+}
+
+// Column descriptor of one lane for one 16-column block.
+struct ColDesc {
+  double f;      // frequency of a trig column
+  double shift;  // 0 (sin) or 1/4 (cos)
+  int kind;      // 0 zero, 1 one, 2 trig, 3 data, 4 t' * trig
+};
+
+__device__ __forceinline__ ColDesc col_desc(int col, int n, int mode, const double* f) {
+  ColDesc d{0.0, 0.0, 0};
+  const int K = 2 * n + 1;
+  if (col == 0) {
+    d.kind = 1;
+  } else if (col < K) {
+    d.kind = 2;
+    d.f = f[(col - 1) >> 1];
+    d.shift = ((col - 1) & 1) ? 0.0 : 0.25;
+  } else if (col == K) {
+    d.kind = 3;
+  } else if (mode == TUPLE_GN && col < 4 * n + 2) {
+    const int c2 = col - K - 1;
+    d.kind = 4;
+    d.f = f[c2 >> 1];
+    d.shift = (c2 & 1) ? 0.0 : 0.25;
+  }
+  return d;
+}
+
+template <int NB>
+__global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __restrict__ desc,
+                                                           const int32_t* __restrict__ order, int n_order,
+                                                           const TupleCommon* __restrict__ com,
+                                                           const double* __restrict__ tau, const double* __restrict__ xt,
+                                                           const double* __restrict__ wt,
+                                                           const double* __restrict__ ftry,
+                                                           const TupleState* __restrict__ state,
+                                                           double* __restrict__ gram, int mode) {
+  const int wave = (blockIdx.x * BLOCK + threadIdx.x) >> 6;
+  if (wave >= n_order) return;
+  const int lane = threadIdx.x & 63;
+  const int ti = order[wave];
+  const TupleDesc& d = desc[ti];
+  if (state[ti].done) return;
+  const int n = d.n;
+  const int C = (mode == TUPLE_GN) ? 4 * n + 2 : 2 * n + 2;
+  const double* f = ftry + d.foff;
+  const int c16 = lane & 15;
+  const int kq = lane >> 4;
+  ColDesc cd[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) cd[b] = col_desc(16 * b + c16, n, mode, f);
+  const double inv_sig = com->inv_sigma_t;
+  constexpr int NTILE = NB * (NB + 1) / 2;
+  v4d acc[NTILE];
+#pragma unroll
+  for (int q = 0; q < NTILE; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int64_t N = com->N;
+  for (int64_t i0 = 0; i0 < N; i0 += 4) {
+    const int64_t i = i0 + kq;
+    const bool in = i < N;
+    const double ta = in ? tau[i] : 0.0;
+    const double xi = in ? xt[i] : 0.0;
+    const double wi = in ? wt[i] : 0.0;
+    double a[NB], bw[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      double v;
+      switch (cd[b].kind) {
+        case 1: v = 1.0; break;
+        case 2: v = sin_rev(cd[b].f * ta + cd[b].shift); break;
+        case 3: v = xi; break;
+        case 4: v = ta * inv_sig * sin_rev(cd[b].f * ta + cd[b].shift); break;
+        default: v = 0.0;
+      }
+      a[b] = v;
+      bw[b] = wi * v;
+    }
+    int q = 0;
+#pragma unroll
+    for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+      for (int b2 = 0; b2 <= b1; ++b2) {
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[b1], bw[b2], acc[q], 0, 0, 0);
+        ++q;
+      }
+  }
+  // D[i][j] of block (b1, b2) sits in lane j + 16 (i % 4), register i / 4
+  double* G = gram + d.goff;
+  int q = 0;
+#pragma unroll
+  for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+    for (int b2 = 0; b2 <= b1; ++b2) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * b1 + kq + 4 * v;
+        const int c = 16 * b2 + c16;
+        if (r < C && c <= r) G[r * (r + 1) / 2 + c] = acc[q][v];
+      }
+      ++q;
+    }
+}
+
+__device__ __forceinline__ double& P_(double* G, int r, int c) { return G[r * (r + 1) / 2 + c]; }
+
+// In-place Cholesky of the leading K x K block of the packed lower matrix G.
+__device__ bool chol_inplace(double* G, int K) {
+  for (int j = 0; j < K; ++j) {
+    const double diag = P_(G, j, j);
+    double dsum = diag;
+    for (int k = 0; k < j; ++k) dsum -= P_(G, j, k) * P_(G, j, k);
+    if (!(dsum > PIVOT_TOL * diag)) return false;
+    const double ljj = sqrt(dsum);
+    P_(G, j, j) = ljj;
+    for (int i = j + 1; i < K; ++i) {
+      double v = P_(G, i, j);
+      for (int k = 0; k < j; ++k) v -= P_(G, i, k) * P_(G, j, k);
+      P_(G, i, j) = v / ljj;
+    }
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(BLOCK) void tuple_solve_kernel(const TupleDesc* __restrict__ desc, int n_tuples,
+                                                            const TupleCommon* __restrict__ com,
+                                                            double* __restrict__ gram, double* __restrict__ scratch,
+                                                            double* __restrict__ ftry, double* __restrict__ facc,
+                                                            double* __restrict__ step, double* __restrict__ theta,
+                                                            TupleState* __restrict__ state, int mode, int last) {
+  const int ti = blockIdx.x * BLOCK + threadIdx.x;
+  if (ti >= n_tuples) return;
+  const TupleDesc& d = desc[ti];
+  TupleState& S = state[ti];
+  if (S.done) return;
+  const int n = d.n;
+  const int K = 2 * n + 1;
+  double* G = gram + d.goff;
+  double* ft = ftry + d.foff;
+  double* fa = facc + d.foff;
+  double* st = step + d.foff;
+  double* th = theta + d.thoff;
+  const double T = com->T_eff;
+  // degenerate trial point: two frequencies merged
+  bool degen = false;
+  for (int k = 0; k < n; ++k)
+    for (int l = k + 1; l < n; ++l) degen |= fabs(ft[k] - ft[l]) * T < MASK_WIDTH;
+  // l_0 of the constant model and D from the Gram
+  const double D = P_(G, K, K);
+  const double l0 = D - P_(G, K, 0) * P_(G, K, 0) / P_(G, 0, 0);
+  bool ok = !degen && chol_inplace(G, K);
+  double l = 0.0;
+  if (ok) {
+    // a = L^{-1} g in place on row K; l = D - a.a
+    double aa = 0.0;
+    for (int i = 0; i < K; ++i) {
+      double v = P_(G, K, i);
+      for (int k = 0; k < i; ++k) v -= P_(G, i, k) * P_(G, K, k);
+      v /= P_(G, i, i);
+      P_(G, K, i) = v;
+      aa += v * v;
+    }
+    l = D - aa;
+  }
+  const bool accept = ok && l <= S.l_acc * (1.0 + ACCEPT_RTOL);
+  if (!accept) {
+    if (!S.has_acc) {  // the start point itself is degenerate
+      S.done = 1;
+      S.flags = FREDEC_FLAG_DEGENERATE;
+      return;
+    }
+    for (int k = 0; k < n; ++k) st[k] *= 0.5;
+    if (++S.halvings > MAX_HALVINGS || last) {
+      S.done = 1;
+      return;
+    }
+    for (int k = 0; k < n; ++k) ft[k] = fa[k] + st[k];
+    return;
+  }
+  // accepted: theta* = L^{-T} a
+  for (int i = K - 1; i >= 0; --i) {
+    double v = P_(G, K, i);
+    for (int k = i + 1; k < K; ++k) v -= P_(G, k, i) * th[k];
+    th[i] = v / P_(G, i, i);
+  }
+  S.has_acc = 1;
+  S.l_acc = l;
+  S.l0 = l0;
+  S.halvings = 0;
+  for (int k = 0; k < n; ++k) fa[k] = ft[k];
+  if (mode != TUPLE_GN) {
+    S.done = 1;
+    return;
+  }
+  // Gauss-Newton step on the frequencies: J'_k = t'(-a_k sin + b_k cos),
+  // P = <phi J'>, JJ = <J' J'>, rJ = <x J'> - P^T theta, V = L^{-1} P,
+  // H = JJ - V^T V, dnu = H^{-1} rJ, df = dnu / (2 pi sigma_t).
+  const int ts0 = K + 1;  // first t' column
+  double* V = scratch + d.soff;          // K x n
+  double* H = V + static_cast<int64_t>(K) * n;  // packed n x n
+  double* rJ = H + n * (n + 1) / 2;     // n
+  for (int k = 0; k < n; ++k) {
+    const double ak = th[1 + 2 * k], bk = th[2 + 2 * k];
+    const int rc = ts0 + 2 * k, rs = ts0 + 2 * k + 1;
+    // P column k, then forward substitution into V column k
+    for (int j = 0; j < K; ++j) {
+      double p = -ak * P_(G, rs, j) + bk * P_(G, rc, j);
+      for (int m = 0; m < j; ++m) p -= P_(G, j, m) * V[m * n + k];
+      V[j * n + k] = p / P_(G, j, j);
+    }
+    // <x J'_k> - sum_j theta_j P_jk, with P recomputed
+    double r = -ak * P_(G, rs, K) + bk * P_(G, rc, K);
+    for (int j = 0; j < K; ++j) r -= th[j] * (-ak * P_(G, rs, j) + bk * P_(G, rc, j));
+    rJ[k] = r;
+  }
+  for (int k = 0; k < n; ++k) {
+    const double ak = th[1 + 2 * k], bk = th[2 + 2 * k];
+    const int kc = ts0 + 2 * k, ks = ts0 + 2 * k + 1;
+    for (int m = 0; m <= k; ++m) {
+      const double am = th[1 + 2 * m], bm = th[2 + 2 * m];
+      const int mc = ts0 + 2 * m, ms = ts0 + 2 * m + 1;
+      // <J'_k J'_m> from the packed lower Gram (row index >= column index)
+      auto g = [&](int r1, int r2) { return r1 >= r2 ? P_(G, r1, r2) : P_(G, r2, r1); };
+      double jj = ak * am * g(ks, ms) - ak * bm * g(ks, mc) - bk * am * g(kc, ms) + bk * bm * g(kc, mc);
+      for (int j = 0; j < K; ++j) jj -= V[j * n + k] * V[j * n + m];
+      H[k * (k + 1) / 2 + m] = jj;
+    }
+  }
+  bool hok = chol_inplace(H, n);
+  double big = 0.0;
+  if (hok) {
+    // solve H dnu = rJ (in place in rJ)
+    for (int i = 0; i < n; ++i) {
+      double v = rJ[i];
+      for (int k = 0; k < i; ++k) v -= H[i * (i + 1) / 2 + k] * rJ[k];
+      rJ[i] = v / H[i * (i + 1) / 2 + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double v = rJ[i];
+      for (int k = i + 1; k < n; ++k) v -= H[k * (k + 1) / 2 + i] * rJ[k];
+      rJ[i] = v / H[i * (i + 1) / 2 + i];
+    }
+    const double scale = com->inv_two_pi_sigma_t;
+    for (int k = 0; k < n; ++k) {
+      st[k] = rJ[k] * scale;
+      big = fmax(big, fabs(st[k]) * T);
+    }
+  }
+  if (!hok || big < GN_TOL) {
+    S.done = 1;
+    if (hok) S.flags |= FREDEC_FLAG_CONVERGED;
+    return;
+  }
+  if (last) {  // no pass is left to evaluate the step
+    S.done = 1;
+    return;
+  }
+  if (big > GN_CLAMP)
+    for (int k = 0; k < n; ++k) st[k] *= GN_CLAMP / big;
+  for (int k = 0; k < n; ++k) ft[k] = fa[k] + st[k];
+}
+
+__global__ void tuple_finish_kernel(const TupleDesc* __restrict__ desc, int n_tuples,
+                                    const TupleCommon* __restrict__ com, const TupleState* __restrict__ state,
+                                    const double* __restrict__ facc, double* __restrict__ l_out,
+                                    double* __restrict__ z_out, uint8_t* __restrict__ flags_out,
+                                    double* __restrict__ f_out, const int8_t* __restrict__ members, int f_stride) {
+  const int ti = blockIdx.x * BLOCK + threadIdx.x;
+  if (ti >= n_tuples) return;
+  const TupleDesc& d = desc[ti];
+  const TupleState& S = state[ti];
+  const int n = d.n;
+  double l = S.has_acc ? S.l_acc : __builtin_nan("");
+  double z;
+  uint8_t fl = S.flags;
+  if (!S.has_acc) {
+    z = -__builtin_inf();
+    fl |= FREDEC_FLAG_DEGENERATE;
+  } else if (!(l > 0.0)) {
+    z = __builtin_inf();
+    fl |= FREDEC_FLAG_PERFECT;
+  } else {
+    const double NH = static_cast<double>(com->N - 3 * n - 1);
+    z = 0.5 * NH * log(S.l0 / l);
+  }
+  if (l_out) l_out[ti] = l;
+  if (z_out) z_out[ti] = z;
+  if (flags_out) flags_out[ti] = fl;
+  if (f_out) {
+    if (members) {
+      double* row = f_out + static_cast<int64_t>(ti) * f_stride;
+      for (int k = 0; k < f_stride; ++k) row[k] = __builtin_nan("");
+      for (int k = 0; k < n; ++k) row[members[d.foff + k]] = facc[d.foff + k];
+    } else {
+      for (int k = 0; k < n; ++k) f_out[d.foff + k] = facc[d.foff + k];
+    }
+  }
+}
+
+// Adjoint: <r J_k> and <J_k^2> with J_k = 2 pi t (-a_k sin 2 pi f_k t + b_k cos 2 pi f_k t),
+// r = x~ - Phi theta*; dz/df_k = (N_H / l) <r J_k>, h_k = (N_H / l) <J_k^2>.
+__global__ __launch_bounds__(BLOCK) void tuple_adjoint_kernel(const TupleDesc* __restrict__ desc, int n_tuples,
+                                                              const TupleCommon* __restrict__ com,
+                                                              const double* __restrict__ tau,
+                                                              const double* __restrict__ xt,
+                                                              const double* __restrict__ wt,
+                                                              const double* __restrict__ f,
+                                                              const double* __restrict__ theta,
+                                                              const TupleState* __restrict__ state,
+                                                              double* __restrict__ dzdf, double* __restrict__ hout) {
+  const int wave = (blockIdx.x * BLOCK + threadIdx.x) >> 6;
+  if (wave >= n_tuples) return;
+  const int lane = threadIdx.x & 63;
+  const TupleDesc& d = desc[wave];
+  const TupleState& S = state[wave];
+  const int n = d.n;
+  const double* fk = f + d.foff;
+  const double* th = theta + d.thoff;
+  if (!S.has_acc || !(S.l_acc > 0.0)) {
+    if (lane < n) {
+      if (dzdf) dzdf[d.foff + lane] = __builtin_nan("");
+      if (hout) hout[d.foff + lane] = __builtin_nan("");
+    }
+    return;
+  }
+  double g[MAXPOOL], h2[MAXPOOL];
+#pragma unroll
+  for (int k = 0; k < MAXPOOL; ++k) g[k] = h2[k] = 0.0;
+  const int64_t N = com->N;
+  for (int64_t i = lane; i < N; i += 64) {
+    const double ta = tau[i];
+    double r = xt[i] - th[0];
+#pragma unroll
+    for (int k = 0; k < MAXPOOL; ++k) {
+      if (k < n) {
+        double s, c;
+        sincos_rev(fk[k] * ta, s, c);
+        r -= th[1 + 2 * k] * c + th[2 + 2 * k] * s;
+      }
+    }
+    const double wi = wt[i];
+#pragma unroll
+    for (int k = 0; k < MAXPOOL; ++k) {
+      if (k < n) {
+        double s, c;
+        sincos_rev(fk[k] * ta, s, c);
+        const double J = 2.0 * M_PI * ta * (-th[1 + 2 * k] * s + th[2 + 2 * k] * c);
+        g[k] = __builtin_fma(wi * r, J, g[k]);
+        h2[k] = __builtin_fma(wi * J, J, h2[k]);
+      }
+    }
+  }
+  const double coef = static_cast<double>(N - 3 * n - 1) / S.l_acc;
+#pragma unroll
+  for (int k = 0; k < MAXPOOL; ++k) {
+    if (k < n) {
+      double a = g[k], b = h2[k];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+      }
+      if (lane == 0) {
+        if (dzdf) dzdf[d.foff + k] = coef * a;
+        if (hout) hout[d.foff + k] = coef * b;
+      }
+    }
+  }
+}
+
+// One step of the preconditioned ascent: f_k += clamp(<r J_k> / <J_k^2>, +-c/T).
+__global__ void tuple_ascent_update_kernel(const TupleDesc* __restrict__ desc, int n_tuples,
+                                           const TupleCommon* __restrict__ com, const double* __restrict__ g,
+                                           const double* __restrict__ h, double* __restrict__ f, double clamp,
+                                           TupleState* __restrict__ state) {
+  const int ti = blockIdx.x * BLOCK + threadIdx.x;
+  if (ti >= n_tuples) return;
+  const TupleDesc& d = desc[ti];
+  TupleState& S = state[ti];
+  if (!S.has_acc) return;
+  const double lim = clamp / com->T_eff;
+  for (int k = 0; k < d.n; ++k) {
+    const double gk = g[d.foff + k], hk = h[d.foff + k];
+    if (!isfinite(gk) || !isfinite(hk) || !(hk > 0.0)) continue;
+    const double stp = fmin(fmax(gk / hk, -lim), lim);
+    f[d.foff + k] += stp;
+  }
+  // the next forward evaluation starts afresh
+  S.done = 0;
+  S.has_acc = 0;
+  S.l_acc = __builtin_inf();
+}
+
+__global__ void tuple_init_kernel(int n_tuples, TupleState* __restrict__ state) {
+  const int ti = blockIdx.x * BLOCK + threadIdx.x;
+  if (ti >= n_tuples) return;
+  TupleState s;
+  s.l_acc = __builtin_inf();
+  s.l0 = 0.0;
+  s.halvings = 0;
+  s.done = 0;
+  s.has_acc = 0;
+  s.flags = 0;
+  state[ti] = s;
+}
+
+__global__ void tuple_common_kernel(const SeriesHdr* __restrict__ hdr, int64_t N, TupleCommon* __restrict__ com) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double sig = sqrt(hdr->stats[3]);
+  com->N = N;
+  com->T_eff = hdr->T_eff;
+  com->inv_sigma_t = 1.0 / sig;
+  com->inv_two_pi_sigma_t = 1.0 / (2.0 * M_PI * sig);
+}
+
+__global__ void copy_f64_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+template <int NB>
+hipError_t gram_nb(hipStream_t st, const TupleDesc* desc, const int32_t* order, int n_order, const TupleCommon* com,
+                   const double* tau, const double* xt, const double* wt, const double* ftry, const TupleState* state,
+                   double* gram, int mode) {
+  const int blocks = (n_order + 3) / 4;
+  tuple_gram_kernel<NB><<<blocks, BLOCK, 0, st>>>(desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_tuple_gram(hipStream_t st, int NB, const TupleDesc* desc, const int32_t* order, int n_order,
+                             const TupleCommon* com, const double* tau, const double* xt, const double* wt,
+                             const double* ftry, const TupleState* state, double* gram, int mode) {
+  if (n_order <= 0) return hipSuccess;
+  switch (NB) {
+    case 1: return gram_nb<1>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    case 2: return gram_nb<2>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    case 3: return gram_nb<3>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    case 4: return gram_nb<4>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    case 5: return gram_nb<5>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    case 6: return gram_nb<6>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    case 7: return gram_nb<7>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_tuple_solve(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
+                              double* gram, double* scratch, double* ftry, double* facc, double* step, double* theta,
+                              TupleState* state, int mode, int last) {
+  if (n_tuples <= 0) return hipSuccess;
+  tuple_solve_kernel<<<(n_tuples + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(desc, n_tuples, com, gram, scratch, ftry, facc,
+                                                                       step, theta, state, mode, last);
+  return hipGetLastError();
+}
+
+hipError_t launch_tuple_finish(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
+                               const TupleState* state, const double* facc, double* l_out, double* z_out,
+                               uint8_t* flags_out, double* f_out, const int8_t* members, int f_stride) {
+  if (n_tuples <= 0) return hipSuccess;
+  tuple_finish_kernel<<<(n_tuples + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(desc, n_tuples, com, state, facc, l_out, z_out,
+                                                                        flags_out, f_out, members, f_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_tuple_adjoint(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
+                                const double* tau, const double* xt, const double* wt, const double* f,
+                                const double* theta, const TupleState* state, double* dzdf, double* hout) {
+  if (n_tuples <= 0) return hipSuccess;
+  const int blocks = (n_tuples + 3) / 4;
+  tuple_adjoint_kernel<<<blocks, BLOCK, 0, st>>>(desc, n_tuples, com, tau, xt, wt, f, theta, state, dzdf, hout);
+  return hipGetLastError();
+}
+
+hipError_t launch_tuple_ascent_update(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
+                                      const double* g, const double* h, double* f, double clamp, TupleState* state) {
+  if (n_tuples <= 0) return hipSuccess;
+  tuple_ascent_update_kernel<<<(n_tuples + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(desc, n_tuples, com, g, h, f, clamp,
+                                                                               state);
+  return hipGetLastError();
+}
+
+hipError_t launch_tuple_init(hipStream_t st, int n_tuples, TupleState* state) {
+  if (n_tuples <= 0) return hipSuccess;
+  tuple_init_kernel<<<(n_tuples + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(n_tuples, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_tuple_common(hipStream_t st, const SeriesHdr* hdr, int64_t N, TupleCommon* com) {
+  tuple_common_kernel<<<1, 64, 0, st>>>(hdr, N, com);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(hipStream_t st, const double* src, double* dst, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  copy_f64_kernel<<<static_cast<unsigned>((n + BLOCK - 1) / BLOCK), BLOCK, 0, st>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace fredec

@@ -24,6 +24,7 @@ FP32 = 1
 OK, EINVAL, EDOF, EWEIGHT, EDEGEN, ESINGULAR, ENOMEM, EDEVICE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7, -8
 TILE_SCAN_MFMA = 1
 FLAG_MASKED, FLAG_SINGULAR, FLAG_PERFECT, FLAG_DEGENERATE, FLAG_BADSERIES = 1, 2, 4, 8, 128
+FLAG_CONVERGED, FLAG_RESCORED = 16, 64
 
 c_i32, c_i64, c_sz, c_p, c_d = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
 c_pp = ctypes.POINTER(ctypes.c_void_p)
@@ -42,6 +43,14 @@ _SIGS = {
     "fredec_scan_workspace": (c_i32, [c_i32, c_p, c_p, c_p, c_i32, c_szp]),
     "fredec_scan": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_i32, c_p, c_sz,
                             c_p, c_p, c_p, c_p]),
+    "fredec_tuples_workspace": (c_i32, [c_i64, c_i32, c_p, c_i64, c_i32, c_szp]),
+    "fredec_tuples": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_i32, c_p, c_i64, c_i32, c_i32, c_p, c_sz,
+                              c_p, c_p, c_p, c_p]),
+    "fredec_grad_workspace": (c_i32, [c_i64, c_p, c_i64, c_szp]),
+    "fredec_grad": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_i64, c_i32, c_p, c_sz, c_p, c_p, c_p, c_p,
+                            c_p, c_p]),
+    "fredec_ascent": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_i64, c_i32, c_d, c_i32, c_p, c_sz, c_p,
+                              c_p, c_p]),
     "fredec_scan_at_workspace": (c_i32, [c_i64, c_i32, c_szp]),
     "fredec_scan_at": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_i32, c_d, c_p, c_i64, c_p, c_sz, c_p, c_p]),
 }
@@ -236,6 +245,65 @@ class Context:
                                      _ptr(base_f) if base_f.size else None, base_f.size, float(df), _ptr(idx), n_idx,
                                      _ptr(ws), need.value, _ptr(z), _ptr(fl)), "fredec_scan_at")
         return z, fl
+
+
+    # ------------------------------------------------------------ tuples
+    def tuples(self, t, x, w, pool, masks=None, refine_steps=0, precision=FP64):
+        """Statistics of subsets of a frequency pool.  Returns device tensors
+        (l, z, f[n_tuples, n_pool], flags)."""
+        torch = _torch()
+        t, x, w = self._f64(t), self._f64(x), self._f64(w)
+        pool = np.ascontiguousarray(pool, np.float64)
+        npool = pool.size
+        mk = None if masks is None else np.ascontiguousarray(masks, np.uint64)
+        nt = (1 << npool) - 1 if mk is None else mk.size
+        need = ctypes.c_size_t()
+        _check(load().fredec_tuples_workspace(t.numel(), npool, _ptr(mk), nt, refine_steps, ctypes.byref(need)),
+               "fredec_tuples_workspace")
+        ws = self._workspace(need.value)
+        l, z = self._empty(nt, torch.float64), self._empty(nt, torch.float64)
+        f = self._empty(nt * npool, torch.float64)
+        fl = self._empty(nt, torch.uint8)
+        _check(load().fredec_tuples(self.handle, _stream(self.device), _ptr(t), _ptr(x), _ptr(w), t.numel(),
+                                    _ptr(pool), npool, _ptr(mk), nt, refine_steps, precision, _ptr(ws), need.value,
+                                    _ptr(l), _ptr(z), _ptr(f), _ptr(fl)), "fredec_tuples")
+        return l, z, f.view(nt, npool), fl
+
+    def grad(self, t, x, w, f, toff, want_grad=True, precision=FP64):
+        """z, l, theta, dz/df, h, flags of ragged tuples (f device float64)."""
+        torch = _torch()
+        t, x, w, f = self._f64(t), self._f64(x), self._f64(w), self._f64(f)
+        toff = np.ascontiguousarray(toff, np.int64)
+        nt = toff.size - 1
+        need = ctypes.c_size_t()
+        _check(load().fredec_grad_workspace(t.numel(), _ptr(toff), nt, ctypes.byref(need)), "fredec_grad_workspace")
+        ws = self._workspace(need.value)
+        z, l = self._empty(nt, torch.float64), self._empty(nt, torch.float64)
+        th = self._empty(2 * int(toff[-1]) + nt, torch.float64)
+        g = self._empty(int(toff[-1]), torch.float64) if want_grad else None
+        h = self._empty(int(toff[-1]), torch.float64) if want_grad else None
+        fl = self._empty(nt, torch.uint8)
+        _check(load().fredec_grad(self.handle, _stream(self.device), _ptr(t), _ptr(x), _ptr(w), t.numel(), _ptr(f),
+                                  _ptr(toff), nt, precision, _ptr(ws), need.value, _ptr(z), _ptr(l), _ptr(th),
+                                  _ptr(g), _ptr(h), _ptr(fl)), "fredec_grad")
+        return z, l, th, g, h, fl
+
+    def ascent(self, t, x, w, f, toff, steps=20, clamp=0.1, precision=FP64):
+        """Preconditioned ascent; returns (f, z, l, flags) with f a new device tensor."""
+        torch = _torch()
+        t, x, w = self._f64(t), self._f64(x), self._f64(w)
+        f = self._f64(f).clone()
+        toff = np.ascontiguousarray(toff, np.int64)
+        nt = toff.size - 1
+        need = ctypes.c_size_t()
+        _check(load().fredec_grad_workspace(t.numel(), _ptr(toff), nt, ctypes.byref(need)), "fredec_grad_workspace")
+        ws = self._workspace(need.value)
+        z, l = self._empty(nt, torch.float64), self._empty(nt, torch.float64)
+        fl = self._empty(nt, torch.uint8)
+        _check(load().fredec_ascent(self.handle, _stream(self.device), _ptr(t), _ptr(x), _ptr(w), t.numel(), _ptr(f),
+                                    _ptr(toff), nt, steps, float(clamp), precision, _ptr(ws), need.value, _ptr(z),
+                                    _ptr(l), _ptr(fl)), "fredec_ascent")
+        return f, z, l, fl
 
 
 @dataclass

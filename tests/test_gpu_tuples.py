@@ -1,0 +1,172 @@
+"""GPU parity of the tuple statistics (fredec_tuples), their Gauss-Newton
+refinement, the adjoint gradient (fredec_grad) and the preconditioned ascent
+(fredec_ascent) against the float64 oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1309_0100_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-9
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1309_0100_amd import fredec as F
+    return F.Context(0)
+
+
+def zerr(z, zr):
+    return np.abs(z - zr) / np.maximum(np.abs(zr), 1.0)
+
+
+def members(mask, n):
+    return [k for k in range(n) if mask >> k & 1]
+
+
+def test_plain_workload_top3_subtuples(ctx):
+    """Workload 1: the 7 subtuples of the 3 highest peaks of the m=0 scan."""
+    s = synth.plain()
+    print("case: plain top-3 subtuples", flush=True)
+    r = O.scan(s.t, s.x, s.w, [], s.df, s.F)
+    pk = O.local_maxima(r.z, r.flags)
+    top = pk[np.lexsort((pk, -r.z[pk]))[:3]]
+    pool = np.sort(r.freqs[top])
+    l, z, f, fl = (a.cpu().numpy() for a in ctx.tuples(s.t, s.x, s.w, pool))
+    nrm = O.normalize(s.t, s.x, s.w)
+    for mask in range(1, 8):
+        zr, lr, _, flr = O.tuple_fit(nrm, pool[members(mask, 3)])
+        assert fl[mask - 1] == flr == 0
+        assert zerr(z[mask - 1], zr) <= TOL64 and abs(l[mask - 1] - lr) <= 1e-12
+        assert np.array_equal(np.isnan(f[mask - 1]), [not (mask >> k & 1) for k in range(3)])
+
+
+@pytest.mark.parametrize("n,N", [(6, 400), (9, 700)])
+def test_all_subsets_fixed(ctx, n, N):
+    s = synth.random_series(700 + n, N, span=300.0, n_sin=4)
+    rng = np.random.default_rng(n)
+    pool = np.sort(rng.uniform(0.02, 1.0, size=n))
+    print(f"case: all subsets n={n} N={N}", flush=True)
+    l, z, f, fl = (a.cpu().numpy() for a in ctx.tuples(s.t, s.x, s.w, pool))
+    nrm = O.normalize(s.t, s.x, s.w)
+    for mask in range(1, 1 << n):
+        zr, lr, _, flr = O.tuple_fit(nrm, pool[members(mask, n)])
+        assert fl[mask - 1] == flr
+        if flr == 0:
+            assert zerr(z[mask - 1], zr) <= TOL64, (mask, z[mask - 1], zr)
+
+
+def test_explicit_masks_and_degenerate(ctx):
+    s = synth.random_series(720, 300, span=200.0, n_sin=2)
+    nrm = O.normalize(s.t, s.x, s.w)
+    pool = np.array([0.05, 0.2, 0.2 + 0.01 / nrm.T_eff, 0.4])
+    masks = np.array([0b0001, 0b0110, 0b1011, 0b1111, 0b0010], np.uint64)
+    l, z, f, fl = (a.cpu().numpy() for a in ctx.tuples(s.t, s.x, s.w, pool, masks=masks))
+    for k, m in enumerate(masks):
+        zr, lr, _, flr = O.tuple_fit(nrm, pool[members(int(m), 4)])
+        assert fl[k] == flr
+        if flr:
+            assert z[k] == -np.inf
+        else:
+            assert zerr(z[k], zr) <= TOL64
+
+
+def test_refined_subsets_match_oracle_gn(ctx):
+    """Phase-2 style: every subset of a pool near the injected frequencies,
+    refined by Gauss-Newton with the shared step control."""
+    s = synth.random_series(730, 500, span=400.0, n_sin=3, noise=0.5)
+    nrm = O.normalize(s.t, s.x, s.w)
+    pool = np.sort(s.true_f + np.array([0.12, -0.1, 0.07]) / nrm.T_eff)
+    pool = np.concatenate([pool, [0.61]])
+    n = pool.size
+    R = 8
+    print("case: refined subsets n=4 R=8", flush=True)
+    l, z, f, fl = (a.cpu().numpy() for a in ctx.tuples(s.t, s.x, s.w, pool, refine_steps=R))
+    ltab, fref = O.phase2(nrm, pool, refine_steps=R)
+    for mask in range(1, 1 << n):
+        mem = members(mask, n)
+        assert abs(l[mask - 1] - ltab[mask]) <= 1e-9 * ltab[mask], (mask, l[mask - 1], ltab[mask])
+        assert np.max(np.abs(f[mask - 1][mem] - fref[mask][mem])) * nrm.T_eff < 1e-7
+        r = O.gn_refine(nrm, pool[mem], R)
+        assert zerr(z[mask - 1], r.z) <= TOL64
+        assert bool(fl[mask - 1] & 16) == r.converged
+
+
+def _ragged(rng, pool, n_tuples, n_max, T):
+    sizes = rng.integers(1, n_max + 1, size=n_tuples)
+    toff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    f = np.concatenate([np.sort(rng.choice(pool, size=k, replace=False)) + rng.uniform(-0.2, 0.2, size=k) / T
+                        for k in sizes])
+    return f, toff
+
+
+def test_grad_matches_oracle_and_fd(ctx):
+    s = synth.random_series(740, 600, span=300.0, n_sin=4)
+    nrm = O.normalize(s.t, s.x, s.w)
+    rng = np.random.default_rng(4)
+    pool = np.concatenate([s.true_f, rng.uniform(0.05, 0.9, size=4)])
+    f, toff = _ragged(rng, pool, 40, 6, nrm.T_eff)
+    print("case: grad 40 ragged tuples", flush=True)
+    z, l, th, g, h, fl = (a.cpu().numpy() for a in ctx.grad(s.t, s.x, s.w, f, toff))
+    for k in range(toff.size - 1):
+        fk = f[toff[k]:toff[k + 1]]
+        zr, lr, gr, hr = O.tuple_grad(nrm, fk)
+        if not np.isfinite(zr):
+            assert fl[k] & 8
+            continue
+        assert zerr(z[k], zr) <= TOL64
+        scale = np.maximum(np.abs(gr), 1e-3 * nrm.T_eff * max(zr, 1.0))
+        assert np.max(np.abs(g[toff[k]:toff[k + 1]] - gr) / scale) < 1e-8
+        assert np.max(np.abs(h[toff[k]:toff[k + 1]] - hr) / np.abs(hr)) < 1e-9
+        n = fk.size
+        t0 = 2 * toff[k] + k
+        _, _, thr, _ = O.tuple_fit(nrm, fk)
+        assert np.max(np.abs(th[t0:t0 + 2 * n + 1] - thr)) < 1e-9
+    # central differences of the GPU's own z
+    hstep = 1e-5 / nrm.T_eff
+    for k in range(6):
+        a, b = toff[k], toff[k + 1]
+        for j in range(a, b):
+            fp, fm = f.copy(), f.copy()
+            fp[j] += hstep
+            fm[j] -= hstep
+            zp = ctx.grad(s.t, s.x, s.w, fp[a:b], [0, b - a], want_grad=False)[0].item()
+            zm = ctx.grad(s.t, s.x, s.w, fm[a:b], [0, b - a], want_grad=False)[0].item()
+            fd = (zp - zm) / (2 * hstep)
+            assert abs(fd - g[j]) <= 1e-6 * max(abs(g[j]), nrm.T_eff)
+
+
+def test_ascent_matches_oracle(ctx):
+    """Differentiable-refinement workload shape (N=1000 over 3000 d, tuples of
+    1..6 perturbed peaks), 20 ascent steps, on 64 tuples."""
+    s = synth.tuples_series()
+    r = O.scan(s.t, s.x, s.w, [], s.df, 4096)
+    pk = O.local_maxima(r.z, r.flags)
+    peaks = r.freqs[pk[np.lexsort((pk, -r.z[pk]))[:12]]]
+    f, toff = synth.tuples_draw(peaks, n_tuples=64)
+    print("case: ascent 64 tuples x 20 steps", flush=True)
+    fa, z, l, fl = (a.cpu().numpy() for a in ctx.ascent(s.t, s.x, s.w, f, toff, steps=20, clamp=0.1))
+    nrm = O.normalize(s.t, s.x, s.w)
+    for k in range(toff.size - 1):
+        fk = f[toff[k]:toff[k + 1]]
+        fr, zr, lr = O.ascent(nrm, fk, steps=20, clamp=0.1)
+        if not np.isfinite(zr):
+            assert fl[k] & 8
+            continue
+        assert np.max(np.abs(fa[toff[k]:toff[k + 1]] - fr)) * nrm.T_eff < 1e-8
+        assert zerr(z[k], zr) <= 1e-8
+
+
+def test_tuple_errors(ctx):
+    from paper_1309_0100_amd import fredec as F
+    s = synth.random_series(750, 20, span=50.0, n_sin=1)
+    with pytest.raises(F.FredecError) as e:
+        ctx.tuples(s.t, s.x, s.w, np.linspace(0.1, 0.9, 7))      # N - 3*7 - 1 < 0
+    assert e.value.code == F.EDOF
+    with pytest.raises(F.FredecError) as e:
+        ctx.tuples(s.t, s.x, s.w, [0.1, 0.2], masks=np.array([0b100], np.uint64))
+    assert e.value.code == F.EINVAL
