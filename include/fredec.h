@@ -165,7 +165,8 @@ int fredec_scan_at(fredec_ctx* ctx, void* stream, const double* t, const double*
  * f_out[n_tuples * n_pool] (the accepted frequencies of the members at their
  * pool index, NaN elsewhere), flags_out[n_tuples] (FREDEC_FLAG_DEGENERATE:
  * two frequencies within 0.05 / T_eff or a singular normal matrix, z = -inf;
- * FREDEC_FLAG_PERFECT: l <= 0, z = +inf).  The sums are float64 (MFMA) for
+ * FREDEC_FLAG_PERFECT: l <= 0, z = +inf), l0_out[1] (l_0 of the constant
+ * model, the entry l(empty set) of the Phase 3 table).  The sums are float64 (MFMA) for
  * both precisions.  Errors: EINVAL, ENOTSUP (n_pool > FREDEC_MAX_POOL),
  * EDOF (N - 3 n_max - 1 <= 0), ENOMEM. */
 int fredec_tuples_workspace(int64_t N, int32_t n_pool, const uint64_t* masks_host, int64_t n_tuples,
@@ -173,7 +174,7 @@ int fredec_tuples_workspace(int64_t N, int32_t n_pool, const uint64_t* masks_hos
 int fredec_tuples(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
                   const double* pool_host, int32_t n_pool, const uint64_t* masks_host, int64_t n_tuples,
                   int32_t refine_steps, int32_t precision, void* workspace, size_t ws_bytes,
-                  double* l_out, double* z_out, double* f_out, uint8_t* flags_out);
+                  double* l_out, double* z_out, double* f_out, uint8_t* flags_out, double* l0_out);
 
 /* z and its gradient for ragged tuples: tuple k owns the frequencies
  * f[toff[k] .. toff[k+1]) (f device float64, toff host int64, toff[0] = 0,
@@ -199,6 +200,60 @@ int fredec_ascent(fredec_ctx* ctx, void* stream, const double* t, const double* 
                   double* f, const int64_t* toff_host, int64_t n_tuples, int32_t steps, double clamp,
                   int32_t precision, void* workspace, size_t ws_bytes, double* z_out, double* l_out,
                   uint8_t* flags_out);
+
+/* FAP thresholds (eq. zFAP) ------------------------------------------------
+ * zc[d], d = 1..n (zc[0] = 0): the z with A_d W^d e^{-z} z^{3d/2-1} = fap on
+ * the decreasing branch z > 3d/2 - 1 (bisection, float64, host only).
+ * A (host [n+1], nullable = all 1): the constants A~_d, which the paper does
+ * not print.  W = f_max T_eff (Sect. 2).  zc: host [n+1]. */
+int fredec_zcrit(double W, int32_t n, double fap, const double* A_host, double* zc_host);
+
+/* Periodogram peaks (Sect. 4.2): interior grid points with
+ * z_{j-1} < z_j >= z_{j+1}, no flag other than FREDEC_FLAG_RESCORED, and
+ * z_j > zmin.  z, flags: device [F] (flags nullable).  Synchronises `stream`;
+ * writes up to `cap` peaks sorted by index to the host arrays idx_host,
+ * z_host and the total count (possibly above cap) to *n_found. */
+int fredec_peaks_workspace(int64_t cap, size_t* bytes);
+int fredec_peaks(fredec_ctx* ctx, void* stream, const double* z, const uint8_t* flags, int64_t F, double zmin,
+                 void* workspace, size_t ws_bytes, int64_t cap, int64_t* idx_host, double* z_host,
+                 int64_t* n_found);
+
+/* Phase 3 backward cascade (Sect. 4.4; the 2^m - 1 joint tests of Sect. 2)
+ * over all subsets of a pool of n <= FREDEC_MAX_POOL frequencies.  ltab
+ * (device [2^n], float64): l of every subset indexed by its mask, ltab[0] =
+ * l_0 (constant model); non-finite entries fail every test.  Subset S
+ * survives iff for every proper subset S' (the empty one included)
+ *   (N - 3|S| - 1)/2 ln(l(S') / l(S)) > zcrit[|S| - |S'|]
+ * (zcrit host [n+1]).  Outputs (device [2^n]): survive_out, maximal_out
+ * (survivors with no surviving strict superset: the output sets, which are
+ * never nested) and G_out (nullable) = l(S) (N - 1) / (N - 3|S| - 1), the
+ * goodness of fit of Sect. 6. */
+int fredec_cascade_workspace(int32_t n, size_t* bytes);
+int fredec_cascade(fredec_ctx* ctx, void* stream, const double* ltab, int32_t n, int64_t N,
+                   const double* zcrit_host, void* workspace, size_t ws_bytes, uint8_t* survive_out,
+                   uint8_t* maximal_out, double* G_out);
+
+/* Phase 1 preliminary scan (Sect. 4.2): residual scans on the grid
+ * f_j = (j+1) df, j < F, starting from the constant model.  In each scan the
+ * peaks with z > zc1 (single-frequency FAP below fap1) and z >= z_max / 2 join
+ * the pool unless within 0.5 / T_eff of a member (the earlier one is kept);
+ * the highest peak's grid frequency joins the base model while its z exceeds
+ * zc0 (FAP below fap0); otherwise the phase ends.  The pool is then capped at
+ * pool_cap (N/10 if pool_cap <= 0) by dropping the largest-FAP candidates
+ * (ties: the higher frequency) and sorted by frequency.  A1: A~_1 of eq. zFAP.
+ * With FREDEC_FP32 the scans use the reduced-precision sums and every peak is
+ * followed uphill in float64 (fredec_scan_at) before any decision, so that
+ * the decisions are taken on float64 values.  Synchronises `stream`.
+ * Host outputs: pool_out / pool_z_out [pool capacity], *n_pool, base_out
+ * [max_scans], *n_base, *n_scans, *truncated (candidates dropped by the cap),
+ * *W_out = F df T_eff.  Errors: EINVAL (including fap1 < fap0), a per-series
+ * status code of the first scan (EWEIGHT, EDEGEN), ENOMEM. */
+int fredec_phase1_workspace(int64_t N, int64_t F, int32_t max_scans, int32_t precision, size_t* bytes);
+int fredec_phase1(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                  double df, int64_t F, double fap0, double fap1, double A1, int32_t pool_cap, int32_t max_scans,
+                  int32_t precision, void* workspace, size_t ws_bytes, double* pool_out, double* pool_z_out,
+                  int32_t* n_pool, double* base_out, int32_t* n_base, int32_t* n_scans, int32_t* truncated,
+                  double* W_out);
 
 #ifdef __cplusplus
 }

@@ -226,7 +226,7 @@ int fredec_tuples_workspace(int64_t N, int32_t n_pool, const uint64_t* masks, in
 int fredec_tuples(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
                   const double* pool, int32_t n_pool, const uint64_t* masks, int64_t n_tuples, int32_t refine_steps,
                   int32_t precision, void* ws, size_t ws_bytes, double* l_out, double* z_out, double* f_out,
-                  uint8_t* flags_out) {
+                  uint8_t* flags_out, double* l0_out) {
   int rc = check_series_args(t, x, w, N);
   if (rc) return rc;
   if (!pool || refine_steps < 0) return FREDEC_EINVAL;
@@ -262,6 +262,7 @@ int fredec_tuples(fredec_ctx* ctx, void* stream, const double* t, const double* 
   if (launch_tuple_finish(st, D.desc, static_cast<int>(n_tuples), D.com, D.state, D.facc, l_out, z_out, flags_out,
                           f_out, D.members, n_pool) != hipSuccess)
     return FREDEC_EDEVICE;
+  if (l0_out && launch_tuple_l0(st, D.state, l0_out) != hipSuccess) return FREDEC_EDEVICE;
   return FREDEC_OK;
 }
 

@@ -447,6 +447,11 @@ __global__ void tuple_common_kernel(const SeriesHdr* __restrict__ hdr, int64_t N
   com->inv_two_pi_sigma_t = 1.0 / (2.0 * M_PI * sig);
 }
 
+// l_0 of the constant model as evaluated with the first tuple.
+__global__ void tuple_l0_kernel(const TupleState* __restrict__ state, double* __restrict__ l0_out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) l0_out[0] = state[0].l0;
+}
+
 __global__ void copy_f64_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
   if (i < n) dst[i] = src[i];
@@ -522,6 +527,11 @@ hipError_t launch_tuple_init(hipStream_t st, int n_tuples, TupleState* state) {
 
 hipError_t launch_tuple_common(hipStream_t st, const SeriesHdr* hdr, int64_t N, TupleCommon* com) {
   tuple_common_kernel<<<1, 64, 0, st>>>(hdr, N, com);
+  return hipGetLastError();
+}
+
+hipError_t launch_tuple_l0(hipStream_t st, const TupleState* state, double* l0_out) {
+  tuple_l0_kernel<<<1, 64, 0, st>>>(state, l0_out);
   return hipGetLastError();
 }
 

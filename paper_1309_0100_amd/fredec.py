@@ -45,12 +45,20 @@ _SIGS = {
                             c_p, c_p, c_p, c_p]),
     "fredec_tuples_workspace": (c_i32, [c_i64, c_i32, c_p, c_i64, c_i32, c_szp]),
     "fredec_tuples": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_i32, c_p, c_i64, c_i32, c_i32, c_p, c_sz,
-                              c_p, c_p, c_p, c_p]),
+                              c_p, c_p, c_p, c_p, c_p]),
     "fredec_grad_workspace": (c_i32, [c_i64, c_p, c_i64, c_szp]),
     "fredec_grad": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_i64, c_i32, c_p, c_sz, c_p, c_p, c_p, c_p,
                             c_p, c_p]),
     "fredec_ascent": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_i64, c_i32, c_d, c_i32, c_p, c_sz, c_p,
                               c_p, c_p]),
+    "fredec_zcrit": (c_i32, [c_d, c_i32, c_d, c_p, c_p]),
+    "fredec_peaks_workspace": (c_i32, [c_i64, c_szp]),
+    "fredec_peaks": (c_i32, [c_p, c_p, c_p, c_p, c_i64, c_d, c_p, c_sz, c_i64, c_p, c_p, c_p]),
+    "fredec_cascade_workspace": (c_i32, [c_i32, c_szp]),
+    "fredec_cascade": (c_i32, [c_p, c_p, c_p, c_i32, c_i64, c_p, c_p, c_sz, c_p, c_p, c_p]),
+    "fredec_phase1_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_szp]),
+    "fredec_phase1": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_d, c_i64, c_d, c_d, c_d, c_i32, c_i32, c_i32, c_p,
+                              c_sz, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
     "fredec_scan_at_workspace": (c_i32, [c_i64, c_i32, c_szp]),
     "fredec_scan_at": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_i32, c_d, c_p, c_i64, c_p, c_sz, c_p, c_p]),
 }
@@ -248,9 +256,10 @@ class Context:
 
 
     # ------------------------------------------------------------ tuples
-    def tuples(self, t, x, w, pool, masks=None, refine_steps=0, precision=FP64):
+    def tuples(self, t, x, w, pool, masks=None, refine_steps=0, precision=FP64, l_out=None, l0_out=None):
         """Statistics of subsets of a frequency pool.  Returns device tensors
-        (l, z, f[n_tuples, n_pool], flags)."""
+        (l, z, f[n_tuples, n_pool], flags); l may be written into a caller
+        tensor l_out, and l_0 of the constant model into l0_out."""
         torch = _torch()
         t, x, w = self._f64(t), self._f64(x), self._f64(w)
         pool = np.ascontiguousarray(pool, np.float64)
@@ -261,12 +270,13 @@ class Context:
         _check(load().fredec_tuples_workspace(t.numel(), npool, _ptr(mk), nt, refine_steps, ctypes.byref(need)),
                "fredec_tuples_workspace")
         ws = self._workspace(need.value)
-        l, z = self._empty(nt, torch.float64), self._empty(nt, torch.float64)
+        l = self._empty(nt, torch.float64) if l_out is None else l_out
+        z = self._empty(nt, torch.float64)
         f = self._empty(nt * npool, torch.float64)
         fl = self._empty(nt, torch.uint8)
         _check(load().fredec_tuples(self.handle, _stream(self.device), _ptr(t), _ptr(x), _ptr(w), t.numel(),
                                     _ptr(pool), npool, _ptr(mk), nt, refine_steps, precision, _ptr(ws), need.value,
-                                    _ptr(l), _ptr(z), _ptr(f), _ptr(fl)), "fredec_tuples")
+                                    _ptr(l), _ptr(z), _ptr(f), _ptr(fl), _ptr(l0_out)), "fredec_tuples")
         return l, z, f.view(nt, npool), fl
 
     def grad(self, t, x, w, f, toff, want_grad=True, precision=FP64):
@@ -304,6 +314,66 @@ class Context:
                                     _ptr(toff), nt, steps, float(clamp), precision, _ptr(ws), need.value, _ptr(z),
                                     _ptr(l), _ptr(fl)), "fredec_ascent")
         return f, z, l, fl
+
+
+    # ------------------------------------------------------------ selection
+    def peaks(self, z, flags, zmin, cap=1 << 16):
+        """Local maxima of z above zmin: (idx, z) host arrays sorted by index."""
+        F = z.numel()
+        need = ctypes.c_size_t()
+        _check(load().fredec_peaks_workspace(cap, ctypes.byref(need)), "fredec_peaks_workspace")
+        ws = self._workspace(need.value)
+        idx = np.zeros(cap, np.int64)
+        zp = np.zeros(cap, np.float64)
+        nf = ctypes.c_int64()
+        _check(load().fredec_peaks(self.handle, _stream(self.device), _ptr(z), _ptr(flags), F, float(zmin), _ptr(ws),
+                                   need.value, cap, _ptr(idx), _ptr(zp), ctypes.byref(nf)), "fredec_peaks")
+        n = min(nf.value, cap)
+        return idx[:n].copy(), zp[:n].copy()
+
+    def cascade(self, ltab, n, N, zcrit):
+        """Phase 3: (survive, maximal, G) device tensors of length 2^n."""
+        torch = _torch()
+        ltab = self._f64(ltab)
+        zc = np.ascontiguousarray(zcrit, np.float64)
+        need = ctypes.c_size_t()
+        _check(load().fredec_cascade_workspace(n, ctypes.byref(need)), "fredec_cascade_workspace")
+        ws = self._workspace(need.value)
+        M = 1 << n
+        surv, maxi = self._empty(M, torch.uint8), self._empty(M, torch.uint8)
+        G = self._empty(M, torch.float64)
+        _check(load().fredec_cascade(self.handle, _stream(self.device), _ptr(ltab), n, int(N), _ptr(zc), _ptr(ws),
+                                     need.value, _ptr(surv), _ptr(maxi), _ptr(G)), "fredec_cascade")
+        return surv, maxi, G
+
+    def phase1(self, t, x, w, df, F, fap0=0.05, fap1=0.1, A1=1.0, pool_cap=0, max_scans=25, precision=FP64):
+        """Phase 1 preliminary scan: dict with pool, pool_z, base, n_scans, truncated, W."""
+        t, x, w = self._f64(t), self._f64(x), self._f64(w)
+        N = t.numel()
+        need = ctypes.c_size_t()
+        _check(load().fredec_phase1_workspace(N, F, max_scans, precision, ctypes.byref(need)),
+               "fredec_phase1_workspace")
+        ws = self._workspace(need.value)
+        capn = max(pool_cap, N // 10, 1)
+        pool, pz = np.zeros(capn), np.zeros(capn)
+        base = np.zeros(max_scans)
+        n_pool, n_base, n_scans, trunc = (ctypes.c_int32() for _ in range(4))
+        W = ctypes.c_double()
+        _check(load().fredec_phase1(self.handle, _stream(self.device), _ptr(t), _ptr(x), _ptr(w), N, float(df),
+                                    int(F), fap0, fap1, A1, pool_cap, max_scans, precision, _ptr(ws), need.value,
+                                    _ptr(pool), _ptr(pz), ctypes.byref(n_pool), _ptr(base), ctypes.byref(n_base),
+                                    ctypes.byref(n_scans), ctypes.byref(trunc), ctypes.byref(W)), "fredec_phase1")
+        return {"pool": pool[:n_pool.value].copy(), "pool_z": pz[:n_pool.value].copy(),
+                "base": base[:n_base.value].copy(), "n_scans": n_scans.value, "truncated": trunc.value,
+                "W": W.value}
+
+
+def zcrit(W, n, fap, A=None):
+    """Thresholds zc[0..n] of eq. zFAP (host computation in libfredec)."""
+    zc = np.zeros(n + 1)
+    Aa = None if A is None else np.ascontiguousarray(A, np.float64)
+    _check(load().fredec_zcrit(float(W), int(n), float(fap), _ptr(Aa), _ptr(zc)), "fredec_zcrit")
+    return zc
 
 
 @dataclass

@@ -107,3 +107,46 @@ def test_create_without_gpu_reports_device_error(lib):
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
     assert lib.fredec_create(ctypes.byref(h), 0) == F.EDEVICE
+
+
+def test_zcrit_host_entry_point_matches_oracle(lib):
+    import oracle as O
+    zc = F.zcrit(1234.5, 8, 0.05)
+    for d in range(1, 9):
+        assert abs(zc[d] - O.zcrit(d, 1234.5, 0.05)) <= 1e-12 * zc[d]
+    A = np.linspace(0.5, 2.0, 9)
+    zc2 = F.zcrit(50.0, 8, 0.1, A)
+    for d in range(1, 9):
+        assert abs(zc2[d] - O.zcrit(d, 50.0, 0.1, A[d])) <= 1e-12 * zc2[d]
+    with pytest.raises(F.FredecError):
+        F.zcrit(-1.0, 3, 0.05)
+    with pytest.raises(F.FredecError):
+        F.zcrit(10.0, 3, 1.5)
+
+
+def test_selection_entry_points_validate_host_arguments(lib):
+    d = ctypes.c_void_p(16)
+    n = ctypes.c_size_t()
+    assert lib.fredec_cascade_workspace(30, ctypes.byref(n)) == F.ENOTSUP
+    assert lib.fredec_cascade_workspace(10, ctypes.byref(n)) == F.OK and n.value >= 1024
+    zc = np.zeros(11)
+    assert lib.fredec_cascade(None, None, d, 10, 100, _p(zc), d, n.value, d, d, None) == F.EINVAL
+    assert lib.fredec_cascade(None, None, d, 10, 100, _p(zc), d, 10, d, d, None) == F.ENOMEM
+    zc[3] = np.nan
+    assert lib.fredec_cascade(None, None, d, 10, 100, _p(zc), d, n.value, d, d, None) == F.EINVAL
+    assert lib.fredec_phase1_workspace(100, 1000, 5, 0, ctypes.byref(n)) == F.OK
+    out = np.zeros(16)
+    i32 = [ctypes.c_int32() for _ in range(4)]
+    W = ctypes.c_double()
+    args = lambda fap0, fap1: (None, None, d, d, d, 100, 1e-3, 1000, fap0, fap1, 1.0, 0, 5, 0, d, n.value, _p(out),
+                               _p(out), ctypes.byref(i32[0]), _p(out), ctypes.byref(i32[1]), ctypes.byref(i32[2]),
+                               ctypes.byref(i32[3]), ctypes.byref(W))
+    assert lib.fredec_phase1(*args(0.2, 0.1)) == F.EINVAL        # FAP_1 >= FAP_0 violated
+    assert lib.fredec_phase1(*args(0.05, 0.1)) == F.EINVAL       # valid, null context
+    masks = np.array([1, 3], np.uint64)
+    assert lib.fredec_tuples_workspace(100, 2, _p(masks), 2, 0, ctypes.byref(n)) == F.OK
+    assert lib.fredec_tuples_workspace(100, 30, None, 3, 0, ctypes.byref(n)) == F.ENOTSUP
+    assert lib.fredec_tuples_workspace(100, 3, None, 5, 0, ctypes.byref(n)) == F.EINVAL   # need 2^3 - 1
+    assert lib.fredec_tuples_workspace(10, 3, None, 7, 0, ctypes.byref(n)) == F.EDOF
+    toff = np.array([0, 2, 2], np.int64)
+    assert lib.fredec_grad_workspace(100, _p(toff), 2, ctypes.byref(n)) == F.EINVAL       # empty tuple

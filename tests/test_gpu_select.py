@@ -1,0 +1,95 @@
+"""GPU parity of the selection steps: periodogram peaks, Phase 1 (the pool of
+candidates, bit-exact in both precisions), Phase 3 (surviving and maximal
+subsets, bit-exact) and the whole pipeline against the oracle pipeline."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1309_0100_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1309_0100_amd import fredec as F
+    return F.Context(0)
+
+
+def test_peaks_match_oracle(ctx):
+    s = synth.plain()
+    z, fl, _, _ = ctx.scan_series(s.t, s.x, s.w, [], s.df, s.F)
+    ref = O.scan(s.t, s.x, s.w, [], s.df, s.F)
+    pk = O.local_maxima(ref.z, ref.flags)
+    for zmin in (0.0, 5.0, 30.0):
+        idx, zp = ctx.peaks(z, fl, zmin)
+        exp = pk[ref.z[pk] > zmin]
+        assert np.array_equal(idx, exp)
+
+
+@pytest.mark.parametrize("n", [1, 3, 6, 10, 14])
+def test_cascade_matches_oracle(ctx, n):
+    rng = np.random.default_rng(100 + n)
+    N = 400
+    # a nested signal structure plus noise so that survivors are non-trivial
+    q = rng.uniform(0.6, 0.999, size=n)
+    ltab = np.array([np.prod(q[[k for k in range(n) if S >> k & 1]]) for S in range(1 << n)])
+    ltab *= rng.uniform(0.98, 1.0, size=ltab.size)
+    ltab[0] = 1.0
+    if n > 3:
+        ltab[5] = np.nan                                   # a degenerate tuple fails every test
+    zc = O.zcrit_table(n, 200.0, 0.05)
+    surv, maxi, G = (a.cpu().numpy() for a in ctx.cascade(ltab, n, N, zc))
+    s_ref, m_ref, tests = O.phase3(ltab, n, N, zc)
+    assert tests == 3 ** n - 2 ** n
+    assert np.array_equal(surv.astype(bool), s_ref)
+    assert sorted(np.flatnonzero(maxi)) == sorted(m_ref.tolist())
+    for S in m_ref:
+        assert abs(G[S] - O.goodness(ltab[S], N, O.popcount(int(S)))) <= 1e-14 * G[S]
+
+
+def test_cascade_multiplicative_pin(ctx):
+    n = 6
+    q = np.array([0.5, 0.999, 0.5, 0.999, 0.5, 0.999])
+    ltab = np.array([np.prod(q[[k for k in range(n) if S >> k & 1]]) for S in range(1 << n)])
+    surv, maxi, G = (a.cpu().numpy() for a in ctx.cascade(ltab, n, 1000, O.zcrit_table(n, 300.0, 0.05)))
+    assert list(np.flatnonzero(maxi)) == [0b010101]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_phase1_matches_oracle(ctx, prec):
+    s = synth.plain()
+    p = ctx.phase1(s.t, s.x, s.w, s.df, s.F, precision=prec)
+    r = O.phase1(s.t, s.x, s.w, s.df, s.F)
+    print(f"case: phase1 plain precision={prec}: pool {p['pool']} base {p['base']} scans {p['n_scans']}",
+          flush=True)
+    assert np.array_equal(p["pool"], r.pool)
+    assert np.array_equal(p["base"], r.base)
+    assert p["n_scans"] == r.n_scans and p["truncated"] == r.truncated
+    assert np.allclose(p["pool_z"], r.pool_z, rtol=1e-9)
+    assert abs(p["W"] - r.W) <= 1e-12 * r.W
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_pipeline_alias_example_matches_oracle(ctx, prec):
+    from paper_1309_0100_amd import pipeline
+    s = synth.two_frequency_alias()
+    df, F, R = 1e-3, 2000, 8
+    res = pipeline.run(ctx, s.t, s.x, s.w, df, F, refine_steps=R, precision=prec)
+    r1 = O.phase1(s.t, s.x, s.w, df, F)
+    assert np.array_equal(res.pool, r1.pool)
+    nrm = O.normalize(s.t, s.x, s.w)
+    n = r1.pool.size
+    ltab, fref = O.phase2(nrm, r1.pool, refine_steps=R)
+    surv, maximal, _ = O.phase3(ltab, n, nrm.N, O.zcrit_table(n, r1.W, 0.05))
+    print(f"case: pipeline precision={prec}: {len(res.solutions)} solutions", flush=True)
+    assert [sol.mask for sol in res.solutions] == maximal.tolist()
+    assert np.array_equal(res.survive.astype(bool), surv)
+    for sol in res.solutions:
+        mem = [k for k in range(n) if sol.mask >> k & 1]
+        assert np.max(np.abs(sol.freqs - np.sort(fref[sol.mask][mem]))) * nrm.T_eff < 1e-7
+        assert abs(sol.l - ltab[sol.mask]) <= 1e-9 * ltab[sol.mask]
+    pairs = [sol for sol in res.solutions if len(sol.freqs) == 2]
+    assert len(pairs) == 1 and np.allclose(pairs[0].freqs, [0.9, 1.1], atol=0.05 / nrm.T_eff)
