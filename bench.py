@@ -1,16 +1,27 @@
-"""Benchmark of the FREDEC residual-periodogram hot path on one MI355X.
+"""Benchmark of the FREDEC multifrequency-periodogram hot path on one MI355X.
 
-Workload (default): the residual scan - one series of N=2000 irregular times
-over 4000 d with seasonal gaps (8 months on / 4 off), 4 injected sinusoids,
-base model = constant + the 4 injected frequencies (m = 4), F = 10^6 grid
-frequencies up to 2 cycles/day.  One step = normalisation, base-model
-precomputation, trig sums and 2x2 Schur solves for every grid frequency
-(fredec_scan).  Inputs are resident in HBM before the timed region.
+Default workload (the metric's configuration): the residual scan - one series
+of N=2000 irregular times over 4000 d with seasonal gaps (8 months on / 4 off),
+4 injected sinusoids, base model = constant + the 4 injected frequencies
+(m = 4), F = 10^6 grid frequencies up to 2 cycles/day.  One step = the scan
+path: normalisation, base-model precomputation (orthonormal basis), trig
+generation and sums, 2x2 Schur solves and z for every grid frequency, float64
+re-scoring of ill-conditioned points (float32 form), and the list of
+periodogram peaks above the FAP_1 threshold (fredec_scan + fredec_peaks).
+Both forms are timed; the headline is the faster float32-MFMA form, the
+float64 path is reported beside it.  Inputs are resident in HBM before the
+timed region starts.
 
-Prints one JSON line: points/s = N * F per second (whole job), the roofline of
-the dominant kernel (its duration measured live with HIP events on its own
-stream), and the float64 CPU oracle timed on a bounded sample of the same
-workload on the host cores.
+The JSON line also carries the tuple workload (N=1000 over 3000 d, 65536
+tuples of 1..6 perturbed periodogram peaks, forward z + adjoint dz/df + update
+for 20 ascent steps: fredec_ascent) as tuples/s, the roofline of each dominant
+kernel (its average duration measured live with HIP events on the call's
+stream), the error against the float64 oracle on a sample, and the oracle
+itself timed on a bounded sample of the same workload on the host cores.
+
+--workload batched: 4096 series of uneven N and m (CSR batch), F = 65536.
+--workload full: the whole method on N = 10^4 (Phase 1 scans on F = 4e6, a
+16-frequency pool, 65535 refined subtuples, Phase 3).
 """
 from __future__ import annotations
 
@@ -30,7 +41,7 @@ METRIC = "periodogram points/s (N×F) + tuples/s at stated rel-err vs FP64 oracl
 # MI355X published peaks
 PEAK_FP64_VALU = 78.6e12      # flop/s, FMA = 2 flops
 PEAK_FP32_MFMA = 157.3e12     # flop/s, dense
-PEAK_HBM = 8.0e12             # B/s
+PEAK_FP64_MFMA = 78.6e12
 
 
 def parse():
@@ -38,130 +49,271 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time of the CPU baseline")
+    ap.add_argument("--workload", choices=["residual", "batched", "full"], default="residual")
+    ap.add_argument("--precision", choices=["fp32", "fp64", "both"], default="both")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time of the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tuples", action="store_true")
+    ap.add_argument("--tuple-steps", type=int, default=3, help="timed fredec_ascent calls of the tuple workload")
     ap.add_argument("--tile", type=int, default=0, help="MFMA frequency tiles per wave (0 = tuned/default)")
     return ap.parse_args()
 
 
-def cpu_baseline(s, z_gpu, seconds):
-    """The float64 oracle on a bounded, strided sample of the grid, single
-    thread; also the error of the GPU result on those frequencies."""
+def timed(ctx, step, steps, warmup):
+    """Wall time per step over `steps` timed steps (after `warmup`), and the
+    HIP-event time of the library's profiled kernels per step."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kms, nl = ctx.profile_read()
+    ctx.profile(False)
+    return el / steps, kms / 1e3 / max(steps, 1), nl
+
+
+def fap_pool_threshold(s):
+    from paper_1309_0100_amd import fredec
+    span = float(s.t.max() - s.t.min())
+    return float(fredec.zcrit(s.F * s.df * span, 1, 0.1)[1])
+
+
+# ------------------------------------------------------------------ residual
+def residual_leg(ctx, args, prec_name, s):
+    import torch
+    from paper_1309_0100_amd import fredec
+    prec = fredec.FP64 if prec_name == "fp64" else fredec.FP32
+    dev = torch.device("cuda", 0)
+    t, x, w = (torch.as_tensor(a, device=dev) for a in (s.t, s.x, s.w))
+    soff = np.array([0, s.N], np.int64)
+    boff = np.array([0, s.base_f.size], np.int64)
+    ws = torch.empty(ctx.scan_workspace(soff, boff, [s.F], prec), dtype=torch.uint8, device=dev)
+    out = (torch.empty(s.F, dtype=torch.float64, device=dev), torch.empty(s.F, dtype=torch.uint8, device=dev),
+           torch.empty(1, dtype=torch.float64, device=dev), torch.empty(1, dtype=torch.int32, device=dev))
+    zc1 = fap_pool_threshold(s)
+    peaks = {}
+
+    def step():
+        ctx.scan(t, x, w, soff, s.base_f, boff, [s.df], [s.F], prec, workspace=ws, out=out)
+        peaks["p"] = ctx.peaks(out[0], out[1], zc1)
+
+    sec, ksec, nl = timed(ctx, step, args.steps, args.warmup)
+    points = s.N * s.F
+    m = s.base_f.size
+    KP, K = 2 * m + 2, 2 * m + 1
+    if prec == fredec.FP64:
+        fpp = 2 * (2 * KP + 3)
+        roof = {"bound": "alu", "peak": PEAK_FP64_VALU, "kernel": "scan_f64_kernel",
+                "algorithmic": f"{fpp} flop per (frequency, sample) pair: {2 * KP + 3} float64 multiply-adds "
+                               f"(cos and sin against {KP} columns, cos^2, cos sin, sin^2)"}
+    else:
+        fpp = 4 * K
+        roof = {"bound": "mfma", "peak": PEAK_FP32_MFMA, "kernel": "scan_mfma_kernel",
+                "algorithmic": f"{fpp} flop per (frequency, sample) pair: cos and sin against the {K} "
+                               "orthonormal base columns, one float32 multiply-add each, on MFMA (unpadded)"}
+    achieved = fpp * points / ksec
+    z = out[0].cpu().numpy()
+    fl = out[1].cpu().numpy()
+    leg = {"value": points / sec, "ms_per_step": sec * 1e3,
+           "roofline": {"bound": roof["bound"], "achieved": achieved / 1e12, "peak": roof["peak"] / 1e12,
+                        "unit": "TFLOP/s", "frac": achieved / roof["peak"], "traffic": None,
+                        "kernel": roof["kernel"], "kernel_ms": ksec * 1e3, "launches_per_step": nl / args.steps,
+                        "algorithmic": roof["algorithmic"]},
+           "rescored_points": int(((fl & 64) != 0).sum()), "n_peaks_above_fap1": int(len(peaks["p"][0]))}
+    return leg, z
+
+
+def oracle_sample(s, z_gpu, seconds):
+    """The float64 oracle on a bounded strided sample of the grid, one thread,
+    and the error of each GPU form there."""
     try:
         from threadpoolctl import threadpool_limits
         limiter = threadpool_limits(limits=1)
     except Exception:  # pragma: no cover
         limiter = None
     import oracle as O
-    stride = 11
+    stride = 7
     idx_all = np.arange(0, s.F, stride)
-    done = []
-    errs = []
+    done = 0
+    err = {k: 0.0 for k in z_gpu}
     t0 = time.perf_counter()
-    block = 256
-    for b in range(0, idx_all.size, block):
-        idx = idx_all[b:b + block]
+    for b in range(0, idx_all.size, 256):
+        idx = idx_all[b:b + 256]
         ref = O.scan(s.t, s.x, s.w, s.base_f, s.df, s.F, idx=idx)
         good = ref.flags == 0
-        zg = z_gpu[idx]
-        errs.append(np.max(np.abs(zg[good] - ref.z[good]) / np.maximum(np.abs(ref.z[good]), 1.0), initial=0.0))
-        done.append(idx.size)
+        for k, v in z_gpu.items():
+            e = np.abs(v[idx][good] - ref.z[good]) / np.maximum(np.abs(ref.z[good]), 1.0)
+            err[k] = max(err[k], float(np.max(e, initial=0.0)))
+        done += idx.size
         if time.perf_counter() - t0 > seconds:
             break
     el = time.perf_counter() - t0
-    nf = int(np.sum(done))
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
-    return {
-        "value": s.N * nf / el,
-        "unit": "points/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"{nf} grid frequencies (every {stride}th of F={s.F}) of the same series, N={s.N}, m={s.base_f.size}; {el:.1f} s",
-    }, float(np.max(errs))
+    del limiter
+    return {"value": s.N * done / el, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} grid frequencies (every {stride}th from the low end of F={s.F}) of the same series, "
+                      f"N={s.N}, m={s.base_f.size}; {el:.1f} s single-threaded"}, err
+
+
+# ------------------------------------------------------------------ tuples
+def tuples_leg(ctx, args, n_steps=20):
+    import torch
+    from paper_1309_0100_amd import synth
+    s = synth.tuples_series()
+    dev = torch.device("cuda", 0)
+    t, x, w = (torch.as_tensor(a, device=dev) for a in (s.t, s.x, s.w))
+    z, fl, _, _ = ctx.scan_series(t, x, w, [], s.df, s.F)
+    idx, zp = ctx.peaks(z, fl, 0.0)
+    top = idx[np.lexsort((idx, -zp))[:12]]
+    peaks = (top + 1).astype(np.float64) * s.df
+    f0, toff = synth.tuples_draw(peaks, n_tuples=65536)
+    f0d = torch.as_tensor(f0, device=dev)
+    nt = toff.size - 1
+    res = {}
+
+    def step():
+        res["r"] = ctx.ascent(t, x, w, f0d, toff, steps=n_steps, clamp=0.1)
+
+    sec, ksec, nl = timed(ctx, step, args.tuple_steps, 1)
+    # Gram pass: C(C+1)/2 multiply-adds per (tuple, sample), C = 2n + 2 columns
+    C = 2 * np.diff(toff).astype(np.float64) + 2
+    gram_flops = float(np.sum(C * (C + 1))) * s.N * (n_steps + 1)
+    achieved = gram_flops / ksec
+    fa, zz, ll, ff = res["r"]
+    leg = {"value": nt / sec, "unit": "tuples/s", "tuple_steps_per_s": nt * n_steps / sec,
+           "ms_per_call": sec * 1e3, "dtype": "f64",
+           "workload": f"N={s.N} over 3000 d, {nt} tuples of 1..6 perturbed peaks of the m=0 scan, "
+                       f"{n_steps} ascent steps (forward z + adjoint dz/df + update) per call",
+           "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64_MFMA / 1e12,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
+                        "kernel": "tuple_gram_kernel", "kernel_ms_per_call": ksec * 1e3,
+                        "launches_per_call": nl / args.tuple_steps,
+                        "algorithmic": "C(C+1) flop per (tuple, sample) per pass, C = 2n+2 Gram columns "
+                                       f"(lower triangle incl. data column), {n_steps + 1} passes per call"}}
+    return leg, (s, f0, toff, fa.cpu().numpy(), zz.cpu().numpy(), ff.cpu().numpy())
+
+
+def tuples_error(data, n_check=48):
+    import oracle as O
+    s, f0, toff, fa, zz, ff = data
+    nrm = O.normalize(s.t, s.x, s.w)
+    err_f, err_z = 0.0, 0.0
+    nt = toff.size - 1
+    for k in range(0, nt, max(1, nt // n_check)):
+        fr, zr, lr = O.ascent(nrm, f0[toff[k]:toff[k + 1]], steps=20, clamp=0.1)
+        if not np.isfinite(zr):
+            continue
+        err_f = max(err_f, float(np.max(np.abs(fa[toff[k]:toff[k + 1]] - fr)) * nrm.T_eff))
+        err_z = max(err_z, float(abs(zz[k] - zr) / max(abs(zr), 1.0)))
+    return {"z": err_z, "f_times_T_eff": err_f, "tuples_checked": len(range(0, nt, max(1, nt // n_check)))}
+
+
+# ------------------------------------------------------------------ batched
+def batched_leg(ctx, args, prec_name, b):
+    import torch
+    from paper_1309_0100_amd import fredec
+    prec = fredec.FP64 if prec_name == "fp64" else fredec.FP32
+    dev = torch.device("cuda", 0)
+    t, x, w = (torch.as_tensor(a, device=dev) for a in (b.t, b.x, b.w))
+    ws = torch.empty(ctx.scan_workspace(b.soff, b.boff, b.F, prec), dtype=torch.uint8, device=dev)
+    tot = int(np.sum(b.F))
+    ns = b.soff.size - 1
+    out = (torch.empty(tot, dtype=torch.float64, device=dev), torch.empty(tot, dtype=torch.uint8, device=dev),
+           torch.empty(ns, dtype=torch.float64, device=dev), torch.empty(ns, dtype=torch.int32, device=dev))
+
+    def step():
+        ctx.scan(t, x, w, b.soff, b.base_f, b.boff, b.df, b.F, prec, workspace=ws, out=out)
+
+    steps = max(2, args.steps // 4)
+    sec, ksec, _ = timed(ctx, step, steps, 1)
+    points = float(np.sum(np.diff(b.soff) * np.asarray(b.F)))
+    return {"value": points / sec, "ms_per_step": sec * 1e3, "kernel_ms": ksec * 1e3, "pairs": points}
+
+
+# ------------------------------------------------------------------ full
+def full_leg(ctx, args, prec_name, s):
+    import torch
+    from paper_1309_0100_amd import fredec, pipeline
+    prec = fredec.FP64 if prec_name == "fp64" else fredec.FP32
+    dev = torch.device("cuda", 0)
+    t, x, w = (torch.as_tensor(a, device=dev) for a in (s.t, s.x, s.w))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = pipeline.run(ctx, t, x, w, s.df, s.F, pool_cap=16, refine_steps=8, precision=prec)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    n = res.pool.size
+    return {"seconds": el, "n_scans": res.n_scans, "pool": [float(f) for f in res.pool],
+            "n_tuples": (1 << n) - 1, "n_solutions": len(res.solutions),
+            "solutions": [[float(f) for f in sol.freqs] for sol in res.solutions[:5]],
+            "scan_pairs": float(s.N) * s.F * res.n_scans}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
-    import torch
     from paper_1309_0100_amd import fredec, synth
-
-    prec = fredec.FP64 if args.precision == "fp64" else fredec.FP32
     ctx = fredec.Context(0)
     if args.tile:
         ctx.set_tile(fredec.TILE_SCAN_MFMA, 1, args.tile)
-    s = synth.residual()
-    dev = torch.device("cuda", 0)
-    t = torch.as_tensor(s.t, device=dev)
-    x = torch.as_tensor(s.x, device=dev)
-    w = torch.as_tensor(s.w, device=dev)
-    soff = np.array([0, s.N], np.int64)
-    boff = np.array([0, s.base_f.size], np.int64)
-    need = ctx.scan_workspace(soff, boff, [s.F], prec)
-    ws = torch.empty(need, dtype=torch.uint8, device=dev)
-    out = (torch.empty(s.F, dtype=torch.float64, device=dev), torch.empty(s.F, dtype=torch.uint8, device=dev),
-           torch.empty(1, dtype=torch.float64, device=dev), torch.empty(1, dtype=torch.int32, device=dev))
+    forms = ["fp32", "fp64"] if args.precision == "both" else [args.precision]
+    res = {"metric": METRIC, "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
 
-    def step():
-        ctx.scan(t, x, w, soff, s.base_f, boff, [s.df], [s.F], prec, workspace=ws, out=out)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    kms, nl = ctx.profile_read()
-    ctx.profile(False)
-    points = s.N * s.F
-    value = points * args.steps / el
-    m = s.base_f.size
-    KP = 2 * m + 2
-    kernel_s = kms / 1e3 / max(nl, 1)
-    if prec == fredec.FP64:
-        sums = 2 * KP + 3                  # trig sums per (frequency, sample) pair
-        flops_per_pair = 2 * sums          # one multiply-add each
-        roof = {"bound": "alu", "peak": PEAK_FP64_VALU, "kernel": "scan_f64_kernel",
-                "algorithmic": f"{flops_per_pair} flop per (frequency, sample) pair: {sums} float64 multiply-adds"}
+    if args.workload == "residual":
+        s = synth.residual()
+        legs, zs = {}, {}
+        for fm in forms:
+            legs[fm], zs[fm] = residual_leg(ctx, args, fm, s)
+        head = max(forms, key=lambda k: legs[k]["value"])
+        res.update({"value": legs[head]["value"], "ms_per_step": legs[head]["ms_per_step"],
+                    "dtype": "f32" if head == "fp32" else "f64",
+                    "config": {"workload": "residual scan: N=2000 over 4000 d, seasonal gaps, m=4 base sinusoids, "
+                                           "F=10^6 grid to 2 c/d; scan + peak list per step",
+                               "N": s.N, "F": s.F, "m": int(s.base_f.size), "form": head},
+                    "roofline": legs[head]["roofline"],
+                    "rescored_points": legs[head]["rescored_points"]})
+        for fm in forms:
+            if fm != head:
+                res[f"{fm}_form"] = legs[fm]
+        if len(forms) == 2:
+            res["speedup_fp32_over_fp64"] = legs["fp32"]["value"] / legs["fp64"]["value"]
+        data = None
+        if not args.no_tuples:
+            res["tuples"], data = tuples_leg(ctx, args)
+        if not args.no_cpu:
+            cb, err = oracle_sample(s, zs, args.cpu_seconds)
+            res["cpu_baseline"] = cb
+            res["max_rel_err_vs_oracle"] = err
+            if data is not None:
+                res["tuples"]["max_err_vs_oracle"] = tuples_error(data)
+    elif args.workload == "batched":
+        b = synth.batched()
+        legs = {fm: batched_leg(ctx, args, fm, b) for fm in forms}
+        head = max(forms, key=lambda k: legs[k]["value"])
+        res.update({"value": legs[head]["value"], "ms_per_step": legs[head]["ms_per_step"],
+                    "dtype": "f32" if head == "fp32" else "f64",
+                    "config": {"workload": "batched scan: 4096 series, N log-uniform in [50, 5000], "
+                                           "m uniform in 0..6, F=65536", "series": int(b.soff.size - 1),
+                               "samples": int(b.soff[-1]), "form": head},
+                    "forms": legs})
     else:
-        flops_per_pair = 4 * KP            # (cos, sin) x KP columns, one multiply-add each, on MFMA
-        roof = {"bound": "mfma", "peak": PEAK_FP32_MFMA, "kernel": "scan_mfma_kernel",
-                "algorithmic": f"{flops_per_pair} flop per (frequency, sample) pair: 2 x {KP} float32 "
-                               "multiply-adds on MFMA (unpadded)"}
-    achieved = flops_per_pair * points / kernel_s
-    res = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "points/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": el / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == fredec.FP64 else "f32",
-        "data": "synthetic",
-        "config": {"workload": "residual scan: N=2000 over 4000 d, seasonal gaps, m=4 base sinusoids, "
-                               "F=10^6 grid to 2 c/d", "N": s.N, "F": s.F, "m": m,
-                   "precision": args.precision},
-        "roofline": {"bound": roof["bound"], "achieved": achieved / 1e12, "peak": roof["peak"] / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / roof["peak"], "traffic": None,
-                     "kernel": roof["kernel"], "kernel_ms": kernel_s * 1e3, "algorithmic": roof["algorithmic"]},
-    }
-    if not args.no_cpu:
-        z_gpu = out[0].cpu().numpy()
-        cb, err = cpu_baseline(s, z_gpu, args.cpu_seconds)
-        res["cpu_baseline"] = cb
-        res["max_rel_err_vs_oracle"] = err
+        s = synth.full()
+        legs = {fm: full_leg(ctx, args, fm, s) for fm in forms}
+        head = min(forms, key=lambda k: legs[k]["seconds"])
+        res.update({"value": legs[head]["scan_pairs"] / legs[head]["seconds"],
+                    "ms_per_step": legs[head]["seconds"] * 1e3, "steps": 1, "warmup": 0,
+                    "dtype": "f32" if head == "fp32" else "f64",
+                    "config": {"workload": "full method: N=10^4 over 20000 d, Phase 1 scans on F=4e6, pool cap 16, "
+                                           "every subtuple refined (8 Gauss-Newton steps), Phase 3", "form": head},
+                    "forms": legs})
     print(json.dumps(res), flush=True)
 
 

@@ -147,6 +147,36 @@ int fredec_scan_at(fredec_ctx* ctx, void* stream, const double* t, const double*
                    const int64_t* idx, int64_t n_idx, void* workspace, size_t ws_bytes,
                    double* z_out, uint8_t* flags_out);
 
+/* Prepared calls for HIP-graph capture --------------------------------------
+ * A plan does the host part of a call once: it checks the host arguments,
+ * lays out the workspace, uploads the descriptors into it and waits for that
+ * upload (synchronous on `stream`).  Launching a plan (fredec_plan_*) then
+ * only enqueues kernels - no host-to-device copy, no allocation, no memset,
+ * no synchronisation - so a launch can be captured into a HIP graph and the
+ * graph replayed; every launch reads t, x, w (and f) afresh from the given
+ * device pointers, so new data written into the same buffers are picked up.
+ * Between plan creation and its last launch the plan's workspace belongs to
+ * the plan: it must not be freed or passed to another call.  Launches of one
+ * plan that overlap in time (two streams) race on its workspace.  Tile
+ * settings (fredec_set_tile) are fixed when the plan is made.  Timing events
+ * (fredec_profile) must be off while a launch is captured.  A plan is bound
+ * to the context's device and is freed by fredec_plan_destroy (host memory
+ * only; NULL is ignored). */
+typedef struct fredec_plan fredec_plan;
+void fredec_plan_destroy(fredec_plan* plan);
+
+/* Plan of fredec_scan for a fixed CSR batch (arguments and errors as for
+ * fredec_scan; workspace size from fredec_scan_workspace). */
+int fredec_scan_plan(fredec_ctx* ctx, void* stream, int32_t n_series, const int64_t* soff_host,
+                     const double* base_f_host, const int64_t* boff_host, const double* df_host,
+                     const int64_t* F_host, int32_t precision, void* workspace, size_t ws_bytes,
+                     fredec_plan** plan_out);
+/* Launch of a scan plan; t, x, w and the outputs as for fredec_scan.
+ * Errors: EINVAL (null pointer, a plan of another kind or device), EDEVICE. */
+int fredec_plan_scan(fredec_ctx* ctx, fredec_plan* plan, void* stream,
+                     const double* t, const double* x, const double* w,
+                     double* z_out, uint8_t* flags_out, double* l_base_out, int32_t* status_out);
+
 /* Tuple statistics (eq. zpow; Sects. 2, 3, 4.3) --------------------------
  * One series t, x, w (device, N samples) and a pool of n_pool <= FREDEC_MAX_POOL
  * frequencies (host pool[n_pool]).  Tuple k is the subset of the pool given by
@@ -200,6 +230,27 @@ int fredec_ascent(fredec_ctx* ctx, void* stream, const double* t, const double* 
                   double* f, const int64_t* toff_host, int64_t n_tuples, int32_t steps, double clamp,
                   int32_t precision, void* workspace, size_t ws_bytes, double* z_out, double* l_out,
                   uint8_t* flags_out);
+
+/* Plans of fredec_tuples and fredec_ascent (see "Prepared calls" above).
+ * fredec_tuples_plan takes the arguments of fredec_tuples that are fixed per
+ * batch (N, pool, masks, refine_steps, precision; workspace from
+ * fredec_tuples_workspace) and fredec_plan_tuples the series and outputs;
+ * fredec_ascent_plan takes N, the tuple offsets, steps, clamp and precision
+ * (workspace from fredec_grad_workspace) and fredec_plan_ascent the series,
+ * the frequencies f (device, updated in place) and outputs.  Results equal
+ * those of the unplanned calls.  Errors as for those calls. */
+int fredec_tuples_plan(fredec_ctx* ctx, void* stream, int64_t N, const double* pool_host, int32_t n_pool,
+                       const uint64_t* masks_host, int64_t n_tuples, int32_t refine_steps, int32_t precision,
+                       void* workspace, size_t ws_bytes, fredec_plan** plan_out);
+int fredec_plan_tuples(fredec_ctx* ctx, fredec_plan* plan, void* stream,
+                       const double* t, const double* x, const double* w,
+                       double* l_out, double* z_out, double* f_out, uint8_t* flags_out, double* l0_out);
+int fredec_ascent_plan(fredec_ctx* ctx, void* stream, int64_t N, const int64_t* toff_host, int64_t n_tuples,
+                       int32_t steps, double clamp, int32_t precision, void* workspace, size_t ws_bytes,
+                       fredec_plan** plan_out);
+int fredec_plan_ascent(fredec_ctx* ctx, fredec_plan* plan, void* stream,
+                       const double* t, const double* x, const double* w, double* f,
+                       double* z_out, double* l_out, uint8_t* flags_out);
 
 /* FAP thresholds (eq. zFAP) ------------------------------------------------
  * zc[d], d = 1..n (zc[0] = 0): the z with A_d W^d e^{-z} z^{3d/2-1} = fap on

@@ -14,8 +14,9 @@ using namespace fredec;
 namespace fredec {
 
 DeviceGuard::DeviceGuard(int dev) {
-  if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
-  if (prev_ != dev) (void)hipSetDevice(dev);
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+  if (cur != dev && hipSetDevice(dev) == hipSuccess) prev_ = cur;
 }
 DeviceGuard::~DeviceGuard() {
   if (prev_ >= 0) (void)hipSetDevice(prev_);
@@ -41,6 +42,13 @@ int upload(fredec_ctx* ctx, hipStream_t st, void* dst, const void* src, size_t b
   if (hipMemcpyAsync(dst, ctx->staging, bytes, hipMemcpyHostToDevice, st) != hipSuccess) return FREDEC_EDEVICE;
   if (hipEventRecord(ctx->staging_done, st) != hipSuccess) return FREDEC_EDEVICE;
   ctx->staging_pending = true;
+  return FREDEC_OK;
+}
+
+int upload_wait(fredec_ctx* ctx) {
+  if (!ctx->staging_pending) return FREDEC_OK;
+  if (hipEventSynchronize(ctx->staging_done) != hipSuccess) return FREDEC_EDEVICE;
+  ctx->staging_pending = false;
   return FREDEC_OK;
 }
 
@@ -136,6 +144,149 @@ int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, cons
 template <typename T>
 T* at(void* base, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+// A scan batch ready to launch: layout, per-series descriptors, the work list
+// and its grouping by kernel instance.
+struct ScanPlan : fredec_plan {
+  ScanPlan() : fredec_plan(SCAN) {}
+  ScanLayout L;
+  int32_t n_series = 0;
+  int32_t precision = FREDEC_FP64;
+  int64_t base_off = 0;  // soff[0]: t, x, w are indexed from the caller's pointers
+  std::vector<SeriesIn> sin;
+  std::vector<ScanWork> work;
+  struct Group {
+    int key;         // KP (float64) or column tiles NT (MFMA)
+    int ft;          // MFMA: 16-frequency tiles per wave the work list was cut for
+    int64_t begin, end;
+  };
+  std::vector<Group> groups;
+};
+
+// Host part of a scan: checks, workspace layout, descriptors and work list.
+int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, const double* base_f,
+               const int64_t* boff, const double* df, const int64_t* F, int32_t precision, void* ws, size_t ws_bytes,
+               ScanPlan& P) {
+  if (!df) return FREDEC_EINVAL;
+  ScanLayout& L = P.L;
+  int rc = scan_layout(n_series, soff, boff, F, precision, L);
+  if (rc) return rc;
+  if (boff[n_series] > boff[0] && !base_f) return FREDEC_EINVAL;
+  if (!ws || ws_bytes < L.total) return FREDEC_ENOMEM;
+  P.ws = ws;
+  P.ws_bytes = ws_bytes;
+  P.n_series = n_series;
+  P.precision = precision;
+  P.base_off = soff[0];
+  std::vector<SeriesIn>& sin = P.sin;
+  sin.assign(n_series, SeriesIn{});
+  std::memset(sin.data(), 0, sizeof(SeriesIn) * n_series);
+  int64_t goff = 0, rec_off = 0, phi_off = 0, g32_off = 0, aux_off = 0;
+  for (int32_t s = 0; s < n_series; ++s) {
+    SeriesIn& d = sin[s];
+    d.soff = soff[s];
+    d.N = soff[s + 1] - soff[s];
+    d.goff = goff;
+    d.F = F[s];
+    d.df = df[s];
+    if (!std::isfinite(df[s]) || df[s] == 0.0) return FREDEC_EINVAL;
+    d.rot_step = static_cast<double>(BLOCK) * df[s];
+    d.rot_tile = 16.0 * df[s];
+    d.m = static_cast<int32_t>(boff[s + 1] - boff[s]);
+    d.KP = 2 * d.m + 2;
+    d.NT = col_tiles(d.KP);
+    for (int k = 0; k < d.m; ++k) {
+      d.base_f[k] = base_f[boff[s] - boff[0] + k];
+      if (!std::isfinite(d.base_f[k])) return FREDEC_EINVAL;
+    }
+    d.rec_off = rec_off;
+    d.phi_off = phi_off;
+    d.g32_off = g32_off;
+    d.aux_off = aux_off;
+    goff += F[s];
+    phi_off += d.N * d.KP;
+    rec_off += d.N * rec_stride(d.KP);
+    if (precision == FREDEC_FP32) {
+      g32_off += d.N * 16 * d.NT;
+      aux_off += d.N * AUX_STRIDE;
+    }
+  }
+  // Work list: tiles grouped by kernel instance (KP for float64, column
+  // tiles NT for MFMA), longest series first inside a group.
+  auto key = [&](int32_t s) { return precision == FREDEC_FP64 ? sin[s].KP : sin[s].NT; };
+  std::vector<int32_t> order(n_series);
+  for (int32_t s = 0; s < n_series; ++s) order[s] = s;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    if (key(a) != key(b)) return key(a) < key(b);
+    return sin[a].N > sin[b].N;
+  });
+  P.work.clear();
+  P.work.reserve(L.n_work);
+  P.groups.clear();
+  for (int32_t s : order) {
+    const int ft = precision == FREDEC_FP32 ? mfma_ft_for(ctx, sin[s].NT) : 0;
+    const int64_t tile = precision == FREDEC_FP32 ? 64 * static_cast<int64_t>(ft) : scan_tile(sin[s].KP, precision);
+    if (P.groups.empty() || P.groups.back().key != key(s))
+      P.groups.push_back(ScanPlan::Group{key(s), ft, static_cast<int64_t>(P.work.size()), 0});
+    for (int64_t j0 = 0; j0 < sin[s].F; j0 += tile) P.work.push_back(ScanWork{s, 0, j0});
+    P.groups.back().end = static_cast<int64_t>(P.work.size());
+  }
+  return FREDEC_OK;
+}
+
+// Descriptors and work list into the workspace (asynchronous on `st`).
+int scan_upload(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P) {
+  int rc;
+  if ((rc = upload(ctx, st, at<SeriesIn>(P.ws, P.L.off_sin), P.sin.data(), sizeof(SeriesIn) * P.sin.size())))
+    return rc;
+  return upload(ctx, st, at<ScanWork>(P.ws, P.L.off_work), P.work.data(), sizeof(ScanWork) * P.work.size());
+}
+
+// Kernel launches of a scan whose descriptors are in the workspace: no host
+// to device copies, allocations or synchronisation (capturable).
+int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const double* t, const double* x, const double* w,
+                double* z_out, uint8_t* flags_out, double* l_base_out, int32_t* status_out) {
+  const ScanLayout& L = P.L;
+  void* ws = P.ws;
+  SeriesIn* d_sin = at<SeriesIn>(ws, L.off_sin);
+  SeriesHdr* d_hdr = at<SeriesHdr>(ws, L.off_hdr);
+  ScanWork* d_work = at<ScanWork>(ws, L.off_work);
+  double* d_tau = at<double>(ws, L.off_tau);
+  double* d_xt = at<double>(ws, L.off_xt);
+  double* d_wt = at<double>(ws, L.off_wt);
+  double* d_rec = at<double>(ws, L.off_rec);
+  double* d_phi = at<double>(ws, L.off_phi);
+  float* d_g32 = at<float>(ws, L.off_g32);
+  double* d_aux = at<double>(ws, L.off_aux);
+  Rescore* d_list = at<Rescore>(ws, L.off_list);
+  unsigned long long* d_count = at<unsigned long long>(ws, L.off_count);
+  const bool f32 = P.precision == FREDEC_FP32;
+  // soff is absolute into t/x/w; the normalised copies use the same indexing
+  // shifted by soff[0] (the batch is contiguous).
+  const int64_t base_off = P.base_off;
+  const int flags = PREP_BASE | PREP_REC64 | (f32 ? PREP_F32 : 0);
+  if (f32 && launch_zero_u64(st, d_count, 1) != hipSuccess) return FREDEC_EDEVICE;
+  if (launch_prep(st, P.n_series, d_sin, d_hdr, t, x, w, d_tau - base_off, d_xt - base_off, d_wt - base_off, d_rec,
+                  d_phi, d_g32, d_aux, flags) != hipSuccess)
+    return FREDEC_EDEVICE;
+  {
+    ProfScope prof(ctx, st);
+    for (const auto& gr : P.groups) {
+      const int n = static_cast<int>(gr.end - gr.begin);
+      const hipError_t err =
+          f32 ? launch_scan_mfma(st, gr.key, gr.ft, n, d_work + gr.begin, d_sin, d_hdr, d_g32, d_aux, z_out,
+                                 flags_out, d_list, d_count)
+              : launch_scan_f64(st, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_rec, z_out, flags_out);
+      if (err != hipSuccess) return FREDEC_EDEVICE;
+    }
+  }
+  if (f32 && launch_rescore(st, L.max_nt, 4 * std::max(ctx->n_cu, 1), d_sin, d_hdr, d_rec, d_list, d_count, z_out,
+                            flags_out) != hipSuccess)
+    return FREDEC_EDEVICE;
+  if (launch_copy_stats(st, P.n_series, d_hdr, d_sin, l_base_out, status_out, nullptr) != hipSuccess)
+    return FREDEC_EDEVICE;
+  return FREDEC_OK;
 }
 
 }  // namespace
@@ -282,111 +433,53 @@ int fredec_scan(fredec_ctx* ctx, void* stream, int32_t n_series, const double* t
                 int32_t precision, void* ws, size_t ws_bytes, double* z_out, uint8_t* flags_out, double* l_base_out,
                 int32_t* status_out) {
   // host-side checks first (they need no device), the context last
-  if (!t || !x || !w || !df || !z_out) return FREDEC_EINVAL;
-  ScanLayout L;
-  int rc = scan_layout(n_series, soff, boff, F, precision, L);
+  if (!t || !x || !w || !z_out) return FREDEC_EINVAL;
+  ScanPlan P;
+  int rc = scan_build(ctx, n_series, soff, base_f, boff, df, F, precision, ws, ws_bytes, P);
   if (rc) return rc;
-  if (boff[n_series] > boff[0] && !base_f) return FREDEC_EINVAL;
-  if (!ws || ws_bytes < L.total) return FREDEC_ENOMEM;
-
-  std::vector<SeriesIn> sin(n_series);
-  std::memset(sin.data(), 0, sizeof(SeriesIn) * n_series);
-  int64_t goff = 0, rec_off = 0, phi_off = 0, g32_off = 0, aux_off = 0;
-  for (int32_t s = 0; s < n_series; ++s) {
-    SeriesIn& d = sin[s];
-    d.soff = soff[s];
-    d.N = soff[s + 1] - soff[s];
-    d.goff = goff;
-    d.F = F[s];
-    d.df = df[s];
-    if (!std::isfinite(df[s]) || df[s] == 0.0) return FREDEC_EINVAL;
-    d.rot_step = static_cast<double>(BLOCK) * df[s];
-    d.rot_tile = 16.0 * df[s];
-    d.m = static_cast<int32_t>(boff[s + 1] - boff[s]);
-    d.KP = 2 * d.m + 2;
-    d.NT = col_tiles(d.KP);
-    for (int k = 0; k < d.m; ++k) {
-      d.base_f[k] = base_f[boff[s] - boff[0] + k];
-      if (!std::isfinite(d.base_f[k])) return FREDEC_EINVAL;
-    }
-    d.rec_off = rec_off;
-    d.phi_off = phi_off;
-    d.g32_off = g32_off;
-    d.aux_off = aux_off;
-    goff += F[s];
-    phi_off += d.N * d.KP;
-    rec_off += d.N * rec_stride(d.KP);
-    if (precision == FREDEC_FP32) {
-      g32_off += d.N * 16 * d.NT;
-      aux_off += d.N * AUX_STRIDE;
-    }
-  }
-  // Work list: tiles grouped by kernel instance (KP for float64, column
-  // tiles NT for MFMA), longest series first inside a group.
-  auto key = [&](int32_t s) { return precision == FREDEC_FP64 ? sin[s].KP : sin[s].NT; };
-  std::vector<int32_t> order(n_series);
-  for (int32_t s = 0; s < n_series; ++s) order[s] = s;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    if (key(a) != key(b)) return key(a) < key(b);
-    return sin[a].N > sin[b].N;
-  });
-  std::vector<ScanWork> work;
-  work.reserve(L.n_work);
-  std::vector<std::pair<int, std::pair<int64_t, int64_t>>> groups;  // key -> [begin, end)
-  for (int32_t s : order) {
-    const int64_t tile = precision == FREDEC_FP32 ? 64 * static_cast<int64_t>(mfma_ft_for(ctx, sin[s].NT))
-                                                  : scan_tile(sin[s].KP, precision);
-    if (groups.empty() || groups.back().first != key(s)) groups.push_back({key(s), {(int64_t)work.size(), 0}});
-    for (int64_t j0 = 0; j0 < sin[s].F; j0 += tile) work.push_back(ScanWork{s, 0, j0});
-    groups.back().second.second = static_cast<int64_t>(work.size());
-  }
-
   if (!ctx) return FREDEC_EINVAL;
   DeviceGuard g(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  SeriesIn* d_sin = at<SeriesIn>(ws, L.off_sin);
-  SeriesHdr* d_hdr = at<SeriesHdr>(ws, L.off_hdr);
-  ScanWork* d_work = at<ScanWork>(ws, L.off_work);
-  double* d_tau = at<double>(ws, L.off_tau);
-  double* d_xt = at<double>(ws, L.off_xt);
-  double* d_wt = at<double>(ws, L.off_wt);
-  double* d_rec = at<double>(ws, L.off_rec);
-  double* d_phi = at<double>(ws, L.off_phi);
-  float* d_g32 = at<float>(ws, L.off_g32);
-  double* d_aux = at<double>(ws, L.off_aux);
-  Rescore* d_list = at<Rescore>(ws, L.off_list);
-  unsigned long long* d_count = at<unsigned long long>(ws, L.off_count);
-  if ((rc = upload(ctx, st, d_sin, sin.data(), sizeof(SeriesIn) * n_series))) return rc;
-  if ((rc = upload(ctx, st, d_work, work.data(), sizeof(ScanWork) * work.size()))) return rc;
-  // soff is absolute into t/x/w; the normalised copies use the same indexing
-  // shifted by soff[0] (the batch is contiguous).
-  const int64_t base_off = soff[0];
-  const int flags = PREP_BASE | PREP_REC64 | (precision == FREDEC_FP32 ? PREP_F32 : 0);
-  if (precision == FREDEC_FP32 && launch_zero_u64(st, d_count, 1) != hipSuccess) return FREDEC_EDEVICE;
-  if (launch_prep(st, n_series, d_sin, d_hdr, t, x, w, d_tau - base_off, d_xt - base_off, d_wt - base_off, d_rec,
-                  d_phi, d_g32, d_aux, flags) != hipSuccess)
-    return FREDEC_EDEVICE;
-  {
-    ProfScope prof(ctx, st);
-    for (auto& gr : groups) {
-      const int64_t b = gr.second.first, e = gr.second.second;
-      hipError_t err;
-      if (precision == FREDEC_FP64)
-        err = launch_scan_f64(st, gr.first, static_cast<int>(e - b), d_work + b, d_sin, d_hdr, d_rec, z_out, flags_out);
-      else
-        err = launch_scan_mfma(st, gr.first, mfma_ft_for(ctx, gr.first), static_cast<int>(e - b), d_work + b, d_sin,
-                               d_hdr, d_g32, d_aux, z_out, flags_out, d_list, d_count);
-      if (err != hipSuccess) return FREDEC_EDEVICE;
-    }
+  if ((rc = scan_upload(ctx, st, P))) return rc;
+  return scan_launch(ctx, st, P, t, x, w, z_out, flags_out, l_base_out, status_out);
+}
+
+int fredec_scan_plan(fredec_ctx* ctx, void* stream, int32_t n_series, const int64_t* soff, const double* base_f,
+                     const int64_t* boff, const double* df, const int64_t* F, int32_t precision, void* ws,
+                     size_t ws_bytes, fredec_plan** plan_out) {
+  if (!plan_out) return FREDEC_EINVAL;
+  *plan_out = nullptr;
+  ScanPlan* P = new (std::nothrow) ScanPlan();
+  if (!P) return FREDEC_ENOMEM;
+  int rc = scan_build(ctx, n_series, soff, base_f, boff, df, F, precision, ws, ws_bytes, *P);
+  if (!rc && !ctx) rc = FREDEC_EINVAL;
+  if (!rc) {
+    DeviceGuard g(ctx->device);
+    P->device = ctx->device;
+    rc = scan_upload(ctx, static_cast<hipStream_t>(stream), *P);
+    if (!rc) rc = upload_wait(ctx);
+    // the descriptors are on the device now; the host copies are not needed
+    std::vector<SeriesIn>().swap(P->sin);
+    std::vector<ScanWork>().swap(P->work);
   }
-  if (precision == FREDEC_FP32 &&
-      launch_rescore(st, L.max_nt, 4 * std::max(ctx->n_cu, 1), d_sin, d_hdr, d_rec, d_list, d_count, z_out,
-                     flags_out) != hipSuccess)
-    return FREDEC_EDEVICE;
-  if (launch_copy_stats(st, n_series, d_hdr, d_sin, l_base_out, status_out, nullptr) != hipSuccess)
-    return FREDEC_EDEVICE;
+  if (rc) {
+    delete P;
+    return rc;
+  }
+  *plan_out = P;
   return FREDEC_OK;
 }
+
+int fredec_plan_scan(fredec_ctx* ctx, fredec_plan* plan, void* stream, const double* t, const double* x,
+                     const double* w, double* z_out, uint8_t* flags_out, double* l_base_out, int32_t* status_out) {
+  if (!ctx || !plan || plan->kind != fredec_plan::SCAN || !t || !x || !w || !z_out) return FREDEC_EINVAL;
+  if (plan->device != ctx->device) return FREDEC_EINVAL;
+  DeviceGuard g(ctx->device);
+  return scan_launch(ctx, static_cast<hipStream_t>(stream), *static_cast<ScanPlan*>(plan), t, x, w, z_out, flags_out,
+                     l_base_out, status_out);
+}
+
+void fredec_plan_destroy(fredec_plan* plan) { delete plan; }
 
 int fredec_scan_at_workspace(int64_t N, int32_t m, size_t* bytes) {
   if (!bytes || N <= 0 || m < 0) return FREDEC_EINVAL;

@@ -25,10 +25,23 @@ struct fredec_ctx {
   size_t prof_used = 0;
 };
 
+// A prepared call (fredec_*_plan): the host-side launch schedule of a batch
+// whose device descriptors already sit in the caller's workspace, so that a
+// launch only enqueues kernels.
+struct fredec_plan {
+  enum Kind { SCAN = 1, TUPLES = 2, ASCENT = 3 };
+  explicit fredec_plan(int k) : kind(k) {}
+  virtual ~fredec_plan() = default;
+  int kind;
+  int device = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+};
+
 namespace fredec {
 
 // Makes `dev` current for the lifetime of the guard and restores the
-// caller's device afterwards.
+// caller's device afterwards (no device call at all when `dev` is current).
 class DeviceGuard {
  public:
   explicit DeviceGuard(int dev);
@@ -41,6 +54,8 @@ class DeviceGuard {
 };
 
 int upload(fredec_ctx* ctx, hipStream_t st, void* dst, const void* src, size_t bytes);
+// Waits until every upload enqueued so far has reached the device.
+int upload_wait(fredec_ctx* ctx);
 
 // Records a pair of HIP events on `st` around the dominant kernel launches of
 // a call when the context has profiling enabled.

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "fredec_api_internal.h"
@@ -29,7 +30,7 @@ struct TuplePlan {
   int max_n = 0;
   size_t off_sin = 0, off_hdr = 0, off_com = 0, off_tau = 0, off_xt = 0, off_wt = 0, off_desc = 0, off_order = 0,
          off_state = 0, off_ftry = 0, off_facc = 0, off_step = 0, off_theta = 0, off_gram = 0, off_scr = 0,
-         off_g = 0, off_h = 0, off_members = 0, total = 0;
+         off_g = 0, off_h = 0, off_members = 0, off_f0 = 0, total = 0;
 };
 
 // sizes[k] = number of frequencies of tuple k; gn = whether Gauss-Newton
@@ -90,6 +91,7 @@ int make_plan(int64_t N, const std::vector<int>& sizes, bool gn, TuplePlan& P) {
   P.off_g = take(sizeof(double) * P.nf);
   P.off_h = take(sizeof(double) * P.nf);
   P.off_members = take(P.nf);
+  P.off_f0 = take(sizeof(double) * P.nf);
   P.total = off;
   return FREDEC_OK;
 }
@@ -105,6 +107,7 @@ struct TupleDev {
   TupleState* state;
   double *ftry, *facc, *step, *theta, *gram, *scr, *g, *h;
   int8_t* members;
+  double* f0;  // starting frequencies of a subset batch
 };
 
 TupleDev dev_ptrs(void* ws, const TuplePlan& P) {
@@ -127,12 +130,12 @@ TupleDev dev_ptrs(void* ws, const TuplePlan& P) {
   D.g = at<double>(ws, P.off_g);
   D.h = at<double>(ws, P.off_h);
   D.members = at<int8_t>(ws, P.off_members);
+  D.f0 = at<double>(ws, P.off_f0);
   return D;
 }
 
-// Normalisation of the series and the tuple descriptors on the device.
-int upload_and_normalise(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, const double* t,
-                         const double* x, const double* w, int64_t N) {
+// Series and tuple descriptors into the workspace (asynchronous on `st`).
+int upload_descriptors(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, int64_t N) {
   SeriesIn si;
   std::memset(&si, 0, sizeof(si));
   si.N = N;
@@ -140,7 +143,12 @@ int upload_and_normalise(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, co
   int rc;
   if ((rc = upload(ctx, st, D.sin, &si, sizeof(si)))) return rc;
   if ((rc = upload(ctx, st, D.desc, P.desc.data(), sizeof(TupleDesc) * P.desc.size()))) return rc;
-  if ((rc = upload(ctx, st, D.order, P.order.data(), sizeof(int32_t) * P.order.size()))) return rc;
+  return upload(ctx, st, D.order, P.order.data(), sizeof(int32_t) * P.order.size());
+}
+
+// Normalisation of the series and reset of the per-tuple state (kernels only).
+int normalise(hipStream_t st, const TuplePlan& P, const TupleDev& D, const double* t, const double* x,
+              const double* w, int64_t N) {
   if (launch_prep(st, 1, D.sin, D.hdr, t, x, w, D.tau, D.xt, D.wt, nullptr, nullptr, nullptr, nullptr, 0) !=
       hipSuccess)
     return FREDEC_EDEVICE;
@@ -207,6 +215,121 @@ int sizes_from_masks(int32_t n_pool, const uint64_t* masks, int64_t n_tuples, st
   return FREDEC_OK;
 }
 
+// A batch of pool subsets (fredec_tuples) ready to launch.
+struct SubsetPlan : fredec_plan {
+  SubsetPlan() : fredec_plan(TUPLES) {}
+  TuplePlan T;
+  int64_t N = 0;
+  int32_t n_pool = 0, refine_steps = 0;
+  std::vector<double> f0;   // starting frequencies of the members, in bit order
+  std::vector<int8_t> mem;  // pool index of each member
+};
+
+int subset_build(int64_t N, const double* pool, int32_t n_pool, const uint64_t* masks, int64_t n_tuples,
+                 int32_t refine_steps, int32_t precision, void* ws, size_t ws_bytes, SubsetPlan& P) {
+  if (!pool || refine_steps < 0) return FREDEC_EINVAL;
+  if (precision != FREDEC_FP64 && precision != FREDEC_FP32) return FREDEC_EINVAL;
+  std::vector<int> sizes;
+  int rc;
+  if ((rc = sizes_from_masks(n_pool, masks, n_tuples, sizes))) return rc;
+  for (int k = 0; k < n_pool; ++k)
+    if (!std::isfinite(pool[k])) return FREDEC_EINVAL;
+  if ((rc = make_plan(N, sizes, refine_steps > 0, P.T))) return rc;
+  if (!ws || ws_bytes < P.T.total) return FREDEC_ENOMEM;
+  P.ws = ws;
+  P.ws_bytes = ws_bytes;
+  P.N = N;
+  P.n_pool = n_pool;
+  P.refine_steps = refine_steps;
+  P.f0.resize(P.T.nf);
+  P.mem.resize(P.T.nf);
+  for (int64_t k = 0; k < n_tuples; ++k) {
+    const uint64_t m = masks ? masks[k] : static_cast<uint64_t>(k + 1);
+    int64_t o = P.T.desc[k].foff;
+    for (int b = 0; b < n_pool; ++b)
+      if (m >> b & 1) {
+        P.f0[o] = pool[b];
+        P.mem[o] = static_cast<int8_t>(b);
+        ++o;
+      }
+  }
+  return FREDEC_OK;
+}
+
+int subset_upload(fredec_ctx* ctx, hipStream_t st, const SubsetPlan& P) {
+  const TupleDev D = dev_ptrs(P.ws, P.T);
+  int rc;
+  if ((rc = upload_descriptors(ctx, st, P.T, D, P.N))) return rc;
+  if ((rc = upload(ctx, st, D.f0, P.f0.data(), sizeof(double) * P.T.nf))) return rc;
+  return upload(ctx, st, D.members, P.mem.data(), P.T.nf);
+}
+
+// Kernels only (capturable).
+int subset_launch(fredec_ctx* ctx, hipStream_t st, const SubsetPlan& P, const double* t, const double* x,
+                  const double* w, double* l_out, double* z_out, double* f_out, uint8_t* flags_out, double* l0_out) {
+  const TupleDev D = dev_ptrs(P.ws, P.T);
+  int rc;
+  if ((rc = normalise(st, P.T, D, t, x, w, P.N))) return rc;
+  if (launch_copy_f64(st, D.f0, D.ftry, P.T.nf) != hipSuccess) return FREDEC_EDEVICE;
+  if ((rc = run_fit(ctx, st, P.T, D, P.refine_steps))) return rc;
+  if (launch_tuple_finish(st, D.desc, static_cast<int>(P.T.desc.size()), D.com, D.state, D.facc, l_out, z_out,
+                          flags_out, f_out, D.members, P.n_pool) != hipSuccess)
+    return FREDEC_EDEVICE;
+  if (l0_out && launch_tuple_l0(st, D.state, l0_out) != hipSuccess) return FREDEC_EDEVICE;
+  return FREDEC_OK;
+}
+
+// A batch of ragged tuples for the fixed-step ascent, ready to launch.
+struct AscentPlan : fredec_plan {
+  AscentPlan() : fredec_plan(ASCENT) {}
+  TuplePlan T;
+  int64_t N = 0;
+  int32_t steps = 0;
+  double clamp = 0.0;
+};
+
+int ascent_build(int64_t N, const int64_t* toff, int64_t n_tuples, int32_t steps, double clamp, int32_t precision,
+                 void* ws, size_t ws_bytes, AscentPlan& P) {
+  if (steps < 0 || !(clamp > 0.0) || !std::isfinite(clamp)) return FREDEC_EINVAL;
+  if (precision != FREDEC_FP64 && precision != FREDEC_FP32) return FREDEC_EINVAL;
+  std::vector<int> sizes;
+  int rc;
+  if ((rc = sizes_from_toff(toff, n_tuples, sizes))) return rc;
+  if ((rc = make_plan(N, sizes, false, P.T))) return rc;
+  if (!ws || ws_bytes < P.T.total) return FREDEC_ENOMEM;
+  P.ws = ws;
+  P.ws_bytes = ws_bytes;
+  P.N = N;
+  P.steps = steps;
+  P.clamp = clamp;
+  return FREDEC_OK;
+}
+
+// Kernels only (capturable): `steps` times forward, adjoint and update, then
+// the final forward evaluation.
+int ascent_launch(fredec_ctx* ctx, hipStream_t st, const AscentPlan& P, const double* t, const double* x,
+                  const double* w, double* f, double* z_out, double* l_out, uint8_t* flags_out) {
+  const TupleDev D = dev_ptrs(P.ws, P.T);
+  const int nt = static_cast<int>(P.T.desc.size());
+  int rc;
+  if ((rc = normalise(st, P.T, D, t, x, w, P.N))) return rc;
+  if (launch_copy_f64(st, f, D.ftry, P.T.nf) != hipSuccess) return FREDEC_EDEVICE;
+  for (int s = 0; s < P.steps; ++s) {
+    if ((rc = run_fit(ctx, st, P.T, D, 0))) return rc;
+    if (launch_tuple_adjoint(st, D.desc, nt, D.com, D.tau, D.xt, D.wt, D.ftry, D.theta, D.state, D.g, D.h) !=
+        hipSuccess)
+      return FREDEC_EDEVICE;
+    if (launch_tuple_ascent_update(st, D.desc, nt, D.com, D.g, D.h, D.ftry, P.clamp, D.state) != hipSuccess)
+      return FREDEC_EDEVICE;
+  }
+  if ((rc = run_fit(ctx, st, P.T, D, 0))) return rc;
+  if (launch_tuple_finish(st, D.desc, nt, D.com, D.state, D.facc, l_out, z_out, flags_out, nullptr, nullptr, 0) !=
+      hipSuccess)
+    return FREDEC_EDEVICE;
+  if (launch_copy_f64(st, D.ftry, f, P.T.nf) != hipSuccess) return FREDEC_EDEVICE;
+  return FREDEC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -229,41 +352,50 @@ int fredec_tuples(fredec_ctx* ctx, void* stream, const double* t, const double* 
                   uint8_t* flags_out, double* l0_out) {
   int rc = check_series_args(t, x, w, N);
   if (rc) return rc;
-  if (!pool || refine_steps < 0) return FREDEC_EINVAL;
-  if (precision != FREDEC_FP64 && precision != FREDEC_FP32) return FREDEC_EINVAL;
-  std::vector<int> sizes;
-  if ((rc = sizes_from_masks(n_pool, masks, n_tuples, sizes))) return rc;
-  for (int k = 0; k < n_pool; ++k)
-    if (!std::isfinite(pool[k])) return FREDEC_EINVAL;
-  TuplePlan P;
-  if ((rc = make_plan(N, sizes, refine_steps > 0, P))) return rc;
-  if (!ws || ws_bytes < P.total) return FREDEC_ENOMEM;
+  SubsetPlan P;
+  if ((rc = subset_build(N, pool, n_pool, masks, n_tuples, refine_steps, precision, ws, ws_bytes, P))) return rc;
   if (!ctx) return FREDEC_EINVAL;
-  // starting frequencies and pool indices of the members, in bit order
-  std::vector<double> f0(P.nf);
-  std::vector<int8_t> mem(P.nf);
-  for (int64_t k = 0; k < n_tuples; ++k) {
-    const uint64_t m = masks ? masks[k] : static_cast<uint64_t>(k + 1);
-    int64_t o = P.desc[k].foff;
-    for (int b = 0; b < n_pool; ++b)
-      if (m >> b & 1) {
-        f0[o] = pool[b];
-        mem[o] = static_cast<int8_t>(b);
-        ++o;
-      }
-  }
   DeviceGuard g(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  TupleDev D = dev_ptrs(ws, P);
-  if ((rc = upload_and_normalise(ctx, st, P, D, t, x, w, N))) return rc;
-  if ((rc = upload(ctx, st, D.ftry, f0.data(), sizeof(double) * P.nf))) return rc;
-  if ((rc = upload(ctx, st, D.members, mem.data(), P.nf))) return rc;
-  if ((rc = run_fit(ctx, st, P, D, refine_steps))) return rc;
-  if (launch_tuple_finish(st, D.desc, static_cast<int>(n_tuples), D.com, D.state, D.facc, l_out, z_out, flags_out,
-                          f_out, D.members, n_pool) != hipSuccess)
-    return FREDEC_EDEVICE;
-  if (l0_out && launch_tuple_l0(st, D.state, l0_out) != hipSuccess) return FREDEC_EDEVICE;
+  if ((rc = subset_upload(ctx, st, P))) return rc;
+  return subset_launch(ctx, st, P, t, x, w, l_out, z_out, f_out, flags_out, l0_out);
+}
+
+int fredec_tuples_plan(fredec_ctx* ctx, void* stream, int64_t N, const double* pool, int32_t n_pool,
+                       const uint64_t* masks, int64_t n_tuples, int32_t refine_steps, int32_t precision, void* ws,
+                       size_t ws_bytes, fredec_plan** plan_out) {
+  if (!plan_out) return FREDEC_EINVAL;
+  *plan_out = nullptr;
+  if (N <= 0) return FREDEC_EINVAL;
+  SubsetPlan* P = new (std::nothrow) SubsetPlan();
+  if (!P) return FREDEC_ENOMEM;
+  int rc = subset_build(N, pool, n_pool, masks, n_tuples, refine_steps, precision, ws, ws_bytes, *P);
+  if (!rc && !ctx) rc = FREDEC_EINVAL;
+  if (!rc) {
+    DeviceGuard g(ctx->device);
+    P->device = ctx->device;
+    rc = subset_upload(ctx, static_cast<hipStream_t>(stream), *P);
+    if (!rc) rc = upload_wait(ctx);
+    std::vector<double>().swap(P->f0);
+    std::vector<int8_t>().swap(P->mem);
+  }
+  if (rc) {
+    delete P;
+    return rc;
+  }
+  *plan_out = P;
   return FREDEC_OK;
+}
+
+int fredec_plan_tuples(fredec_ctx* ctx, fredec_plan* plan, void* stream, const double* t, const double* x,
+                       const double* w, double* l_out, double* z_out, double* f_out, uint8_t* flags_out,
+                       double* l0_out) {
+  if (!ctx || !plan || plan->kind != fredec_plan::TUPLES || plan->device != ctx->device) return FREDEC_EINVAL;
+  const SubsetPlan& P = *static_cast<SubsetPlan*>(plan);
+  int rc = check_series_args(t, x, w, P.N);
+  if (rc) return rc;
+  DeviceGuard g(ctx->device);
+  return subset_launch(ctx, static_cast<hipStream_t>(stream), P, t, x, w, l_out, z_out, f_out, flags_out, l0_out);
 }
 
 int fredec_grad_workspace(int64_t N, const int64_t* toff, int64_t n_tuples, size_t* bytes) {
@@ -293,7 +425,8 @@ int fredec_grad(fredec_ctx* ctx, void* stream, const double* t, const double* x,
   DeviceGuard g(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   TupleDev D = dev_ptrs(ws, P);
-  if ((rc = upload_and_normalise(ctx, st, P, D, t, x, w, N))) return rc;
+  if ((rc = upload_descriptors(ctx, st, P, D, N))) return rc;
+  if ((rc = normalise(st, P, D, t, x, w, N))) return rc;
   if (launch_copy_f64(st, f, D.ftry, P.nf) != hipSuccess) return FREDEC_EDEVICE;
   if ((rc = run_fit(ctx, st, P, D, 0))) return rc;
   const int nt = static_cast<int>(n_tuples);
@@ -312,34 +445,47 @@ int fredec_ascent(fredec_ctx* ctx, void* stream, const double* t, const double* 
                   void* ws, size_t ws_bytes, double* z_out, double* l_out, uint8_t* flags_out) {
   int rc = check_series_args(t, x, w, N);
   if (rc) return rc;
-  if (!f || steps < 0 || !(clamp > 0.0) || !std::isfinite(clamp)) return FREDEC_EINVAL;
-  if (precision != FREDEC_FP64 && precision != FREDEC_FP32) return FREDEC_EINVAL;
-  std::vector<int> sizes;
-  if ((rc = sizes_from_toff(toff, n_tuples, sizes))) return rc;
-  TuplePlan P;
-  if ((rc = make_plan(N, sizes, false, P))) return rc;
-  if (!ws || ws_bytes < P.total) return FREDEC_ENOMEM;
+  if (!f) return FREDEC_EINVAL;
+  AscentPlan P;
+  if ((rc = ascent_build(N, toff, n_tuples, steps, clamp, precision, ws, ws_bytes, P))) return rc;
   if (!ctx) return FREDEC_EINVAL;
   DeviceGuard g(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  TupleDev D = dev_ptrs(ws, P);
-  const int nt = static_cast<int>(n_tuples);
-  if ((rc = upload_and_normalise(ctx, st, P, D, t, x, w, N))) return rc;
-  if (launch_copy_f64(st, f, D.ftry, P.nf) != hipSuccess) return FREDEC_EDEVICE;
-  for (int s = 0; s < steps; ++s) {
-    if ((rc = run_fit(ctx, st, P, D, 0))) return rc;
-    if (launch_tuple_adjoint(st, D.desc, nt, D.com, D.tau, D.xt, D.wt, D.ftry, D.theta, D.state, D.g, D.h) !=
-        hipSuccess)
-      return FREDEC_EDEVICE;
-    if (launch_tuple_ascent_update(st, D.desc, nt, D.com, D.g, D.h, D.ftry, clamp, D.state) != hipSuccess)
-      return FREDEC_EDEVICE;
+  if ((rc = upload_descriptors(ctx, st, P.T, dev_ptrs(ws, P.T), N))) return rc;
+  return ascent_launch(ctx, st, P, t, x, w, f, z_out, l_out, flags_out);
+}
+
+int fredec_ascent_plan(fredec_ctx* ctx, void* stream, int64_t N, const int64_t* toff, int64_t n_tuples, int32_t steps,
+                       double clamp, int32_t precision, void* ws, size_t ws_bytes, fredec_plan** plan_out) {
+  if (!plan_out) return FREDEC_EINVAL;
+  *plan_out = nullptr;
+  if (N <= 0) return FREDEC_EINVAL;
+  AscentPlan* P = new (std::nothrow) AscentPlan();
+  if (!P) return FREDEC_ENOMEM;
+  int rc = ascent_build(N, toff, n_tuples, steps, clamp, precision, ws, ws_bytes, *P);
+  if (!rc && !ctx) rc = FREDEC_EINVAL;
+  if (!rc) {
+    DeviceGuard g(ctx->device);
+    P->device = ctx->device;
+    rc = upload_descriptors(ctx, static_cast<hipStream_t>(stream), P->T, dev_ptrs(ws, P->T), N);
+    if (!rc) rc = upload_wait(ctx);
   }
-  if ((rc = run_fit(ctx, st, P, D, 0))) return rc;
-  if (launch_tuple_finish(st, D.desc, nt, D.com, D.state, D.facc, l_out, z_out, flags_out, nullptr, nullptr, 0) !=
-      hipSuccess)
-    return FREDEC_EDEVICE;
-  if (launch_copy_f64(st, D.ftry, f, P.nf) != hipSuccess) return FREDEC_EDEVICE;
+  if (rc) {
+    delete P;
+    return rc;
+  }
+  *plan_out = P;
   return FREDEC_OK;
+}
+
+int fredec_plan_ascent(fredec_ctx* ctx, fredec_plan* plan, void* stream, const double* t, const double* x,
+                       const double* w, double* f, double* z_out, double* l_out, uint8_t* flags_out) {
+  if (!ctx || !plan || plan->kind != fredec_plan::ASCENT || plan->device != ctx->device || !f) return FREDEC_EINVAL;
+  const AscentPlan& P = *static_cast<AscentPlan*>(plan);
+  int rc = check_series_args(t, x, w, P.N);
+  if (rc) return rc;
+  DeviceGuard g(ctx->device);
+  return ascent_launch(ctx, static_cast<hipStream_t>(stream), P, t, x, w, f, z_out, l_out, flags_out);
 }
 
 }  // extern "C"

@@ -61,6 +61,13 @@ _SIGS = {
                               c_sz, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
     "fredec_scan_at_workspace": (c_i32, [c_i64, c_i32, c_szp]),
     "fredec_scan_at": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_i32, c_d, c_p, c_i64, c_p, c_sz, c_p, c_p]),
+    "fredec_plan_destroy": (None, [c_p]),
+    "fredec_scan_plan": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_i32, c_p, c_sz, c_pp]),
+    "fredec_plan_scan": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
+    "fredec_tuples_plan": (c_i32, [c_p, c_p, c_i64, c_p, c_i32, c_p, c_i64, c_i32, c_i32, c_p, c_sz, c_pp]),
+    "fredec_plan_tuples": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
+    "fredec_ascent_plan": (c_i32, [c_p, c_p, c_i64, c_p, c_i64, c_i32, c_d, c_i32, c_p, c_sz, c_pp]),
+    "fredec_plan_ascent": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
 }
 
 _lib = None
@@ -123,6 +130,54 @@ def _torch():
 def _stream(device):
     torch = _torch()
     return torch.cuda.current_stream(device).cuda_stream
+
+
+class Plan:
+    """A prepared libfredec call (fredec_*_plan).  Its launches enqueue
+    kernels only, so they may be captured into a HIP graph
+    (torch.cuda.graph) and replayed.  The plan owns its workspace tensor and
+    keeps the output tensors it was given; every launch reads the series from
+    the tensors passed to `run`, so new data copied into those tensors are
+    picked up by a replay."""
+
+    def __init__(self, ctx: "Context", handle, kind: str, ws, meta: dict):
+        self.ctx, self.handle, self.kind, self.ws, self.meta = ctx, handle, kind, ws, meta
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.fredec_plan_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # pragma: no cover - interpreter shutdown
+            pass
+
+    def run(self, *args, **kw):
+        return getattr(self, "_run_" + self.kind)(*args, **kw)
+
+    def _run_scan(self, t, x, w, out):
+        """out = (z, flags, l_base, status) preallocated device tensors."""
+        z, fl, lb, st = out
+        _check(load().fredec_plan_scan(self.ctx.handle, self.handle, _stream(self.ctx.device), _ptr(t), _ptr(x),
+                                       _ptr(w), _ptr(z), _ptr(fl), _ptr(lb), _ptr(st)), "fredec_plan_scan")
+        return out
+
+    def _run_tuples(self, t, x, w, out):
+        """out = (l, z, f[n_tuples, n_pool], flags, l0) preallocated device tensors."""
+        l, z, f, fl, l0 = out
+        _check(load().fredec_plan_tuples(self.ctx.handle, self.handle, _stream(self.ctx.device), _ptr(t), _ptr(x),
+                                         _ptr(w), _ptr(l), _ptr(z), _ptr(f), _ptr(fl), _ptr(l0)),
+               "fredec_plan_tuples")
+        return out
+
+    def _run_ascent(self, t, x, w, f, out):
+        """f: device float64 frequencies, updated in place; out = (z, l, flags)."""
+        z, l, fl = out
+        _check(load().fredec_plan_ascent(self.ctx.handle, self.handle, _stream(self.ctx.device), _ptr(t), _ptr(x),
+                                         _ptr(w), _ptr(f), _ptr(z), _ptr(l), _ptr(fl)), "fredec_plan_ascent")
+        return f, z, l, fl
 
 
 class Context:
@@ -314,6 +369,63 @@ class Context:
                                     _ptr(toff), nt, steps, float(clamp), precision, _ptr(ws), need.value, _ptr(z),
                                     _ptr(l), _ptr(fl)), "fredec_ascent")
         return f, z, l, fl
+
+
+    # ------------------------------------------------------------ plans
+    def scan_plan(self, soff, base_f, boff, df, F, precision=FP64):
+        """Plan of fredec_scan for a fixed batch; returns (plan, out) with out
+        the preallocated (z, flags, l_base, status) for plan.run(t, x, w, out)."""
+        torch = _torch()
+        soff = np.ascontiguousarray(soff, np.int64)
+        boff = np.ascontiguousarray(boff, np.int64)
+        base_f = np.ascontiguousarray(base_f, np.float64)
+        ns = soff.size - 1
+        df = np.ascontiguousarray(np.broadcast_to(df, (ns,)), np.float64)
+        F = np.ascontiguousarray(np.broadcast_to(F, (ns,)), np.int64)
+        ws = self._workspace(self.scan_workspace(soff, boff, F, precision))
+        h = ctypes.c_void_p()
+        _check(load().fredec_scan_plan(self.handle, _stream(self.device), ns, _ptr(soff),
+                                       _ptr(base_f) if base_f.size else None, _ptr(boff), _ptr(df), _ptr(F),
+                                       precision, _ptr(ws), ws.numel(), ctypes.byref(h)), "fredec_scan_plan")
+        total = int(F.sum())
+        out = (self._empty(total, torch.float64), self._empty(total, torch.uint8), self._empty(ns, torch.float64),
+               self._empty(ns, torch.int32))
+        return Plan(self, h, "scan", ws, {"n_series": ns, "F": F}), out
+
+    def tuples_plan(self, N, pool, masks=None, refine_steps=0, precision=FP64):
+        """Plan of fredec_tuples; returns (plan, out) with out = (l, z, f, flags, l0)."""
+        torch = _torch()
+        pool = np.ascontiguousarray(pool, np.float64)
+        npool = pool.size
+        mk = None if masks is None else np.ascontiguousarray(masks, np.uint64)
+        nt = (1 << npool) - 1 if mk is None else mk.size
+        need = ctypes.c_size_t()
+        _check(load().fredec_tuples_workspace(int(N), npool, _ptr(mk), nt, refine_steps, ctypes.byref(need)),
+               "fredec_tuples_workspace")
+        ws = self._workspace(need.value)
+        h = ctypes.c_void_p()
+        _check(load().fredec_tuples_plan(self.handle, _stream(self.device), int(N), _ptr(pool), npool, _ptr(mk), nt,
+                                         refine_steps, precision, _ptr(ws), need.value, ctypes.byref(h)),
+               "fredec_tuples_plan")
+        out = (self._empty(nt, torch.float64), self._empty(nt, torch.float64),
+               self._empty(nt * npool, torch.float64).view(nt, npool), self._empty(nt, torch.uint8),
+               self._empty(1, torch.float64))
+        return Plan(self, h, "tuples", ws, {"n_tuples": nt}), out
+
+    def ascent_plan(self, N, toff, steps=20, clamp=0.1, precision=FP64):
+        """Plan of fredec_ascent; returns (plan, out) with out = (z, l, flags)."""
+        torch = _torch()
+        toff = np.ascontiguousarray(toff, np.int64)
+        nt = toff.size - 1
+        need = ctypes.c_size_t()
+        _check(load().fredec_grad_workspace(int(N), _ptr(toff), nt, ctypes.byref(need)), "fredec_grad_workspace")
+        ws = self._workspace(need.value)
+        h = ctypes.c_void_p()
+        _check(load().fredec_ascent_plan(self.handle, _stream(self.device), int(N), _ptr(toff), nt, steps,
+                                         float(clamp), precision, _ptr(ws), need.value, ctypes.byref(h)),
+               "fredec_ascent_plan")
+        out = (self._empty(nt, torch.float64), self._empty(nt, torch.float64), self._empty(nt, torch.uint8))
+        return Plan(self, h, "ascent", ws, {"n_tuples": nt}), out
 
 
     # ------------------------------------------------------------ selection

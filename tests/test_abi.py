@@ -150,3 +150,58 @@ def test_selection_entry_points_validate_host_arguments(lib):
     assert lib.fredec_tuples_workspace(10, 3, None, 7, 0, ctypes.byref(n)) == F.EDOF
     toff = np.array([0, 2, 2], np.int64)
     assert lib.fredec_grad_workspace(100, _p(toff), 2, ctypes.byref(n)) == F.EINVAL       # empty tuple
+
+
+def test_plan_entry_points_validate_host_arguments(lib):
+    """The prepared-call entry points run the same host checks as the plain
+    calls, return no plan on failure, and refuse a missing context or plan."""
+    N, Fg = 100, 500
+    soff = np.array([0, N], np.int64)
+    boff = np.array([0, 1], np.int64)
+    base = np.array([0.1])
+    df = np.array([1e-3])
+    Fs = np.array([Fg], np.int64)
+    rc, need = _scan_ws(lib, soff, boff, Fs)
+    d = ctypes.c_void_p(16)   # never dereferenced: every call below fails a host check
+    plan = ctypes.c_void_p(12345)
+
+    def scan_plan(soff=soff, base=base, df=df, prec=0, wsb=need, out=True):
+        plan.value = 12345
+        return lib.fredec_scan_plan(None, None, soff.size - 1, _p(soff), _p(base) if base is not None else None,
+                                    _p(boff), _p(df), _p(Fs), prec, d, wsb, ctypes.byref(plan) if out else None)
+
+    assert scan_plan() == F.EINVAL and plan.value is None       # valid arguments, null context
+    assert scan_plan(wsb=need - 1) == F.ENOMEM and plan.value is None
+    assert scan_plan(base=None) == F.EINVAL
+    assert scan_plan(df=np.array([np.inf])) == F.EINVAL
+    assert scan_plan(soff=np.array([0, 6], np.int64)) == F.EDOF
+    assert scan_plan(prec=2) == F.EINVAL
+    assert scan_plan(out=False) == F.EINVAL
+    assert lib.fredec_plan_scan(None, None, None, d, d, d, d, None, None, None) == F.EINVAL
+
+    pool = np.array([0.1, 0.2, 0.3])
+    n = ctypes.c_size_t()
+    assert lib.fredec_tuples_workspace(200, 3, None, 7, 2, ctypes.byref(n)) == F.OK
+    assert lib.fredec_tuples_plan(None, None, 200, _p(pool), 3, None, 7, 2, 0, d, n.value,
+                                  ctypes.byref(plan)) == F.EINVAL and plan.value is None
+    assert lib.fredec_tuples_plan(None, None, 200, _p(pool), 3, None, 7, 2, 0, d, n.value - 1,
+                                  ctypes.byref(plan)) == F.ENOMEM
+    assert lib.fredec_tuples_plan(None, None, 200, _p(pool), 3, None, 6, 2, 0, d, n.value,
+                                  ctypes.byref(plan)) == F.EINVAL           # n_tuples != 2^n - 1 without masks
+    assert lib.fredec_tuples_plan(None, None, 9, _p(pool), 3, None, 7, 2, 0, d, 1 << 30,
+                                  ctypes.byref(plan)) == F.EDOF
+    assert lib.fredec_plan_tuples(None, None, None, d, d, d, None, None, None, None, None) == F.EINVAL
+
+    toff = np.array([0, 2, 3], np.int64)
+    assert lib.fredec_grad_workspace(200, _p(toff), 2, ctypes.byref(n)) == F.OK
+    assert lib.fredec_ascent_plan(None, None, 200, _p(toff), 2, 20, 0.1, 0, d, n.value,
+                                  ctypes.byref(plan)) == F.EINVAL and plan.value is None
+    assert lib.fredec_ascent_plan(None, None, 200, _p(toff), 2, 20, 0.0, 0, d, n.value,
+                                  ctypes.byref(plan)) == F.EINVAL           # clamp must be > 0
+    assert lib.fredec_ascent_plan(None, None, 200, _p(toff), 2, 20, 0.1, 0, d, n.value - 1,
+                                  ctypes.byref(plan)) == F.ENOMEM
+    bad = np.array([0, 2, 2], np.int64)
+    assert lib.fredec_ascent_plan(None, None, 200, _p(bad), 2, 20, 0.1, 0, d, n.value,
+                                  ctypes.byref(plan)) == F.EINVAL           # empty tuple
+    assert lib.fredec_plan_ascent(None, None, None, d, d, d, d, None, None, None) == F.EINVAL
+    lib.fredec_plan_destroy(None)
