@@ -56,7 +56,24 @@ def parse():
     ap.add_argument("--no-tuples", action="store_true")
     ap.add_argument("--tuple-steps", type=int, default=3, help="timed fredec_ascent calls of the tuple workload")
     ap.add_argument("--tile", type=int, default=0, help="MFMA frequency tiles per wave (0 = tuned/default)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many bytes 5 times (the reference kernel "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def copy_reference(nbytes):
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / 5
+    print(json.dumps({"copy_bytes": 4 * n, "seconds_per_copy": el, "GB_per_s": 2 * 4 * n / el / 1e9}), flush=True)
 
 
 def timed(ctx, step, steps, warmup):
@@ -256,6 +273,9 @@ def full_leg(ctx, args, prec_name, s):
 
 def main():
     args = parse()
+    if args.copy_bytes:
+        copy_reference(args.copy_bytes)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)

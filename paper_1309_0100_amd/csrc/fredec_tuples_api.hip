@@ -24,8 +24,14 @@ int popcount64(uint64_t v) { return __builtin_popcountll(v); }
 // Host-side plan of a tuple batch: descriptors and workspace layout.
 struct TuplePlan {
   std::vector<TupleDesc> desc;
-  std::vector<int32_t> order;                 // tuple indices sorted by Gram blocks
-  std::vector<std::pair<int, int>> groups;    // (NB, count) in `order`
+  std::vector<int32_t> order;  // tuple indices sorted by (Gram blocks, size)
+  struct Group {
+    int nb;         // 16-column Gram blocks
+    int nf;         // frequencies of every tuple of the group
+    int64_t begin;  // first position in `order`
+    int count;
+  };
+  std::vector<Group> groups;
   int64_t nf = 0, ngram = 0, nscratch = 0, ntheta = 0;
   int max_n = 0;
   size_t off_sin = 0, off_hdr = 0, off_com = 0, off_tau = 0, off_xt = 0, off_wt = 0, off_desc = 0, off_order = 0,
@@ -61,11 +67,15 @@ int make_plan(int64_t N, const std::vector<int>& sizes, bool gn, TuplePlan& P) {
   if (N - 3 * static_cast<int64_t>(P.max_n) - 1 <= 0) return FREDEC_EDOF;
   P.order.resize(nt);
   for (int64_t k = 0; k < nt; ++k) P.order[k] = static_cast<int32_t>(k);
-  std::stable_sort(P.order.begin(), P.order.end(), [&](int32_t a, int32_t b) { return P.desc[a].nb < P.desc[b].nb; });
+  std::stable_sort(P.order.begin(), P.order.end(), [&](int32_t a, int32_t b) {
+    if (P.desc[a].nb != P.desc[b].nb) return P.desc[a].nb < P.desc[b].nb;
+    return P.desc[a].n < P.desc[b].n;
+  });
   for (int64_t k = 0; k < nt; ++k) {
-    const int nb = P.desc[P.order[k]].nb;
-    if (P.groups.empty() || P.groups.back().first != nb) P.groups.push_back({nb, 0});
-    P.groups.back().second++;
+    const TupleDesc& d = P.desc[P.order[k]];
+    if (P.groups.empty() || P.groups.back().nb != d.nb || P.groups.back().nf != d.n)
+      P.groups.push_back(TuplePlan::Group{d.nb, d.n, k, 0});
+    P.groups.back().count++;
   }
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -159,13 +169,20 @@ int normalise(hipStream_t st, const TuplePlan& P, const TupleDev& D, const doubl
 
 int gram_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, int mode) {
   ProfScope prof(ctx, st);
-  int64_t base = 0;
-  for (auto& g : P.groups) {
-    if (launch_tuple_gram(st, g.first, D.desc, D.order + base, g.second, D.com, D.tau, D.xt, D.wt, D.ftry, D.state,
-                          D.gram, mode) != hipSuccess)
+  for (const auto& g : P.groups) {
+    if (launch_tuple_gram(st, g.nb, g.nf, D.desc, D.order + g.begin, g.count, D.com, D.tau, D.xt, D.wt, D.ftry,
+                          D.state, D.gram, mode) != hipSuccess)
       return FREDEC_EDEVICE;
-    base += g.second;
   }
+  return FREDEC_OK;
+}
+
+// Adjoint gradient of every tuple (forward state, theta* and f in the workspace).
+int adjoint_pass(hipStream_t st, const TuplePlan& P, const TupleDev& D, const double* f, double* dzdf, double* hout) {
+  for (const auto& g : P.groups)
+    if (launch_tuple_adjoint(st, g.nf, D.desc, D.order + g.begin, g.count, D.com, D.tau, D.xt, D.wt, f, D.theta,
+                             D.state, dzdf, hout) != hipSuccess)
+      return FREDEC_EDEVICE;
   return FREDEC_OK;
 }
 
@@ -316,9 +333,7 @@ int ascent_launch(fredec_ctx* ctx, hipStream_t st, const AscentPlan& P, const do
   if (launch_copy_f64(st, f, D.ftry, P.T.nf) != hipSuccess) return FREDEC_EDEVICE;
   for (int s = 0; s < P.steps; ++s) {
     if ((rc = run_fit(ctx, st, P.T, D, 0))) return rc;
-    if (launch_tuple_adjoint(st, D.desc, nt, D.com, D.tau, D.xt, D.wt, D.ftry, D.theta, D.state, D.g, D.h) !=
-        hipSuccess)
-      return FREDEC_EDEVICE;
+    if ((rc = adjoint_pass(st, P.T, D, D.ftry, D.g, D.h))) return rc;
     if (launch_tuple_ascent_update(st, D.desc, nt, D.com, D.g, D.h, D.ftry, P.clamp, D.state) != hipSuccess)
       return FREDEC_EDEVICE;
   }
@@ -434,9 +449,7 @@ int fredec_grad(fredec_ctx* ctx, void* stream, const double* t, const double* x,
       hipSuccess)
     return FREDEC_EDEVICE;
   if (theta_out && launch_copy_f64(st, D.theta, theta_out, P.ntheta) != hipSuccess) return FREDEC_EDEVICE;
-  if ((dz_df || h_out) && launch_tuple_adjoint(st, D.desc, nt, D.com, D.tau, D.xt, D.wt, D.ftry, D.theta, D.state,
-                                               dz_df, h_out) != hipSuccess)
-    return FREDEC_EDEVICE;
+  if ((dz_df || h_out) && (rc = adjoint_pass(st, P, D, D.ftry, dz_df, h_out))) return rc;
   return FREDEC_OK;
 }
 

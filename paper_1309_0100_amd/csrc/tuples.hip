@@ -14,9 +14,18 @@
 // tuple_solve_kernel: one thread per tuple, float64: Cholesky of the model
 // block, l, theta*, z, and the Gauss-Newton step with the step control shared
 // with the oracle (clamp, accept/halve, tolerance).
-// tuple_adjoint_kernel: one wavefront per tuple, samples over lanes:
-// recomputes the trig terms, the residual r = x~ - Phi theta* and
-// <r J_k>, <J_k^2> (J_k = d mu / d f_k), reduced with wavefront shuffles.
+// tuple_gram_quad_kernel<n>: the forward Gram of tuples of exactly n <= 6
+// frequencies on the VALU, four lanes per tuple (each a quarter of the
+// samples): every sin/cos is evaluated once, only the lower triangle
+// (C(C+1)/2 multiply-adds per sample, C = 2n + 2) is accumulated, and the
+// four partial Gram matrices are added with in-quad shuffles.  For these
+// sizes this does less work than the MFMA kernel, whose 16-column blocks are
+// mostly padding and whose lanes each evaluate a sin/cos for a single column
+// (float64 MFMA and float64 VALU have the same peak rate on this chip).
+// tuple_adjoint_kernel (any n, one wavefront per tuple, samples over lanes)
+// and tuple_adjoint_quad_kernel<n> (n <= 6, four lanes per tuple): recompute
+// the trig terms, the residual r = x~ - Phi theta* and <r J_k>, <J_k^2>
+// (J_k = d mu / d f_k), reduced with shuffles.
 #include "fredec_internal.h"
 #include "fredec_tuples_internal.h"
 
@@ -134,6 +143,80 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
       }
       ++q;
     }
+}
+
+
+constexpr int pidx(int r, int c) { return r * (r + 1) / 2 + c; }
+
+// v + (v of the lane whose quad position differs in bit 0, then in bit 1):
+// the sum over the four lanes of a quad, in a fixed order, by DPP quad
+// permutations (quad_perm [1,0,3,2] and [2,3,0,1]).
+__device__ __forceinline__ double quad_sum(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  v += __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false),
+                        __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false));
+  lo = __double2loint(v);
+  hi = __double2hiint(v);
+  v += __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false),
+                        __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false));
+  return v;
+}
+
+// Four lanes (a quad) per tuple; quads of one launch all have NF frequencies.
+template <int NF>
+__global__ __launch_bounds__(BLOCK) void tuple_gram_quad_kernel(const TupleDesc* __restrict__ desc,
+                                                                const int32_t* __restrict__ order, int n_order,
+                                                                const TupleCommon* __restrict__ com,
+                                                                const double* __restrict__ tau,
+                                                                const double* __restrict__ xt,
+                                                                const double* __restrict__ wt,
+                                                                const double* __restrict__ ftry,
+                                                                const TupleState* __restrict__ state,
+                                                                double* __restrict__ gram) {
+  constexpr int C = 2 * NF + 2;
+  constexpr int NACC = C * (C + 1) / 2;
+  const int gq = static_cast<int>((static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x) >> 2);
+  const int r = threadIdx.x & 3;
+  const bool in_range = gq < n_order;
+  const int ti = in_range ? order[gq] : 0;
+  const bool live = in_range && !state[ti].done;
+  double f[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) f[k] = live ? ftry[desc[ti].foff + k] : 0.0;
+  double acc[NACC];
+#pragma unroll
+  for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
+  if (live) {
+    const int64_t N = com->N;
+#pragma unroll 1
+    for (int64_t i = r; i < N; i += 4) {
+      const double ta = tau[i];
+      const double wi = wt[i];
+      double phi[C];
+      phi[0] = 1.0;
+#pragma unroll
+      for (int k = 0; k < NF; ++k) sincos_rev(f[k] * ta, phi[2 + 2 * k], phi[1 + 2 * k]);
+      phi[C - 1] = xt[i];
+#pragma unroll
+      for (int a = 0; a < C; ++a) {
+        const double wa = wi * phi[a];
+        acc[pidx(a, 0)] += wa;
+#pragma unroll
+        for (int b = 1; b <= a; ++b) acc[pidx(a, b)] = __builtin_fma(wa, phi[b], acc[pidx(a, b)]);
+      }
+    }
+  }
+  // add the four partial sums of the quad (fixed order: deterministic)
+#pragma unroll
+  for (int q = 0; q < NACC; ++q) {
+    acc[q] = quad_sum(acc[q]);
+    asm volatile("" : "+v"(acc[q]));  // complete each sum here: keeps the register count of the loop
+  }
+  if (live && r == 0) {
+    double* G = gram + desc[ti].goff;
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) G[q] = acc[q];
+  }
 }
 
 __device__ __forceinline__ double& P_(double* G, int r, int c) { return G[r * (r + 1) / 2 + c]; }
@@ -333,7 +416,8 @@ __global__ void tuple_finish_kernel(const TupleDesc* __restrict__ desc, int n_tu
 
 // Adjoint: <r J_k> and <J_k^2> with J_k = 2 pi t (-a_k sin 2 pi f_k t + b_k cos 2 pi f_k t),
 // r = x~ - Phi theta*; dz/df_k = (N_H / l) <r J_k>, h_k = (N_H / l) <J_k^2>.
-__global__ __launch_bounds__(BLOCK) void tuple_adjoint_kernel(const TupleDesc* __restrict__ desc, int n_tuples,
+__global__ __launch_bounds__(BLOCK) void tuple_adjoint_kernel(const TupleDesc* __restrict__ desc,
+                                                              const int32_t* __restrict__ order, int n_tuples,
                                                               const TupleCommon* __restrict__ com,
                                                               const double* __restrict__ tau,
                                                               const double* __restrict__ xt,
@@ -345,8 +429,9 @@ __global__ __launch_bounds__(BLOCK) void tuple_adjoint_kernel(const TupleDesc* _
   const int wave = (blockIdx.x * BLOCK + threadIdx.x) >> 6;
   if (wave >= n_tuples) return;
   const int lane = threadIdx.x & 63;
-  const TupleDesc& d = desc[wave];
-  const TupleState& S = state[wave];
+  const int ti = order[wave];
+  const TupleDesc& d = desc[ti];
+  const TupleState& S = state[ti];
   const int n = d.n;
   const double* fk = f + d.foff;
   const double* th = theta + d.thoff;
@@ -364,20 +449,19 @@ __global__ __launch_bounds__(BLOCK) void tuple_adjoint_kernel(const TupleDesc* _
   for (int64_t i = lane; i < N; i += 64) {
     const double ta = tau[i];
     double r = xt[i] - th[0];
+    double sv[MAXPOOL], cv[MAXPOOL];
 #pragma unroll
     for (int k = 0; k < MAXPOOL; ++k) {
       if (k < n) {
-        double s, c;
-        sincos_rev(fk[k] * ta, s, c);
-        r -= th[1 + 2 * k] * c + th[2 + 2 * k] * s;
+        sincos_rev(fk[k] * ta, sv[k], cv[k]);
+        r -= th[1 + 2 * k] * cv[k] + th[2 + 2 * k] * sv[k];
       }
     }
     const double wi = wt[i];
 #pragma unroll
     for (int k = 0; k < MAXPOOL; ++k) {
       if (k < n) {
-        double s, c;
-        sincos_rev(fk[k] * ta, s, c);
+        const double s = sv[k], c = cv[k];
         const double J = 2.0 * M_PI * ta * (-th[1 + 2 * k] * s + th[2 + 2 * k] * c);
         g[k] = __builtin_fma(wi * r, J, g[k]);
         h2[k] = __builtin_fma(wi * J, J, h2[k]);
@@ -399,6 +483,72 @@ __global__ __launch_bounds__(BLOCK) void tuple_adjoint_kernel(const TupleDesc* _
         if (hout) hout[d.foff + k] = coef * b;
       }
     }
+  }
+}
+
+
+// Adjoint for tuples of exactly NF <= 6 frequencies, four lanes per tuple.
+template <int NF>
+__global__ __launch_bounds__(BLOCK) void tuple_adjoint_quad_kernel(const TupleDesc* __restrict__ desc,
+                                                                   const int32_t* __restrict__ order, int n_order,
+                                                                   const TupleCommon* __restrict__ com,
+                                                                   const double* __restrict__ tau,
+                                                                   const double* __restrict__ xt,
+                                                                   const double* __restrict__ wt,
+                                                                   const double* __restrict__ f,
+                                                                   const double* __restrict__ theta,
+                                                                   const TupleState* __restrict__ state,
+                                                                   double* __restrict__ dzdf,
+                                                                   double* __restrict__ hout) {
+  const int gq = static_cast<int>((static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x) >> 2);
+  const int r = threadIdx.x & 3;
+  const bool in_range = gq < n_order;
+  const int ti = in_range ? order[gq] : 0;
+  const TupleState& S = state[ti];
+  const bool live = in_range && S.has_acc && S.l_acc > 0.0;
+  const int64_t foff = desc[ti].foff;
+  double fk[NF], th[2 * NF + 1];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) fk[k] = live ? f[foff + k] : 0.0;
+#pragma unroll
+  for (int k = 0; k < 2 * NF + 1; ++k) th[k] = live ? theta[desc[ti].thoff + k] : 0.0;
+  double g[NF], h2[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) g[k] = h2[k] = 0.0;
+  const int64_t N = com->N;
+  if (live) {
+    for (int64_t i = r; i < N; i += 4) {
+      const double ta = tau[i];
+      double sv[NF], cv[NF];
+      double res = xt[i] - th[0];
+#pragma unroll
+      for (int k = 0; k < NF; ++k) {
+        sincos_rev(fk[k] * ta, sv[k], cv[k]);
+        res -= th[1 + 2 * k] * cv[k] + th[2 + 2 * k] * sv[k];
+      }
+      const double wi = wt[i];
+      const double tpi = 2.0 * M_PI * ta;
+      const double wr = wi * res;
+#pragma unroll
+      for (int k = 0; k < NF; ++k) {
+        const double J = tpi * (-th[1 + 2 * k] * sv[k] + th[2 + 2 * k] * cv[k]);
+        g[k] = __builtin_fma(wr, J, g[k]);
+        h2[k] = __builtin_fma(wi * J, J, h2[k]);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    g[k] = quad_sum(g[k]);
+    h2[k] = quad_sum(h2[k]);
+  }
+  if (!in_range) return;
+  const double coef = static_cast<double>(N - 3 * NF - 1) / S.l_acc;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    if ((k & 3) != r) continue;
+    if (dzdf) dzdf[foff + k] = live ? coef * g[k] : __builtin_nan("");
+    if (hout) hout[foff + k] = live ? coef * h2[k] : __builtin_nan("");
   }
 }
 
@@ -466,12 +616,34 @@ hipError_t gram_nb(hipStream_t st, const TupleDesc* desc, const int32_t* order, 
   return hipGetLastError();
 }
 
+template <int NF>
+hipError_t gram_quad(hipStream_t st, const TupleDesc* desc, const int32_t* order, int n_order,
+                     const TupleCommon* com, const double* tau, const double* xt, const double* wt,
+                     const double* ftry, const TupleState* state, double* gram) {
+  const int blocks = (n_order + BLOCK / 4 - 1) / (BLOCK / 4);
+  tuple_gram_quad_kernel<NF><<<blocks, BLOCK, 0, st>>>(desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+  return hipGetLastError();
+}
+
 }  // namespace
 
-hipError_t launch_tuple_gram(hipStream_t st, int NB, const TupleDesc* desc, const int32_t* order, int n_order,
-                             const TupleCommon* com, const double* tau, const double* xt, const double* wt,
-                             const double* ftry, const TupleState* state, double* gram, int mode) {
+bool tuple_quad_supported(int n, int mode) { return mode == TUPLE_FWD && n >= 1 && n <= QUAD_MAX_N; }
+
+hipError_t launch_tuple_gram(hipStream_t st, int NB, int nf, const TupleDesc* desc, const int32_t* order,
+                             int n_order, const TupleCommon* com, const double* tau, const double* xt,
+                             const double* wt, const double* ftry, const TupleState* state, double* gram, int mode) {
   if (n_order <= 0) return hipSuccess;
+  if (tuple_quad_supported(nf, mode)) {
+    switch (nf) {
+      case 1: return gram_quad<1>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+      case 2: return gram_quad<2>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+      case 3: return gram_quad<3>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+      case 4: return gram_quad<4>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+      case 5: return gram_quad<5>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+      case 6: return gram_quad<6>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (NB) {
     case 1: return gram_nb<1>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
     case 2: return gram_nb<2>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
@@ -502,12 +674,32 @@ hipError_t launch_tuple_finish(hipStream_t st, const TupleDesc* desc, int n_tupl
   return hipGetLastError();
 }
 
-hipError_t launch_tuple_adjoint(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
-                                const double* tau, const double* xt, const double* wt, const double* f,
-                                const double* theta, const TupleState* state, double* dzdf, double* hout) {
-  if (n_tuples <= 0) return hipSuccess;
-  const int blocks = (n_tuples + 3) / 4;
-  tuple_adjoint_kernel<<<blocks, BLOCK, 0, st>>>(desc, n_tuples, com, tau, xt, wt, f, theta, state, dzdf, hout);
+hipError_t launch_tuple_adjoint(hipStream_t st, int nf, const TupleDesc* desc, const int32_t* order, int n_order,
+                                const TupleCommon* com, const double* tau, const double* xt, const double* wt,
+                                const double* f, const double* theta, const TupleState* state, double* dzdf,
+                                double* hout) {
+  if (n_order <= 0) return hipSuccess;
+  if (tuple_quad_supported(nf, TUPLE_FWD)) {
+    const int blocks = (n_order + BLOCK / 4 - 1) / (BLOCK / 4);
+#define FREDEC_ADJ_QUAD(K)                                                                                          \
+  case K:                                                                                                           \
+    tuple_adjoint_quad_kernel<K><<<blocks, BLOCK, 0, st>>>(desc, order, n_order, com, tau, xt, wt, f, theta, state, \
+                                                           dzdf, hout);                                            \
+    break;
+    switch (nf) {
+      FREDEC_ADJ_QUAD(1)
+      FREDEC_ADJ_QUAD(2)
+      FREDEC_ADJ_QUAD(3)
+      FREDEC_ADJ_QUAD(4)
+      FREDEC_ADJ_QUAD(5)
+      FREDEC_ADJ_QUAD(6)
+      default: return hipErrorInvalidValue;
+    }
+#undef FREDEC_ADJ_QUAD
+    return hipGetLastError();
+  }
+  const int blocks = (n_order + 3) / 4;
+  tuple_adjoint_kernel<<<blocks, BLOCK, 0, st>>>(desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
   return hipGetLastError();
 }
 
