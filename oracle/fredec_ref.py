@@ -102,22 +102,26 @@ def design(tau, freqs) -> np.ndarray:
     return np.stack(cols, axis=1)
 
 
-def cholesky_checked(Q, rel_tol=PIVOT_TOL):
+def cholesky_checked(Q, rel_tol=PIVOT_TOL, pivots=False):
     """Textbook Cholesky Q = L L^T over a stack of matrices (..., n, n).
     Returns (L, ok) where ok is False if any pivot falls below rel_tol times
-    its diagonal entry (Sect. 3: Q = L L^T)."""
+    its diagonal entry (Sect. 3: Q = L L^T); with pivots=True also the
+    relative pivots d_j / Q_jj (..., n), the conditioning of each column
+    against the ones before it."""
     Q = np.asarray(Q, np.float64)
     n = Q.shape[-1]
     L = np.zeros_like(Q)
     ok = np.ones(Q.shape[:-2], bool)
+    rel = np.zeros(Q.shape[:-1])
     for j in range(n):
         d = Q[..., j, j] - np.sum(L[..., j, :j] ** 2, axis=-1)
         ok &= d > rel_tol * Q[..., j, j]
+        rel[..., j] = d / Q[..., j, j]
         ljj = np.sqrt(np.where(d > 0, d, 1.0))
         L[..., j, j] = ljj
         for i in range(j + 1, n):
             L[..., i, j] = (Q[..., i, j] - np.sum(L[..., i, :j] * L[..., j, :j], axis=-1)) / ljj
-    return L, ok
+    return (L, ok, rel) if pivots else (L, ok)
 
 
 def forward_subst(L, g):
@@ -178,6 +182,7 @@ class ScanResult:
     l_base: float
     T_eff: float
     freqs: np.ndarray
+    rho: np.ndarray = None  # smaller relative Cholesky pivot of the two trial columns per frequency
 
 
 def scan(t, x, w, base_f, df: float, F: int, idx=None, block: int = 256) -> ScanResult:
@@ -199,6 +204,7 @@ def scan(t, x, w, base_f, df: float, F: int, idx=None, block: int = 256) -> Scan
     f = grid(df, F, idx)
     z = np.zeros(f.size)
     flags = np.zeros(f.size, np.uint8)
+    rho = np.zeros(f.size)
     Phi_b = design(nrm.tau, base_f)
     D = float(np.sum(nrm.wt * nrm.xt * nrm.xt))
     for s in range(0, f.size, block):
@@ -209,7 +215,8 @@ def scan(t, x, w, base_f, df: float, F: int, idx=None, block: int = 256) -> Scan
         WPhi = Phi * nrm.wt[None, :, None]
         Q = np.matmul(np.transpose(WPhi, (0, 2, 1)), Phi)
         g = np.einsum('bnk,n->bk', WPhi, nrm.xt)
-        L, ok = cholesky_checked(Q)
+        L, ok, rel = cholesky_checked(Q, pivots=True)
+        rho[s:s + block] = np.min(rel[:, -2:], axis=1)
         a = forward_subst(L, g)
         l1 = D - np.sum(a * a, axis=1)
         zb = np.zeros(fb.size)
@@ -227,7 +234,7 @@ def scan(t, x, w, base_f, df: float, F: int, idx=None, block: int = 256) -> Scan
             zb[near] = 0.0
         z[s:s + block] = zb
         flags[s:s + block] = fl
-    return ScanResult(z, flags, lm, nrm.T_eff, f)
+    return ScanResult(z, flags, lm, nrm.T_eff, f, rho)
 
 
 # ------------------------------------------------------------------ tuples
@@ -519,6 +526,34 @@ def popcount(m: int) -> int:
     return bin(m).count("1")
 
 
+def proper_subsets(S: int) -> np.ndarray:
+    """Every proper subset S' of the mask S, the empty set included."""
+    subs = []
+    sub = (S - 1) & S
+    while True:
+        subs.append(sub)
+        if sub == 0:
+            break
+        sub = (sub - 1) & S
+    return np.asarray(subs, np.int64)
+
+
+def survives(ltab, S: int, N: int, zc) -> bool:
+    """Sect. 4.4 / Sect. 2: the subset S passes every relative test against
+    its proper subsets S' (including the empty one):
+    z_{S|S'} = (N - 3|S| - 1)/2 * ln(l(S') / l(S)) > z_crit[|S| - |S'|]."""
+    k = popcount(S)
+    NH = n_dof(N, k)
+    lS = ltab[S]
+    if not np.isfinite(lS) or lS <= 0 or NH <= 0:
+        return False
+    subs = proper_subsets(S)
+    d = k - np.array([popcount(int(s)) for s in subs])
+    with np.errstate(invalid="ignore", divide="ignore"):
+        zrel = 0.5 * NH * np.log(ltab[subs] / lS)
+    return bool(np.all(zrel > zc[d]))
+
+
 def phase3(ltab, n: int, N: int, zc) -> tuple[np.ndarray, np.ndarray, int]:
     """Backward cascade of Sect. 4.4 / the 2^m - 1 joint tests of Sect. 2:
     subset S survives iff for every proper subset S' (including the empty
@@ -529,24 +564,8 @@ def phase3(ltab, n: int, N: int, zc) -> tuple[np.ndarray, np.ndarray, int]:
     surv = np.zeros(1 << n, bool)
     tests = 0
     for S in range(1, 1 << n):
-        k = popcount(S)
-        NH = n_dof(N, k)
-        lS = ltab[S]
-        subs = []
-        sub = (S - 1) & S
-        while True:
-            subs.append(sub)
-            if sub == 0:
-                break
-            sub = (sub - 1) & S
-        subs = np.asarray(subs, np.int64)
-        tests += subs.size
-        if not np.isfinite(lS) or lS <= 0 or NH <= 0:
-            continue
-        d = k - np.array([popcount(int(s)) for s in subs])
-        with np.errstate(invalid="ignore", divide="ignore"):
-            zrel = 0.5 * NH * np.log(ltab[subs] / lS)
-        surv[S] = bool(np.all(zrel > zc[d]))
+        tests += (1 << popcount(S)) - 1
+        surv[S] = survives(ltab, S, N, zc)
     # inclusion-maximal survivors: no surviving strict superset
     has_sup = np.zeros(1 << n, bool)
     for S in range((1 << n) - 1, 0, -1):

@@ -35,7 +35,7 @@ def time_scan(ctx, s, base, df, F, reps=5):
     return ms / max(n, 1)
 
 
-def tune(N=2000, F=1_000_000, buckets=(1, 2), reps=5, verbose=True):
+def tune(N=2000, F=1_000_000, buckets=(1, 2), reps=5, verbose=True, out_path=TUNING):
     ctx = fredec.Context(0, tuning=False)
     s = synth.random_series(7, N, span=4000.0, n_sin=4)
     out = {"N": N, "F": F, "scan_mfma": {}}
@@ -51,7 +51,7 @@ def tune(N=2000, F=1_000_000, buckets=(1, 2), reps=5, verbose=True):
             if best is None or ms < best[1]:
                 best = (ft, ms)
         out["scan_mfma"][str(nt)] = {"FT": best[0], "ms": best[1]}
-    with open(TUNING, "w") as fh:
+    with open(out_path, "w") as fh:
         json.dump(out, fh, indent=1)
     return out
 
@@ -72,5 +72,6 @@ if __name__ == "__main__":
     ap.add_argument("--N", type=int, default=2000)
     ap.add_argument("--F", type=int, default=1_000_000)
     ap.add_argument("--buckets", type=int, nargs="+", default=[1, 2])
+    ap.add_argument("--out", default=TUNING, help="where to write the table (default: tuning.json here)")
     a = ap.parse_args()
-    print(json.dumps(tune(a.N, a.F, tuple(a.buckets))))
+    print(json.dumps(tune(a.N, a.F, tuple(a.buckets), out_path=a.out)))

@@ -69,8 +69,10 @@ struct Rescore {
 // Outputs requested from the preparation kernel.
 enum PrepFlags { PREP_BASE = 1, PREP_REC64 = 2, PREP_F32 = 4 };
 
-__host__ __device__ constexpr int rec_stride(int KP) { return ((KP + 3) + 1) & ~1; }
-constexpr int AUX_STRIDE = 6;  // doubles per sample of the MFMA kernel's aux record
+// float64 scan record per sample: tau, cos/sin(2 pi 256 df tau), the KP
+// weighted columns, cos/sin(2 pi df tau); padded to an even count
+__host__ __device__ constexpr int rec_stride(int KP) { return ((KP + 5) + 1) & ~1; }
+constexpr int AUX_STRIDE = 8;  // doubles per sample of the MFMA kernel's aux record
 __host__ __device__ constexpr int col_tiles(int KP) { return (KP - 1 + 15) / 16; }
 
 // ------------------------------------------------------------ device math
@@ -147,34 +149,6 @@ __device__ __forceinline__ void schur_finish(double Scc, double Scs, double Sss,
     return;
   }
   z = 0.5 * h.NH * log(h.l_m / l1);
-}
-
-// Seed for the reduced-precision scan: float64 phase reduction (as in
-// sincos_rev), then sin/cos(2 pi y) of the reduced |y| <= 1/8 by their Taylor
-// series in float32 (coefficients (2 pi)^n / n!, first omitted terms below
-// 3e-9 and 7e-11), widened to float64.  Error about 1.5 float32 ulp.
-__device__ __forceinline__ void sincos_rev_seed32(double p, double& s, double& c) {
-  const double r = p - __builtin_rint(p);
-  const double q = __builtin_rint(4.0 * r);
-  const float y = static_cast<float>(__builtin_fma(-0.25, q, r));
-  const float y2 = y * y;
-  float sp = 42.058693944897655f;
-  sp = __builtin_fmaf(sp, y2, -76.70585975306139f);
-  sp = __builtin_fmaf(sp, y2, 81.60524927607506f);
-  sp = __builtin_fmaf(sp, y2, -41.34170224039976f);
-  sp = __builtin_fmaf(sp, y2, 6.283185307179586f);
-  sp = sp * y;
-  float cp = -26.4262567833744f;
-  cp = __builtin_fmaf(cp, y2, 60.24464137187666f);
-  cp = __builtin_fmaf(cp, y2, -85.45681720669373f);
-  cp = __builtin_fmaf(cp, y2, 64.9393940226683f);
-  cp = __builtin_fmaf(cp, y2, -19.739208802178716f);
-  cp = __builtin_fmaf(cp, y2, 1.0f);
-  const int iq = static_cast<int>(q) & 3;
-  const float ss = (iq & 1) ? cp : sp;
-  const float cc = (iq & 1) ? sp : cp;
-  s = static_cast<double>((iq & 2) ? -ss : ss);
-  c = static_cast<double>((iq == 1 || iq == 2) ? -cc : cc);
 }
 
 // Deterministic block-wide sum of NV values (fixed tree order).

@@ -32,6 +32,8 @@ struct TuplePlan {
     int count;
   };
   std::vector<Group> groups;
+  int64_t N = 0;  // samples of the series
+  int32_t precision = FREDEC_FP64;
   int64_t nf = 0, ngram = 0, nscratch = 0, ntheta = 0;
   int max_n = 0;
   size_t off_sin = 0, off_hdr = 0, off_com = 0, off_tau = 0, off_xt = 0, off_wt = 0, off_desc = 0, off_order = 0,
@@ -42,6 +44,7 @@ struct TuplePlan {
 // sizes[k] = number of frequencies of tuple k; gn = whether Gauss-Newton
 // columns are needed (refinement).
 int make_plan(int64_t N, const std::vector<int>& sizes, bool gn, TuplePlan& P) {
+  P.N = N;
   const int64_t nt = static_cast<int64_t>(sizes.size());
   if (nt <= 0 || nt > (int64_t(1) << 30)) return FREDEC_EINVAL;
   P.desc.resize(nt);
@@ -170,18 +173,19 @@ int normalise(hipStream_t st, const TuplePlan& P, const TupleDev& D, const doubl
 int gram_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, int mode) {
   ProfScope prof(ctx, st);
   for (const auto& g : P.groups) {
-    if (launch_tuple_gram(st, g.nb, g.nf, D.desc, D.order + g.begin, g.count, D.com, D.tau, D.xt, D.wt, D.ftry,
-                          D.state, D.gram, mode) != hipSuccess)
+    if (launch_tuple_gram(st, g.nb, g.nf, ctx->n_cu, D.desc, D.order + g.begin, g.count, P.N, D.com, D.tau, D.xt,
+                          D.wt, D.ftry, D.state, D.gram, mode, P.precision == FREDEC_FP32) != hipSuccess)
       return FREDEC_EDEVICE;
   }
   return FREDEC_OK;
 }
 
 // Adjoint gradient of every tuple (forward state, theta* and f in the workspace).
-int adjoint_pass(hipStream_t st, const TuplePlan& P, const TupleDev& D, const double* f, double* dzdf, double* hout) {
+int adjoint_pass(const fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, const double* f,
+                 double* dzdf, double* hout) {
   for (const auto& g : P.groups)
-    if (launch_tuple_adjoint(st, g.nf, D.desc, D.order + g.begin, g.count, D.com, D.tau, D.xt, D.wt, f, D.theta,
-                             D.state, dzdf, hout) != hipSuccess)
+    if (launch_tuple_adjoint(st, g.nf, ctx->n_cu, D.desc, D.order + g.begin, g.count, P.N, D.com, D.tau, D.xt, D.wt,
+                             f, D.theta, D.state, dzdf, hout, P.precision == FREDEC_FP32) != hipSuccess)
       return FREDEC_EDEVICE;
   return FREDEC_OK;
 }
@@ -193,8 +197,8 @@ int run_fit(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev&
   for (int it = 0; it <= refine_steps; ++it) {
     int rc = gram_pass(ctx, st, P, D, mode);
     if (rc) return rc;
-    if (launch_tuple_solve(st, D.desc, nt, D.com, D.gram, D.scr, D.ftry, D.facc, D.step, D.theta, D.state, mode,
-                           it == refine_steps ? 1 : 0) != hipSuccess)
+    if (launch_tuple_solve(st, D.desc, D.order, nt, D.com, D.gram, D.scr, D.ftry, D.facc, D.step, D.theta, D.state,
+                           mode, it == refine_steps ? 1 : 0) != hipSuccess)
       return FREDEC_EDEVICE;
   }
   return FREDEC_OK;
@@ -252,6 +256,7 @@ int subset_build(int64_t N, const double* pool, int32_t n_pool, const uint64_t* 
   for (int k = 0; k < n_pool; ++k)
     if (!std::isfinite(pool[k])) return FREDEC_EINVAL;
   if ((rc = make_plan(N, sizes, refine_steps > 0, P.T))) return rc;
+  P.T.precision = precision;
   if (!ws || ws_bytes < P.T.total) return FREDEC_ENOMEM;
   P.ws = ws;
   P.ws_bytes = ws_bytes;
@@ -313,6 +318,7 @@ int ascent_build(int64_t N, const int64_t* toff, int64_t n_tuples, int32_t steps
   int rc;
   if ((rc = sizes_from_toff(toff, n_tuples, sizes))) return rc;
   if ((rc = make_plan(N, sizes, false, P.T))) return rc;
+  P.T.precision = precision;
   if (!ws || ws_bytes < P.T.total) return FREDEC_ENOMEM;
   P.ws = ws;
   P.ws_bytes = ws_bytes;
@@ -333,7 +339,7 @@ int ascent_launch(fredec_ctx* ctx, hipStream_t st, const AscentPlan& P, const do
   if (launch_copy_f64(st, f, D.ftry, P.T.nf) != hipSuccess) return FREDEC_EDEVICE;
   for (int s = 0; s < P.steps; ++s) {
     if ((rc = run_fit(ctx, st, P.T, D, 0))) return rc;
-    if ((rc = adjoint_pass(st, P.T, D, D.ftry, D.g, D.h))) return rc;
+    if ((rc = adjoint_pass(ctx, st, P.T, D, D.ftry, D.g, D.h))) return rc;
     if (launch_tuple_ascent_update(st, D.desc, nt, D.com, D.g, D.h, D.ftry, P.clamp, D.state) != hipSuccess)
       return FREDEC_EDEVICE;
   }
@@ -435,6 +441,7 @@ int fredec_grad(fredec_ctx* ctx, void* stream, const double* t, const double* x,
   if ((rc = sizes_from_toff(toff, n_tuples, sizes))) return rc;
   TuplePlan P;
   if ((rc = make_plan(N, sizes, false, P))) return rc;
+  P.precision = precision;
   if (!ws || ws_bytes < P.total) return FREDEC_ENOMEM;
   if (!ctx) return FREDEC_EINVAL;
   DeviceGuard g(ctx->device);
@@ -449,7 +456,7 @@ int fredec_grad(fredec_ctx* ctx, void* stream, const double* t, const double* x,
       hipSuccess)
     return FREDEC_EDEVICE;
   if (theta_out && launch_copy_f64(st, D.theta, theta_out, P.ntheta) != hipSuccess) return FREDEC_EDEVICE;
-  if ((dz_df || h_out) && (rc = adjoint_pass(st, P, D, D.ftry, dz_df, h_out))) return rc;
+  if ((dz_df || h_out) && (rc = adjoint_pass(ctx, st, P, D, D.ftry, dz_df, h_out))) return rc;
   return FREDEC_OK;
 }
 

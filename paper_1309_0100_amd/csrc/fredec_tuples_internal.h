@@ -12,7 +12,7 @@ constexpr double ACCEPT_RTOL = 1e-12;  // a trial point is accepted if l <= l_ac
 constexpr int MAX_HALVINGS = 5;        // consecutive step halvings before stopping
 constexpr double GN_TOL = 1e-10;       // stop once max |df_k| T_eff falls below this
 constexpr double GN_CLAMP = 0.25;      // largest step max |df_k| T_eff
-constexpr int QUAD_MAX_N = 6;          // largest tuple size of the four-lanes-per-tuple VALU kernels
+constexpr int LANES_MAX_N = 6;         // largest tuple size of the lane-group VALU kernels
 
 struct TupleDesc {
   int64_t foff;   // first frequency of the tuple in the ragged arrays
@@ -39,24 +39,27 @@ struct TupleState {
   int32_t flags;
 };
 
-// Whether tuples of n frequencies in this mode go to the four-lanes-per-tuple
-// VALU kernels (launches then take a group of tuples of exactly n).
-bool tuple_quad_supported(int n, int mode);
-// nf: the exact size of every tuple of the group, or 0 for mixed sizes (MFMA
-// kernel of NB 16-column blocks).
-hipError_t launch_tuple_gram(hipStream_t st, int NB, int nf, const TupleDesc* desc, const int32_t* order,
-                             int n_order, const TupleCommon* com, const double* tau, const double* xt,
-                             const double* wt, const double* ftry, const TupleState* state, double* gram, int mode);
-hipError_t launch_tuple_solve(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
-                              double* gram, double* scratch, double* ftry, double* facc, double* step, double* theta,
-                              TupleState* state, int mode, int last);
+// Whether tuples of n frequencies in this mode go to the lane-group VALU
+// kernels (launches then take a group of tuples of exactly n).
+bool tuple_lanes_supported(int n, int mode);
+// nf: the exact size of every tuple of the group; NB: 16-column blocks of the
+// MFMA kernel used otherwise; n_cu sizes the lane groups; N samples; f32: the
+// reduced-precision trig of the lane-group kernels (the MFMA kernel is float64).
+hipError_t launch_tuple_gram(hipStream_t st, int NB, int nf, int n_cu, const TupleDesc* desc, const int32_t* order,
+                             int n_order, int64_t N, const TupleCommon* com, const double* tau, const double* xt,
+                             const double* wt, const double* ftry, const TupleState* state, double* gram, int mode,
+                             bool f32);
+// The solve for tuples order[0 .. n_tuples).
+hipError_t launch_tuple_solve(hipStream_t st, const TupleDesc* desc, const int32_t* order, int n_tuples,
+                              const TupleCommon* com, double* gram, double* scratch, double* ftry, double* facc,
+                              double* step, double* theta, TupleState* state, int mode, int last);
 hipError_t launch_tuple_finish(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
                                const TupleState* state, const double* facc, double* l_out, double* z_out,
                                uint8_t* flags_out, double* f_out, const int8_t* members, int f_stride);
-hipError_t launch_tuple_adjoint(hipStream_t st, int nf, const TupleDesc* desc, const int32_t* order, int n_order,
-                                const TupleCommon* com, const double* tau, const double* xt, const double* wt,
-                                const double* f, const double* theta, const TupleState* state, double* dzdf,
-                                double* hout);
+hipError_t launch_tuple_adjoint(hipStream_t st, int nf, int n_cu, const TupleDesc* desc, const int32_t* order,
+                                int n_order, int64_t N, const TupleCommon* com, const double* tau, const double* xt,
+                                const double* wt, const double* f, const double* theta, const TupleState* state,
+                                double* dzdf, double* hout, bool f32);
 hipError_t launch_tuple_ascent_update(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
                                       const double* g, const double* h, double* f, double clamp, TupleState* state);
 hipError_t launch_tuple_init(hipStream_t st, int n_tuples, TupleState* state);

@@ -221,20 +221,27 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict_
       q[1] = rc;
       q[2] = rs;
       for (int k = 0; k < KP; ++k) q[3 + k] = wi * ph[k];
+      double s1, c1;
+      sincos_rev(si.df * ta, s1, c1);
+      q[KP + 3] = c1;
+      q[KP + 4] = s1;
     }
     if (flags & PREP_F32) {
       float* g = g32 + si.g32_off + i * G32W;
       for (int k = 0; k < K; ++k) g[k] = static_cast<float>(wi * ph[k]);
       for (int k = K; k < G32W; ++k) g[k] = 0.0f;
       double* a = aux + si.aux_off + i * AUX_STRIDE;
-      double rs, rc;
+      double rs, rc, s1, c1;
       sincos_rev(si.rot_tile * ta, rs, rc);
+      sincos_rev(si.df * ta, s1, c1);
       a[0] = ta;
       a[1] = rc;
       a[2] = rs;
       a[3] = wi;
       a[4] = wi * r;
       a[5] = 0.0;
+      a[6] = c1;
+      a[7] = s1;
     }
   }
 }

@@ -2,13 +2,19 @@
 //
 // Layout: one lane owns R grid frequencies f_{j0+t+256r}, r = 0..R-1, and
 // walks over all samples of its series.  The per-sample record
-// [tau, cos(2 pi s tau), sin(2 pi s tau), w~ q_0 .. w~ q_{K-1}, w~ r_b]
+// [tau, cos(2 pi s tau), sin(2 pi s tau), w~ q_0 .. w~ q_{K-1}, w~ r_b,
+//  cos(2 pi df tau), sin(2 pi df tau)]
 // (s = 256 df; q the orthonormal base columns, r_b the base residual, both
 // from the preparation kernel) is the same for every lane, so it is read with
-// scalar loads and used as a scalar operand: no LDS and no cross-lane
-// reduction is needed.  cos/sin of the first frequency come from the float64
-// phase reduction; the other R-1 follow by rotation with the record's
-// (cos, sin)(2 pi s tau).  Per frequency the lane accumulates
+// scalar loads and used as a scalar operand.  The phasor of the lane's first
+// frequency at a sample is a product of three factors,
+//   e^{2 pi i (j0 + 1 + 16a + b) df tau} = E0 * A_a * B_b   (t = 16a + b),
+// with E0 (the block's first frequency) from the float64 phase reduction and
+// A_a = e^{2 pi i 16 a df tau}, B_b = e^{2 pi i b df tau} from powers of
+// e^{2 pi i df tau}; the block builds E0 A_a and B_b for a tile of 64 samples
+// in LDS, so each lane spends one complex multiplication per sample instead
+// of a sin/cos.  The other R-1 frequencies follow by rotation with the
+// record's (cos, sin)(2 pi s tau).  Per frequency the lane accumulates
 //   U_c[k] = <q_k cos>, U_s[k] = <q_k sin>, h = <r_b cos>, <r_b sin>,
 //   <cos^2>, <cos sin>, <sin^2>
 // and the epilogue extends the base Cholesky factor by the 2x2 Schur block of
@@ -21,8 +27,10 @@ namespace fredec {
 
 namespace {
 
+// Frequencies per lane: as many as keep the R (2 KP + 3) float64 sums within
+// about 190 VGPRs (two waves per SIMD).
 constexpr int R_of(int KP) {
-  int r = 112 / (2 * KP + 3);
+  int r = 92 / (2 * KP + 3);
   return r < 1 ? 1 : (r > 8 ? 8 : r);
 }
 
@@ -77,37 +85,104 @@ __global__ __launch_bounds__(BLOCK) void scan_f64_kernel(const ScanWork* __restr
     }
     return;
   }
-  const double f0 = static_cast<double>(jb + 1) * df;
   double acc[R][NS];
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[r][k] = 0.0;
 
-  const double* __restrict__ q = rec + si.rec_off;
-  for (int64_t i = 0; i < N; ++i, q += P) {
-    double s, c;
-    sincos_rev(f0 * q[0], s, c);
-    const double rc = q[1], rs = q[2];
+  constexpr int TS = 64;  // samples per table tile
+  __shared__ double2 eash[TS][16];  // E0 A_a per sample, a = t / 16
+  __shared__ double2 bsh[TS][16];   // B_b per sample, b = t % 16
+  const int ta_ = threadIdx.x >> 4, tb_ = threadIdx.x & 15;
+  const double fb = static_cast<double>(wk.j0 + 1) * df;  // the block's first frequency
+  const double* __restrict__ q0 = rec + si.rec_off;
+  for (int64_t i0 = 0; i0 < N; i0 += TS) {
+    const int nts = N - i0 < TS ? static_cast<int>(N - i0) : TS;
+    __syncthreads();
+    {
+      // sample threadIdx / 4, table entries 4 q4 .. 4 q4 + 3 of both tables
+      const int sl = threadIdx.x >> 2, q4 = threadIdx.x & 3;
+      if (sl < nts) {
+        const double* qs = q0 + (i0 + sl) * P;
+        const double wc = qs[KP + 3], ws = qs[KP + 4];
+        // p = w^(4 q4) and a = w^(64 q4) by repeated squaring (few values
+        // live at a time: the accumulators of the lane stay in registers)
+        double pc = 1.0, ps = 0.0, ac = 1.0, as = 0.0;
+        double xc = wc, xs = ws;  // w^(2^k)
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (r) {
-        const double cn = __builtin_fma(c, rc, -s * rs);
-        s = __builtin_fma(s, rc, c * rs);
-        c = cn;
+        for (int k = 1; k <= 7; ++k) {
+          const double nc = xc * xc - xs * xs;
+          xs = 2.0 * xc * xs;
+          xc = nc;  // w^(2^k)
+          if ((k == 2 && (q4 & 1)) || (k == 3 && (q4 & 2))) {
+            const double tc = pc * xc - ps * xs;
+            ps = pc * xs + ps * xc;
+            pc = tc;
+          }
+          if ((k == 6 && (q4 & 1)) || (k == 7 && (q4 & 2))) {
+            const double tc = ac * xc - as * xs;
+            as = ac * xs + as * xc;
+            ac = tc;
+          }
+        }
+        // B_b for b = 4 q4 .. 4 q4 + 3
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          bsh[sl][4 * q4 + k] = double2{pc, ps};
+          const double nc = __builtin_fma(pc, wc, -ps * ws);
+          ps = __builtin_fma(ps, wc, pc * ws);
+          pc = nc;
+        }
+        // E0 A_a for a = 4 q4 .. 4 q4 + 3, A_a = (w^16)^a (w^16 by four squarings)
+        double hc = wc, hs = ws;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double nc = hc * hc - hs * hs;
+          hs = 2.0 * hc * hs;
+          hc = nc;
+        }
+        double es, ec;
+        sincos_rev(fb * qs[0], es, ec);
+        pc = __builtin_fma(ec, ac, -es * as);
+        ps = __builtin_fma(es, ac, ec * as);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          eash[sl][4 * q4 + k] = double2{pc, ps};
+          const double nc = __builtin_fma(pc, hc, -ps * hs);
+          ps = __builtin_fma(ps, hc, pc * hs);
+          pc = nc;
+        }
       }
-      const double g0 = q[3];
-      const double tc = g0 * c, tsn = g0 * s;
-      acc[r][0] += tc;
-      acc[r][1] += tsn;
-      acc[r][2] = __builtin_fma(tc, c, acc[r][2]);
-      acc[r][3] = __builtin_fma(tc, s, acc[r][3]);
-      acc[r][4] = __builtin_fma(tsn, s, acc[r][4]);
+    }
+    __syncthreads();
+    const double* __restrict__ q = q0 + i0 * P;
+    for (int sl = 0; sl < nts; ++sl, q += P) {
+      const double2 ea = eash[sl][ta_];
+      const double2 bb = bsh[sl][tb_];
+      double c = __builtin_fma(ea.x, bb.x, -ea.y * bb.y);
+      double s = __builtin_fma(ea.y, bb.x, ea.x * bb.y);
+      const double rc = q[1], rs = q[2];
 #pragma unroll
-      for (int k = 1; k < KP; ++k) {
-        const double g = q[3 + k];
-        acc[r][3 + 2 * k] = __builtin_fma(g, c, acc[r][3 + 2 * k]);
-        acc[r][4 + 2 * k] = __builtin_fma(g, s, acc[r][4 + 2 * k]);
+      for (int r = 0; r < R; ++r) {
+        if (r) {
+          const double cn = __builtin_fma(c, rc, -s * rs);
+          s = __builtin_fma(s, rc, c * rs);
+          c = cn;
+        }
+        const double g0 = q[3];
+        const double tc = g0 * c, tsn = g0 * s;
+        acc[r][0] += tc;
+        acc[r][1] += tsn;
+        acc[r][2] = __builtin_fma(tc, c, acc[r][2]);
+        acc[r][3] = __builtin_fma(tc, s, acc[r][3]);
+        acc[r][4] = __builtin_fma(tsn, s, acc[r][4]);
+#pragma unroll
+        for (int k = 1; k < KP; ++k) {
+          const double g = q[3 + k];
+          acc[r][3 + 2 * k] = __builtin_fma(g, c, acc[r][3 + 2 * k]);
+          acc[r][4 + 2 * k] = __builtin_fma(g, s, acc[r][4 + 2 * k]);
+        }
       }
     }
   }

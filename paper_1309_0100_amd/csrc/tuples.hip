@@ -14,18 +14,21 @@
 // tuple_solve_kernel: one thread per tuple, float64: Cholesky of the model
 // block, l, theta*, z, and the Gauss-Newton step with the step control shared
 // with the oracle (clamp, accept/halve, tolerance).
-// tuple_gram_quad_kernel<n>: the forward Gram of tuples of exactly n <= 6
-// frequencies on the VALU, four lanes per tuple (each a quarter of the
+// tuple_gram_lanes_kernel<n, L>: the forward Gram of tuples of exactly
+// n <= 6 frequencies on the VALU, L lanes per tuple (each 1/L of the
 // samples): every sin/cos is evaluated once, only the lower triangle
-// (C(C+1)/2 multiply-adds per sample, C = 2n + 2) is accumulated, and the
-// four partial Gram matrices are added with in-quad shuffles.  For these
+// (C(C+1)/2 multiply-adds per sample, C = 2n + 2) is accumulated, and the L
+// partial Gram matrices are added with cross-lane permutations.  For these
 // sizes this does less work than the MFMA kernel, whose 16-column blocks are
 // mostly padding and whose lanes each evaluate a sin/cos for a single column
-// (float64 MFMA and float64 VALU have the same peak rate on this chip).
+// (float64 MFMA and float64 VALU have the same peak rate on this chip).  L is
+// chosen per launch so that a group of tuples fills the GPU.
 // tuple_adjoint_kernel (any n, one wavefront per tuple, samples over lanes)
-// and tuple_adjoint_quad_kernel<n> (n <= 6, four lanes per tuple): recompute
+// and tuple_adjoint_lanes_kernel<n, L> (n <= 6, L lanes per tuple): recompute
 // the trig terms, the residual r = x~ - Phi theta* and <r J_k>, <J_k^2>
-// (J_k = d mu / d f_k), reduced with shuffles.
+// (J_k = d mu / d f_k), reduced across lanes.
+#include <algorithm>
+
 #include "fredec_internal.h"
 #include "fredec_tuples_internal.h"
 
@@ -148,37 +151,63 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
 
 constexpr int pidx(int r, int c) { return r * (r + 1) / 2 + c; }
 
-// v + (v of the lane whose quad position differs in bit 0, then in bit 1):
-// the sum over the four lanes of a quad, in a fixed order, by DPP quad
-// permutations (quad_perm [1,0,3,2] and [2,3,0,1]).
-__device__ __forceinline__ double quad_sum(double v) {
-  int lo = __double2loint(v), hi = __double2hiint(v);
-  v += __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false),
-                        __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false));
-  lo = __double2loint(v);
-  hi = __double2hiint(v);
-  v += __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false),
-                        __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false));
+// Sum of v over aligned groups of L lanes (L = 4, 8, 16, 32 or 64), left in
+// every lane of the group; a fixed sequence of exchanges, so the result is
+// deterministic and identical in all lanes: DPP quad permutations (lane ^ 1,
+// lane ^ 2), half-row and row mirrors (the other quad of an 8-lane half row,
+// the other half of a 16-lane row), then swaps of 16 and 32 lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_plus(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return v + __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false),
+                              __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false));
+}
+
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+  static_assert(L == 4 || L == 8 || L == 16 || L == 32 || L == 64, "lane group of 4..64");
+  v = dpp_plus<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = dpp_plus<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (L >= 8) v = dpp_plus<0x141>(v);  // row_half_mirror
+  if (L >= 16) v = dpp_plus<0x140>(v);  // row_mirror
+  if (L >= 32) v += __shfl_xor(v, 16);
+  if (L >= 64) v += __shfl_xor(v, 32);
   return v;
 }
 
-// Four lanes (a quad) per tuple; quads of one launch all have NF frequencies.
-template <int NF>
-__global__ __launch_bounds__(BLOCK) void tuple_gram_quad_kernel(const TupleDesc* __restrict__ desc,
-                                                                const int32_t* __restrict__ order, int n_order,
-                                                                const TupleCommon* __restrict__ com,
-                                                                const double* __restrict__ tau,
-                                                                const double* __restrict__ xt,
-                                                                const double* __restrict__ wt,
-                                                                const double* __restrict__ ftry,
-                                                                const TupleState* __restrict__ state,
-                                                                double* __restrict__ gram) {
+// sin/cos(2 pi p) for the lane-group kernels: float64 (sincos_rev) or, in the
+// reduced-precision form, the float64 phase reduction p - rint(p) followed
+// by the hardware float32 sin/cos of the reduced phase (v_sin_f32 and
+// v_cos_f32 take their argument in revolutions), widened to float64.
+template <bool F32>
+__device__ __forceinline__ void tuple_sincos(double p, double& s, double& c) {
+  if constexpr (F32) {
+    const float r = static_cast<float>(p - __builtin_rint(p));
+    s = static_cast<double>(__builtin_amdgcn_sinf(r));
+    c = static_cast<double>(__builtin_amdgcn_cosf(r));
+  } else {
+    sincos_rev(p, s, c);
+  }
+}
+
+// L lanes per tuple; the tuples of one launch all have NF frequencies.
+template <int NF, int L, bool F32>
+__global__ __launch_bounds__(BLOCK) void tuple_gram_lanes_kernel(const TupleDesc* __restrict__ desc,
+                                                                 const int32_t* __restrict__ order, int n_order,
+                                                                 const TupleCommon* __restrict__ com,
+                                                                 const double* __restrict__ tau,
+                                                                 const double* __restrict__ xt,
+                                                                 const double* __restrict__ wt,
+                                                                 const double* __restrict__ ftry,
+                                                                 const TupleState* __restrict__ state,
+                                                                 double* __restrict__ gram) {
   constexpr int C = 2 * NF + 2;
   constexpr int NACC = C * (C + 1) / 2;
-  const int gq = static_cast<int>((static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x) >> 2);
-  const int r = threadIdx.x & 3;
-  const bool in_range = gq < n_order;
-  const int ti = in_range ? order[gq] : 0;
+  const int64_t gt = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+  const int grp = static_cast<int>(gt / L);
+  const int r = static_cast<int>(gt % L);
+  const bool in_range = grp < n_order;
+  const int ti = in_range ? order[grp] : 0;
   const bool live = in_range && !state[ti].done;
   double f[NF];
 #pragma unroll
@@ -189,13 +218,13 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_quad_kernel(const TupleDesc*
   if (live) {
     const int64_t N = com->N;
 #pragma unroll 1
-    for (int64_t i = r; i < N; i += 4) {
+    for (int64_t i = r; i < N; i += L) {
       const double ta = tau[i];
       const double wi = wt[i];
       double phi[C];
       phi[0] = 1.0;
 #pragma unroll
-      for (int k = 0; k < NF; ++k) sincos_rev(f[k] * ta, phi[2 + 2 * k], phi[1 + 2 * k]);
+      for (int k = 0; k < NF; ++k) tuple_sincos<F32>(f[k] * ta, phi[2 + 2 * k], phi[1 + 2 * k]);
       phi[C - 1] = xt[i];
 #pragma unroll
       for (int a = 0; a < C; ++a) {
@@ -206,10 +235,10 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_quad_kernel(const TupleDesc*
       }
     }
   }
-  // add the four partial sums of the quad (fixed order: deterministic)
+  // add the L partial sums of the group (fixed order: deterministic)
 #pragma unroll
   for (int q = 0; q < NACC; ++q) {
-    acc[q] = quad_sum(acc[q]);
+    acc[q] = group_sum<L>(acc[q]);
     asm volatile("" : "+v"(acc[q]));  // complete each sum here: keeps the register count of the loop
   }
   if (live && r == 0) {
@@ -239,14 +268,16 @@ __device__ bool chol_inplace(double* G, int K) {
   return true;
 }
 
-__global__ __launch_bounds__(BLOCK) void tuple_solve_kernel(const TupleDesc* __restrict__ desc, int n_tuples,
+__global__ __launch_bounds__(BLOCK) void tuple_solve_kernel(const TupleDesc* __restrict__ desc,
+                                                            const int32_t* __restrict__ order, int n_tuples,
                                                             const TupleCommon* __restrict__ com,
                                                             double* __restrict__ gram, double* __restrict__ scratch,
                                                             double* __restrict__ ftry, double* __restrict__ facc,
                                                             double* __restrict__ step, double* __restrict__ theta,
                                                             TupleState* __restrict__ state, int mode, int last) {
-  const int ti = blockIdx.x * BLOCK + threadIdx.x;
-  if (ti >= n_tuples) return;
+  const int oi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (oi >= n_tuples) return;
+  const int ti = order[oi];
   const TupleDesc& d = desc[ti];
   TupleState& S = state[ti];
   if (S.done) return;
@@ -487,23 +518,24 @@ __global__ __launch_bounds__(BLOCK) void tuple_adjoint_kernel(const TupleDesc* _
 }
 
 
-// Adjoint for tuples of exactly NF <= 6 frequencies, four lanes per tuple.
-template <int NF>
-__global__ __launch_bounds__(BLOCK) void tuple_adjoint_quad_kernel(const TupleDesc* __restrict__ desc,
-                                                                   const int32_t* __restrict__ order, int n_order,
-                                                                   const TupleCommon* __restrict__ com,
-                                                                   const double* __restrict__ tau,
-                                                                   const double* __restrict__ xt,
-                                                                   const double* __restrict__ wt,
-                                                                   const double* __restrict__ f,
-                                                                   const double* __restrict__ theta,
-                                                                   const TupleState* __restrict__ state,
-                                                                   double* __restrict__ dzdf,
-                                                                   double* __restrict__ hout) {
-  const int gq = static_cast<int>((static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x) >> 2);
-  const int r = threadIdx.x & 3;
-  const bool in_range = gq < n_order;
-  const int ti = in_range ? order[gq] : 0;
+// Adjoint for tuples of exactly NF <= 6 frequencies, L lanes per tuple.
+template <int NF, int L, bool F32>
+__global__ __launch_bounds__(BLOCK) void tuple_adjoint_lanes_kernel(const TupleDesc* __restrict__ desc,
+                                                                    const int32_t* __restrict__ order, int n_order,
+                                                                    const TupleCommon* __restrict__ com,
+                                                                    const double* __restrict__ tau,
+                                                                    const double* __restrict__ xt,
+                                                                    const double* __restrict__ wt,
+                                                                    const double* __restrict__ f,
+                                                                    const double* __restrict__ theta,
+                                                                    const TupleState* __restrict__ state,
+                                                                    double* __restrict__ dzdf,
+                                                                    double* __restrict__ hout) {
+  const int64_t gt = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+  const int grp = static_cast<int>(gt / L);
+  const int r = static_cast<int>(gt % L);
+  const bool in_range = grp < n_order;
+  const int ti = in_range ? order[grp] : 0;
   const TupleState& S = state[ti];
   const bool live = in_range && S.has_acc && S.l_acc > 0.0;
   const int64_t foff = desc[ti].foff;
@@ -517,13 +549,14 @@ __global__ __launch_bounds__(BLOCK) void tuple_adjoint_quad_kernel(const TupleDe
   for (int k = 0; k < NF; ++k) g[k] = h2[k] = 0.0;
   const int64_t N = com->N;
   if (live) {
-    for (int64_t i = r; i < N; i += 4) {
+#pragma unroll 1
+    for (int64_t i = r; i < N; i += L) {
       const double ta = tau[i];
       double sv[NF], cv[NF];
       double res = xt[i] - th[0];
 #pragma unroll
       for (int k = 0; k < NF; ++k) {
-        sincos_rev(fk[k] * ta, sv[k], cv[k]);
+        tuple_sincos<F32>(fk[k] * ta, sv[k], cv[k]);
         res -= th[1 + 2 * k] * cv[k] + th[2 + 2 * k] * sv[k];
       }
       const double wi = wt[i];
@@ -539,14 +572,13 @@ __global__ __launch_bounds__(BLOCK) void tuple_adjoint_quad_kernel(const TupleDe
   }
 #pragma unroll
   for (int k = 0; k < NF; ++k) {
-    g[k] = quad_sum(g[k]);
-    h2[k] = quad_sum(h2[k]);
+    g[k] = group_sum<L>(g[k]);
+    h2[k] = group_sum<L>(h2[k]);
   }
-  if (!in_range) return;
+  if (!in_range || r != 0) return;
   const double coef = static_cast<double>(N - 3 * NF - 1) / S.l_acc;
 #pragma unroll
   for (int k = 0; k < NF; ++k) {
-    if ((k & 3) != r) continue;
     if (dzdf) dzdf[foff + k] = live ? coef * g[k] : __builtin_nan("");
     if (hout) hout[foff + k] = live ? coef * h2[k] : __builtin_nan("");
   }
@@ -616,31 +648,94 @@ hipError_t gram_nb(hipStream_t st, const TupleDesc* desc, const int32_t* order, 
   return hipGetLastError();
 }
 
-template <int NF>
-hipError_t gram_quad(hipStream_t st, const TupleDesc* desc, const int32_t* order, int n_order,
-                     const TupleCommon* com, const double* tau, const double* xt, const double* wt,
-                     const double* ftry, const TupleState* state, double* gram) {
-  const int blocks = (n_order + BLOCK / 4 - 1) / (BLOCK / 4);
-  tuple_gram_quad_kernel<NF><<<blocks, BLOCK, 0, st>>>(desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+// Lanes per tuple for a group of n_order tuples of N samples: enough groups
+// of lanes to give every CU a few waves, at least 16 samples per lane.
+int lanes_for(int n_order, int64_t N, int n_cu) {
+  const int64_t want = 4LL * std::max(n_cu, 1) * 64;  // threads for ~4 waves per CU
+  int L = 4;
+  while (L < 64 && static_cast<int64_t>(n_order) * L < want && N / (2 * L) >= 16) L *= 2;
+  return L;
+}
+
+template <int NF, int L, bool F32>
+hipError_t gram_lanes(hipStream_t st, const TupleDesc* desc, const int32_t* order, int n_order,
+                      const TupleCommon* com, const double* tau, const double* xt, const double* wt,
+                      const double* ftry, const TupleState* state, double* gram) {
+  const int64_t threads = static_cast<int64_t>(n_order) * L;
+  const int blocks = static_cast<int>((threads + BLOCK - 1) / BLOCK);
+  tuple_gram_lanes_kernel<NF, L, F32><<<blocks, BLOCK, 0, st>>>(desc, order, n_order, com, tau, xt, wt, ftry, state,
+                                                             gram);
   return hipGetLastError();
+}
+
+template <int NF, bool F32>
+hipError_t gram_nf(hipStream_t st, int L, const TupleDesc* desc, const int32_t* order, int n_order,
+                   const TupleCommon* com, const double* tau, const double* xt, const double* wt,
+                   const double* ftry, const TupleState* state, double* gram) {
+  switch (L) {
+    case 4: return gram_lanes<NF, 4, F32>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+    case 8: return gram_lanes<NF, 8, F32>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+    case 16: return gram_lanes<NF, 16, F32>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+    case 32: return gram_lanes<NF, 32, F32>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+    case 64: return gram_lanes<NF, 64, F32>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NF, int L, bool F32>
+hipError_t adjoint_lanes(hipStream_t st, const TupleDesc* desc, const int32_t* order, int n_order,
+                         const TupleCommon* com, const double* tau, const double* xt, const double* wt,
+                         const double* f, const double* theta, const TupleState* state, double* dzdf, double* hout) {
+  const int64_t threads = static_cast<int64_t>(n_order) * L;
+  const int blocks = static_cast<int>((threads + BLOCK - 1) / BLOCK);
+  tuple_adjoint_lanes_kernel<NF, L, F32><<<blocks, BLOCK, 0, st>>>(desc, order, n_order, com, tau, xt, wt, f, theta, state,
+                                                                dzdf, hout);
+  return hipGetLastError();
+}
+
+template <int NF, bool F32>
+hipError_t adjoint_nf(hipStream_t st, int L, const TupleDesc* desc, const int32_t* order, int n_order,
+                      const TupleCommon* com, const double* tau, const double* xt, const double* wt, const double* f,
+                      const double* theta, const TupleState* state, double* dzdf, double* hout) {
+  switch (L) {
+    case 4: return adjoint_lanes<NF, 4, F32>(st, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+    case 8: return adjoint_lanes<NF, 8, F32>(st, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+    case 16: return adjoint_lanes<NF, 16, F32>(st, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+    case 32: return adjoint_lanes<NF, 32, F32>(st, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+    case 64: return adjoint_lanes<NF, 64, F32>(st, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
-bool tuple_quad_supported(int n, int mode) { return mode == TUPLE_FWD && n >= 1 && n <= QUAD_MAX_N; }
+bool tuple_lanes_supported(int n, int mode) { return mode == TUPLE_FWD && n >= 1 && n <= LANES_MAX_N; }
 
-hipError_t launch_tuple_gram(hipStream_t st, int NB, int nf, const TupleDesc* desc, const int32_t* order,
-                             int n_order, const TupleCommon* com, const double* tau, const double* xt,
-                             const double* wt, const double* ftry, const TupleState* state, double* gram, int mode) {
+hipError_t launch_tuple_gram(hipStream_t st, int NB, int nf, int n_cu, const TupleDesc* desc, const int32_t* order,
+                             int n_order, int64_t N, const TupleCommon* com, const double* tau, const double* xt,
+                             const double* wt, const double* ftry, const TupleState* state, double* gram,
+                             int mode, bool f32) {
   if (n_order <= 0) return hipSuccess;
-  if (tuple_quad_supported(nf, mode)) {
+  if (tuple_lanes_supported(nf, mode)) {
+    const int L = lanes_for(n_order, N, n_cu);
+    if (f32) {
+      switch (nf) {
+        case 1: return gram_nf<1, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+        case 2: return gram_nf<2, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+        case 3: return gram_nf<3, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+        case 4: return gram_nf<4, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+        case 5: return gram_nf<5, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+        case 6: return gram_nf<6, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+        default: return hipErrorInvalidValue;
+      }
+    }
     switch (nf) {
-      case 1: return gram_quad<1>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-      case 2: return gram_quad<2>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-      case 3: return gram_quad<3>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-      case 4: return gram_quad<4>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-      case 5: return gram_quad<5>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-      case 6: return gram_quad<6>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+      case 1: return gram_nf<1, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+      case 2: return gram_nf<2, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+      case 3: return gram_nf<3, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+      case 4: return gram_nf<4, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+      case 5: return gram_nf<5, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+      case 6: return gram_nf<6, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
       default: return hipErrorInvalidValue;
     }
   }
@@ -656,12 +751,14 @@ hipError_t launch_tuple_gram(hipStream_t st, int NB, int nf, const TupleDesc* de
   }
 }
 
-hipError_t launch_tuple_solve(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
-                              double* gram, double* scratch, double* ftry, double* facc, double* step, double* theta,
-                              TupleState* state, int mode, int last) {
+hipError_t launch_tuple_solve(hipStream_t st, const TupleDesc* desc, const int32_t* order, int n_tuples,
+                              const TupleCommon* com, double* gram, double* scratch, double* ftry, double* facc,
+                              double* step, double* theta, TupleState* state, int mode, int last) {
   if (n_tuples <= 0) return hipSuccess;
-  tuple_solve_kernel<<<(n_tuples + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(desc, n_tuples, com, gram, scratch, ftry, facc,
-                                                                       step, theta, state, mode, last);
+  // one thread per tuple, serial and latency-bound: small blocks spread the
+  // tuples over every CU
+  tuple_solve_kernel<<<(n_tuples + 63) / 64, 64, 0, st>>>(desc, order, n_tuples, com, gram, scratch, ftry, facc, step,
+                                                          theta, state, mode, last);
   return hipGetLastError();
 }
 
@@ -674,29 +771,33 @@ hipError_t launch_tuple_finish(hipStream_t st, const TupleDesc* desc, int n_tupl
   return hipGetLastError();
 }
 
-hipError_t launch_tuple_adjoint(hipStream_t st, int nf, const TupleDesc* desc, const int32_t* order, int n_order,
-                                const TupleCommon* com, const double* tau, const double* xt, const double* wt,
-                                const double* f, const double* theta, const TupleState* state, double* dzdf,
-                                double* hout) {
+hipError_t launch_tuple_adjoint(hipStream_t st, int nf, int n_cu, const TupleDesc* desc, const int32_t* order,
+                                int n_order, int64_t N, const TupleCommon* com, const double* tau, const double* xt,
+                                const double* wt, const double* f, const double* theta, const TupleState* state,
+                                double* dzdf, double* hout, bool f32) {
   if (n_order <= 0) return hipSuccess;
-  if (tuple_quad_supported(nf, TUPLE_FWD)) {
-    const int blocks = (n_order + BLOCK / 4 - 1) / (BLOCK / 4);
-#define FREDEC_ADJ_QUAD(K)                                                                                          \
-  case K:                                                                                                           \
-    tuple_adjoint_quad_kernel<K><<<blocks, BLOCK, 0, st>>>(desc, order, n_order, com, tau, xt, wt, f, theta, state, \
-                                                           dzdf, hout);                                            \
-    break;
+  if (tuple_lanes_supported(nf, TUPLE_FWD)) {
+    const int L = lanes_for(n_order, N, n_cu);
+    if (f32) {
+      switch (nf) {
+        case 1: return adjoint_nf<1, true>(st, L, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+        case 2: return adjoint_nf<2, true>(st, L, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+        case 3: return adjoint_nf<3, true>(st, L, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+        case 4: return adjoint_nf<4, true>(st, L, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+        case 5: return adjoint_nf<5, true>(st, L, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+        case 6: return adjoint_nf<6, true>(st, L, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+        default: return hipErrorInvalidValue;
+      }
+    }
     switch (nf) {
-      FREDEC_ADJ_QUAD(1)
-      FREDEC_ADJ_QUAD(2)
-      FREDEC_ADJ_QUAD(3)
-      FREDEC_ADJ_QUAD(4)
-      FREDEC_ADJ_QUAD(5)
-      FREDEC_ADJ_QUAD(6)
+      case 1: return adjoint_nf<1, false>(st, L, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+      case 2: return adjoint_nf<2, false>(st, L, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+      case 3: return adjoint_nf<3, false>(st, L, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+      case 4: return adjoint_nf<4, false>(st, L, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+      case 5: return adjoint_nf<5, false>(st, L, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
+      case 6: return adjoint_nf<6, false>(st, L, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);
       default: return hipErrorInvalidValue;
     }
-#undef FREDEC_ADJ_QUAD
-    return hipGetLastError();
   }
   const int blocks = (n_order + 3) / 4;
   tuple_adjoint_kernel<<<blocks, BLOCK, 0, st>>>(desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);

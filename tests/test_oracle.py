@@ -363,3 +363,25 @@ def test_phase1_rejects_inconsistent_thresholds():
     s = _series(92, 50)
     with pytest.raises(ValueError):
         O.phase1(s.t, s.x, s.w, 1e-3, 100, fap0=0.2, fap1=0.1)
+
+
+def test_scan_trial_pivot_matches_schur_complement():
+    """The per-frequency conditioning reported by the scan (smaller relative
+    Cholesky pivot of the two trial columns) equals the Schur complements
+    1 / (Q_jj (Q^-1)_jj) of those columns computed by matrix inversion, and
+    collapses as f T_eff -> 0 where cos(2 pi f t) approaches the constant."""
+    s = synth.random_series(811, 120, span=300.0, n_sin=2)
+    base = np.array([0.07, 0.31])
+    idx = np.array([0, 3, 40, 200])
+    df = 2e-4
+    r = O.scan(s.t, s.x, s.w, base, df, 1000, idx=idx)
+    nrm = O.normalize(s.t, s.x, s.w)
+    for k, j in enumerate(idx):
+        Phi = O.design(nrm.tau, np.concatenate([base, [(j + 1) * df]]))
+        Q = (Phi * nrm.wt[:, None]).T @ Phi
+        n = Q.shape[0]
+        last = 1.0 / (np.linalg.inv(Q)[n - 1, n - 1] * Q[n - 1, n - 1])
+        Q2 = Q[:n - 1, :n - 1]
+        second = 1.0 / (np.linalg.inv(Q2)[n - 2, n - 2] * Q2[n - 2, n - 2])
+        assert abs(r.rho[k] - min(last, second)) <= 1e-6 * min(last, second) + 1e-14
+    assert r.rho[0] < 1e-3 * r.rho[-1]
