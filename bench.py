@@ -42,6 +42,32 @@ METRIC = "periodogram points/s (N×F) + tuples/s at stated rel-err vs FP64 oracl
 PEAK_FP64_VALU = 78.6e12      # flop/s, FMA = 2 flops
 PEAK_FP32_MFMA = 157.3e12     # flop/s, dense
 
+# HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (KiB per dispatch), scaled by
+# what the same counters read for a plain device copy of known size (FETCH x2.0, WRITE x1.0).  A
+# figure is only used while the kernel source still has the hash it was measured with.
+COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
+TRAFFIC = {
+    "scan_f64_kernel": {"src": "scan_f64.hip", "sha1": "08ced70dc01be07b03467ed9f4e19e2a6213e9bb",
+                        "fetch_kib": 1160.2, "write_kib": 8789.1},
+    "scan_mfma_kernel": {"src": "scan_mfma.hip", "sha1": "8407bfa682b2d4ad5de7426d0da0c851edfbf34b",
+                         "fetch_kib": 2156.3, "write_kib": 8802.1},
+    "tuple_gram_lanes_kernel": {"src": "tuples.hip", "sha1": "8b07302fac69d385b9e9710eb7051ee087ee6b47",
+                                "fetch_kib": None, "write_kib": None},
+}
+
+
+def traffic_bytes(kernel):
+    """Measured HBM bytes per launch of `kernel`, or None when not measured for the current source."""
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if not t or t["fetch_kib"] is None:
+        return None
+    path = os.path.join(ROOT, "paper_1309_0100_amd", "csrc", t["src"])
+    with open(path, "rb") as fh:
+        if hashlib.sha1(fh.read()).hexdigest() != t["sha1"]:
+            return None
+    return 1024.0 * (COUNTER_SCALE["fetch"] * t["fetch_kib"] + COUNTER_SCALE["write"] * t["write_kib"])
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -138,7 +164,7 @@ def residual_leg(ctx, args, prec_name, s):
     fl = out[1].cpu().numpy()
     leg = {"value": points / sec, "ms_per_step": sec * 1e3,
            "roofline": {"bound": roof["bound"], "achieved": achieved / 1e12, "peak": roof["peak"] / 1e12,
-                        "unit": "TFLOP/s", "frac": achieved / roof["peak"], "traffic": None,
+                        "unit": "TFLOP/s", "frac": achieved / roof["peak"], "traffic": traffic_bytes(roof["kernel"]),
                         "kernel": roof["kernel"], "kernel_ms": ksec * 1e3, "launches_per_step": nl / args.steps,
                         "algorithmic": roof["algorithmic"]},
            "rescored_points": int(((fl & 64) != 0).sum()), "n_peaks_above_fap1": int(len(peaks["p"][0]))}
