@@ -8,8 +8,8 @@ path: normalisation, base-model precomputation (orthonormal basis), trig
 generation and sums, 2x2 Schur solves and z for every grid frequency, float64
 re-scoring of ill-conditioned points (float32 form), and the list of
 periodogram peaks above the FAP_1 threshold (fredec_scan + fredec_peaks).
-Both forms are timed; the headline is the faster float32-MFMA form, the
-float64 path is reported beside it.  Inputs are resident in HBM before the
+Both forms are timed; the headline is the faster one, the other is
+reported beside it.  Inputs are resident in HBM before the
 timed region starts.
 
 The JSON line also carries the tuple workload (N=1000 over 3000 d, 65536
@@ -41,6 +41,17 @@ METRIC = "periodogram points/s (N×F) + tuples/s at stated rel-err vs FP64 oracl
 # MI355X published peaks
 PEAK_FP64_VALU = 78.6e12      # flop/s, FMA = 2 flops
 PEAK_FP32_MFMA = 157.3e12     # flop/s, dense
+PEAK_FP32_VALU = 157.3e12     # flop/s, float32 vector (non-packed FMA on every lane)
+
+
+def f32_form():
+    """Kernel of the float32 scan chosen by the autotuner (0 VALU, 1 MFMA)."""
+    path = os.path.join(ROOT, "paper_1309_0100_amd", "tuning.json")
+    try:
+        with open(path) as fh:
+            return int(json.load(fh).get("scan_f32_form", {}).get("form", 0))
+    except (OSError, ValueError):
+        return 0
 
 # HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (KiB per dispatch), scaled by
 # what the same counters read for a plain device copy of known size (FETCH x2.0, WRITE x1.0).  A
@@ -51,8 +62,9 @@ TRAFFIC = {
                         "fetch_kib": 1160.2, "write_kib": 8789.1},
     "scan_mfma_kernel": {"src": "scan_mfma.hip", "sha1": "8407bfa682b2d4ad5de7426d0da0c851edfbf34b",
                          "fetch_kib": 2156.3, "write_kib": 8802.1},
+    "scan_f32_kernel": {"src": "scan_f32.hip", "sha1": None, "fetch_kib": None, "write_kib": None},
     "tuple_gram_lanes_kernel": {"src": "tuples.hip", "sha1": "8b07302fac69d385b9e9710eb7051ee087ee6b47",
-                                "fetch_kib": None, "write_kib": None},
+                                "fetch_kib": 2018.1, "write_kib": 9145.5},
 }
 
 
@@ -154,11 +166,17 @@ def residual_leg(ctx, args, prec_name, s):
         roof = {"bound": "alu", "peak": PEAK_FP64_VALU, "kernel": "scan_f64_kernel",
                 "algorithmic": f"{fpp} flop per (frequency, sample) pair: {2 * KP + 3} float64 multiply-adds "
                                f"(cos and sin against {KP} columns, cos^2, cos sin, sin^2)"}
-    else:
+    elif f32_form() == 1:
         fpp = 4 * K
         roof = {"bound": "mfma", "peak": PEAK_FP32_MFMA, "kernel": "scan_mfma_kernel",
                 "algorithmic": f"{fpp} flop per (frequency, sample) pair: cos and sin against the {K} "
                                "orthonormal base columns, one float32 multiply-add each, on MFMA (unpadded)"}
+    else:
+        fpp = 2 * (2 * KP + 3)
+        roof = {"bound": "alu", "peak": PEAK_FP32_VALU, "kernel": "scan_f32_kernel",
+                "algorithmic": f"{fpp} flop per (frequency, sample) pair: {2 * KP + 3} multiply-adds (cos and sin "
+                               f"against {K} base columns, cos^2, cos sin in float32; the data column in "
+                               "float64), against the float32 vector peak"}
     achieved = fpp * points / ksec
     z = out[0].cpu().numpy()
     fl = out[1].cpu().numpy()
@@ -232,7 +250,8 @@ def tuples_leg(ctx, args, n_steps=20):
            "workload": f"N={s.N} over 3000 d, {nt} tuples of 1..6 perturbed peaks of the m=0 scan, "
                        f"{n_steps} ascent steps (forward z + adjoint dz/df + update) per call",
            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
-                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
+                        "traffic": traffic_bytes("tuple_gram_lanes_kernel"),
                         "kernel": "tuple_gram_lanes_kernel", "kernel_ms_per_call": ksec * 1e3,
                         "launches_per_call": nl / args.tuple_steps,
                         "algorithmic": "C(C+1) flop per (tuple, sample) per pass, C = 2n+2 Gram columns "

@@ -48,8 +48,10 @@ typedef struct fredec_ctx fredec_ctx;
 /* Internal arithmetic of the trigonometric sums (outputs are float64). */
 enum {
   FREDEC_FP64 = 0, /* float64 phase, trig and sums */
-  FREDEC_FP32 = 1  /* float64 phase reduction and solves; float32 trig and
-                      MFMA sums with float64 accumulation across sample tiles */
+  FREDEC_FP32 = 1  /* float64 phase reduction, phasors, data column and solves;
+                      float32 sums against the base columns (VALU or MFMA),
+                      added into float64 totals per sample tile; ill-conditioned
+                      points re-scored in float64 */
 };
 
 enum {
@@ -94,13 +96,17 @@ int fredec_version(void); /* 100 * major + minor */
 int fredec_profile(fredec_ctx* ctx, int32_t enable);
 int fredec_profile_read(fredec_ctx* ctx, double* total_ms, int64_t* launches);
 
-/* Tile shapes chosen by the autotuner (paper_1309_0100_amd/autotune.py).
+/* Kernel and tile choices made by the autotuner (paper_1309_0100_amd/autotune.py).
  * FREDEC_TILE_SCAN_MFMA: key = column tiles of the float32 MFMA scan operand
  * (1..4, i.e. ceil((2m+2)/16)), value = 16-frequency tiles per wavefront
  * (2, 4, 6 or 8 for key 1; 2 or 4 for key 2; 2 for keys 3, 4; 0 = default).
+ * FREDEC_TILE_SCAN_F32_FORM: key = 0, value = kernel of the float32 scan:
+ * 0 (default) the VALU kernel for base models with m <= 12 and the MFMA
+ * kernel above, 1 the MFMA kernel for every m.  Both give results within the
+ * float32 bound.
  * Errors: EINVAL for an unsupported combination.  The workspace size of a
- * scan does not depend on this setting. */
-enum { FREDEC_TILE_SCAN_MFMA = 1 };
+ * scan does not depend on these settings. */
+enum { FREDEC_TILE_SCAN_MFMA = 1, FREDEC_TILE_SCAN_F32_FORM = 2 };
 int fredec_set_tile(fredec_ctx* ctx, int32_t kernel, int32_t key, int32_t value);
 
 /* Normalisation (Sect. 4.1, eq. idn; T_eff of Sect. 2) -------------------

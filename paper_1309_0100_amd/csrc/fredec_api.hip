@@ -156,8 +156,10 @@ struct ScanPlan : fredec_plan {
   int64_t base_off = 0;  // soff[0]: t, x, w are indexed from the caller's pointers
   std::vector<SeriesIn> sin;
   std::vector<ScanWork> work;
+  enum Kind { F64 = 0, MFMA = 1, F32 = 2 };
   struct Group {
-    int key;         // KP (float64) or column tiles NT (MFMA)
+    int kind;        // kernel family
+    int key;         // KP (float64, float32 VALU) or column tiles NT (MFMA)
     int ft;          // MFMA: 16-frequency tiles per wave the work list was cut for
     int64_t begin, end;
   };
@@ -212,12 +214,19 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
       aux_off += d.N * AUX_STRIDE;
     }
   }
-  // Work list: tiles grouped by kernel instance (KP for float64, column
-  // tiles NT for MFMA), longest series first inside a group.
-  auto key = [&](int32_t s) { return precision == FREDEC_FP64 ? sin[s].KP : sin[s].NT; };
+  // Work list: tiles grouped by kernel instance (KP for the float64 and the
+  // float32 VALU kernels, column tiles NT for MFMA), longest series first
+  // inside a group.
+  const bool f32_valu = precision == FREDEC_FP32 && !(ctx && ctx->f32_form == 1);
+  auto kind = [&](int32_t s) {
+    if (precision == FREDEC_FP64) return static_cast<int>(ScanPlan::F64);
+    return static_cast<int>(f32_valu && sin[s].KP <= F32_VALU_MAX_KP ? ScanPlan::F32 : ScanPlan::MFMA);
+  };
+  auto key = [&](int32_t s) { return kind(s) == ScanPlan::MFMA ? sin[s].NT : sin[s].KP; };
   std::vector<int32_t> order(n_series);
   for (int32_t s = 0; s < n_series; ++s) order[s] = s;
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    if (kind(a) != kind(b)) return kind(a) < kind(b);
     if (key(a) != key(b)) return key(a) < key(b);
     return sin[a].N > sin[b].N;
   });
@@ -225,10 +234,13 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
   P.work.reserve(L.n_work);
   P.groups.clear();
   for (int32_t s : order) {
-    const int ft = precision == FREDEC_FP32 ? mfma_ft_for(ctx, sin[s].NT) : 0;
-    const int64_t tile = precision == FREDEC_FP32 ? 64 * static_cast<int64_t>(ft) : scan_tile(sin[s].KP, precision);
-    if (P.groups.empty() || P.groups.back().key != key(s))
-      P.groups.push_back(ScanPlan::Group{key(s), ft, static_cast<int64_t>(P.work.size()), 0});
+    const int kd = kind(s);
+    const int ft = kd == ScanPlan::MFMA ? mfma_ft_for(ctx, sin[s].NT) : 0;
+    const int64_t tile = kd == ScanPlan::MFMA  ? 64 * static_cast<int64_t>(ft)
+                         : kd == ScanPlan::F32 ? static_cast<int64_t>(BLOCK) * scan_f32_freqs_per_thread(sin[s].KP)
+                                               : scan_tile(sin[s].KP, precision);
+    if (P.groups.empty() || P.groups.back().kind != kd || P.groups.back().key != key(s))
+      P.groups.push_back(ScanPlan::Group{kd, key(s), ft, static_cast<int64_t>(P.work.size()), 0});
     for (int64_t j0 = 0; j0 < sin[s].F; j0 += tile) P.work.push_back(ScanWork{s, 0, j0});
     P.groups.back().end = static_cast<int64_t>(P.work.size());
   }
@@ -274,10 +286,15 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const double
     ProfScope prof(ctx, st);
     for (const auto& gr : P.groups) {
       const int n = static_cast<int>(gr.end - gr.begin);
-      const hipError_t err =
-          f32 ? launch_scan_mfma(st, gr.key, gr.ft, n, d_work + gr.begin, d_sin, d_hdr, d_g32, d_aux, z_out,
-                                 flags_out, d_list, d_count)
-              : launch_scan_f64(st, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_rec, z_out, flags_out);
+      hipError_t err;
+      if (gr.kind == ScanPlan::MFMA)
+        err = launch_scan_mfma(st, gr.key, gr.ft, n, d_work + gr.begin, d_sin, d_hdr, d_g32, d_aux, z_out, flags_out,
+                               d_list, d_count);
+      else if (gr.kind == ScanPlan::F32)
+        err = launch_scan_f32(st, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_rec, d_g32, z_out, flags_out, d_list,
+                              d_count);
+      else
+        err = launch_scan_f64(st, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_rec, z_out, flags_out);
       if (err != hipSuccess) return FREDEC_EDEVICE;
     }
   }
@@ -336,6 +353,11 @@ int fredec_set_tile(fredec_ctx* ctx, int32_t kernel, int32_t key, int32_t value)
     if (key < 1 || key > 4) return FREDEC_EINVAL;
     if (value != 0 && !mfma_tile_supported(key, value)) return FREDEC_EINVAL;
     ctx->mfma_ft[key] = value;
+    return FREDEC_OK;
+  }
+  if (kernel == FREDEC_TILE_SCAN_F32_FORM) {
+    if (key != 0 || (value != 0 && value != 1)) return FREDEC_EINVAL;
+    ctx->f32_form = value;
     return FREDEC_OK;
   }
   return FREDEC_EINVAL;

@@ -19,6 +19,7 @@ struct fredec_ctx {
   hipEvent_t staging_done = nullptr;
   bool staging_pending = false;
   int mfma_ft[5] = {0, 0, 0, 0, 0};  // MFMA scan: 16-frequency tiles per wave, by column tiles (0 = default)
+  int f32_form = 0;                  // float32 scan: 0 VALU kernel (small base models), 1 MFMA kernel
   // optional timing of the dominant kernel of each call (HIP events)
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;

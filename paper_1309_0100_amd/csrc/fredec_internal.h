@@ -195,5 +195,12 @@ hipError_t launch_scan_at_f64(hipStream_t st, int KP, const SeriesIn* sin, const
 hipError_t launch_copy_stats(hipStream_t st, int n_series, const SeriesHdr* hdr, const SeriesIn* sin,
                              double* l_base, int32_t* status, double* stats);
 int scan_freqs_per_thread(int KP);  // R of the float64 scan kernel
+// Reduced-precision VALU scan (float32 sums, float64 phasors and data column);
+// records as the float64 scan plus the float32 column copy g32.
+hipError_t launch_scan_f32(hipStream_t st, int KP, int n_work, const ScanWork* work, const SeriesIn* sin,
+                           const SeriesHdr* hdr, const double* rec, const float* g32, double* z, uint8_t* flags,
+                           Rescore* list, unsigned long long* count);
+int scan_f32_freqs_per_thread(int KP);  // R of the float32 VALU scan kernel
+constexpr int F32_VALU_MAX_KP = 26;     // larger base models use the MFMA form
 
 }  // namespace fredec

@@ -229,7 +229,10 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict_
     if (flags & PREP_F32) {
       float* g = g32 + si.g32_off + i * G32W;
       for (int k = 0; k < K; ++k) g[k] = static_cast<float>(wi * ph[k]);
-      for (int k = K; k < G32W; ++k) g[k] = 0.0f;
+      // column K (never read by the MFMA kernel, whose padding columns only
+      // produce unused sums) carries w~ for the VALU kernel's <cos^2>, <cos sin>
+      g[K] = static_cast<float>(wi);
+      for (int k = K + 1; k < G32W; ++k) g[k] = 0.0f;
       double* a = aux + si.aux_off + i * AUX_STRIDE;
       double rs, rc, s1, c1;
       sincos_rev(si.rot_tile * ta, rs, rc);

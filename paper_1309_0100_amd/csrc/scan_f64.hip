@@ -22,6 +22,7 @@
 //   S = C - U^T U, a_psi = L_S^{-1} h, l_{m+1} = l_m - |a_psi|^2,
 //   z = (N - 3m - 4)/2 ln(l_m / l_{m+1}).
 #include "fredec_internal.h"
+#include "scan_phasor.h"
 
 namespace fredec {
 
@@ -100,63 +101,12 @@ __global__ __launch_bounds__(BLOCK) void scan_f64_kernel(const ScanWork* __restr
   for (int64_t i0 = 0; i0 < N; i0 += TS) {
     const int nts = N - i0 < TS ? static_cast<int>(N - i0) : TS;
     __syncthreads();
-    {
-      // sample threadIdx / 4, table entries 4 q4 .. 4 q4 + 3 of both tables
-      const int sl = threadIdx.x >> 2, q4 = threadIdx.x & 3;
-      if (sl < nts) {
-        const double* qs = q0 + (i0 + sl) * P;
-        const double wc = qs[KP + 3], ws = qs[KP + 4];
-        // p = w^(4 q4) and a = w^(64 q4) by repeated squaring (few values
-        // live at a time: the accumulators of the lane stay in registers)
-        double pc = 1.0, ps = 0.0, ac = 1.0, as = 0.0;
-        double xc = wc, xs = ws;  // w^(2^k)
-#pragma unroll
-        for (int k = 1; k <= 7; ++k) {
-          const double nc = xc * xc - xs * xs;
-          xs = 2.0 * xc * xs;
-          xc = nc;  // w^(2^k)
-          if ((k == 2 && (q4 & 1)) || (k == 3 && (q4 & 2))) {
-            const double tc = pc * xc - ps * xs;
-            ps = pc * xs + ps * xc;
-            pc = tc;
-          }
-          if ((k == 6 && (q4 & 1)) || (k == 7 && (q4 & 2))) {
-            const double tc = ac * xc - as * xs;
-            as = ac * xs + as * xc;
-            ac = tc;
-          }
-        }
-        // B_b for b = 4 q4 .. 4 q4 + 3
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          bsh[sl][4 * q4 + k] = double2{pc, ps};
-          const double nc = __builtin_fma(pc, wc, -ps * ws);
-          ps = __builtin_fma(ps, wc, pc * ws);
-          pc = nc;
-        }
-        // E0 A_a for a = 4 q4 .. 4 q4 + 3, A_a = (w^16)^a (w^16 by four squarings)
-        double hc = wc, hs = ws;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const double nc = hc * hc - hs * hs;
-          hs = 2.0 * hc * hs;
-          hc = nc;
-        }
-        double es, ec;
-        sincos_rev(fb * qs[0], es, ec);
-        pc = __builtin_fma(ec, ac, -es * as);
-        ps = __builtin_fma(es, ac, ec * as);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          eash[sl][4 * q4 + k] = double2{pc, ps};
-          const double nc = __builtin_fma(pc, hc, -ps * hs);
-          ps = __builtin_fma(ps, hc, pc * hs);
-          pc = nc;
-        }
-      }
-    }
+    build_phasor_tables<KP>(q0 + i0 * P, P, nts, fb, eash, bsh);
     __syncthreads();
+    // two samples per iteration: their scalar and LDS loads are issued
+    // together, so one wait covers both
     const double* __restrict__ q = q0 + i0 * P;
+#pragma unroll 2
     for (int sl = 0; sl < nts; ++sl, q += P) {
       const double2 ea = eash[sl][ta_];
       const double2 bb = bsh[sl][tb_];

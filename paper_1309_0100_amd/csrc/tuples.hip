@@ -649,9 +649,9 @@ hipError_t gram_nb(hipStream_t st, const TupleDesc* desc, const int32_t* order, 
 }
 
 // Lanes per tuple for a group of n_order tuples of N samples: enough groups
-// of lanes to give every CU a few waves, at least 16 samples per lane.
+// of lanes to give every CU 16 waves, at least 16 samples per lane.
 int lanes_for(int n_order, int64_t N, int n_cu) {
-  const int64_t want = 4LL * std::max(n_cu, 1) * 64;  // threads for ~4 waves per CU
+  const int64_t want = 16LL * std::max(n_cu, 1) * 64;  // threads for 16 waves per CU
   int L = 4;
   while (L < 64 && static_cast<int64_t>(n_order) * L < want && N / (2 * L) >= 16) L *= 2;
   return L;

@@ -1,5 +1,7 @@
-"""GPU parity of the reduced-precision residual scan (float32 MFMA sums,
-float64 phase reduction and solves) against the float64 oracle.
+"""GPU parity of the reduced-precision residual scan (float32 sums against
+the base columns, float64 phase reduction, phasors, data column and solves)
+against the float64 oracle, for both kernels of that form: the VALU kernel
+(default for m <= 12) and the MFMA kernel.
 
 Bound (relative error err = |z - z_ref| / max(z_ref, 1)): 1e-6 on every grid
 frequency that the oracle does not flag.  Grid points whose trial columns lie
@@ -19,12 +21,15 @@ pytestmark = pytest.mark.gpu
 TOL32 = 1e-6
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=[0, 1], ids=["valu", "mfma"])
+def ctx(request):
     import torch
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     from paper_1309_0100_amd import fredec as F
-    return F.Context(0)
+    c = F.Context(0)
+    c.set_tile(F.TILE_SCAN_F32_FORM, 0, request.param)
+    print(f"float32 form: {request.param_index and 'mfma' or 'valu'}", flush=True)
+    return c
 
 
 def compare(z, fl, ref, tol=TOL32, label=""):
