@@ -45,13 +45,29 @@ PEAK_FP32_VALU = 157.3e12     # flop/s, float32 vector (non-packed FMA on every 
 
 
 def f32_form():
-    """Kernel of the float32 scan chosen by the autotuner (0 VALU, 1 MFMA)."""
+    """Kernel family of the float32 scan chosen by the autotuner and the VALU
+    boundary of the automatic form: (form, largest 2m + 2 on the VALU kernel);
+    the library defaults (automatic, 6) when no table is stored."""
     path = os.path.join(ROOT, "paper_1309_0100_amd", "tuning.json")
     try:
         with open(path) as fh:
-            return int(json.load(fh).get("scan_f32_form", {}).get("form", 0))
+            tab = json.load(fh)
+        return (int(tab.get("scan_f32_form", {}).get("form", 3)),
+                int(tab.get("scan_f32_auto", {}).get("valu_max_kp", 6)))
     except (OSError, ValueError):
-        return 0
+        return 3, 6
+
+
+def f32_kernel(KP):
+    """Name of the kernel the float32 scan of a base model with 2m + 2 = KP uses."""
+    form, valu_max = f32_form()
+    if form == 0:
+        return "scan_f32_kernel" if KP <= 26 else "scan_mfma_kernel"
+    if form == 1:
+        return "scan_mfma_kernel"
+    if form == 2 or KP > valu_max:
+        return "scan_f16x3_kernel"
+    return "scan_f32_kernel"
 
 # HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (KiB per dispatch), scaled by
 # what the same counters read for a plain device copy of known size (FETCH x2.0, WRITE x1.0).  A
@@ -63,6 +79,7 @@ TRAFFIC = {
     "scan_mfma_kernel": {"src": "scan_mfma.hip", "sha1": "8407bfa682b2d4ad5de7426d0da0c851edfbf34b",
                          "fetch_kib": 2156.3, "write_kib": 8802.1},
     "scan_f32_kernel": {"src": "scan_f32.hip", "sha1": None, "fetch_kib": None, "write_kib": None},
+    "scan_f16x3_kernel": {"src": "scan_f16x3.hip", "sha1": None, "fetch_kib": None, "write_kib": None},
     "tuple_gram_lanes_kernel": {"src": "tuples.hip", "sha1": "8b07302fac69d385b9e9710eb7051ee087ee6b47",
                                 "fetch_kib": 2018.1, "write_kib": 9145.5},
 }
@@ -166,17 +183,20 @@ def residual_leg(ctx, args, prec_name, s):
         roof = {"bound": "alu", "peak": PEAK_FP64_VALU, "kernel": "scan_f64_kernel",
                 "algorithmic": f"{fpp} flop per (frequency, sample) pair: {2 * KP + 3} float64 multiply-adds "
                                f"(cos and sin against {KP} columns, cos^2, cos sin, sin^2)"}
-    elif f32_form() == 1:
+    elif f32_kernel(KP) == "scan_mfma_kernel":
         fpp = 4 * K
         roof = {"bound": "mfma", "peak": PEAK_FP32_MFMA, "kernel": "scan_mfma_kernel",
                 "algorithmic": f"{fpp} flop per (frequency, sample) pair: cos and sin against the {K} "
                                "orthonormal base columns, one float32 multiply-add each, on MFMA (unpadded)"}
     else:
         fpp = 2 * (2 * KP + 3)
-        roof = {"bound": "alu", "peak": PEAK_FP32_VALU, "kernel": "scan_f32_kernel",
+        kern = f32_kernel(KP)
+        roof = {"bound": "alu", "peak": PEAK_FP32_VALU, "kernel": kern,
                 "algorithmic": f"{fpp} flop per (frequency, sample) pair: {2 * KP + 3} multiply-adds (cos and sin "
-                               f"against {K} base columns, cos^2, cos sin in float32; the data column in "
-                               "float64), against the float32 vector peak"}
+                               f"against {K} base columns, cos^2, cos sin; the data column in float64), against the "
+                               "float32 vector peak" + (" (the base-column sums run on the float16 matrix cores with "
+                                                        "split operands, the rest on the VALU)"
+                                                        if kern == "scan_f16x3_kernel" else "")}
     achieved = fpp * points / ksec
     z = out[0].cpu().numpy()
     fl = out[1].cpu().numpy()

@@ -100,13 +100,18 @@ int fredec_profile_read(fredec_ctx* ctx, double* total_ms, int64_t* launches);
  * FREDEC_TILE_SCAN_MFMA: key = column tiles of the float32 MFMA scan operand
  * (1..4, i.e. ceil((2m+2)/16)), value = 16-frequency tiles per wavefront
  * (2, 4, 6 or 8 for key 1; 2 or 4 for key 2; 2 for keys 3, 4; 0 = default).
- * FREDEC_TILE_SCAN_F32_FORM: key = 0, value = kernel of the float32 scan:
- * 0 (default) the VALU kernel for base models with m <= 12 and the MFMA
- * kernel above, 1 the MFMA kernel for every m.  Both give results within the
- * float32 bound.
+ * FREDEC_TILE_SCAN_F32_FORM: key = 0, value = kernel family of the
+ * FREDEC_FP32 scan (FREDEC_F32_FORM_*): VALU = float32 vector sums (base
+ * models with m <= 12; the float32 MFMA kernel above), MFMA32 = float32
+ * matrix cores for every m, F16X3 = float16 matrix cores on split operands
+ * (three products per step) for every m, AUTO (default) = VALU for
+ * 2m + 2 <= the key-1 setting and F16X3 above.  All give results within the
+ * float32 bound.  Key = 1: value = largest 2m + 2 (0..26, default 6) that
+ * the AUTO form gives to the VALU kernel.
  * Errors: EINVAL for an unsupported combination.  The workspace size of a
  * scan does not depend on these settings. */
 enum { FREDEC_TILE_SCAN_MFMA = 1, FREDEC_TILE_SCAN_F32_FORM = 2 };
+enum { FREDEC_F32_FORM_VALU = 0, FREDEC_F32_FORM_MFMA32 = 1, FREDEC_F32_FORM_F16X3 = 2, FREDEC_F32_FORM_AUTO = 3 };
 int fredec_set_tile(fredec_ctx* ctx, int32_t kernel, int32_t key, int32_t value);
 
 /* Normalisation (Sect. 4.1, eq. idn; T_eff of Sect. 2) -------------------

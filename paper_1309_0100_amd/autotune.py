@@ -3,9 +3,10 @@
 For each operand width bucket NT (16-column tiles: 1 for m <= 7, 2 for
 m <= 15, ...) it times every supported frequency-tile count FT of the MFMA
 kernel on a synthetic series of the benchmark's shape (N samples, m base
-frequencies, F grid points) and keeps the fastest; then it times the VALU
-kernel of the float32 form against the tuned MFMA kernel and keeps the
-faster.  The choice is written to
+frequencies, F grid points) and keeps the fastest; then it finds the base
+model sizes where the float32 VALU kernel beats the split-float16 MFMA kernel
+(the boundary of the automatic form), and times every kernel family of the
+float32 form over m = 0, 2, 4, 8 and keeps the fastest.  The choice is written to
 tuning.json next to this file; Context(tuning=True) applies it through
 fredec_set_tile.  Usage: python -m paper_1309_0100_amd.autotune [--N 2000 --F 1000000]
 """
@@ -55,17 +56,38 @@ def tune(N=2000, F=1_000_000, buckets=(1, 2), reps=5, verbose=True, out_path=TUN
                 best = (ft, ms)
         out["scan_mfma"][str(nt)] = {"FT": best[0], "ms": best[1]}
         ctx.set_tile(fredec.TILE_SCAN_MFMA, nt, best[0])
-    # float32 form: VALU kernel against the tuned MFMA kernel, on the m of the first bucket
-    m = BUCKET_M[buckets[0]]
-    base = np.random.default_rng(buckets[0]).uniform(0.01, 1.5, size=m)
-    t_form = {}
-    for form in (1, 0):
-        ctx.set_tile(fredec.TILE_SCAN_F32_FORM, 0, form)
-        t_form[form] = time_scan(ctx, s, base, 2.0 / F, F, reps)
+    # automatic float32 form: the VALU kernel serves base models up to the
+    # largest 2m + 2 where it beats the split-float16 MFMA kernel
+    ms_by_m = {}
+    valu_max_kp = 0
+    for m in range(0, 7):
+        base = np.random.default_rng(100 + m).uniform(0.01, 1.5, size=m)
+        t = {}
+        for form in (fredec.F32_FORM_VALU, fredec.F32_FORM_F16X3):
+            ctx.set_tile(fredec.TILE_SCAN_F32_FORM, 0, form)
+            t[form] = time_scan(ctx, s, base, 2.0 / F, F, reps)
+        ms_by_m[m] = t
         if verbose:
-            print(f"float32 form {'MFMA' if form else 'VALU'} (m={m}): {t_form[form]:.3f} ms", flush=True)
-    best_form = min(t_form, key=t_form.get)
-    out["scan_f32_form"] = {"form": best_form, "ms": t_form[best_form]}
+            print(f"m={m}: VALU {t[fredec.F32_FORM_VALU]:.3f} ms, split-float16 MFMA {t[fredec.F32_FORM_F16X3]:.3f} ms",
+                  flush=True)
+        if t[fredec.F32_FORM_VALU] < t[fredec.F32_FORM_F16X3] and valu_max_kp == 2 * m:
+            valu_max_kp = 2 * m + 2
+    ctx.set_tile(fredec.TILE_SCAN_F32_FORM, 1, valu_max_kp)
+    out["scan_f32_auto"] = {"valu_max_kp": valu_max_kp}
+    # float32 form: every kernel family on a spread of base-model sizes
+    ms_form = {}
+    names = {0: "VALU", 1: "MFMA32", 2: "F16X3", 3: "AUTO"}
+    for form in names:
+        ctx.set_tile(fredec.TILE_SCAN_F32_FORM, 0, form)
+        tot = 0.0
+        for m in (0, 2, 4, 8):
+            base = np.random.default_rng(200 + m).uniform(0.01, 1.5, size=m)
+            tot += time_scan(ctx, s, base, 2.0 / F, F, reps)
+        ms_form[form] = tot
+        if verbose:
+            print(f"float32 form {names[form]}: {tot:.3f} ms over m = 0, 2, 4, 8", flush=True)
+    best_form = min(ms_form, key=ms_form.get)
+    out["scan_f32_form"] = {"form": best_form, "ms": ms_form[best_form]}
     with open(out_path, "w") as fh:
         json.dump(out, fh, indent=1)
     return out
@@ -81,6 +103,8 @@ def apply(ctx, path=TUNING):
         ctx.set_tile(fredec.TILE_SCAN_MFMA, int(nt), int(v["FT"]))
     if "scan_f32_form" in tab:
         ctx.set_tile(fredec.TILE_SCAN_F32_FORM, 0, int(tab["scan_f32_form"]["form"]))
+    if "scan_f32_auto" in tab:
+        ctx.set_tile(fredec.TILE_SCAN_F32_FORM, 1, int(tab["scan_f32_auto"]["valu_max_kp"]))
     return True
 
 

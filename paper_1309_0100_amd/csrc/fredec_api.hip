@@ -74,18 +74,20 @@ namespace {
 
 struct ScanLayout {
   size_t off_sin = 0, off_hdr = 0, off_work = 0, off_tau = 0, off_xt = 0, off_wt = 0, off_rec = 0, off_phi = 0;
-  size_t off_g32 = 0, off_aux = 0, off_list = 0, off_count = 0;
+  size_t off_g32 = 0, off_aux = 0, off_b16 = 0, off_list = 0, off_count = 0;
   size_t total = 0;
-  int64_t Ntot = 0, rec_total = 0, phi_total = 0, g32_total = 0, aux_total = 0, n_work = 0, F_total = 0;
+  int64_t Ntot = 0, rec_total = 0, phi_total = 0, g32_total = 0, aux_total = 0, b16_total = 0, n_work = 0,
+          F_total = 0;
   int max_nt = 1;
 };
 
 constexpr int MFMA_FT_MIN = 2;
 
 // Frequencies per workgroup of the scan kernel used for a series (for the
-// MFMA kernel the smallest tile, which bounds the work list of any setting).
+// reduced-precision forms the smallest tile of any of their kernels, which
+// bounds the work list of any setting).
 int64_t scan_tile(int KP, int32_t precision) {
-  if (precision == FREDEC_FP32) return 64 * MFMA_FT_MIN;
+  if (precision == FREDEC_FP32) return 64;
   return static_cast<int64_t>(BLOCK) * scan_freqs_per_thread(KP);
 }
 
@@ -116,6 +118,7 @@ int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, cons
     if (precision == FREDEC_FP32) {
       L.g32_total += N * 16 * col_tiles(KP);
       L.aux_total += N * AUX_STRIDE;
+      L.b16_total += b16_vectors(N, col_tiles(KP));
       L.max_nt = std::max(L.max_nt, col_tiles(KP));
     }
   }
@@ -135,6 +138,7 @@ int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, cons
   L.off_phi = take(sizeof(double) * L.phi_total);
   L.off_g32 = take(sizeof(float) * L.g32_total);
   L.off_aux = take(sizeof(double) * L.aux_total);
+  L.off_b16 = take(16 * L.b16_total);
   L.off_list = take(precision == FREDEC_FP32 ? sizeof(Rescore) * L.F_total : 0);
   L.off_count = take(sizeof(unsigned long long));
   L.total = off;
@@ -156,10 +160,10 @@ struct ScanPlan : fredec_plan {
   int64_t base_off = 0;  // soff[0]: t, x, w are indexed from the caller's pointers
   std::vector<SeriesIn> sin;
   std::vector<ScanWork> work;
-  enum Kind { F64 = 0, MFMA = 1, F32 = 2 };
+  enum Kind { F64 = 0, MFMA = 1, F32 = 2, F16X3 = 3 };
   struct Group {
     int kind;        // kernel family
-    int key;         // KP (float64, float32 VALU) or column tiles NT (MFMA)
+    int key;         // KP (float64, float32 VALU) or column tiles NT (MFMA forms)
     int ft;          // MFMA: 16-frequency tiles per wave the work list was cut for
     int64_t begin, end;
   };
@@ -184,7 +188,7 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
   std::vector<SeriesIn>& sin = P.sin;
   sin.assign(n_series, SeriesIn{});
   std::memset(sin.data(), 0, sizeof(SeriesIn) * n_series);
-  int64_t goff = 0, rec_off = 0, phi_off = 0, g32_off = 0, aux_off = 0;
+  int64_t goff = 0, rec_off = 0, phi_off = 0, g32_off = 0, aux_off = 0, b16_off = 0;
   for (int32_t s = 0; s < n_series; ++s) {
     SeriesIn& d = sin[s];
     d.soff = soff[s];
@@ -206,23 +210,32 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
     d.phi_off = phi_off;
     d.g32_off = g32_off;
     d.aux_off = aux_off;
+    d.b16_off = b16_off;
     goff += F[s];
     phi_off += d.N * d.KP;
     rec_off += d.N * rec_stride(d.KP);
     if (precision == FREDEC_FP32) {
       g32_off += d.N * 16 * d.NT;
       aux_off += d.N * AUX_STRIDE;
+      b16_off += b16_vectors(d.N, d.NT);
     }
   }
   // Work list: tiles grouped by kernel instance (KP for the float64 and the
   // float32 VALU kernels, column tiles NT for MFMA), longest series first
   // inside a group.
-  const bool f32_valu = precision == FREDEC_FP32 && !(ctx && ctx->f32_form == 1);
+  const int form = ctx ? ctx->f32_form : FREDEC_F32_FORM_AUTO;
+  const int auto_kp = ctx ? ctx->f32_auto_valu_max_kp : F32_AUTO_VALU_MAX_KP;
   auto kind = [&](int32_t s) {
     if (precision == FREDEC_FP64) return static_cast<int>(ScanPlan::F64);
-    return static_cast<int>(f32_valu && sin[s].KP <= F32_VALU_MAX_KP ? ScanPlan::F32 : ScanPlan::MFMA);
+    if (form == FREDEC_F32_FORM_F16X3 || (form == FREDEC_F32_FORM_AUTO && sin[s].KP > auto_kp))
+      return static_cast<int>(ScanPlan::F16X3);
+    if (form == FREDEC_F32_FORM_AUTO) return static_cast<int>(ScanPlan::F32);
+    if (form == FREDEC_F32_FORM_VALU && sin[s].KP <= F32_VALU_MAX_KP) return static_cast<int>(ScanPlan::F32);
+    return static_cast<int>(ScanPlan::MFMA);
   };
-  auto key = [&](int32_t s) { return kind(s) == ScanPlan::MFMA ? sin[s].NT : sin[s].KP; };
+  auto key = [&](int32_t s) {
+    return (kind(s) == ScanPlan::MFMA || kind(s) == ScanPlan::F16X3) ? sin[s].NT : sin[s].KP;
+  };
   std::vector<int32_t> order(n_series);
   for (int32_t s = 0; s < n_series; ++s) order[s] = s;
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
@@ -236,9 +249,10 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
   for (int32_t s : order) {
     const int kd = kind(s);
     const int ft = kd == ScanPlan::MFMA ? mfma_ft_for(ctx, sin[s].NT) : 0;
-    const int64_t tile = kd == ScanPlan::MFMA  ? 64 * static_cast<int64_t>(ft)
-                         : kd == ScanPlan::F32 ? static_cast<int64_t>(BLOCK) * scan_f32_freqs_per_thread(sin[s].KP)
-                                               : scan_tile(sin[s].KP, precision);
+    const int64_t tile = kd == ScanPlan::MFMA    ? 64 * static_cast<int64_t>(ft)
+                         : kd == ScanPlan::F16X3 ? 64 * static_cast<int64_t>(f16x3_freq_tiles(sin[s].NT))
+                         : kd == ScanPlan::F32   ? static_cast<int64_t>(BLOCK) * scan_f32_freqs_per_thread(sin[s].KP)
+                                                 : scan_tile(sin[s].KP, precision);
     if (P.groups.empty() || P.groups.back().kind != kd || P.groups.back().key != key(s))
       P.groups.push_back(ScanPlan::Group{kd, key(s), ft, static_cast<int64_t>(P.work.size()), 0});
     for (int64_t j0 = 0; j0 < sin[s].F; j0 += tile) P.work.push_back(ScanWork{s, 0, j0});
@@ -271,16 +285,19 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const double
   double* d_phi = at<double>(ws, L.off_phi);
   float* d_g32 = at<float>(ws, L.off_g32);
   double* d_aux = at<double>(ws, L.off_aux);
+  void* d_b16 = at<char>(ws, L.off_b16);
   Rescore* d_list = at<Rescore>(ws, L.off_list);
   unsigned long long* d_count = at<unsigned long long>(ws, L.off_count);
   const bool f32 = P.precision == FREDEC_FP32;
   // soff is absolute into t/x/w; the normalised copies use the same indexing
   // shifted by soff[0] (the batch is contiguous).
   const int64_t base_off = P.base_off;
-  const int flags = PREP_BASE | PREP_REC64 | (f32 ? PREP_F32 : 0);
+  bool any_f16x3 = false;
+  for (const auto& gr : P.groups) any_f16x3 |= gr.kind == ScanPlan::F16X3;
+  const int flags = PREP_BASE | PREP_REC64 | (f32 ? PREP_F32 : 0) | (any_f16x3 ? PREP_F16 : 0);
   if (f32 && launch_zero_u64(st, d_count, 1) != hipSuccess) return FREDEC_EDEVICE;
   if (launch_prep(st, P.n_series, d_sin, d_hdr, t, x, w, d_tau - base_off, d_xt - base_off, d_wt - base_off, d_rec,
-                  d_phi, d_g32, d_aux, flags) != hipSuccess)
+                  d_phi, d_g32, d_aux, d_b16, flags) != hipSuccess)
     return FREDEC_EDEVICE;
   {
     ProfScope prof(ctx, st);
@@ -290,6 +307,9 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const double
       if (gr.kind == ScanPlan::MFMA)
         err = launch_scan_mfma(st, gr.key, gr.ft, n, d_work + gr.begin, d_sin, d_hdr, d_g32, d_aux, z_out, flags_out,
                                d_list, d_count);
+      else if (gr.kind == ScanPlan::F16X3)
+        err = launch_scan_f16x3(st, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_aux, d_b16, z_out, flags_out,
+                                d_list, d_count);
       else if (gr.kind == ScanPlan::F32)
         err = launch_scan_f32(st, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_rec, d_g32, z_out, flags_out, d_list,
                               d_count);
@@ -356,9 +376,17 @@ int fredec_set_tile(fredec_ctx* ctx, int32_t kernel, int32_t key, int32_t value)
     return FREDEC_OK;
   }
   if (kernel == FREDEC_TILE_SCAN_F32_FORM) {
-    if (key != 0 || (value != 0 && value != 1)) return FREDEC_EINVAL;
-    ctx->f32_form = value;
-    return FREDEC_OK;
+    if (key == 0) {
+      if (value < FREDEC_F32_FORM_VALU || value > FREDEC_F32_FORM_AUTO) return FREDEC_EINVAL;
+      ctx->f32_form = value;
+      return FREDEC_OK;
+    }
+    if (key == 1) {
+      if (value < 0 || value > F32_VALU_MAX_KP) return FREDEC_EINVAL;
+      ctx->f32_auto_valu_max_kp = value;
+      return FREDEC_OK;
+    }
+    return FREDEC_EINVAL;
   }
   return FREDEC_EINVAL;
 }
@@ -431,7 +459,7 @@ int fredec_normalize(fredec_ctx* ctx, void* stream, int32_t n_series, const int6
   int rc = upload(ctx, st, d_sin, sin.data(), sizeof(SeriesIn) * n_series);
   if (rc) return rc;
   // the prep kernel writes the normalised series at the caller's offsets
-  if (launch_prep(st, n_series, d_sin, d_hdr, t, x, w, tau_out, xt_out, wt_out, nullptr, nullptr, nullptr, nullptr,
+  if (launch_prep(st, n_series, d_sin, d_hdr, t, x, w, tau_out, xt_out, wt_out, nullptr, nullptr, nullptr, nullptr, nullptr,
                   0) != hipSuccess)
     return FREDEC_EDEVICE;
   if (launch_copy_stats(st, n_series, d_hdr, d_sin, nullptr, status_out, stats_out) != hipSuccess)
@@ -558,7 +586,7 @@ int fredec_scan_at(fredec_ctx* ctx, void* stream, const double* t, const double*
   hipStream_t st = static_cast<hipStream_t>(stream);
   int rc = upload(ctx, st, d_sin, &si, sizeof(si));
   if (rc) return rc;
-  if (launch_prep(st, 1, d_sin, d_hdr, t, x, w, d_tau, d_xt, d_wt, d_rec, d_phi, nullptr, nullptr,
+  if (launch_prep(st, 1, d_sin, d_hdr, t, x, w, d_tau, d_xt, d_wt, d_rec, d_phi, nullptr, nullptr, nullptr,
                   PREP_BASE | PREP_REC64) != hipSuccess)
     return FREDEC_EDEVICE;
   if (launch_scan_at_f64(st, si.KP, d_sin, d_hdr, d_rec, idx, n_idx, z_out, flags_out) != hipSuccess)

@@ -19,7 +19,8 @@ struct fredec_ctx {
   hipEvent_t staging_done = nullptr;
   bool staging_pending = false;
   int mfma_ft[5] = {0, 0, 0, 0, 0};  // MFMA scan: 16-frequency tiles per wave, by column tiles (0 = default)
-  int f32_form = 0;                  // float32 scan: 0 VALU kernel (small base models), 1 MFMA kernel
+  int f32_form = FREDEC_F32_FORM_AUTO;   // kernel family of the reduced-precision scan (FREDEC_F32_FORM_*)
+  int f32_auto_valu_max_kp = 6;      // automatic form: VALU kernel up to this KP = 2m + 2 (m <= 2)
   // optional timing of the dominant kernel of each call (HIP events)
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;

@@ -31,6 +31,7 @@ struct SeriesIn {
   int64_t phi_off;  // first double of this series in the basis scratch array
   int64_t g32_off;  // first float of this series in the float32 operand array
   int64_t aux_off;  // first double of this series in the float32 kernel's aux array
+  int64_t b16_off;  // first 8-half vector of this series in the split float16 operand array
   double df;        // grid step: f_j = (j+1) df
   double rot_step;  // frequency step of the float64 kernel's recurrence (BLOCK * df)
   double rot_tile;  // frequency step of the MFMA kernel's recurrence (16 * df)
@@ -49,6 +50,7 @@ struct SeriesHdr {
   double D;         // <x~^2> (= 1 up to rounding)
   double W1;        // <1> = sum of the normalised weights (= 1 up to rounding)
   double stats[6];  // <t>, <x>, s_x, Var(t), T_eff, sum(w)
+  double b16_inv;   // 1 / S, S the power-of-two scale of the split float16 operand
   int32_t status;   // 0 or a negative FREDEC_E* code
   int32_t pad;
 };
@@ -67,7 +69,7 @@ struct Rescore {
 };
 
 // Outputs requested from the preparation kernel.
-enum PrepFlags { PREP_BASE = 1, PREP_REC64 = 2, PREP_F32 = 4 };
+enum PrepFlags { PREP_BASE = 1, PREP_REC64 = 2, PREP_F32 = 4, PREP_F16 = 8 };
 
 // float64 scan record per sample: tau, cos/sin(2 pi 256 df tau), the KP
 // weighted columns, cos/sin(2 pi df tau); padded to an even count
@@ -175,7 +177,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
 hipError_t launch_prep(hipStream_t st, int n_series, const SeriesIn* sin, SeriesHdr* hdr,
                        const double* t, const double* x, const double* w,
                        double* tau, double* xt, double* wt, double* rec, double* phi,
-                       float* g32, double* aux, int flags);
+                       float* g32, double* aux, void* b16, int flags);
 hipError_t launch_scan_mfma(hipStream_t st, int NT, int FT, int n_work, const ScanWork* work,
                             const SeriesIn* sin, const SeriesHdr* hdr, const float* g32,
                             const double* aux, double* z, uint8_t* flags, Rescore* list,
@@ -202,5 +204,15 @@ hipError_t launch_scan_f32(hipStream_t st, int KP, int n_work, const ScanWork* w
                            Rescore* list, unsigned long long* count);
 int scan_f32_freqs_per_thread(int KP);  // R of the float32 VALU scan kernel
 constexpr int F32_VALU_MAX_KP = 26;     // larger base models use the MFMA form
+constexpr int F32_AUTO_VALU_MAX_KP = 6;  // automatic form: VALU kernel for m <= 2, split float16 MFMA above
+// Reduced-precision MFMA scan on split float16 operands (aux records and the
+// preparation kernel's float16 operand array b16, 8-half vectors).
+constexpr int f16x3_freq_tiles(int NT) { return NT <= 1 ? 4 : NT <= 2 ? 2 : 1; }  // 16-frequency tiles per wave
+hipError_t launch_scan_f16x3(hipStream_t st, int NT, int n_work, const ScanWork* work, const SeriesIn* sin,
+                             const SeriesHdr* hdr, const double* aux, const void* b16, double* z, uint8_t* flags,
+                             Rescore* list, unsigned long long* count);
+// 8-half vectors of the float16 operand of a series of N samples and NT column tiles:
+// per step of 32 samples and column tile, a high and a low part of 64 lanes.
+__host__ __device__ constexpr int64_t b16_vectors(int64_t N, int NT) { return (N + 31) / 32 * NT * 2 * 64; }
 
 }  // namespace fredec

@@ -22,7 +22,8 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict_
                                                      const double* __restrict__ w, double* __restrict__ tau,
                                                      double* __restrict__ xt, double* __restrict__ wt,
                                                      double* __restrict__ rec, double* __restrict__ phi,
-                                                     float* __restrict__ g32, double* __restrict__ aux, int flags) {
+                                                     float* __restrict__ g32, double* __restrict__ aux,
+                                                     _Float16* __restrict__ b16, int flags) {
   __shared__ double sh[GRAM_CHUNK * BLOCK];
   __shared__ double gram[MAXKP * (MAXKP + 1) / 2];
   __shared__ double Lsh[MAXK * (MAXK + 1) / 2];
@@ -200,6 +201,7 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict_
   // operand records for the scan kernels
   const int P = rec_stride(KP);
   const int G32W = 16 * si.NT;
+  double gmax = 0.0;  // max |w~ q_k| (scale of the float16 operand)
   for (int64_t i = tid; i < N; i += BLOCK) {
     double* ph = phi + si.phi_off + i * KP;
     const double wi = wts[i];
@@ -210,6 +212,7 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict_
       v *= invd[k];
       ph[k] = v;
       r -= v * ab[k];
+      gmax = fmax(gmax, fabs(wi * v));
     }
     ph[KP - 1] = r;
     const double ta = taus[i];
@@ -247,6 +250,51 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict_
       a[7] = s1;
     }
   }
+  if (!(flags & PREP_F16)) return;
+
+  // pass 6: split float16 operand of the MFMA scan, B = S w~ q_k = hi + lo
+  // (both float16, lo = the float32 remainder), S = 2^e with max |B| in
+  // (2^13, 2^14] so that low parts stay clear of the float16 subnormals.
+  // Layout: per step g of 32 samples and column tile nt, the high part then
+  // the low part, each 64 lanes x 8 halves; lane L holds column
+  // 16 nt + L % 16 at samples 32 g + 8 (L / 16) + e, e < 8 (zero beyond N
+  // and beyond column K).
+  {
+    double mx[1] = {gmax};
+    __syncthreads();
+    sh[tid] = mx[0];
+    __syncthreads();
+    for (int o = BLOCK / 2; o > 0; o >>= 1) {
+      if (tid < o) sh[tid] = fmax(sh[tid], sh[tid + o]);
+      __syncthreads();
+    }
+    gmax = sh[0];
+    __syncthreads();
+  }
+  int ex = 0;
+  if (gmax > 0.0) (void)frexp(gmax, &ex);  // gmax in [2^(ex-1), 2^ex)
+  const double S = gmax > 0.0 ? ldexp(1.0, 14 - ex) : 1.0;
+  if (tid == 0) h.b16_inv = 1.0 / S;
+  const int NT = si.NT;
+  const int64_t n_vec = b16_vectors(N, NT) / 2;  // (step, tile, lane) entries
+  const double* phs5 = phi + si.phi_off;
+  _Float16* bser = b16 + si.b16_off * 8;
+  for (int64_t e = tid; e < n_vec; e += BLOCK) {
+    const int L = static_cast<int>(e & 63);
+    const int64_t gt = e >> 6;  // g * NT + nt
+    const int nt = static_cast<int>(gt % NT);
+    const int col = 16 * nt + (L & 15);
+    const int64_t i0 = (gt / NT) * 32 + 8 * (L >> 4);
+    _Float16* hi = bser + ((gt * 2) * 64 + L) * 8;
+    _Float16* lo = hi + 64 * 8;
+    for (int k = 0; k < 8; ++k) {
+      const int64_t i = i0 + k;
+      const double v = (i < N && col < K) ? S * wts[i] * phs5[i * KP + col] : 0.0;
+      const _Float16 vh = static_cast<_Float16>(v);
+      hi[k] = vh;
+      lo[k] = static_cast<_Float16>(v - static_cast<double>(vh));
+    }
+  }
 }
 
 __global__ void copy_stats_kernel(int n_series, const SeriesHdr* __restrict__ hdr, double* __restrict__ l_base,
@@ -265,9 +313,10 @@ __global__ void copy_stats_kernel(int n_series, const SeriesHdr* __restrict__ hd
 
 hipError_t launch_prep(hipStream_t st, int n_series, const SeriesIn* sin, SeriesHdr* hdr, const double* t,
                        const double* x, const double* w, double* tau, double* xt, double* wt, double* rec,
-                       double* phi, float* g32, double* aux, int flags) {
+                       double* phi, float* g32, double* aux, void* b16, int flags) {
   if (n_series <= 0) return hipSuccess;
-  prep_kernel<<<n_series, BLOCK, 0, st>>>(sin, hdr, t, x, w, tau, xt, wt, rec, phi, g32, aux, flags);
+  prep_kernel<<<n_series, BLOCK, 0, st>>>(sin, hdr, t, x, w, tau, xt, wt, rec, phi, g32, aux,
+                                          static_cast<_Float16*>(b16), flags);
   return hipGetLastError();
 }
 

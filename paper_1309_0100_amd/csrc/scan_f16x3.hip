@@ -1,0 +1,374 @@
+// Residual periodogram scan, reduced-precision MFMA form with split float16
+// operands (eq. zpowrel with n = 1, Sects. 3, 5).
+//
+// The sums against the base columns, U = <q_k cos>, <q_k sin>, are the
+// (F x N) by (N x K) product of the generated trial columns with the weighted
+// orthonormal base columns, computed on the float16 matrix cores
+// (v_mfma_f32_16x16x32_f16, float32 accumulation) with every operand split
+// in two float16 parts, x = x_hi + x_lo, and three products per step:
+//   A B ~ A_hi B_hi + A_hi B_lo + A_lo B_hi,
+// which keeps about 22 significant bits of every product (the dropped
+// A_lo B_lo is below 2^-22 of it).  B = S w~ q_k with a power of two S per
+// series (the preparation kernel's float16 operand array, scaled so that its
+// low parts stay normal); U = D / S.  The float16 matrix cores have sixteen
+// times the float32 matrix rate, so the three products cost less than one
+// float32 step.
+//
+// Per wave: 16 FT consecutive grid frequencies over all samples of the
+// series; one MFMA step covers 16 frequencies x 32 samples.  The lane
+// (row = lane % 16, kb = lane / 16) generates A for its frequency row at the
+// eight samples 8 kb .. 8 kb + 7 of the step: the float32 complex product
+// eat[a][s] * bt[row][s] of two unit phasors that the block computes in
+// float64 per tile of 64 samples and rounds once (eat = e^{2 pi i (j0 + 1 +
+// 16 a) df tau_s}, a = the wave's 16-frequency tile; bt = e^{2 pi i row df
+// tau_s}).  The same lane accumulates, for its row and its samples,
+//   <cos^2>, <cos sin>  float32 per tile of 64 samples, then float64,
+//   h = <r_b cos>, <r_b sin>  float64 (the data column enters z linearly),
+// reduced over the four kb lanes at the end; <sin^2> = <1> - <cos^2>.  MFMA
+// accumulators are added into float32 running sums at the end of every tile
+// (U enters z only through U^T U in the Schur block).  The epilogue forms
+// U^T U per frequency from the accumulator layout (D[i][j] in lane j + 16
+// (i / 4), element i % 4) with cross-lane sums, without an LDS transpose.
+// Points where reduced precision loses accuracy (relative Schur pivot below
+// RHO_MIN, or l_{m+1} / l_m below LRATIO_MIN) are listed and re-scored in
+// float64 by rescore_kernel, as for the other reduced-precision forms.
+#include "fredec_internal.h"
+
+namespace fredec {
+
+namespace {
+
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int F16X3_TS = 64;  // samples per table tile (two MFMA steps of 32)
+
+// c = hi + lo with both parts float16: hi = c rounded toward zero (packed
+// conversion), lo = the remainder c - hi, which is exact in float32, rounded
+// to float16 by one mixed-precision multiply-add (v_fma_mix{lo,hi}_f16:
+// fma(hi, -1, c) with hi read as float16 and c as float32).
+__device__ __forceinline__ void split8(const float (&c)[8], v8h& hi, v8h& lo) {
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  u4v H, L;
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) {
+    const unsigned ph = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(c[e], c[e + 1]));
+    unsigned q;
+    asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(q) : "v"(ph), "v"(c[e]));
+    asm("v_fma_mixhi_f16 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(q) : "v"(ph), "v"(c[e + 1]));
+    H[e / 2] = ph;
+    L[e / 2] = q;
+  }
+  hi = __builtin_bit_cast(v8h, H);
+  lo = __builtin_bit_cast(v8h, L);
+}
+
+// The aux-record values of one sample that the tables need.
+struct SampleRec {
+  double tau, wt, gr, wc, ws;  // tau, w~, w~ r_b, cos and sin of 2 pi df tau
+};
+
+// Sample `sl` of the tile starting at i0 (neutral values beyond nts).
+__device__ __forceinline__ SampleRec fetch_rec(const double* __restrict__ aser, int64_t i0, int nts, int sl) {
+  SampleRec r{0.0, 0.0, 0.0, 1.0, 0.0};
+  if (sl < nts) {
+    const double* a = aser + (i0 + sl) * AUX_STRIDE;
+    r.tau = a[0];
+    r.wt = a[3];
+    r.gr = a[4];
+    r.wc = a[6];
+    r.ws = a[7];
+  }
+  return r;
+}
+
+// Tables of one tile of TS samples: eat[a][s] = e^{2 pi i fb tau_s} w_s^(16 a),
+// bt[b][s] = w_s^b (a, b < 16, w_s = e^{2 pi i df tau_s}), rounded to
+// float32; wts[s] = w~_s (float32), grs[s] = w~_s r_b(tau_s).  Samples
+// nts .. TS - 1 get zero entries, so that they contribute nothing.
+// BLOCK / TS threads per sample, each taking 16 TS / BLOCK values of a and of
+// b; rows a >= AMAX of eat are not used by the kernel and not written.
+template <int TS, int AMAX>
+__device__ __forceinline__ void build_tables(const SampleRec& r, int nts, double fb, float2* __restrict__ eat,
+                                             float2* __restrict__ bt, float* __restrict__ wts,
+                                             double* __restrict__ grs) {
+  constexpr int TPS = BLOCK / TS;  // threads per sample
+  constexpr int PER = 16 / TPS;    // values of a and of b per thread
+  constexpr int TSP = TS + 2;
+  static_assert(TPS * PER == 16, "tile size must divide the block");
+  const int sl = threadIdx.x / TPS, part = threadIdx.x % TPS;
+  const int eb = PER * part;
+  if (sl >= nts) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      if (eb + k < AMAX) eat[(eb + k) * TSP + sl] = float2{0.0f, 0.0f};
+      bt[(eb + k) * TSP + sl] = float2{0.0f, 0.0f};
+    }
+    if (part == 0) {
+      wts[sl] = 0.0f;
+      grs[sl] = 0.0;
+    }
+    return;
+  }
+  const double wc = r.wc, ws = r.ws;
+  const int ea = 16 * eb;  // exponent of w in the first eat entry of this thread
+  double pc = 1.0, ps = 0.0, ac = 1.0, as = 0.0, hc = 1.0, hs = 0.0;
+  double xc = wc, xs = ws;  // w^(2^k)
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (k == 4) {
+      hc = xc;
+      hs = xs;
+    }
+    if ((eb >> k) & 1) {
+      const double tc = __builtin_fma(pc, xc, -ps * xs);
+      ps = __builtin_fma(pc, xs, ps * xc);
+      pc = tc;
+    }
+    if ((ea >> k) & 1) {
+      const double tc = __builtin_fma(ac, xc, -as * xs);
+      as = __builtin_fma(ac, xs, as * xc);
+      ac = tc;
+    }
+    const double nc = __builtin_fma(xc, xc, -xs * xs);
+    xs = 2.0 * xc * xs;
+    xc = nc;
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    bt[(eb + k) * TSP + sl] = float2{static_cast<float>(pc), static_cast<float>(ps)};
+    const double nc = __builtin_fma(pc, wc, -ps * ws);
+    ps = __builtin_fma(ps, wc, pc * ws);
+    pc = nc;
+  }
+  if (part == 0) {
+    wts[sl] = static_cast<float>(r.wt);
+    grs[sl] = r.gr;
+  }
+  if (eb >= AMAX) return;
+  double es, ec;
+  sincos_rev(fb * r.tau, es, ec);
+  double vc = __builtin_fma(ec, ac, -es * as);
+  double vs = __builtin_fma(es, ac, ec * as);
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    if (eb + k < AMAX) eat[(eb + k) * TSP + sl] = float2{static_cast<float>(vc), static_cast<float>(vs)};
+    const double nc = __builtin_fma(vc, hc, -vs * hs);
+    vs = __builtin_fma(vs, hc, vc * hs);
+    vc = nc;
+  }
+}
+
+template <int NT, int FT, int TS>
+__global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __restrict__ work,
+                                                           const SeriesIn* __restrict__ sin_,
+                                                           const SeriesHdr* __restrict__ hdr,
+                                                           const double* __restrict__ aux,
+                                                           const v8h* __restrict__ b16,
+                                                           double* __restrict__ z_out, uint8_t* __restrict__ flags_out,
+                                                           Rescore* __restrict__ list,
+                                                           unsigned long long* __restrict__ count) {
+  static_assert(FT >= 1 && FT <= 4, "the epilogue gives one lane group per frequency tile");
+  static_assert(TS % 32 == 0 && BLOCK % TS == 0, "tiles hold whole MFMA steps");
+  constexpr int TSP = TS + 2;  // row length (float2) of the transposed tables
+  __shared__ float2 eat[4 * FT * TSP];
+  __shared__ float2 bt[16 * TSP];
+  __shared__ float wts[TS];
+  __shared__ double grs[TS];
+
+  const ScanWork wk = work[blockIdx.x];
+  const SeriesIn& si = sin_[wk.series];
+  const SeriesHdr& h = hdr[wk.series];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int row = lane & 15;  // frequency row of A, column of B and D
+  const int kb = lane >> 4;   // eight-sample block of the MFMA step
+  const int64_t N = si.N;
+  const int64_t F = si.F;
+  const int64_t jw = wk.j0 + static_cast<int64_t>(wave) * 16 * FT;
+  double* zs = z_out + si.goff;
+  uint8_t* fs = flags_out ? flags_out + si.goff : nullptr;
+  if (h.status != 0) {
+    for (int ft = 0; ft < FT; ++ft) {
+      const int64_t j = jw + ft * 16 + row;
+      if (kb == 0 && j < F) {
+        zs[j] = __builtin_nan("");
+        if (fs) fs[j] = FREDEC_FLAG_BADSERIES;
+      }
+    }
+    return;
+  }
+
+  v4f accc[FT][NT], accs[FT][NT];  // MFMA accumulators of the current tile
+  v4f uoc[FT][NT], uos[FT][NT];    // float32 running sums of the tile results
+  float cc32[FT], cs32[FT];
+  double cc[FT], cs[FT], hc[FT], hs[FT];
+#pragma unroll
+  for (int ft = 0; ft < FT; ++ft) {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      accc[ft][nt] = accs[ft][nt] = uoc[ft][nt] = uos[ft][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+    cc32[ft] = cs32[ft] = 0.0f;
+    cc[ft] = cs[ft] = hc[ft] = hs[ft] = 0.0;
+  }
+
+  const double fb = static_cast<double>(wk.j0 + 1) * si.df;
+  const double* __restrict__ aser = aux + si.aux_off;
+  const v8h* __restrict__ bser = b16 + si.b16_off;
+  const int slb = threadIdx.x / (BLOCK / TS);  // sample of this thread in the table build
+  for (int64_t i0 = 0; i0 < N; i0 += TS) {
+    const int nts = N - i0 < TS ? static_cast<int>(N - i0) : TS;
+    __syncthreads();
+    build_tables<TS, 4 * FT>(fetch_rec(aser, i0, nts, slb), nts, fb, eat, bt, wts, grs);
+    __syncthreads();
+    const int ng = (nts + 31) >> 5;
+    for (int gg = 0; gg < ng; ++gg) {
+      const int64_t g = (i0 >> 5) + gg;  // MFMA step of the series
+      v8h bh[NT], bl[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        bh[nt] = bser[((g * NT + nt) * 2) * 64 + lane];
+        bl[nt] = bser[((g * NT + nt) * 2 + 1) * 64 + lane];
+      }
+      const int s0 = 32 * gg + 8 * kb;  // first sample of this lane in the tile
+      float2 bv[8];
+      float w8[8];
+      double g8[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        bv[e] = bt[row * TSP + s0 + e];
+        w8[e] = wts[s0 + e];
+        g8[e] = grs[s0 + e];
+      }
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft) {
+        const int a = FT * wave + ft;
+        float c[8], s[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float2 ev = eat[a * TSP + s0 + e];
+          c[e] = __builtin_fmaf(ev.x, bv[e].x, -ev.y * bv[e].y);
+          s[e] = __builtin_fmaf(ev.y, bv[e].x, ev.x * bv[e].y);
+        }
+        v8h ch, cl, sh, sl;
+        split8(c, ch, cl);
+        split8(s, sh, sl);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          accc[ft][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ch, bh[nt], accc[ft][nt], 0, 0, 0);
+          accs[ft][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(sh, bh[nt], accs[ft][nt], 0, 0, 0);
+          accc[ft][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ch, bl[nt], accc[ft][nt], 0, 0, 0);
+          accs[ft][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(sh, bl[nt], accs[ft][nt], 0, 0, 0);
+          accc[ft][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(cl, bh[nt], accc[ft][nt], 0, 0, 0);
+          accs[ft][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(sl, bh[nt], accs[ft][nt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float wc = w8[e] * c[e];
+          cc32[ft] = __builtin_fmaf(wc, c[e], cc32[ft]);
+          cs32[ft] = __builtin_fmaf(wc, s[e], cs32[ft]);
+          hc[ft] = __builtin_fma(g8[e], static_cast<double>(c[e]), hc[ft]);
+          hs[ft] = __builtin_fma(g8[e], static_cast<double>(s[e]), hs[ft]);
+        }
+      }
+    }
+    // end of a tile: tile sums into the running sums
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        uoc[ft][nt] += accc[ft][nt];
+        uos[ft][nt] += accs[ft][nt];
+        accc[ft][nt] = accs[ft][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
+      cc[ft] += static_cast<double>(cc32[ft]);
+      cs[ft] += static_cast<double>(cs32[ft]);
+      cc32[ft] = cs32[ft] = 0.0f;
+    }
+  }
+
+  const double inv = h.b16_inv;  // 1 / S
+  const int c4 = lane & 15;      // in the epilogue: row 4 kb + c4 for c4 < 4
+#pragma unroll
+  for (int ft = 0; ft < FT; ++ft) {
+    // C block and h of frequency row `row`: sum over the four kb lanes
+    double v[4] = {cc[ft], cs[ft], hc[ft], hs[ft]};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] += __shfl_xor(v[q], 16);
+      v[q] += __shfl_xor(v[q], 32);
+    }
+    // U^T U of rows 4 kb + i (i < 4): this lane's columns 16 nt + row, then
+    // the sum over the 16 column lanes
+    double p[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      p[i][0] = p[i][1] = p[i][2] = 0.0;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const double uc = static_cast<double>(uoc[ft][nt][i]) * inv;
+        const double us = static_cast<double>(uos[ft][nt][i]) * inv;
+        p[i][0] = __builtin_fma(uc, uc, p[i][0]);
+        p[i][1] = __builtin_fma(uc, us, p[i][1]);
+        p[i][2] = __builtin_fma(us, us, p[i][2]);
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) p[i][q] += __shfl_xor(p[i][q], o);
+      }
+    }
+    // lane 16 kb + c4 (c4 < 4) finishes frequency row r = 4 kb + c4, whose
+    // C block and h sit in lane r
+    const int r = 4 * kb + (c4 & 3);
+    const double ccr = __shfl(v[0], r), csr = __shfl(v[1], r), hcr = __shfl(v[2], r), hsr = __shfl(v[3], r);
+    const int64_t j = jw + ft * 16 + r;
+    if (c4 < 4 && j < F) {
+      const int i = c4;
+      const double q0 = i == 0 ? p[0][0] : i == 1 ? p[1][0] : i == 2 ? p[2][0] : p[3][0];
+      const double q1 = i == 0 ? p[0][1] : i == 1 ? p[1][1] : i == 2 ? p[2][1] : p[3][1];
+      const double q2 = i == 0 ? p[0][2] : i == 1 ? p[1][2] : i == 2 ? p[2][2] : p[3][2];
+      const double ss = h.W1 - ccr;
+      const double Scc = ccr - q0, Scs = csr - q1, Sss = ss - q2;
+      double z;
+      uint8_t fl;
+      double lratio;
+      schur_finish(Scc, Scs, Sss, ccr, ss, hcr, hsr, static_cast<double>(j + 1) * si.df, si, h, z, fl, &lratio);
+      const double l21 = Scs / sqrt(fmax(Scc, 1e-300));
+      const double rho = fmin(Scc / ccr, (Sss - l21 * l21) / ss);
+      if (!(fl & FREDEC_FLAG_MASKED) && (!(rho >= RHO_MIN) || !(lratio >= LRATIO_MIN))) {
+        const unsigned long long slot = atomicAdd(count, 1ull);
+        list[slot] = Rescore{wk.series, 0, j};
+      }
+      zs[j] = z;
+      if (fs) fs[j] = fl;
+    }
+  }
+}
+
+template <int NT>
+hipError_t launch_nt(hipStream_t st, int n_work, const ScanWork* work, const SeriesIn* sin, const SeriesHdr* hdr,
+                     const double* aux, const void* b16, double* z, uint8_t* flags, Rescore* list,
+                     unsigned long long* count) {
+  scan_f16x3_kernel<NT, f16x3_freq_tiles(NT), F16X3_TS><<<n_work, BLOCK, 0, st>>>(
+      work, sin, hdr, aux, static_cast<const v8h*>(b16), z, flags, list, count);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_scan_f16x3(hipStream_t st, int NT, int n_work, const ScanWork* work, const SeriesIn* sin,
+                             const SeriesHdr* hdr, const double* aux, const void* b16, double* z, uint8_t* flags,
+                             Rescore* list, unsigned long long* count) {
+  if (n_work <= 0) return hipSuccess;
+  switch (NT) {
+    case 1: return launch_nt<1>(st, n_work, work, sin, hdr, aux, b16, z, flags, list, count);
+    case 2: return launch_nt<2>(st, n_work, work, sin, hdr, aux, b16, z, flags, list, count);
+    case 3: return launch_nt<3>(st, n_work, work, sin, hdr, aux, b16, z, flags, list, count);
+    case 4: return launch_nt<4>(st, n_work, work, sin, hdr, aux, b16, z, flags, list, count);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fredec

@@ -3,22 +3,31 @@
 //
 // Same layout as the float64 scan: one lane owns R grid frequencies
 // f_{j0+t+256r}, the per-sample records are uniform across the block and read
-// as scalars, and the phasor of the lane's first frequency is E0 A_a B_b from
-// the block's LDS tables (float64), rotated in float64 to the other R-1.
-// The arithmetic per (frequency, sample) pair differs:
-//   cos, sin                 rounded to float32 after the float64 phasor;
-//   U_c[k], U_s[k] = <q_k cos>, <q_k sin>, and <cos^2>, <cos sin>
-//                            float32 multiply-adds against float32 copies of
-//                            the weighted columns (w~ q_k, w~), added into
-//                            float64 totals at the end of every 64-sample tile;
-//   h = <r_b cos>, <r_b sin> float64 (the data column enters z linearly);
+// as scalars.  The inner loop runs in float32 except for the data column:
+//   phasor      the float32 complex product eat[s][a][r] * bt[s][b] of two
+//               unit phasors computed in float64 by the block and rounded
+//               once (the tables of build_phasor_tables32), so no rotation
+//               chain accumulates rounding;
+//   U_c[k], U_s[k] = <q_k cos>, <q_k sin>
+//               float32 multiply-adds against a float32 copy of the weighted
+//               columns w~ q_k, summed per tile of TS samples and the tile
+//               sums added in float32 (they enter z only through U^T U in the
+//               Schur block, where a relative error e moves z by about
+//               2 e |U|^2 / S: small wherever the trial columns are not close
+//               to the base span, and those points are re-scored);
+//   <cos^2>, <cos sin>
+//               float32 per tile, tile sums added in float64;
+//   h = <r_b cos>, <r_b sin>
+//               float64 multiply-adds of the float32 phasor (the data column
+//               enters z linearly, and float32 accumulation of it costs
+//               several 1e-7 in z at N = 10^4);
 //   <sin^2> = <1> - <cos^2>.
-// On this GPU a float32 VALU multiply-add costs half a float64 one and runs
-// at the float32 matrix-core rate (which it does not overlap), so the 2K + 2
-// float32 sums cost what K + 1 float64 ones do.  Grid points where float32
-// loses accuracy - relative Schur pivot of the trial columns below RHO_MIN,
-// or l_{m+1} / l_m below LRATIO_MIN - are listed and re-scored in float64 by
-// rescore_kernel, exactly as for the MFMA form.
+// Non-packed float32 VALU instructions issue at twice the float64 rate when
+// at least two waves per SIMD issue them, so R is chosen to keep the
+// accumulators within about 128 VGPRs (four waves per SIMD).  Grid points
+// where float32 loses accuracy - relative Schur pivot of the trial columns
+// below RHO_MIN, or l_{m+1} / l_m below LRATIO_MIN - are listed and re-scored
+// in float64 by rescore_kernel, as for the MFMA form.
 #include "fredec_internal.h"
 #include "scan_phasor.h"
 
@@ -26,12 +35,17 @@ namespace fredec {
 
 namespace {
 
-// Frequencies per lane: R (6 KP + 4) accumulator registers (float32 sums,
-// their float64 totals, the float64 data column) within about 128 VGPRs.
+// Frequencies per lane: R (4 K + 10) accumulator registers (float32 tile and
+// running sums of U, float32 tile sums of C, float64 C and h) within about
+// 96 VGPRs, leaving room for the operands below 128.
 constexpr int R32_of(int KP) {
-  int r = 128 / (6 * KP + 4);
+  int r = 96 / (4 * KP + 6);
   return r < 1 ? 1 : (r > 8 ? 8 : r);
 }
+
+// Samples per phasor-table tile: 64 for R <= 2, else 32 (LDS of a block
+// TS 16 (R + 1) 8 bytes <= 29 KB, four blocks per CU).
+constexpr int TS32_of(int R) { return R <= 2 ? 64 : 32; }
 
 template <int KP, int R>
 __global__ __launch_bounds__(BLOCK) void scan_f32_kernel(const ScanWork* __restrict__ work,
@@ -44,6 +58,7 @@ __global__ __launch_bounds__(BLOCK) void scan_f32_kernel(const ScanWork* __restr
                                                          unsigned long long* __restrict__ count) {
   constexpr int K = KP - 1;
   constexpr int P = rec_stride(KP);
+  constexpr int TS = TS32_of(R);
   const ScanWork wk = work[blockIdx.x];
   const SeriesIn& si = sin_[wk.series];
   const SeriesHdr& h = hdr[wk.series];
@@ -65,32 +80,32 @@ __global__ __launch_bounds__(BLOCK) void scan_f32_kernel(const ScanWork* __restr
     }
     return;
   }
-  // float32 tile sums: U_c[k], U_s[k] (k < K), <cos^2>, <cos sin>
-  float uc[R][K], us[R][K], cc32[R], cs32[R];
-  // float64 totals and the float64 data column
-  double Uc[R][K], Us[R][K], cc[R], cs[R], hc[R], hs[R];
+  float uc[R][K], us[R][K];  // tile sums of U
+  float Uc[R][K], Us[R][K];  // running sums of the tile sums
+  float cc32[R], cs32[R];    // tile sums of <cos^2>, <cos sin>
+  double cc[R], cs[R], hc[R], hs[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      uc[r][k] = us[r][k] = 0.0f;
-      Uc[r][k] = Us[r][k] = 0.0;
-    }
+    for (int k = 0; k < K; ++k) uc[r][k] = us[r][k] = Uc[r][k] = Us[r][k] = 0.0f;
     cc32[r] = cs32[r] = 0.0f;
     cc[r] = cs[r] = hc[r] = hs[r] = 0.0;
   }
 
-  constexpr int TS = 64;  // samples per table tile (and per float32 partial sum)
-  __shared__ double2 eash[TS][16];
-  __shared__ double2 bsh[TS][16];
-  const int ta_ = threadIdx.x >> 4, tb_ = threadIdx.x & 15;
+  __shared__ float2 eat[TS * 16 * R];
+  __shared__ float2 bt[TS * 16];
+  const int ta = threadIdx.x >> 4, tb = threadIdx.x & 15;
+  // a zero in a VGPR that the compiler cannot fold: g[k] + zv is a copy of
+  // the scalar g[k] into a vector register
+  float zv;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(zv));
   const double fb = static_cast<double>(wk.j0 + 1) * df;
   const double* __restrict__ q0 = rec + si.rec_off;
   const float* __restrict__ g0 = g32 + si.g32_off;
   for (int64_t i0 = 0; i0 < N; i0 += TS) {
     const int nts = N - i0 < TS ? static_cast<int>(N - i0) : TS;
     __syncthreads();
-    build_phasor_tables<KP>(q0 + i0 * P, P, nts, fb, eash, bsh);
+    build_phasor_tables32<KP, R, TS>(q0 + i0 * P, P, nts, fb, eat, bt);
     __syncthreads();
     const double* __restrict__ q = q0 + i0 * P;
     const float* __restrict__ g = g0 + i0 * GW;
@@ -98,40 +113,37 @@ __global__ __launch_bounds__(BLOCK) void scan_f32_kernel(const ScanWork* __restr
     // together, so one wait covers them
 #pragma unroll 4
     for (int sl = 0; sl < nts; ++sl, q += P, g += GW) {
-      const double2 ea = eash[sl][ta_];
-      const double2 bb = bsh[sl][tb_];
-      double c = __builtin_fma(ea.x, bb.x, -ea.y * bb.y);
-      double s = __builtin_fma(ea.y, bb.x, ea.x * bb.y);
-      const double rc = q[1], rs = q[2];
+      const float2 bv = bt[sl * 16 + tb];
       const double gr = q[3 + K];  // w~ r_b
-      const float wf = g[K];       // w~
+      // the sample's float32 columns (w~ q_k, then w~) copied into VGPRs:
+      // one scalar-operand read per value instead of 2R
+      float gv[K + 1];
+#pragma unroll
+      for (int k = 0; k <= K; ++k) gv[k] = g[k] + zv;
+      const float wf = gv[K];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if (r) {
-          const double cn = __builtin_fma(c, rc, -s * rs);
-          s = __builtin_fma(s, rc, c * rs);
-          c = cn;
-        }
-        const float cf = static_cast<float>(c), sf = static_cast<float>(s);
+        const float2 e = eat[(sl * 16 + ta) * R + r];
+        const float c = __builtin_fmaf(e.x, bv.x, -e.y * bv.y);
+        const float s = __builtin_fmaf(e.y, bv.x, e.x * bv.y);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          uc[r][k] = __builtin_fmaf(g[k], cf, uc[r][k]);
-          us[r][k] = __builtin_fmaf(g[k], sf, us[r][k]);
+          uc[r][k] = __builtin_fmaf(gv[k], c, uc[r][k]);
+          us[r][k] = __builtin_fmaf(gv[k], s, us[r][k]);
         }
-        const float wc = wf * cf;
-        cc32[r] = __builtin_fmaf(wc, cf, cc32[r]);
-        cs32[r] = __builtin_fmaf(wc, sf, cs32[r]);
-        hc[r] = __builtin_fma(gr, c, hc[r]);
-        hs[r] = __builtin_fma(gr, s, hs[r]);
+        const float wc = wf * c;
+        cc32[r] = __builtin_fmaf(wc, c, cc32[r]);
+        cs32[r] = __builtin_fmaf(wc, s, cs32[r]);
+        hc[r] = __builtin_fma(gr, static_cast<double>(c), hc[r]);
+        hs[r] = __builtin_fma(gr, static_cast<double>(s), hs[r]);
       }
     }
-    // float32 tile sums into the float64 totals
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        Uc[r][k] += static_cast<double>(uc[r][k]);
-        Us[r][k] += static_cast<double>(us[r][k]);
+        Uc[r][k] += uc[r][k];
+        Us[r][k] += us[r][k];
         uc[r][k] = us[r][k] = 0.0f;
       }
       cc[r] += static_cast<double>(cc32[r]);
@@ -147,9 +159,10 @@ __global__ __launch_bounds__(BLOCK) void scan_f32_kernel(const ScanWork* __restr
     double Scc = cc[r], Scs = cs[r], Sss = ss;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      Scc = __builtin_fma(-Uc[r][k], Uc[r][k], Scc);
-      Scs = __builtin_fma(-Uc[r][k], Us[r][k], Scs);
-      Sss = __builtin_fma(-Us[r][k], Us[r][k], Sss);
+      const double u = static_cast<double>(Uc[r][k]), v = static_cast<double>(Us[r][k]);
+      Scc = __builtin_fma(-u, u, Scc);
+      Scs = __builtin_fma(-u, v, Scs);
+      Sss = __builtin_fma(-v, v, Sss);
     }
     double z;
     uint8_t fl;

@@ -24,6 +24,7 @@ FP32 = 1
 OK, EINVAL, EDOF, EWEIGHT, EDEGEN, ESINGULAR, ENOMEM, EDEVICE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7, -8
 TILE_SCAN_MFMA = 1
 TILE_SCAN_F32_FORM = 2
+F32_FORM_VALU, F32_FORM_MFMA32, F32_FORM_F16X3, F32_FORM_AUTO = 0, 1, 2, 3
 FLAG_MASKED, FLAG_SINGULAR, FLAG_PERFECT, FLAG_DEGENERATE, FLAG_BADSERIES = 1, 2, 4, 8, 128
 FLAG_CONVERGED, FLAG_RESCORED = 16, 64
 

@@ -1,7 +1,8 @@
 """GPU parity of the reduced-precision residual scan (float32 sums against
 the base columns, float64 phase reduction, phasors, data column and solves)
-against the float64 oracle, for both kernels of that form: the VALU kernel
-(default for m <= 12) and the MFMA kernel.
+against the float64 oracle, for each kernel family of that form: float32
+VALU sums (m <= 12), float32 matrix cores, and float16 matrix cores on split
+operands (the default).
 
 Bound (relative error err = |z - z_ref| / max(z_ref, 1)): 1e-6 on every grid
 frequency that the oracle does not flag.  Grid points whose trial columns lie
@@ -21,14 +22,17 @@ pytestmark = pytest.mark.gpu
 TOL32 = 1e-6
 
 
-@pytest.fixture(scope="module", params=[0, 1], ids=["valu", "mfma"])
+FORMS = {0: "valu", 1: "mfma32", 2: "f16x3"}
+
+
+@pytest.fixture(scope="module", params=list(FORMS), ids=list(FORMS.values()))
 def ctx(request):
     import torch
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     from paper_1309_0100_amd import fredec as F
     c = F.Context(0)
     c.set_tile(F.TILE_SCAN_F32_FORM, 0, request.param)
-    print(f"float32 form: {request.param_index and 'mfma' or 'valu'}", flush=True)
+    print(f"float32 form: {FORMS[request.param]}", flush=True)
     return c
 
 
