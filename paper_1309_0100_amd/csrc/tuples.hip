@@ -10,7 +10,8 @@
 //                    Fisher matrix Q_f of the frequencies follows (eqs. avrg1, avrg2).
 // Each lane of an MFMA step owns one (column, sample) pair; A = column values,
 // B = w~ * column values, so D accumulates the Gram block by block (lower
-// triangle of 16x16 blocks only).
+// triangle of 16x16 blocks only).  The sin/cos of each (frequency, sample) is
+// evaluated once per step by one lane and shared through LDS.
 // tuple_solve_kernel: one thread per tuple, float64: Cholesky of the model
 // block, l, theta*, z, and the Gauss-Newton step with the step control shared
 // with the oracle (clamp, accept/halve, tolerance).
@@ -20,8 +21,8 @@
 // (C(C+1)/2 multiply-adds per sample, C = 2n + 2) is accumulated, and the L
 // partial Gram matrices are added with cross-lane permutations.  For these
 // sizes this does less work than the MFMA kernel, whose 16-column blocks are
-// mostly padding and whose lanes each evaluate a sin/cos for a single column
-// (float64 MFMA and float64 VALU have the same peak rate on this chip).  L is
+// mostly padding (float64 MFMA and float64 VALU have the same peak rate on
+// this chip).  L is
 // chosen per launch so that a group of tuples fills the GPU.
 // tuple_adjoint_kernel (any n, one wavefront per tuple, samples over lanes)
 // and tuple_adjoint_lanes_kernel<n, L> (n <= 6, L lanes per tuple): recompute
@@ -38,41 +39,38 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// sin(2 pi p) for a phase p in revolutions (float64), by the reduction and
-// polynomials of sincos_rev; cos is obtained as sin(2 pi (p + 1/4)).
-__device__ __forceinline__ double sin_rev(double p) {
-  double s, c;
-  sincos_rev(p, s, c);
-  return s;
-}
-
-// Column descriptor of one lane for one 16-column block.
-struct ColDesc {
-  double f;      // frequency of a trig column
-  double shift;  // 0 (sin) or 1/4 (cos)
-  int kind;      // 0 zero, 1 one, 2 trig, 3 data, 4 t' * trig
+// Column of one lane for one 16-column block: kind 0 zero, 1 one, 2 trig,
+// 3 data, 4 t' * trig; kf = the frequency of a trig column, sel = 0 cos, 1 sin.
+struct ColSel {
+  int kind, kf, sel;
 };
 
-__device__ __forceinline__ ColDesc col_desc(int col, int n, int mode, const double* f) {
-  ColDesc d{0.0, 0.0, 0};
+__device__ __forceinline__ ColSel col_sel(int col, int n, int mode) {
+  ColSel d{0, 0, 0};
   const int K = 2 * n + 1;
   if (col == 0) {
     d.kind = 1;
   } else if (col < K) {
     d.kind = 2;
-    d.f = f[(col - 1) >> 1];
-    d.shift = ((col - 1) & 1) ? 0.0 : 0.25;
+    d.kf = (col - 1) >> 1;
+    d.sel = (col - 1) & 1;
   } else if (col == K) {
     d.kind = 3;
   } else if (mode == TUPLE_GN && col < 4 * n + 2) {
     const int c2 = col - K - 1;
     d.kind = 4;
-    d.f = f[c2 >> 1];
-    d.shift = (c2 & 1) ? 0.0 : 0.25;
+    d.kf = c2 >> 1;
+    d.sel = c2 & 1;
   }
   return d;
 }
 
+// One wavefront per tuple.  Per step of four samples, lane (c16, kq) first
+// evaluates cos and sin of the frequencies c16, c16 + 16, ... at sample kq
+// (one float64 sin/cos pair per frequency and sample, shared through a
+// wave-private LDS table), then reads the value of its own column for each
+// 16-column block, and the wave accumulates the lower-triangle blocks of the
+// Gram on float64 MFMA.
 template <int NB>
 __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __restrict__ desc,
                                                            const int32_t* __restrict__ order, int n_order,
@@ -82,6 +80,8 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
                                                            const double* __restrict__ ftry,
                                                            const TupleState* __restrict__ state,
                                                            double* __restrict__ gram, int mode) {
+  constexpr int NRMAX = (NB + 1) / 2;  // frequencies per lane: n <= 8 NB - 1 columns' worth
+  __shared__ double2 trig[BLOCK / 64][4][16 * NRMAX];
   const int wave = (blockIdx.x * BLOCK + threadIdx.x) >> 6;
   if (wave >= n_order) return;
   const int lane = threadIdx.x & 63;
@@ -93,9 +93,14 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
   const double* f = ftry + d.foff;
   const int c16 = lane & 15;
   const int kq = lane >> 4;
-  ColDesc cd[NB];
+  const int nr = (n + 15) >> 4;
+  double fk[NRMAX];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) cd[b] = col_desc(16 * b + c16, n, mode, f);
+  for (int r = 0; r < NRMAX; ++r) fk[r] = (c16 + 16 * r < n) ? f[c16 + 16 * r] : 0.0;
+  ColSel cd[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) cd[b] = col_sel(16 * b + c16, n, mode);
+  double2(*tw)[16 * NRMAX] = trig[threadIdx.x >> 6];
   const double inv_sig = com->inv_sigma_t;
   constexpr int NTILE = NB * (NB + 1) / 2;
   v4d acc[NTILE];
@@ -108,20 +113,32 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
     const double ta = in ? tau[i] : 0.0;
     const double xi = in ? xt[i] : 0.0;
     const double wi = in ? wt[i] : 0.0;
+#pragma unroll
+    for (int r = 0; r < NRMAX; ++r) {
+      if (r < nr) {
+        double sv, cv;
+        sincos_rev(fk[r] * ta, sv, cv);
+        tw[kq][c16 + 16 * r] = double2{cv, sv};
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
     double a[NB], bw[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      double v;
-      switch (cd[b].kind) {
-        case 1: v = 1.0; break;
-        case 2: v = sin_rev(cd[b].f * ta + cd[b].shift); break;
-        case 3: v = xi; break;
-        case 4: v = ta * inv_sig * sin_rev(cd[b].f * ta + cd[b].shift); break;
-        default: v = 0.0;
+      double v = 0.0;
+      if (cd[b].kind == 1) {
+        v = 1.0;
+      } else if (cd[b].kind == 3) {
+        v = xi;
+      } else if (cd[b].kind != 0) {
+        const double2 cs = tw[kq][cd[b].kf];
+        v = cd[b].sel ? cs.y : cs.x;
+        if (cd[b].kind == 4) v *= ta * inv_sig;
       }
       a[b] = v;
       bw[b] = wi * v;
     }
+    __builtin_amdgcn_wave_barrier();
     int q = 0;
 #pragma unroll
     for (int b1 = 0; b1 < NB; ++b1)
