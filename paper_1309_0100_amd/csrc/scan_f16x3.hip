@@ -28,7 +28,7 @@
 // accumulators are added into float32 running sums at the end of every tile
 // (U enters z only through U^T U in the Schur block).  The epilogue forms
 // U^T U per frequency from the accumulator layout (D[i][j] in lane j + 16
-// (i / 4), element i % 4) with cross-lane sums, without an LDS transpose.
+// (i / 4), element i % 4) with cross-lane sums.
 // Points where reduced precision loses accuracy (relative Schur pivot below
 // RHO_MIN, or l_{m+1} / l_m below LRATIO_MIN) are listed and re-scored in
 // float64 by rescore_kernel, as for the other reduced-precision forms.
@@ -61,6 +61,21 @@ __device__ __forceinline__ void split8(const float (&c)[8], v8h& hi, v8h& lo) {
   }
   hi = __builtin_bit_cast(v8h, H);
   lo = __builtin_bit_cast(v8h, L);
+}
+
+// Sum over the 16 lanes of a DPP row, left in every lane of the row: quad
+// permutations (lane ^ 1, lane ^ 2), then the half-row and row mirrors.  All
+// lanes add the same pairs, so they hold the same value.
+template <int CTRL>
+__device__ __forceinline__ float dpp_plus(float v) {
+  return v + __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float row_sum16(float v) {
+  v = dpp_plus<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = dpp_plus<0x4E>(v);   // quad_perm [2,3,0,1]
+  v = dpp_plus<0x141>(v);  // row_half_mirror
+  return dpp_plus<0x140>(v);  // row_mirror
 }
 
 // The aux-record values of one sample that the tables need.
@@ -171,10 +186,16 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
   static_assert(FT >= 1 && FT <= 4, "the epilogue gives one lane group per frequency tile");
   static_assert(TS % 32 == 0 && BLOCK % TS == 0, "tiles hold whole MFMA steps");
   constexpr int TSP = TS + 2;  // row length (float2) of the transposed tables
-  __shared__ float2 eat[4 * FT * TSP];
-  __shared__ float2 bt[16 * TSP];
-  __shared__ float wts[TS];
-  __shared__ double grs[TS];
+  // LDS: the tables during the sample loop; the epilogue reuses the memory
+  // for the per-frequency sums (EPF doubles per frequency)
+  constexpr int EPF = 7;
+  constexpr int TAB_DOUBLES = (4 * FT + 16) * TSP + TS / 2 + TS;
+  constexpr int EP_DOUBLES = (BLOCK / 64) * 16 * FT * EPF;
+  __shared__ double lds[TAB_DOUBLES > EP_DOUBLES ? TAB_DOUBLES : EP_DOUBLES];
+  float2* eat = reinterpret_cast<float2*>(lds);
+  float2* bt = eat + 4 * FT * TSP;
+  float* wts = reinterpret_cast<float*>(bt + 16 * TSP);
+  double* grs = reinterpret_cast<double*>(wts + TS);
 
   const ScanWork wk = work[blockIdx.x];
   const SeriesIn& si = sin_[wk.series];
@@ -288,53 +309,63 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
     }
   }
 
-  const double inv = h.b16_inv;  // 1 / S
-  const int c4 = lane & 15;      // in the epilogue: row 4 kb + c4 for c4 < 4
+  // Epilogue.  Per frequency row: <cos^2>, <cos sin>, h summed over the four
+  // kb lanes (shuffles); U^T U = sum over the 16 column lanes of this lane's
+  // products, in float32 (a relative error e of U^T U moves S by e |U|^2,
+  // well below the float32 bound where the point is not re-scored) with DPP
+  // row sums.  The seven sums of every frequency go to LDS, and one lane per
+  // frequency finishes it.
+  const double inv2 = h.b16_inv * h.b16_inv;  // 1 / S^2
+  __syncthreads();  // every wave is done with the tables
+  double* ep = lds + wave * 16 * FT * EPF;
 #pragma unroll
   for (int ft = 0; ft < FT; ++ft) {
-    // C block and h of frequency row `row`: sum over the four kb lanes
     double v[4] = {cc[ft], cs[ft], hc[ft], hs[ft]};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       v[q] += __shfl_xor(v[q], 16);
       v[q] += __shfl_xor(v[q], 32);
     }
-    // U^T U of rows 4 kb + i (i < 4): this lane's columns 16 nt + row, then
-    // the sum over the 16 column lanes
-    double p[4][3];
+    float p[4][3];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      p[i][0] = p[i][1] = p[i][2] = 0.0;
+      p[i][0] = p[i][1] = p[i][2] = 0.0f;
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        const double uc = static_cast<double>(uoc[ft][nt][i]) * inv;
-        const double us = static_cast<double>(uos[ft][nt][i]) * inv;
-        p[i][0] = __builtin_fma(uc, uc, p[i][0]);
-        p[i][1] = __builtin_fma(uc, us, p[i][1]);
-        p[i][2] = __builtin_fma(us, us, p[i][2]);
+        const float uc = uoc[ft][nt][i], us = uos[ft][nt][i];
+        p[i][0] = __builtin_fmaf(uc, uc, p[i][0]);
+        p[i][1] = __builtin_fmaf(uc, us, p[i][1]);
+        p[i][2] = __builtin_fmaf(us, us, p[i][2]);
       }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) p[i][q] = row_sum16(p[i][q]);
+    }
+    // row = lane & 15 holds the C block and h of frequency row `row`;
+    // lane 16 kb + i (i < 4) the U^T U sums of row 4 kb + i
+    if (kb == 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ep[(ft * 16 + row) * EPF + 3 + q] = v[q];
+    }
+    if (row < 4) {
+      const int r = 4 * kb + row;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) p[i][q] += __shfl_xor(p[i][q], o);
+        const float pq = row == 0 ? p[0][q] : row == 1 ? p[1][q] : row == 2 ? p[2][q] : p[3][q];
+        ep[(ft * 16 + r) * EPF + q] = static_cast<double>(pq) * inv2;
       }
     }
-    // lane 16 kb + c4 (c4 < 4) finishes frequency row r = 4 kb + c4, whose
-    // C block and h sit in lane r
-    const int r = 4 * kb + (c4 & 3);
-    const double ccr = __shfl(v[0], r), csr = __shfl(v[1], r), hcr = __shfl(v[2], r), hsr = __shfl(v[3], r);
-    const int64_t j = jw + ft * 16 + r;
-    if (c4 < 4 && j < F) {
-      const int i = c4;
-      const double q0 = i == 0 ? p[0][0] : i == 1 ? p[1][0] : i == 2 ? p[2][0] : p[3][0];
-      const double q1 = i == 0 ? p[0][1] : i == 1 ? p[1][1] : i == 2 ? p[2][1] : p[3][1];
-      const double q2 = i == 0 ? p[0][2] : i == 1 ? p[1][2] : i == 2 ? p[2][2] : p[3][2];
-      const double ss = h.W1 - ccr;
-      const double Scc = ccr - q0, Scs = csr - q1, Sss = ss - q2;
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane < 16 * FT) {
+    const double* e = ep + lane * EPF;
+    const int64_t j = jw + lane;
+    if (j < F) {
+      const double ccr = e[3], csr = e[4], ss = h.W1 - ccr;
+      const double Scc = ccr - e[0], Scs = csr - e[1], Sss = ss - e[2];
       double z;
       uint8_t fl;
       double lratio;
-      schur_finish(Scc, Scs, Sss, ccr, ss, hcr, hsr, static_cast<double>(j + 1) * si.df, si, h, z, fl, &lratio);
+      schur_finish(Scc, Scs, Sss, ccr, ss, e[5], e[6], static_cast<double>(j + 1) * si.df, si, h, z, fl, &lratio);
       const double l21 = Scs / sqrt(fmax(Scc, 1e-300));
       const double rho = fmin(Scc / ccr, (Sss - l21 * l21) / ss);
       if (!(fl & FREDEC_FLAG_MASKED) && (!(rho >= RHO_MIN) || !(lratio >= LRATIO_MIN))) {
