@@ -74,7 +74,7 @@ namespace {
 
 struct ScanLayout {
   size_t off_sin = 0, off_hdr = 0, off_work = 0, off_tau = 0, off_xt = 0, off_wt = 0, off_rec = 0, off_phi = 0;
-  size_t off_g32 = 0, off_aux = 0, off_b16 = 0, off_list = 0, off_count = 0;
+  size_t off_g32 = 0, off_aux = 0, off_b16 = 0, off_list = 0, off_count = 0, off_chunk = 0;
   size_t total = 0;
   int64_t Ntot = 0, rec_total = 0, phi_total = 0, g32_total = 0, aux_total = 0, b16_total = 0, n_work = 0,
           F_total = 0;
@@ -140,7 +140,8 @@ int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, cons
   L.off_aux = take(sizeof(double) * L.aux_total);
   L.off_b16 = take(16 * L.b16_total);
   L.off_list = take(precision == FREDEC_FP32 ? sizeof(Rescore) * L.F_total : 0);
-  L.off_count = take(sizeof(unsigned long long));
+  L.off_count = take(sizeof(unsigned long long) * n_series);
+  L.off_chunk = take(precision == FREDEC_FP32 ? sizeof(int64_t) * (n_series + 1) : 0);
   L.total = off;
   return FREDEC_OK;
 }
@@ -243,6 +244,13 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
     if (key(a) != key(b)) return key(a) < key(b);
     return sin[a].N > sin[b].N;
   });
+  for (int32_t s = 0; s < n_series; ++s) {
+    const int kd = kind(s);
+    sin[s].outputs = kd == ScanPlan::F32     ? PREP_G32
+                     : kd == ScanPlan::MFMA  ? PREP_G32 | PREP_AUX
+                     : kd == ScanPlan::F16X3 ? PREP_AUX | PREP_F16
+                                             : 0;
+  }
   P.work.clear();
   P.work.reserve(L.n_work);
   P.groups.clear();
@@ -288,14 +296,14 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const double
   void* d_b16 = at<char>(ws, L.off_b16);
   Rescore* d_list = at<Rescore>(ws, L.off_list);
   unsigned long long* d_count = at<unsigned long long>(ws, L.off_count);
+  int64_t* d_chunk = at<int64_t>(ws, L.off_chunk);
   const bool f32 = P.precision == FREDEC_FP32;
   // soff is absolute into t/x/w; the normalised copies use the same indexing
   // shifted by soff[0] (the batch is contiguous).
   const int64_t base_off = P.base_off;
-  bool any_f16x3 = false;
-  for (const auto& gr : P.groups) any_f16x3 |= gr.kind == ScanPlan::F16X3;
-  const int flags = PREP_BASE | PREP_REC64 | (f32 ? PREP_F32 : 0) | (any_f16x3 ? PREP_F16 : 0);
-  if (f32 && launch_zero_u64(st, d_count, 1) != hipSuccess) return FREDEC_EDEVICE;
+  // per series, the prep kernel writes only what its scan kernel reads (SeriesIn::outputs)
+  const int flags = PREP_BASE | PREP_REC64 | PREP_G32 | PREP_AUX | PREP_F16;
+  if (f32 && launch_zero_u64(st, d_count, P.n_series) != hipSuccess) return FREDEC_EDEVICE;
   if (launch_prep(st, P.n_series, d_sin, d_hdr, t, x, w, d_tau - base_off, d_xt - base_off, d_wt - base_off, d_rec,
                   d_phi, d_g32, d_aux, d_b16, flags) != hipSuccess)
     return FREDEC_EDEVICE;
@@ -318,7 +326,8 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const double
       if (err != hipSuccess) return FREDEC_EDEVICE;
     }
   }
-  if (f32 && launch_rescore(st, L.max_nt, 4 * std::max(ctx->n_cu, 1), d_sin, d_hdr, d_rec, d_list, d_count, z_out,
+  if (f32 && launch_rescore(st, L.max_nt, 4 * std::max(ctx->n_cu, 1), P.n_series, d_sin, d_hdr, d_rec, d_list,
+                            d_count, d_chunk, z_out,
                             flags_out) != hipSuccess)
     return FREDEC_EDEVICE;
   if (launch_copy_stats(st, P.n_series, d_hdr, d_sin, l_base_out, status_out, nullptr) != hipSuccess)

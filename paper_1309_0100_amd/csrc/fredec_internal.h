@@ -38,7 +38,7 @@ struct SeriesIn {
   int32_t m;        // base frequencies
   int32_t KP;       // 2m + 2 columns: orthonormal base columns q_0..q_{2m}, residual r_b
   int32_t NT;       // 16-column tiles of the MFMA operand (K = KP - 1 base columns)
-  int32_t pad;
+  int32_t outputs;  // PREP_* operand sets the scan kernel of this series reads
   double base_f[MAXM];
 };
 
@@ -69,7 +69,13 @@ struct Rescore {
 };
 
 // Outputs requested from the preparation kernel.
-enum PrepFlags { PREP_BASE = 1, PREP_REC64 = 2, PREP_F32 = 4, PREP_F16 = 8 };
+enum PrepFlags {
+  PREP_BASE = 1,   // base-model precomputation (otherwise only the normalised series)
+  PREP_REC64 = 2,  // float64 records (float64 scan, float32 VALU scan, re-scoring)
+  PREP_G32 = 4,    // float32 column copy g32 (float32 VALU and MFMA scans)
+  PREP_AUX = 8,    // aux records (float32 MFMA and split-float16 scans)
+  PREP_F16 = 16    // split float16 operand b16
+};
 
 // float64 scan record per sample: tau, cos/sin(2 pi 256 df tau), the KP
 // weighted columns, cos/sin(2 pi df tau); padded to an even count
@@ -113,6 +119,30 @@ __device__ __forceinline__ void sincos_rev(double p, double& s, double& c) {
   const double cc = (iq & 1) ? sp : cp;
   s = (iq & 2) ? -ss : ss;
   c = (iq == 1 || iq == 2) ? -cc : cc;
+}
+
+// Sum of v over aligned groups of L lanes (L = 4, 8, 16, 32 or 64), left in
+// every lane of the group; a fixed sequence of exchanges, so the result is
+// deterministic and identical in all lanes: DPP quad permutations (lane ^ 1,
+// lane ^ 2), half-row and row mirrors (the other quad of an 8-lane half row,
+// the other half of a 16-lane row), then swaps of 16 and 32 lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_plus(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return v + __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false),
+                              __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false));
+}
+
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+  static_assert(L == 4 || L == 8 || L == 16 || L == 32 || L == 64, "lane group of 4..64");
+  v = dpp_plus<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = dpp_plus<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (L >= 8) v = dpp_plus<0x141>(v);  // row_half_mirror
+  if (L >= 16) v = dpp_plus<0x140>(v);  // row_mirror
+  if (L >= 32) v += __shfl_xor(v, 16);
+  if (L >= 64) v += __shfl_xor(v, 32);
+  return v;
 }
 
 // Final step of one scan frequency: 2x2 Cholesky of the Schur block
@@ -182,8 +212,10 @@ hipError_t launch_scan_mfma(hipStream_t st, int NT, int FT, int n_work, const Sc
                             const SeriesIn* sin, const SeriesHdr* hdr, const float* g32,
                             const double* aux, double* z, uint8_t* flags, Rescore* list,
                             unsigned long long* count);
-hipError_t launch_rescore(hipStream_t st, int NT, int grid, const SeriesIn* sin, const SeriesHdr* hdr,
-                          const double* rec, const Rescore* list, const unsigned long long* count,
+// float64 re-scoring of the listed points (per-series lists at list[goff_s ..],
+// count[s] entries each; chunk_off: n_series + 1 int64 of workspace)
+hipError_t launch_rescore(hipStream_t st, int NT, int grid, int n_series, const SeriesIn* sin, const SeriesHdr* hdr,
+                          const double* rec, const Rescore* list, const unsigned long long* count, int64_t* chunk_off,
                           double* z, uint8_t* flags);
 hipError_t launch_zero_u64(hipStream_t st, unsigned long long* p, int n);
 int mfma_freq_tiles(int NT);  // default FT of the MFMA scan kernel (16-frequency tiles per wave)

@@ -229,13 +229,15 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict_
       q[KP + 3] = c1;
       q[KP + 4] = s1;
     }
-    if (flags & PREP_F32) {
+    if (flags & si.outputs & PREP_G32) {
       float* g = g32 + si.g32_off + i * G32W;
       for (int k = 0; k < K; ++k) g[k] = static_cast<float>(wi * ph[k]);
       // column K (never read by the MFMA kernel, whose padding columns only
       // produce unused sums) carries w~ for the VALU kernel's <cos^2>, <cos sin>
       g[K] = static_cast<float>(wi);
       for (int k = K + 1; k < G32W; ++k) g[k] = 0.0f;
+    }
+    if (flags & si.outputs & PREP_AUX) {
       double* a = aux + si.aux_off + i * AUX_STRIDE;
       double rs, rc, s1, c1;
       sincos_rev(si.rot_tile * ta, rs, rc);
@@ -250,7 +252,7 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict_
       a[7] = s1;
     }
   }
-  if (!(flags & PREP_F16)) return;
+  if (!(flags & si.outputs & PREP_F16)) return;
 
   // pass 6: split float16 operand of the MFMA scan, B = S w~ q_k = hi + lo
   // (both float16, lo = the float32 remainder), S = 2^e with max |B| in

@@ -369,8 +369,8 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
       const double l21 = Scs / sqrt(fmax(Scc, 1e-300));
       const double rho = fmin(Scc / ccr, (Sss - l21 * l21) / ss);
       if (!(fl & FREDEC_FLAG_MASKED) && (!(rho >= RHO_MIN) || !(lratio >= LRATIO_MIN))) {
-        const unsigned long long slot = atomicAdd(count, 1ull);
-        list[slot] = Rescore{wk.series, 0, j};
+        const unsigned long long slot = atomicAdd(count + wk.series, 1ull);
+        list[si.goff + slot] = Rescore{wk.series, 0, j};
       }
       zs[j] = z;
       if (fs) fs[j] = fl;

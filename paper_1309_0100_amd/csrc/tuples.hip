@@ -168,30 +168,6 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
 
 constexpr int pidx(int r, int c) { return r * (r + 1) / 2 + c; }
 
-// Sum of v over aligned groups of L lanes (L = 4, 8, 16, 32 or 64), left in
-// every lane of the group; a fixed sequence of exchanges, so the result is
-// deterministic and identical in all lanes: DPP quad permutations (lane ^ 1,
-// lane ^ 2), half-row and row mirrors (the other quad of an 8-lane half row,
-// the other half of a 16-lane row), then swaps of 16 and 32 lanes.
-template <int CTRL>
-__device__ __forceinline__ double dpp_plus(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  return v + __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false),
-                              __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false));
-}
-
-template <int L>
-__device__ __forceinline__ double group_sum(double v) {
-  static_assert(L == 4 || L == 8 || L == 16 || L == 32 || L == 64, "lane group of 4..64");
-  v = dpp_plus<0xB1>(v);   // quad_perm [1,0,3,2]
-  v = dpp_plus<0x4E>(v);   // quad_perm [2,3,0,1]
-  if (L >= 8) v = dpp_plus<0x141>(v);  // row_half_mirror
-  if (L >= 16) v = dpp_plus<0x140>(v);  // row_mirror
-  if (L >= 32) v += __shfl_xor(v, 16);
-  if (L >= 64) v += __shfl_xor(v, 32);
-  return v;
-}
-
 // sin/cos(2 pi p) for the lane-group kernels: float64 (sincos_rev) or, in the
 // reduced-precision form, the float64 phase reduction p - rint(p) followed
 // by the hardware float32 sin/cos of the reduced phase (v_sin_f32 and

@@ -147,9 +147,26 @@ class Batch:
                       df=float(self.df[s]), F=int(self.F[s]))
 
 
+def _resolved_base(rng, injected, m, res):
+    """m base frequencies as the method would have detected them: resolved
+    from zero and from each other (f >= res, |f - f'| >= res, res = 1.5 / T):
+    the injected frequencies that qualify, in order, then log-uniform draws
+    in [res, 0.5] c/d (periods of 2 d and longer), rejecting unresolved ones."""
+    base = []
+    for f in injected:
+        if len(base) < m and f >= res and all(abs(f - g) >= res for g in base):
+            base.append(f)
+    while len(base) < m:
+        f = _log_uniform(rng, res, 0.5)
+        if all(abs(f - g) >= res for g in base):
+            base.append(f)
+    return np.asarray(base, np.float64)
+
+
 def batched(n_series: int = 4096, F: int = 65536, fmax: float = 2.0,
             n_lo: int = 50, n_hi: int = 5000, m_max: int = 6) -> Batch:
-    """Workload 3: many independent series of uneven length and base size."""
+    """Workload 3: many independent series of uneven length and base size
+    (base frequencies resolved, see _resolved_base)."""
     root = np.random.SeedSequence(SEED_BASE + 3)
     ts, xs, ws, bfs = [], [], [], []
     soff = [0]
@@ -165,9 +182,7 @@ def batched(n_series: int = 4096, F: int = 65536, fmax: float = 2.0,
         sigma = rng.uniform(1.0, 3.0, size=N)
         x = _signal(rng, t, 1.0 / periods, amps, sigma)
         m = int(rng.integers(0, m_max + 1))
-        k = min(m, n_inj)
-        extra = 1.0 / _log_uniform(rng, 2.0, 1000.0, size=m - k)
-        base = np.concatenate([1.0 / periods[:k], extra])
+        base = _resolved_base(rng, 1.0 / periods, m, 1.5 / T)
         ts.append(t)
         xs.append(x)
         ws.append(1.0 / sigma**2)
