@@ -141,7 +141,7 @@ int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, cons
   L.off_b16 = take(16 * L.b16_total);
   L.off_list = take(precision == FREDEC_FP32 ? sizeof(Rescore) * L.F_total : 0);
   L.off_count = take(sizeof(unsigned long long) * n_series);
-  L.off_chunk = take(precision == FREDEC_FP32 ? sizeof(int64_t) * (n_series + 1) : 0);
+  L.off_chunk = take(precision == FREDEC_FP32 ? sizeof(int64_t) * (2 * n_series + 3) : 0);
   L.total = off;
   return FREDEC_OK;
 }

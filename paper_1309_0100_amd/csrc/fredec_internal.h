@@ -213,9 +213,9 @@ hipError_t launch_scan_mfma(hipStream_t st, int NT, int FT, int n_work, const Sc
                             const double* aux, double* z, uint8_t* flags, Rescore* list,
                             unsigned long long* count);
 // float64 re-scoring of the listed points (per-series lists at list[goff_s ..],
-// count[s] entries each; chunk_off: n_series + 1 int64 of workspace)
+// count[s] entries each; off: 2 n_series + 3 int64 of workspace for the plan)
 hipError_t launch_rescore(hipStream_t st, int NT, int grid, int n_series, const SeriesIn* sin, const SeriesHdr* hdr,
-                          const double* rec, const Rescore* list, const unsigned long long* count, int64_t* chunk_off,
+                          const double* rec, const Rescore* list, const unsigned long long* count, int64_t* off,
                           double* z, uint8_t* flags);
 hipError_t launch_zero_u64(hipStream_t st, unsigned long long* p, int n);
 int mfma_freq_tiles(int NT);  // default FT of the MFMA scan kernel (16-frequency tiles per wave)
