@@ -15,7 +15,7 @@ namespace fredec {
 
 namespace {
 
-constexpr int GRAM_CHUNK = 8;  // Gram entries accumulated per pass
+constexpr int SUMS = 4;  // most values of one block reduction
 
 __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict__ sin_, SeriesHdr* __restrict__ hdr,
                                                      const double* __restrict__ t, const double* __restrict__ x,
@@ -24,7 +24,7 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict_
                                                      double* __restrict__ rec, double* __restrict__ phi,
                                                      float* __restrict__ g32, double* __restrict__ aux,
                                                      _Float16* __restrict__ b16, int flags) {
-  __shared__ double sh[GRAM_CHUNK * BLOCK];
+  __shared__ double sh[SUMS * BLOCK];
   __shared__ double gram[MAXKP * (MAXKP + 1) / 2];
   __shared__ double Lsh[MAXK * (MAXK + 1) / 2];
   __shared__ double invd[MAXK];
@@ -120,53 +120,70 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(const SeriesIn* __restrict_
   __syncthreads();
 
   // Gram of the columns (1, cos f'_k, sin f'_k, x~): base normal matrix A,
-  // right-hand side g_b (last row) and D = <x~^2> (last diagonal entry).
-  const int n_ent = KP * (KP + 1) / 2;
-  const double* phs = phi + si.phi_off;
-  for (int e0 = 0; e0 < n_ent; e0 += GRAM_CHUNK) {
-    double acc[GRAM_CHUNK];
-    int ka[GRAM_CHUNK], la[GRAM_CHUNK];
+  // right-hand side g_b (last row) and D = <x~^2> (last diagonal entry), on
+  // float64 MFMA: the lower 16x16 tiles of the KP x KP Gram are dealt to the
+  // four waves, each tile accumulated over all samples four at a time
+  // (lane (c16, kq): column c16 of the tile's row / column block at sample
+  // i0 + kq; D[r][c] in lane c + 16 (r % 4), register r / 4).
+  {
+    typedef double v4d __attribute__((ext_vector_type(4)));
+    const int lane = tid & 63, wave = tid >> 6;
+    const int c16 = lane & 15, kq = lane >> 4;
+    const int nbk = (KP + 15) / 16;
+    const int ntiles = nbk * (nbk + 1) / 2;
+    const double* phs = phi + si.phi_off;
+    for (int tl = wave; tl < ntiles; tl += BLOCK / 64) {
+      int b1 = 0;
+      while ((b1 + 1) * (b1 + 2) / 2 <= tl) ++b1;
+      const int b2 = tl - b1 * (b1 + 1) / 2;
+      const int ca = 16 * b1 + c16, cb = 16 * b2 + c16;
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int64_t i0 = 0; i0 < N; i0 += 4) {
+        const int64_t i = i0 + kq;
+        const bool in = i < N;
+        const double av = (in && ca < KP) ? phs[i * KP + ca] : 0.0;
+        const double bv = (in && cb < KP) ? wts[i] * phs[i * KP + cb] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
 #pragma unroll
-    for (int c = 0; c < GRAM_CHUNK; ++c) {
-      acc[c] = 0.0;
-      int e = e0 + c;
-      if (e >= n_ent) e = n_ent - 1;
-      int k = 0;
-      while ((k + 1) * (k + 2) / 2 <= e) ++k;
-      ka[c] = k;
-      la[c] = e - k * (k + 1) / 2;
-    }
-    for (int64_t i = tid; i < N; i += BLOCK) {
-      const double* ph = phs + i * KP;
-      const double wi = wts[i];
-#pragma unroll
-      for (int c = 0; c < GRAM_CHUNK; ++c) acc[c] += wi * ph[ka[c]] * ph[la[c]];
-    }
-    block_sum(acc, sh);
-    if (tid == 0) {
-      for (int c = 0; c < GRAM_CHUNK && e0 + c < n_ent; ++c) gram[e0 + c] = acc[c];
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * b1 + kq + 4 * v;
+        const int c = 16 * b2 + c16;
+        if (r < KP && c <= r) gram[r * (r + 1) / 2 + c] = acc[v];
+      }
     }
   }
   __syncthreads();
 
-  if (tid == 0) {
-    // Cholesky A = L L^T (Sect. 3), a_b = L^{-1} g_b, l_m = D - a_b.a_b
-    for (int j = 0; j < K && status == 0; ++j) {
+  // Cholesky A = L L^T (Sect. 3), column by column: the pivot by thread 0,
+  // the entries below it by one thread each.
+  __shared__ int bad_sh;
+  if (tid == 0) bad_sh = 0;
+  __syncthreads();
+  for (int j = 0; j < K; ++j) {
+    if (tid == 0) {
       double d = gram[j * (j + 1) / 2 + j];
       for (int k = 0; k < j; ++k) d -= Lsh[j * (j + 1) / 2 + k] * Lsh[j * (j + 1) / 2 + k];
       if (!(d > PIVOT_TOL * gram[j * (j + 1) / 2 + j])) {
-        status = FREDEC_ESINGULAR;
-        break;
-      }
-      const double ljj = sqrt(d);
-      Lsh[j * (j + 1) / 2 + j] = ljj;
-      invd[j] = 1.0 / ljj;
-      for (int i = j + 1; i < K; ++i) {
-        double v = gram[i * (i + 1) / 2 + j];
-        for (int k = 0; k < j; ++k) v -= Lsh[i * (i + 1) / 2 + k] * Lsh[j * (j + 1) / 2 + k];
-        Lsh[i * (i + 1) / 2 + j] = v / ljj;
+        bad_sh = 1;
+      } else {
+        const double ljj = sqrt(d);
+        Lsh[j * (j + 1) / 2 + j] = ljj;
+        invd[j] = 1.0 / ljj;
       }
     }
+    __syncthreads();
+    if (bad_sh) break;
+    for (int i = j + 1 + tid; i < K; i += BLOCK) {
+      double v = gram[i * (i + 1) / 2 + j];
+      for (int k = 0; k < j; ++k) v -= Lsh[i * (i + 1) / 2 + k] * Lsh[j * (j + 1) / 2 + k];
+      Lsh[i * (i + 1) / 2 + j] = v * invd[j];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (status == 0 && bad_sh) status = FREDEC_ESINGULAR;
+    // a_b = L^{-1} g_b, l_m = D - a_b.a_b
     double lm = 0.0;
     if (status == 0) {
       const double* gb = gram + K * (K + 1) / 2;  // row K: <x~ phi_k>, then D

@@ -149,7 +149,10 @@ __global__ __launch_bounds__(BLOCK) void scan_f64_kernel(const ScanWork* __restr
   }
 }
 
-// Same statistic at an explicit list of grid indices of one series (R = 1).
+// Same statistic at an explicit list of grid indices of one series: one
+// wavefront per index, the samples spread over the lanes (float64 phase
+// reduction and sin/cos per sample), the 2 KP + 3 partial sums reduced across
+// the wave with DPP and shuffles in a fixed order.
 template <int KP>
 __global__ __launch_bounds__(BLOCK) void scan_at_f64_kernel(const SeriesIn* __restrict__ sin_,
                                                             const SeriesHdr* __restrict__ hdr,
@@ -160,22 +163,24 @@ __global__ __launch_bounds__(BLOCK) void scan_at_f64_kernel(const SeriesIn* __re
   constexpr int P = rec_stride(KP);
   const SeriesIn& si = sin_[0];
   const SeriesHdr& h = hdr[0];
-  const int64_t g = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
-  const int64_t gi = g < n_idx ? g : n_idx - 1;
-  const int64_t j = idx[gi];
+  const int lane = threadIdx.x & 63;
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * (BLOCK / 64) + (threadIdx.x >> 6);
+  if (g >= n_idx) return;
   if (h.status != 0) {
-    if (g < n_idx) {
+    if (lane == 0) {
       z_out[g] = __builtin_nan("");
       if (flags_out) flags_out[g] = FREDEC_FLAG_BADSERIES;
     }
     return;
   }
+  const int64_t j = idx[g];
   const double f = static_cast<double>(j + 1) * si.df;
   double acc[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) acc[k] = 0.0;
-  const double* __restrict__ q = rec + si.rec_off;
-  for (int64_t i = 0; i < si.N; ++i, q += P) {
+  const double* __restrict__ q0 = rec + si.rec_off;
+  for (int64_t i = lane; i < si.N; i += 64) {
+    const double* q = q0 + i * P;
     double s, c;
     sincos_rev(f * q[0], s, c);
     const double g0 = q[3];
@@ -192,7 +197,9 @@ __global__ __launch_bounds__(BLOCK) void scan_at_f64_kernel(const SeriesIn* __re
       acc[4 + 2 * k] = __builtin_fma(gk, s, acc[4 + 2 * k]);
     }
   }
-  if (g < n_idx) {
+#pragma unroll
+  for (int k = 0; k < NS; ++k) acc[k] = group_sum<64>(acc[k]);
+  if (lane == 0) {
     double z;
     uint8_t fl;
     scan_epilogue<KP>(acc, f, si, h, z, fl);
@@ -211,7 +218,7 @@ hipError_t launch_kp(hipStream_t st, int n_work, const ScanWork* work, const Ser
 template <int KP>
 hipError_t launch_at_kp(hipStream_t st, const SeriesIn* sin, const SeriesHdr* hdr, const double* rec,
                         const int64_t* idx, int64_t n_idx, double* z, uint8_t* flags) {
-  const int64_t blocks = (n_idx + BLOCK - 1) / BLOCK;
+  const int64_t blocks = (n_idx + BLOCK / 64 - 1) / (BLOCK / 64);  // one wavefront per index
   scan_at_f64_kernel<KP><<<static_cast<unsigned>(blocks), BLOCK, 0, st>>>(sin, hdr, rec, idx, n_idx, z, flags);
   return hipGetLastError();
 }

@@ -148,7 +148,10 @@ def test_scan_at_matches_scan(ctx):
     idx = np.array([0, 1, 17, 255, 256, 257, 2999, 1234], np.int64)
     za, fa = ctx.scan_at(s.t, s.x, s.w, base, 3e-4, idx)
     assert np.array_equal(fa.cpu().numpy(), fl.cpu().numpy()[idx])
-    assert zerr(za.cpu().numpy(), z.cpu().numpy()[idx]).max() < 1e-11
+    # two float64 evaluations (phasor tables and per-lane sums vs a sin/cos per
+    # sample and a cross-lane tree): the float64 bound; index 0 (f T_eff << 1)
+    # is where their rounding differs most (~1e-10)
+    assert zerr(za.cpu().numpy(), z.cpu().numpy()[idx]).max() < 1e-9
 
 
 def test_normalize_matches_oracle(ctx):
