@@ -74,7 +74,7 @@ enum {
   FREDEC_FLAG_DEGENERATE = 8, /* tuple with merged frequencies or singular matrix: z := -inf */
   FREDEC_FLAG_CONVERGED = 16, /* tuple refinement stopped on the step tolerance */
   FREDEC_FLAG_RESCORED = 64,  /* FREDEC_FP32 scan: trial columns nearly in the base span (relative
-                                 Schur pivot < 0.5) or a strong peak (l_{m+1} < l_m / 2):
+                                 Schur pivot < 0.6) or a strong peak (l_{m+1} < l_m / 2):
                                  value recomputed in float64 */
   FREDEC_FLAG_BADSERIES = 128 /* the series failed validation (see status_out): z := NaN */
 };

@@ -16,7 +16,7 @@ constexpr int MAXK = 2 * MAXM + 1;       // base columns 1, cos, sin, ...
 constexpr int MAXKP = MAXK + 1;          // base columns plus the data column
 constexpr double MASK_WIDTH = 0.05;      // |f - f'| T_eff below this is masked
 constexpr double PIVOT_TOL = 1e-13;      // relative Cholesky pivot threshold
-constexpr double RHO_MIN = 0.5;          // reduced-precision scan: re-score in float64 below this
+constexpr double RHO_MIN = 0.6;          // reduced-precision scan: re-score in float64 below this
                                          // relative Schur pivot (trial columns nearly in the base span)
 constexpr double LRATIO_MIN = 0.5;       // ... and where l_{m+1} / l_m falls below this (strong peaks,
                                          // where l_{m+1} = l_m - |a_psi|^2 cancels)

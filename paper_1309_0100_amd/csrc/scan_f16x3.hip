@@ -19,10 +19,10 @@
 // (row = lane % 16, kb = lane / 16) generates A for its frequency row at the
 // eight samples 8 kb .. 8 kb + 7 of the step: the float32 complex product
 // eat[a][s] * bt[row][s] of two unit phasors that the block computes in
-// float64 per tile of 64 samples and rounds once (eat = e^{2 pi i (j0 + 1 +
+// float64 per tile of 128 samples and rounds once (eat = e^{2 pi i (j0 + 1 +
 // 16 a) df tau_s}, a = the wave's 16-frequency tile; bt = e^{2 pi i row df
 // tau_s}).  The same lane accumulates, for its row and its samples,
-//   <cos^2>, <cos sin>  float32 per tile of 64 samples, then float64,
+//   <cos^2>, <cos sin>  float32 per tile of 128 samples, then float64,
 //   h = <r_b cos>, <r_b sin>  float64 (the data column enters z linearly),
 // reduced over the four kb lanes at the end; <sin^2> = <1> - <cos^2>.  MFMA
 // accumulators are added into float32 running sums at the end of every tile
@@ -41,7 +41,7 @@ namespace {
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int F16X3_TS = 64;  // samples per table tile (two MFMA steps of 32)
+constexpr int F16X3_TS = 128;  // samples per table tile (four MFMA steps of 32)
 
 // c = hi + lo with both parts float16: hi = c rounded toward zero (packed
 // conversion), lo = the remainder c - hi, which is exact in float32, rounded

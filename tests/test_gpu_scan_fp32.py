@@ -6,7 +6,7 @@ operands (the default).
 
 Bound (relative error err = |z - z_ref| / max(z_ref, 1)): 1e-6 on every grid
 frequency that the oracle does not flag.  Grid points whose trial columns lie
-nearly in the span of the base model (relative Schur pivot < 0.5: next to a
+nearly in the span of the base model (relative Schur pivot < 0.6: next to a
 base frequency, or f T_eff of order 1 and below) and the tops of strong peaks
 (l_{m+1} < l_m / 2) are re-scored in float64 by the library and carry flag
 bit 6; the rest come from the float32 MFMA sums.
