@@ -81,13 +81,16 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
                                                            const TupleState* __restrict__ state,
                                                            double* __restrict__ gram, int mode) {
   constexpr int NRMAX = (NB + 1) / 2;  // frequencies per lane: n <= 8 NB - 1 columns' worth
+  constexpr int TSZ = 256;             // samples per block-wide staging tile
   __shared__ double2 trig[BLOCK / 64][4][16 * NRMAX];
+  __shared__ double stage[3][TSZ];     // tau, x~, w~ of the tile, shared by the block's four tuples
   const int wave = (blockIdx.x * BLOCK + threadIdx.x) >> 6;
-  if (wave >= n_order) return;
   const int lane = threadIdx.x & 63;
-  const int ti = order[wave];
+  // every wave takes part in the staging and its barriers; waves without a
+  // live tuple skip the arithmetic
+  const int ti = wave < n_order ? order[wave] : 0;
+  const bool live = wave < n_order && !state[ti].done;
   const TupleDesc& d = desc[ti];
-  if (state[ti].done) return;
   const int n = d.n;
   const int C = (mode == TUPLE_GN) ? 4 * n + 2 : 2 * n + 2;
   const double* f = ftry + d.foff;
@@ -96,7 +99,7 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
   const int nr = (n + 15) >> 4;
   double fk[NRMAX];
 #pragma unroll
-  for (int r = 0; r < NRMAX; ++r) fk[r] = (c16 + 16 * r < n) ? f[c16 + 16 * r] : 0.0;
+  for (int r = 0; r < NRMAX; ++r) fk[r] = (live && c16 + 16 * r < n) ? f[c16 + 16 * r] : 0.0;
   ColSel cd[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) cd[b] = col_sel(16 * b + c16, n, mode);
@@ -107,47 +110,59 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
 #pragma unroll
   for (int q = 0; q < NTILE; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
   const int64_t N = com->N;
-  for (int64_t i0 = 0; i0 < N; i0 += 4) {
-    const int64_t i = i0 + kq;
-    const bool in = i < N;
-    const double ta = in ? tau[i] : 0.0;
-    const double xi = in ? xt[i] : 0.0;
-    const double wi = in ? wt[i] : 0.0;
-#pragma unroll
-    for (int r = 0; r < NRMAX; ++r) {
-      if (r < nr) {
-        double sv, cv;
-        sincos_rev(fk[r] * ta, sv, cv);
-        tw[kq][c16 + 16 * r] = double2{cv, sv};
-      }
+  for (int64_t t0 = 0; t0 < N; t0 += TSZ) {
+    const int ns = N - t0 < TSZ ? static_cast<int>(N - t0) : TSZ;
+    __syncthreads();
+    for (int k = threadIdx.x; k < TSZ; k += BLOCK) {
+      const bool in = k < ns;
+      stage[0][k] = in ? tau[t0 + k] : 0.0;
+      stage[1][k] = in ? xt[t0 + k] : 0.0;
+      stage[2][k] = in ? wt[t0 + k] : 0.0;
     }
-    __builtin_amdgcn_wave_barrier();
-    double a[NB], bw[NB];
+    __syncthreads();
+    if (!live) continue;
+    for (int s0 = 0; s0 < ns; s0 += 4) {
+      const int il = s0 + kq;  // beyond ns the staged weight is 0
+      const double ta = stage[0][il];
+      const double xi = stage[1][il];
+      const double wi = stage[2][il];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      double v = 0.0;
-      if (cd[b].kind == 1) {
-        v = 1.0;
-      } else if (cd[b].kind == 3) {
-        v = xi;
-      } else if (cd[b].kind != 0) {
-        const double2 cs = tw[kq][cd[b].kf];
-        v = cd[b].sel ? cs.y : cs.x;
-        if (cd[b].kind == 4) v *= ta * inv_sig;
+      for (int r = 0; r < NRMAX; ++r) {
+        if (r < nr) {
+          double sv, cv;
+          sincos_rev(fk[r] * ta, sv, cv);
+          tw[kq][c16 + 16 * r] = double2{cv, sv};
+        }
       }
-      a[b] = v;
-      bw[b] = wi * v;
+      __builtin_amdgcn_wave_barrier();
+      double a[NB], bw[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        double v = 0.0;
+        if (cd[b].kind == 1) {
+          v = 1.0;
+        } else if (cd[b].kind == 3) {
+          v = xi;
+        } else if (cd[b].kind != 0) {
+          const double2 cs = tw[kq][cd[b].kf];
+          v = cd[b].sel ? cs.y : cs.x;
+          if (cd[b].kind == 4) v *= ta * inv_sig;
+        }
+        a[b] = v;
+        bw[b] = wi * v;
+      }
+      __builtin_amdgcn_wave_barrier();
+      int q = 0;
+#pragma unroll
+      for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+        for (int b2 = 0; b2 <= b1; ++b2) {
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[b1], bw[b2], acc[q], 0, 0, 0);
+          ++q;
+        }
     }
-    __builtin_amdgcn_wave_barrier();
-    int q = 0;
-#pragma unroll
-    for (int b1 = 0; b1 < NB; ++b1)
-#pragma unroll
-      for (int b2 = 0; b2 <= b1; ++b2) {
-        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[b1], bw[b2], acc[q], 0, 0, 0);
-        ++q;
-      }
   }
+  if (!live) return;
   // D[i][j] of block (b1, b2) sits in lane j + 16 (i % 4), register i / 4
   double* G = gram + d.goff;
   int q = 0;
