@@ -75,9 +75,11 @@ namespace {
 struct ScanLayout {
   size_t off_sin = 0, off_hdr = 0, off_work = 0, off_tau = 0, off_xt = 0, off_wt = 0, off_rec = 0, off_phi = 0;
   size_t off_g32 = 0, off_aux = 0, off_b16 = 0, off_list = 0, off_count = 0, off_chunk = 0;
+  size_t off_ppart = 0, off_pm = 0;
   size_t total = 0;
   int64_t Ntot = 0, rec_total = 0, phi_total = 0, g32_total = 0, aux_total = 0, b16_total = 0, n_work = 0,
           F_total = 0;
+  int64_t ptiles = 0, ppart_total = 0, pm_total = 0;  // preparation tiles, Gram partials, basis changes
   int max_nt = 1;
 };
 
@@ -115,6 +117,12 @@ int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, cons
     L.phi_total += N * KP;
     L.rec_total += N * rec_stride(KP);
     L.F_total += F[s];
+    {
+      SeriesIn d{};
+      d.N = N;
+      d.KP = KP;
+      prep_assign(d, L.ptiles, L.ppart_total, L.pm_total);
+    }
     if (precision == FREDEC_FP32) {
       L.g32_total += N * 16 * col_tiles(KP);
       L.aux_total += N * AUX_STRIDE;
@@ -142,6 +150,8 @@ int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, cons
   L.off_list = take(precision == FREDEC_FP32 ? sizeof(Rescore) * L.F_total : 0);
   L.off_count = take(sizeof(unsigned long long) * n_series);
   L.off_chunk = take(precision == FREDEC_FP32 ? sizeof(int64_t) * (2 * n_series + 3) : 0);
+  L.off_ppart = take(sizeof(double) * L.ppart_total);
+  L.off_pm = take(sizeof(double) * L.pm_total);
   L.total = off;
   return FREDEC_OK;
 }
@@ -159,6 +169,7 @@ struct ScanPlan : fredec_plan {
   int32_t n_series = 0;
   int32_t precision = FREDEC_FP64;
   int64_t base_off = 0;  // soff[0]: t, x, w are indexed from the caller's pointers
+  int32_t kp_max = 2;    // largest KP of the series
   std::vector<SeriesIn> sin;
   std::vector<ScanWork> work;
   enum Kind { F64 = 0, MFMA = 1, F32 = 2, F16X3 = 3 };
@@ -184,12 +195,14 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
   P.ws = ws;
   P.ws_bytes = ws_bytes;
   P.n_series = n_series;
+  P.kp_max = 2;
   P.precision = precision;
   P.base_off = soff[0];
   std::vector<SeriesIn>& sin = P.sin;
   sin.assign(n_series, SeriesIn{});
   std::memset(sin.data(), 0, sizeof(SeriesIn) * n_series);
   int64_t goff = 0, rec_off = 0, phi_off = 0, g32_off = 0, aux_off = 0, b16_off = 0;
+  int64_t ptile = 0, ppart = 0, pmo = 0;
   for (int32_t s = 0; s < n_series; ++s) {
     SeriesIn& d = sin[s];
     d.soff = soff[s];
@@ -202,6 +215,8 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
     d.rot_tile = 16.0 * df[s];
     d.m = static_cast<int32_t>(boff[s + 1] - boff[s]);
     d.KP = 2 * d.m + 2;
+    if (d.KP > P.kp_max) P.kp_max = d.KP;
+    prep_assign(d, ptile, ppart, pmo);
     d.NT = col_tiles(d.KP);
     for (int k = 0; k < d.m; ++k) {
       d.base_f[k] = base_f[boff[s] - boff[0] + k];
@@ -304,8 +319,9 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const double
   // per series, the prep kernel writes only what its scan kernel reads (SeriesIn::outputs)
   const int flags = PREP_BASE | PREP_REC64 | PREP_G32 | PREP_AUX | PREP_F16;
   if (f32 && launch_zero_u64(st, d_count, P.n_series) != hipSuccess) return FREDEC_EDEVICE;
-  if (launch_prep(st, P.n_series, d_sin, d_hdr, t, x, w, d_tau - base_off, d_xt - base_off, d_wt - base_off, d_rec,
-                  d_phi, d_g32, d_aux, d_b16, flags) != hipSuccess)
+  if (launch_prep(st, P.n_series, P.kp_max, L.ptiles, d_sin, d_hdr, t, x, w, d_tau - base_off, d_xt - base_off,
+                  d_wt - base_off, d_rec, d_phi, d_g32, d_aux, d_b16, at<double>(ws, L.off_ppart),
+                  at<double>(ws, L.off_pm), flags) != hipSuccess)
     return FREDEC_EDEVICE;
   {
     ProfScope prof(ctx, st);
@@ -468,8 +484,8 @@ int fredec_normalize(fredec_ctx* ctx, void* stream, int32_t n_series, const int6
   int rc = upload(ctx, st, d_sin, sin.data(), sizeof(SeriesIn) * n_series);
   if (rc) return rc;
   // the prep kernel writes the normalised series at the caller's offsets
-  if (launch_prep(st, n_series, d_sin, d_hdr, t, x, w, tau_out, xt_out, wt_out, nullptr, nullptr, nullptr, nullptr, nullptr,
-                  0) != hipSuccess)
+  if (launch_prep(st, n_series, 0, 0, d_sin, d_hdr, t, x, w, tau_out, xt_out, wt_out, nullptr, nullptr, nullptr,
+                  nullptr, nullptr, nullptr, nullptr, 0) != hipSuccess)
     return FREDEC_EDEVICE;
   if (launch_copy_stats(st, n_series, d_hdr, d_sin, nullptr, status_out, stats_out) != hipSuccess)
     return FREDEC_EDEVICE;
@@ -544,8 +560,14 @@ int fredec_scan_at_workspace(int64_t N, int32_t m, size_t* bytes) {
   if (!bytes || N <= 0 || m < 0) return FREDEC_EINVAL;
   if (m > MAXM) return FREDEC_ENOTSUP;
   const int KP = 2 * m + 2;
+  SeriesIn d{};
+  d.N = N;
+  d.KP = KP;
+  int64_t ptile = 0, ppart = 0, pmo = 0;
+  prep_assign(d, ptile, ppart, pmo);
   *bytes = align_up(sizeof(SeriesIn)) + align_up(sizeof(SeriesHdr)) + 3 * align_up(sizeof(double) * N) +
-           align_up(sizeof(double) * N * rec_stride(KP)) + align_up(sizeof(double) * N * KP);
+           align_up(sizeof(double) * N * rec_stride(KP)) + align_up(sizeof(double) * N * KP) +
+           align_up(sizeof(double) * ppart) + align_up(sizeof(double) * pmo);
   return FREDEC_OK;
 }
 
@@ -571,6 +593,8 @@ int fredec_scan_at(fredec_ctx* ctx, void* stream, const double* t, const double*
   si.m = m;
   si.KP = 2 * m + 2;
   si.NT = col_tiles(si.KP);
+  int64_t ptile = 0, ppart = 0, pmo = 0;
+  prep_assign(si, ptile, ppart, pmo);
   for (int k = 0; k < m; ++k) {
     if (!std::isfinite(base_f[k])) return FREDEC_EINVAL;
     si.base_f[k] = base_f[k];
@@ -591,12 +615,16 @@ int fredec_scan_at(fredec_ctx* ctx, void* stream, const double* t, const double*
   double* d_rec = at<double>(ws, off);
   off += align_up(sizeof(double) * N * rec_stride(si.KP));
   double* d_phi = at<double>(ws, off);
+  off += align_up(sizeof(double) * N * si.KP);
+  double* d_ppart = at<double>(ws, off);
+  off += align_up(sizeof(double) * ppart);
+  double* d_pm = at<double>(ws, off);
   DeviceGuard g(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   int rc = upload(ctx, st, d_sin, &si, sizeof(si));
   if (rc) return rc;
-  if (launch_prep(st, 1, d_sin, d_hdr, t, x, w, d_tau, d_xt, d_wt, d_rec, d_phi, nullptr, nullptr, nullptr,
-                  PREP_BASE | PREP_REC64) != hipSuccess)
+  if (launch_prep(st, 1, si.KP, ptile, d_sin, d_hdr, t, x, w, d_tau, d_xt, d_wt, d_rec, d_phi, nullptr, nullptr,
+                  nullptr, d_ppart, d_pm, PREP_BASE | PREP_REC64) != hipSuccess)
     return FREDEC_EDEVICE;
   if (launch_scan_at_f64(st, si.KP, d_sin, d_hdr, d_rec, idx, n_idx, z_out, flags_out) != hipSuccess)
     return FREDEC_EDEVICE;

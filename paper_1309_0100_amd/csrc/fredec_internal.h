@@ -39,6 +39,11 @@ struct SeriesIn {
   int32_t KP;       // 2m + 2 columns: orthonormal base columns q_0..q_{2m}, residual r_b
   int32_t NT;       // 16-column tiles of the MFMA operand (K = KP - 1 base columns)
   int32_t outputs;  // PREP_* operand sets the scan kernel of this series reads
+  int64_t ptile0;   // first sample tile of this series in the preparation launch
+  int64_t ppart_off;  // first double of its per-tile Gram partials (pntiles KP(KP+1)/2)
+  int64_t pm_off;   // first double of its basis-change matrix (KP(KP+1)/2)
+  int32_t prows;    // samples per preparation tile (prep_rows(KP))
+  int32_t pntiles;  // preparation tiles, ceil(N / prows)
   double base_f[MAXM];
 };
 
@@ -51,6 +56,7 @@ struct SeriesHdr {
   double W1;        // <1> = sum of the normalised weights (= 1 up to rounding)
   double stats[6];  // <t>, <x>, s_x, Var(t), T_eff, sum(w)
   double b16_inv;   // 1 / S, S the power-of-two scale of the split float16 operand
+  double wmax;      // largest normalised weight
   int32_t status;   // 0 or a negative FREDEC_E* code
   int32_t pad;
 };
@@ -204,10 +210,38 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
 }
 
 // ------------------------------------------------------------ launchers
-hipError_t launch_prep(hipStream_t st, int n_series, const SeriesIn* sin, SeriesHdr* hdr,
-                       const double* t, const double* x, const double* w,
-                       double* tau, double* xt, double* wt, double* rec, double* phi,
-                       float* g32, double* aux, void* b16, int flags);
+// Samples per preparation tile of a series with KP columns: up to 256 rows
+// of prep_rs(KP) + PREP_PSS doubles within PREP_TILE doubles of LDS, a
+// multiple of 32.
+constexpr int PREP_TILE = 5120;
+constexpr int PREP_PSS = 9;
+__host__ __device__ constexpr int prep_rs(int KP) { return KP | 1; }
+__host__ __device__ constexpr int prep_rows(int KP) {
+  return ((PREP_TILE / (prep_rs(KP) + PREP_PSS)) & ~31) < BLOCK ? ((PREP_TILE / (prep_rs(KP) + PREP_PSS)) & ~31)
+                                                                  : BLOCK;
+}
+// Tile fields of a series for the preparation launch (host); advances the
+// running tile, Gram-partial and matrix offsets.
+inline void prep_assign(SeriesIn& d, int64_t& ptile, int64_t& ppart, int64_t& pm) {
+  const int64_t kpp = static_cast<int64_t>(d.KP) * (d.KP + 1) / 2;
+  d.prows = prep_rows(d.KP);
+  d.pntiles = static_cast<int32_t>((d.N + d.prows - 1) / d.prows);
+  d.ptile0 = ptile;
+  d.ppart_off = ppart;
+  d.pm_off = pm;
+  ptile += d.pntiles;
+  ppart += d.pntiles * kpp;
+  pm += kpp;
+}
+// Normalisation and (flags & PREP_BASE) base-model precomputation of
+// n_series series.  With PREP_BASE the series' SeriesIn carry the tile fields
+// (ptile0, ppart_off, pm_off, prows, pntiles; n_tiles tiles in all) and the
+// workspace arrays ppart (per-tile Gram partials) and pm (per-series basis
+// change) are used; kp_max is the largest KP.
+hipError_t launch_prep(hipStream_t st, int n_series, int kp_max, int64_t n_tiles, const SeriesIn* sin,
+                       SeriesHdr* hdr, const double* t, const double* x, const double* w, double* tau, double* xt,
+                       double* wt, double* rec, double* phi, float* g32, double* aux, void* b16, double* ppart,
+                       double* pm, int flags);
 hipError_t launch_scan_mfma(hipStream_t st, int NT, int FT, int n_work, const ScanWork* work,
                             const SeriesIn* sin, const SeriesHdr* hdr, const float* g32,
                             const double* aux, double* z, uint8_t* flags, Rescore* list,
