@@ -41,7 +41,9 @@ METRIC = "periodogram points/s (N×F) + tuples/s at stated rel-err vs FP64 oracl
 # MI355X published peaks
 PEAK_FP64_VALU = 78.6e12      # flop/s, FMA = 2 flops
 PEAK_FP32_MFMA = 157.3e12     # flop/s, dense
-PEAK_FP32_VALU = 157.3e12     # flop/s, float32 vector (non-packed FMA on every lane)
+PEAK_FP32_VALU = 157.3e12     # flop/s, float32 vector (the published peak counts packed FMA; a
+                              # non-packed FMA per lane and cycle reaches half of it)
+PEAK_FP64_MFMA = 78.6e12      # flop/s, float64 matrix cores
 
 
 def f32_form():
@@ -320,9 +322,20 @@ def batched_leg(ctx, args, prec_name, b):
 
     steps = max(2, args.steps // 4)
     sec, ksec, _ = timed(ctx, step, steps, 1)
-    points = float(np.sum(np.diff(b.soff) * np.asarray(b.F)))
+    Ns = np.diff(b.soff).astype(np.float64)
+    KP = 2 * np.diff(b.boff).astype(np.float64) + 2
+    points = float(np.sum(Ns * np.asarray(b.F)))
+    # the scans' sums: 2 KP + 3 multiply-adds per (frequency, sample) pair
+    flops = float(np.sum(Ns * np.asarray(b.F) * 2 * (2 * KP + 3)))
+    achieved = flops / ksec
+    peak = PEAK_FP64_VALU if prec == fredec.FP64 else PEAK_FP32_VALU
     leg = {"value": points / sec, "ms_per_step": sec * 1e3, "kernel_ms": ksec * 1e3, "pairs": points,
-           "rescored_points": int(((out[1] & 64) != 0).sum().item())}
+           "rescored_points": int(((out[1] & 64) != 0).sum().item()),
+           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                        "frac": achieved / peak, "traffic": None,
+                        "kernel": "scan_f64_kernel" if prec == fredec.FP64 else "scan_f16x3_kernel + scan_f32_kernel",
+                        "algorithmic": "2 (2 KP + 3) flop per (frequency, sample) pair summed over the series "
+                                       "(KP = 2 m_s + 2), over the HIP-event time of all scan kernel launches"}}
     return leg, out[0].clone(), out[1].clone()
 
 
@@ -339,10 +352,30 @@ def full_leg(ctx, args, prec_name, s):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     n = res.pool.size
+    # Phase-2 Gram kernel at the pass's shape: one Gauss-Newton step of every subtuple of the final
+    # pool (two Gram passes, every tuple live in both), timed by HIP events around the Gram launches
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    ctx.tuples(t, x, w, res.pool, refine_steps=1, precision=prec)
+    torch.cuda.synchronize()
+    kms, nl = ctx.profile_read()
+    ctx.profile(False)
+    from math import comb
+    C = np.array([4 * k + 2 for k in range(1, n + 1)], np.float64)
+    cnt = np.array([comb(n, k) for k in range(1, n + 1)], np.float64)
+    flops = 2.0 * float(np.sum(cnt * C * (C + 1))) * s.N
+    achieved = flops / (kms / 1e3)
     return {"seconds": el, "n_scans": res.n_scans, "pool": [float(f) for f in res.pool],
             "n_tuples": (1 << n) - 1, "n_solutions": len(res.solutions),
             "solutions": [[float(f) for f in sol.freqs] for sol in res.solutions[:5]],
-            "scan_pairs": float(s.N) * s.F * res.n_scans}
+            "scan_pairs": float(s.N) * s.F * res.n_scans,
+            "phase2_roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64_MFMA / 1e12,
+                                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
+                                "kernel": "tuple_gram_kernel", "kernel_ms_per_pass": kms / max(nl, 1),
+                                "passes": int(nl),
+                                "algorithmic": "C(C+1) flop per (tuple, sample) per Gauss-Newton Gram pass, C = 4n+2 "
+                                               "columns (1, cos, sin, x~, t' cos, t' sin; lower triangle), float64 "
+                                               "matrix cores"}}
 
 
 def main():
@@ -410,6 +443,7 @@ def main():
                     "config": {"workload": "batched scan: 4096 series, N log-uniform in [50, 5000], "
                                            "m uniform in 0..6, F=65536", "series": int(b.soff.size - 1),
                                "samples": int(b.soff[-1]), "form": head},
+                    "roofline": legs[head]["roofline"],
                     "forms": legs})
     else:
         s = synth.full()
@@ -420,6 +454,7 @@ def main():
                     "dtype": "f32" if head == "fp32" else "f64",
                     "config": {"workload": "full method: N=10^4 over 20000 d, Phase 1 scans on F=4e6, pool cap 16, "
                                            "every subtuple refined (8 Gauss-Newton steps), Phase 3", "form": head},
+                    "roofline": legs[head]["phase2_roofline"],
                     "forms": legs})
     print(json.dumps(res), flush=True)
 

@@ -127,6 +127,39 @@ __device__ __forceinline__ void sincos_rev(double p, double& s, double& c) {
   c = (iq == 1 || iq == 2) ? -cc : cc;
 }
 
+// Table of e^{2 pi i k / 256}, k = 0..255 (cos, sin), for sincos_tab; filled
+// by the threads of a block (one sincos_rev of an exact phase each).
+constexpr int TRIG_TAB = 256;
+__device__ __forceinline__ void trig_table_fill(double2* tab) {
+  for (int k = threadIdx.x; k < TRIG_TAB; k += blockDim.x) {
+    double s, c;
+    sincos_rev(static_cast<double>(k) / TRIG_TAB, s, c);
+    tab[k] = double2{c, s};
+  }
+}
+
+// sin(2 pi p) and cos(2 pi p) from the table: p = n + k/256 + y with
+// |y| <= 1/512 (both reductions exact), e^{2 pi i p} = T[k] e^{2 pi i y},
+// e^{2 pi i y} by its Taylor series in y (coefficients (2 pi)^j / j!; the
+// first omitted terms are below 2e-23 (sin) and 2e-20 (cos)).  About two
+// thirds of the instructions of sincos_rev, and within a few float64 ulps.
+__device__ __forceinline__ void sincos_tab(double p, const double2* __restrict__ tab, double& s, double& c) {
+  const double r = p - __builtin_rint(p);                    // exact, |r| <= 1/2
+  const double kf = __builtin_rint(static_cast<double>(TRIG_TAB) * r);  // -128..128
+  const double y = __builtin_fma(-1.0 / TRIG_TAB, kf, r);    // exact, |y| <= 1/512
+  const double y2 = y * y;
+  double sp = __builtin_fma(y2, -76.70585975306139, 81.60524927607506);
+  sp = __builtin_fma(sp, y2, -41.34170224039976);
+  sp = __builtin_fma(sp, y2, 6.283185307179586);
+  sp = sp * y;
+  double cp = __builtin_fma(y2, -85.45681720669373, 64.9393940226683);
+  cp = __builtin_fma(cp, y2, -19.739208802178716);
+  cp = __builtin_fma(cp, y2, 1.0);
+  const double2 t = tab[static_cast<int>(kf) & (TRIG_TAB - 1)];
+  c = __builtin_fma(t.x, cp, -t.y * sp);
+  s = __builtin_fma(t.y, cp, t.x * sp);
+}
+
 // Sum of v over aligned groups of L lanes (L = 4, 8, 16, 32 or 64), left in
 // every lane of the group; a fixed sequence of exchanges, so the result is
 // deterministic and identical in all lanes: DPP quad permutations (lane ^ 1,

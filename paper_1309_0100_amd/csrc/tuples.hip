@@ -84,6 +84,8 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
   constexpr int TSZ = 256;             // samples per block-wide staging tile
   __shared__ double2 trig[BLOCK / 64][4][16 * NRMAX];
   __shared__ double stage[3][TSZ];     // tau, x~, w~ of the tile, shared by the block's four tuples
+  __shared__ double2 tab[TRIG_TAB];
+  trig_table_fill(tab);
   const int wave = (blockIdx.x * BLOCK + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   // every wave takes part in the staging and its barriers; waves without a
@@ -130,24 +132,24 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
       for (int r = 0; r < NRMAX; ++r) {
         if (r < nr) {
           double sv, cv;
-          sincos_rev(fk[r] * ta, sv, cv);
+          sincos_tab(fk[r] * ta, tab, sv, cv);
           tw[kq][c16 + 16 * r] = double2{cv, sv};
         }
       }
       __builtin_amdgcn_wave_barrier();
+      // the lane's column value per block without divergent branches: one
+      // table read (frequency 0 for non-trig columns), then selects
+      const double tt = ta * inv_sig;
       double a[NB], bw[NB];
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        double v = 0.0;
-        if (cd[b].kind == 1) {
-          v = 1.0;
-        } else if (cd[b].kind == 3) {
-          v = xi;
-        } else if (cd[b].kind != 0) {
-          const double2 cs = tw[kq][cd[b].kf];
-          v = cd[b].sel ? cs.y : cs.x;
-          if (cd[b].kind == 4) v *= ta * inv_sig;
-        }
+        const double2 cs = tw[kq][cd[b].kf];
+        const double tv = cd[b].sel ? cs.y : cs.x;
+        const double v = cd[b].kind == 2   ? tv
+                         : cd[b].kind == 4 ? tv * tt
+                         : cd[b].kind == 1 ? 1.0
+                         : cd[b].kind == 3 ? xi
+                                           : 0.0;
         a[b] = v;
         bw[b] = wi * v;
       }
@@ -183,18 +185,19 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
 
 constexpr int pidx(int r, int c) { return r * (r + 1) / 2 + c; }
 
-// sin/cos(2 pi p) for the lane-group kernels: float64 (sincos_rev) or, in the
-// reduced-precision form, the float64 phase reduction p - rint(p) followed
-// by the hardware float32 sin/cos of the reduced phase (v_sin_f32 and
-// v_cos_f32 take their argument in revolutions), widened to float64.
+// sin/cos(2 pi p) for the lane-group kernels: float64 (sincos_tab with the
+// block's table) or, in the reduced-precision form, the float64 phase
+// reduction p - rint(p) followed by the hardware float32 sin/cos of the
+// reduced phase (v_sin_f32 and v_cos_f32 take their argument in
+// revolutions), widened to float64.
 template <bool F32>
-__device__ __forceinline__ void tuple_sincos(double p, double& s, double& c) {
+__device__ __forceinline__ void tuple_sincos(double p, const double2* __restrict__ tab, double& s, double& c) {
   if constexpr (F32) {
     const float r = static_cast<float>(p - __builtin_rint(p));
     s = static_cast<double>(__builtin_amdgcn_sinf(r));
     c = static_cast<double>(__builtin_amdgcn_cosf(r));
   } else {
-    sincos_rev(p, s, c);
+    sincos_tab(p, tab, s, c);
   }
 }
 
@@ -211,6 +214,11 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_lanes_kernel(const TupleDesc
                                                                  double* __restrict__ gram) {
   constexpr int C = 2 * NF + 2;
   constexpr int NACC = C * (C + 1) / 2;
+  __shared__ double2 tab[F32 ? 1 : TRIG_TAB];
+  if constexpr (!F32) {
+    trig_table_fill(tab);
+    __syncthreads();
+  }
   const int64_t gt = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
   const int grp = static_cast<int>(gt / L);
   const int r = static_cast<int>(gt % L);
@@ -232,7 +240,7 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_lanes_kernel(const TupleDesc
       double phi[C];
       phi[0] = 1.0;
 #pragma unroll
-      for (int k = 0; k < NF; ++k) tuple_sincos<F32>(f[k] * ta, phi[2 + 2 * k], phi[1 + 2 * k]);
+      for (int k = 0; k < NF; ++k) tuple_sincos<F32>(f[k] * ta, tab, phi[2 + 2 * k], phi[1 + 2 * k]);
       phi[C - 1] = xt[i];
 #pragma unroll
       for (int a = 0; a < C; ++a) {
@@ -465,6 +473,9 @@ __global__ __launch_bounds__(BLOCK) void tuple_adjoint_kernel(const TupleDesc* _
                                                               const double* __restrict__ theta,
                                                               const TupleState* __restrict__ state,
                                                               double* __restrict__ dzdf, double* __restrict__ hout) {
+  __shared__ double2 tab[TRIG_TAB];
+  trig_table_fill(tab);
+  __syncthreads();
   const int wave = (blockIdx.x * BLOCK + threadIdx.x) >> 6;
   if (wave >= n_tuples) return;
   const int lane = threadIdx.x & 63;
@@ -492,7 +503,7 @@ __global__ __launch_bounds__(BLOCK) void tuple_adjoint_kernel(const TupleDesc* _
 #pragma unroll
     for (int k = 0; k < MAXPOOL; ++k) {
       if (k < n) {
-        sincos_rev(fk[k] * ta, sv[k], cv[k]);
+        sincos_tab(fk[k] * ta, tab, sv[k], cv[k]);
         r -= th[1 + 2 * k] * cv[k] + th[2 + 2 * k] * sv[k];
       }
     }
@@ -539,6 +550,11 @@ __global__ __launch_bounds__(BLOCK) void tuple_adjoint_lanes_kernel(const TupleD
                                                                     const TupleState* __restrict__ state,
                                                                     double* __restrict__ dzdf,
                                                                     double* __restrict__ hout) {
+  __shared__ double2 tab[F32 ? 1 : TRIG_TAB];
+  if constexpr (!F32) {
+    trig_table_fill(tab);
+    __syncthreads();
+  }
   const int64_t gt = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
   const int grp = static_cast<int>(gt / L);
   const int r = static_cast<int>(gt % L);
@@ -564,7 +580,7 @@ __global__ __launch_bounds__(BLOCK) void tuple_adjoint_lanes_kernel(const TupleD
       double res = xt[i] - th[0];
 #pragma unroll
       for (int k = 0; k < NF; ++k) {
-        tuple_sincos<F32>(fk[k] * ta, sv[k], cv[k]);
+        tuple_sincos<F32>(fk[k] * ta, tab, sv[k], cv[k]);
         res -= th[1 + 2 * k] * cv[k] + th[2 + 2 * k] * sv[k];
       }
       const double wi = wt[i];
