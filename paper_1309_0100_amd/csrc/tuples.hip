@@ -102,9 +102,21 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
   double fk[NRMAX];
 #pragma unroll
   for (int r = 0; r < NRMAX; ++r) fk[r] = (live && c16 + 16 * r < n) ? f[c16 + 16 * r] : 0.0;
-  ColSel cd[NB];
+  // the lane's column in every 16-column block as arithmetic weights, so
+  // that the per-sample column values need no branches:
+  //   v = (sel ? sin : cos) (w_trig + w_ttrig t') + w_one + w_x x~
+  int kf[NB];
+  double w_sel[NB], w_trig[NB], w_ttrig[NB], w_one[NB], w_x[NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) cd[b] = col_sel(16 * b + c16, n, mode);
+  for (int b = 0; b < NB; ++b) {
+    const ColSel cd = col_sel(16 * b + c16, n, mode);
+    kf[b] = cd.kf;
+    w_sel[b] = cd.sel ? 1.0 : 0.0;
+    w_trig[b] = cd.kind == 2 ? 1.0 : 0.0;
+    w_ttrig[b] = cd.kind == 4 ? 1.0 : 0.0;
+    w_one[b] = cd.kind == 1 ? 1.0 : 0.0;
+    w_x[b] = cd.kind == 3 ? 1.0 : 0.0;
+  }
   double2(*tw)[16 * NRMAX] = trig[threadIdx.x >> 6];
   const double inv_sig = com->inv_sigma_t;
   constexpr int NTILE = NB * (NB + 1) / 2;
@@ -137,19 +149,15 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
         }
       }
       __builtin_amdgcn_wave_barrier();
-      // the lane's column value per block without divergent branches: one
-      // table read (frequency 0 for non-trig columns), then selects
+      // the lane's column value per block: one table read (frequency 0 for
+      // the non-trig columns) and the weights above
       const double tt = ta * inv_sig;
       double a[NB], bw[NB];
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const double2 cs = tw[kq][cd[b].kf];
-        const double tv = cd[b].sel ? cs.y : cs.x;
-        const double v = cd[b].kind == 2   ? tv
-                         : cd[b].kind == 4 ? tv * tt
-                         : cd[b].kind == 1 ? 1.0
-                         : cd[b].kind == 3 ? xi
-                                           : 0.0;
+        const double2 cs = tw[kq][kf[b]];
+        const double tv = __builtin_fma(cs.y - cs.x, w_sel[b], cs.x);
+        const double v = __builtin_fma(tv, __builtin_fma(w_ttrig[b], tt, w_trig[b]), __builtin_fma(w_x[b], xi, w_one[b]));
         a[b] = v;
         bw[b] = wi * v;
       }
