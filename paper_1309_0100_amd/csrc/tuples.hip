@@ -39,38 +39,14 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Column of one lane for one 16-column block: kind 0 zero, 1 one, 2 trig,
-// 3 data, 4 t' * trig; kf = the frequency of a trig column, sel = 0 cos, 1 sin.
-struct ColSel {
-  int kind, kf, sel;
-};
-
-__device__ __forceinline__ ColSel col_sel(int col, int n, int mode) {
-  ColSel d{0, 0, 0};
-  const int K = 2 * n + 1;
-  if (col == 0) {
-    d.kind = 1;
-  } else if (col < K) {
-    d.kind = 2;
-    d.kf = (col - 1) >> 1;
-    d.sel = (col - 1) & 1;
-  } else if (col == K) {
-    d.kind = 3;
-  } else if (mode == TUPLE_GN && col < 4 * n + 2) {
-    const int c2 = col - K - 1;
-    d.kind = 4;
-    d.kf = c2 >> 1;
-    d.sel = c2 & 1;
-  }
-  return d;
-}
-
 // One wavefront per tuple.  Per step of four samples, lane (c16, kq) first
 // evaluates cos and sin of the frequencies c16, c16 + 16, ... at sample kq
-// (one float64 sin/cos pair per frequency and sample, shared through a
-// wave-private LDS table), then reads the value of its own column for each
-// 16-column block, and the wave accumulates the lower-triangle blocks of the
-// Gram on float64 MFMA.
+// (one float64 sin/cos pair per frequency and sample) and writes the columns
+// they make (cos, sin, and in the Gauss-Newton mode t' cos, t' sin) into a
+// wave-private LDS table of the four samples' column values (the columns 1
+// and x~ by lane c16 = 0, the padding columns zero), then reads the value of
+// its own column for each 16-column block, and the wave accumulates the
+// lower-triangle blocks of the Gram on float64 MFMA.
 template <int NB>
 __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __restrict__ desc,
                                                            const int32_t* __restrict__ order, int n_order,
@@ -82,7 +58,7 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
                                                            double* __restrict__ gram, int mode) {
   constexpr int NRMAX = (NB + 1) / 2;  // frequencies per lane: n <= 8 NB - 1 columns' worth
   constexpr int TSZ = 256;             // samples per block-wide staging tile
-  __shared__ double2 trig[BLOCK / 64][4][16 * NRMAX];
+  __shared__ double colv[BLOCK / 64][4][16 * NB];  // per wave: the column values of the step's samples
   __shared__ double stage[3][TSZ];     // tau, x~, w~ of the tile, shared by the block's four tuples
   __shared__ double2 tab[TRIG_TAB];
   trig_table_fill(tab);
@@ -102,22 +78,11 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
   double fk[NRMAX];
 #pragma unroll
   for (int r = 0; r < NRMAX; ++r) fk[r] = (live && c16 + 16 * r < n) ? f[c16 + 16 * r] : 0.0;
-  // the lane's column in every 16-column block as arithmetic weights, so
-  // that the per-sample column values need no branches:
-  //   v = (sel ? sin : cos) (w_trig + w_ttrig t') + w_one + w_x x~
-  int kf[NB];
-  double w_sel[NB], w_trig[NB], w_ttrig[NB], w_one[NB], w_x[NB];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const ColSel cd = col_sel(16 * b + c16, n, mode);
-    kf[b] = cd.kf;
-    w_sel[b] = cd.sel ? 1.0 : 0.0;
-    w_trig[b] = cd.kind == 2 ? 1.0 : 0.0;
-    w_ttrig[b] = cd.kind == 4 ? 1.0 : 0.0;
-    w_one[b] = cd.kind == 1 ? 1.0 : 0.0;
-    w_x[b] = cd.kind == 3 ? 1.0 : 0.0;
-  }
-  double2(*tw)[16 * NRMAX] = trig[threadIdx.x >> 6];
+  const int K = 2 * n + 1;  // the x~ column; the t' columns follow it
+  const bool gn = mode == TUPLE_GN;
+  double(*cw)[16 * NB] = colv[threadIdx.x >> 6];
+  for (int e = lane; e < 4 * 16 * NB; e += 64) cw[e / (16 * NB)][e % (16 * NB)] = 0.0;  // padding stays zero
+  __builtin_amdgcn_wave_barrier();
   const double inv_sig = com->inv_sigma_t;
   constexpr int NTILE = NB * (NB + 1) / 2;
   v4d acc[NTILE];
@@ -140,26 +105,33 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
       const double ta = stage[0][il];
       const double xi = stage[1][il];
       const double wi = stage[2][il];
+      const double tt = ta * inv_sig;
 #pragma unroll
       for (int r = 0; r < NRMAX; ++r) {
         if (r < nr) {
+          const int kk = c16 + 16 * r;
           double sv, cv;
           sincos_tab(fk[r] * ta, tab, sv, cv);
-          tw[kq][c16 + 16 * r] = double2{cv, sv};
+          if (kk < n) {
+            cw[kq][1 + 2 * kk] = cv;
+            cw[kq][2 + 2 * kk] = sv;
+            if (gn) {
+              cw[kq][K + 1 + 2 * kk] = cv * tt;
+              cw[kq][K + 2 + 2 * kk] = sv * tt;
+            }
+          }
         }
       }
+      if (c16 == 0) {
+        cw[kq][0] = 1.0;
+        cw[kq][K] = xi;
+      }
       __builtin_amdgcn_wave_barrier();
-      // the lane's column value per block: one table read (frequency 0 for
-      // the non-trig columns) and the weights above
-      const double tt = ta * inv_sig;
       double a[NB], bw[NB];
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const double2 cs = tw[kq][kf[b]];
-        const double tv = __builtin_fma(cs.y - cs.x, w_sel[b], cs.x);
-        const double v = __builtin_fma(tv, __builtin_fma(w_ttrig[b], tt, w_trig[b]), __builtin_fma(w_x[b], xi, w_one[b]));
-        a[b] = v;
-        bw[b] = wi * v;
+        a[b] = cw[kq][16 * b + c16];
+        bw[b] = wi * a[b];
       }
       __builtin_amdgcn_wave_barrier();
       int q = 0;
