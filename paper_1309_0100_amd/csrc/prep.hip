@@ -319,6 +319,7 @@ __global__ __launch_bounds__(BLOCK) void prep_factor_kernel(const SeriesIn* __re
       gram[e] = v;
     }
   }
+  __syncthreads();  // the pivots below read entries summed by other threads
   // Cholesky A = L L^T (Sect. 3), right-looking: per column j the pivot and
   // the column below it, then the rank-one update of the trailing block, each
   // entry by its own thread (gram's rows 0..K-1 are overwritten; the original
