@@ -213,15 +213,21 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_lanes_kernel(const TupleDesc
   for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
   if (live) {
     const int64_t N = com->N;
+    // the next sample's tau, w~, x~ are loaded while this one is processed
+    double nta = r < N ? tau[r] : 0.0, nwi = r < N ? wt[r] : 0.0, nxi = r < N ? xt[r] : 0.0;
 #pragma unroll 1
     for (int64_t i = r; i < N; i += L) {
-      const double ta = tau[i];
-      const double wi = wt[i];
+      const double ta = nta, wi = nwi, xi = nxi;
+      if (i + L < N) {
+        nta = tau[i + L];
+        nwi = wt[i + L];
+        nxi = xt[i + L];
+      }
       double phi[C];
       phi[0] = 1.0;
 #pragma unroll
       for (int k = 0; k < NF; ++k) tuple_sincos<F32>(f[k] * ta, tab, phi[2 + 2 * k], phi[1 + 2 * k]);
-      phi[C - 1] = xt[i];
+      phi[C - 1] = xi;
 #pragma unroll
       for (int a = 0; a < C; ++a) {
         const double wa = wi * phi[a];
@@ -553,17 +559,23 @@ __global__ __launch_bounds__(BLOCK) void tuple_adjoint_lanes_kernel(const TupleD
   for (int k = 0; k < NF; ++k) g[k] = h2[k] = 0.0;
   const int64_t N = com->N;
   if (live) {
+    // the next sample's tau, w~, x~ are loaded while this one is processed
+    double nta = r < N ? tau[r] : 0.0, nwi = r < N ? wt[r] : 0.0, nxi = r < N ? xt[r] : 0.0;
 #pragma unroll 1
     for (int64_t i = r; i < N; i += L) {
-      const double ta = tau[i];
+      const double ta = nta, wi = nwi, xi = nxi;
+      if (i + L < N) {
+        nta = tau[i + L];
+        nwi = wt[i + L];
+        nxi = xt[i + L];
+      }
       double sv[NF], cv[NF];
-      double res = xt[i] - th[0];
+      double res = xi - th[0];
 #pragma unroll
       for (int k = 0; k < NF; ++k) {
         tuple_sincos<F32>(fk[k] * ta, tab, sv[k], cv[k]);
         res -= th[1 + 2 * k] * cv[k] + th[2 + 2 * k] * sv[k];
       }
-      const double wi = wt[i];
       const double tpi = 2.0 * M_PI * ta;
       const double wr = wi * res;
 #pragma unroll
