@@ -50,7 +50,10 @@ def test_plain_workload_full_grid(ctx):
     assert np.array_equal(O.local_maxima(zz, fl.cpu().numpy()), O.local_maxima(ref.z, ref.flags))
 
 
-@pytest.mark.parametrize("m,N,F", [(1, 150, 3001), (2, 300, 5000), (4, 257, 2049), (7, 400, 1500), (12, 300, 700)])
+# (the preparation works in tiles of 256 samples for KP <= 18, 64 for the
+# largest base model m = 24: exact multiples, ragged tails and many tiles)
+@pytest.mark.parametrize("m,N,F", [(1, 150, 3001), (2, 300, 5000), (4, 257, 2049), (7, 400, 1500), (12, 300, 700),
+                                   (0, 256, 999), (4, 512, 1000), (24, 400, 600)])
 def test_base_models_ragged(ctx, m, N, F):
     s = synth.random_series(100 + m, N, span=300.0, n_sin=3)
     rng = np.random.default_rng(m)

@@ -72,7 +72,7 @@ def test_fp32_residual_workload_sampled(ctx):
 
 
 @pytest.mark.parametrize("m,N,F", [(0, 500, 3001), (3, 400, 2500), (7, 600, 2049), (8, 700, 1500),
-                                   (12, 500, 1300), (20, 900, 700)])
+                                   (12, 500, 1300), (20, 900, 700), (24, 400, 600)])
 def test_fp32_base_models(ctx, m, N, F):
     from paper_1309_0100_amd import fredec as Fr
     s = synth.random_series(400 + m, N, span=500.0, n_sin=3)
