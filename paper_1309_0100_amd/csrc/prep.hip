@@ -172,7 +172,7 @@ __global__ __launch_bounds__(BLOCK) void prep_stats_kernel(const SeriesIn* __res
 
 // ------------------------------------------------------- rows and factorisation
 __global__ __launch_bounds__(BLOCK) void prep_rows_kernel(int n_series, const SeriesIn* __restrict__ sin_,
-                                                          SeriesHdr* __restrict__ hdr, const double* __restrict__ t,
+                                                          const SeriesHdr* __restrict__ hdr, const double* __restrict__ t,
                                                           const double* __restrict__ x,
                                                           const double* __restrict__ w, double* __restrict__ tau,
                                                           double* __restrict__ xt, double* __restrict__ wt,
@@ -182,11 +182,10 @@ __global__ __launch_bounds__(BLOCK) void prep_rows_kernel(int n_series, const Se
   const int tid = threadIdx.x;
   const int s = tile_series(sin_, n_series, blockIdx.x);
   const SeriesIn& si = sin_[s];
-  SeriesHdr& h = hdr[s];
+  const SeriesHdr& h = hdr[s];
   if (h.status != 0) return;
   const int64_t N = si.N;
   const int KP = si.KP;
-  const int K = KP - 1;
   const int m = si.m;
   const int RS = prep_rs(KP);
   const int T = si.prows;
