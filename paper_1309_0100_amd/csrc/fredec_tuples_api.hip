@@ -174,7 +174,7 @@ int normalise(hipStream_t st, const TuplePlan& P, const TupleDev& D, const doubl
 int gram_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, int mode) {
   ProfScope prof(ctx, st);
   for (const auto& g : P.groups) {
-    if (launch_tuple_gram(st, g.nb, g.nf, ctx->n_cu, D.desc, D.order + g.begin, g.count, P.N, D.com, D.tau, D.xt,
+    if (launch_tuple_gram(st, g.nf, ctx->n_cu, D.desc, D.order + g.begin, g.count, P.N, D.com, D.tau, D.xt,
                           D.wt, D.ftry, D.state, D.gram, mode, P.precision == FREDEC_FP32) != hipSuccess)
       return FREDEC_EDEVICE;
   }

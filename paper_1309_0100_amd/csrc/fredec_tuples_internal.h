@@ -42,10 +42,11 @@ struct TupleState {
 // Whether tuples of n frequencies in this mode go to the lane-group VALU
 // kernels (launches then take a group of tuples of exactly n).
 bool tuple_lanes_supported(int n, int mode);
-// nf: the exact size of every tuple of the group; NB: 16-column blocks of the
-// MFMA kernel used otherwise; n_cu sizes the lane groups; N samples; f32: the
-// reduced-precision trig of the lane-group kernels (the MFMA kernel is float64).
-hipError_t launch_tuple_gram(hipStream_t st, int NB, int nf, int n_cu, const TupleDesc* desc, const int32_t* order,
+// nf: the exact size of every tuple of the group (it and the mode fix the
+// MFMA kernel's column layout otherwise); n_cu sizes the lane groups; N
+// samples; f32: the reduced-precision trig of the lane-group kernels (the MFMA
+// kernel is float64).
+hipError_t launch_tuple_gram(hipStream_t st, int nf, int n_cu, const TupleDesc* desc, const int32_t* order,
                              int n_order, int64_t N, const TupleCommon* com, const double* tau, const double* xt,
                              const double* wt, const double* ftry, const TupleState* state, double* gram, int mode,
                              bool f32);

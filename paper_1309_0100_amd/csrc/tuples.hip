@@ -1,7 +1,7 @@
 // Tuple statistics z_n(f_1..f_n) (eq. zpow), their local refinement by
 // Gauss-Newton steps (Sect. 3, eq. lsqf) and the adjoint gradient.
 //
-// tuple_gram_kernel: one wavefront per tuple builds the weighted Gram matrix
+// tuple_gram_kernel: one workgroup per tuple builds the weighted Gram matrix
 //   G = sum_i w~_i phi(t_i) phi(t_i)^T
 // of on-the-fly generated columns on float64 MFMA (v_mfma_f64_16x16x4_f64):
 //   forward columns  1, cos 2 pi f_k t, sin 2 pi f_k t (k = 1..n), x~
@@ -39,7 +39,10 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// One wavefront per tuple.  Per step of four samples, lane (c16, kq) first
+// One workgroup per tuple; its four wavefronts take every fourth step of four
+// samples and add their partial Gram matrices in wave order at the end (short
+// workgroups, so that the last round of a launch leaves little of the GPU
+// idle).  Per step, lane (c16, kq) first
 // evaluates cos and sin of the frequencies c16, c16 + 16, ... at sample kq
 // (one float64 sin/cos pair per frequency and sample) and writes the columns
 // they make (cos, sin, and in the Gauss-Newton mode t' cos, t' sin) into a
@@ -47,7 +50,16 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // and x~ by lane c16 = 0, the padding columns zero), then reads the value of
 // its own column for each 16-column block, and the wave accumulates the
 // lower-triangle blocks of the Gram on float64 MFMA.
-template <int NB>
+//
+// Column layout.  TV = 0: the blocks hold the Gram's own column order
+// (1, cos/sin pairs, x~, t' cos/sin pairs), padded to 16 NB.  TV > 0: the
+// blocks hold only the trigonometric columns (the cos/sin pairs, then the
+// t' pairs) and TV extra columns, 1, x~ and the trigonometric columns past
+// 16 NB, are accumulated against every column on the VALU (TV multiply-adds
+// per block and sample, summed over the four sample lanes at the end).  The
+// host picks TV > 0 where it saves a block: a 16x16x4 float64 MFMA costs the
+// issue time of 16 float64 multiply-adds.
+template <int NB, int TV>
 __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __restrict__ desc,
                                                            const int32_t* __restrict__ order, int n_order,
                                                            const TupleCommon* __restrict__ com,
@@ -56,38 +68,62 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
                                                            const double* __restrict__ ftry,
                                                            const TupleState* __restrict__ state,
                                                            double* __restrict__ gram, int mode) {
-  constexpr int NRMAX = (NB + 1) / 2;  // frequencies per lane: n <= 8 NB - 1 columns' worth
-  constexpr int TSZ = 256;             // samples per block-wide staging tile
-  __shared__ double colv[BLOCK / 64][4][16 * NB];  // per wave: the column values of the step's samples
-  __shared__ double stage[3][TSZ];     // tau, x~, w~ of the tile, shared by the block's four tuples
+  // frequencies per lane: n <= 8 NB - 1 (TV = 0) or 2 n <= 16 NB + 4
+  constexpr int NRMAX = TV == 0 ? (NB + 1) / 2 : (8 * NB + 2 + 15) / 16;
+  constexpr int XO = 16 * NB;             // first extra slot (TV > 0)
+  constexpr int CW = XO + (TV > 0 ? 16 : 0);
+  constexpr int TSZ = 1024;               // samples per block-wide staging tile
+  constexpr int NW = BLOCK / 64;
+  __shared__ double colv[NW][4][CW];      // per wave: the column values of the step's samples
+  __shared__ double stage[3][TSZ];        // tau, x~, w~ of the tile
   __shared__ double2 tab[TRIG_TAB];
+  // one tuple per block (the launch has n_order blocks)
+  const int ti = order[blockIdx.x];
+  if (state[ti].done) return;  // uniform over the block
   trig_table_fill(tab);
-  const int wave = (blockIdx.x * BLOCK + threadIdx.x) >> 6;
+  const int wb = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  // every wave takes part in the staging and its barriers; waves without a
-  // live tuple skip the arithmetic
-  const int ti = wave < n_order ? order[wave] : 0;
-  const bool live = wave < n_order && !state[ti].done;
   const TupleDesc& d = desc[ti];
   const int n = d.n;
-  const int C = (mode == TUPLE_GN) ? 4 * n + 2 : 2 * n + 2;
+  const bool gn = mode == TUPLE_GN;
+  const int C = gn ? 4 * n + 2 : 2 * n + 2;
+  const int T = C - 2;       // trigonometric columns
+  const int K = 2 * n + 1;   // the x~ column; the t' columns follow it
   const double* f = ftry + d.foff;
   const int c16 = lane & 15;
   const int kq = lane >> 4;
   const int nr = (n + 15) >> 4;
+  // Gram column of trigonometric column q (cos/sin pairs, then t' pairs)
+  auto gcol = [&](int q) { return q < 2 * n ? q + 1 : q + 2; };
+  // table slot of trigonometric column q
+  auto tslot = [&](int q) { return TV == 0 ? gcol(q) : (q < XO ? q : q + 2); };
+  // frequency, and the slots of its cos/sin and t' cos/sin pairs (a pair
+  // never straddles 16 NB: both are even)
   double fk[NRMAX];
+  int sl[NRMAX], st[NRMAX];
 #pragma unroll
-  for (int r = 0; r < NRMAX; ++r) fk[r] = (live && c16 + 16 * r < n) ? f[c16 + 16 * r] : 0.0;
-  const int K = 2 * n + 1;  // the x~ column; the t' columns follow it
-  const bool gn = mode == TUPLE_GN;
-  double(*cw)[16 * NB] = colv[threadIdx.x >> 6];
-  for (int e = lane; e < 4 * 16 * NB; e += 64) cw[e / (16 * NB)][e % (16 * NB)] = 0.0;  // padding stays zero
+  for (int r = 0; r < NRMAX; ++r) {
+    const int kk = c16 + 16 * r;
+    fk[r] = kk < n ? f[kk] : 0.0;
+    sl[r] = kk < n ? tslot(2 * kk) : 0;
+    st[r] = kk < n ? tslot(2 * n + 2 * kk) : 0;
+  }
+  const int slot1 = TV == 0 ? 0 : XO;
+  const int slotx = TV == 0 ? K : XO + 1;
+  double(*cw)[CW] = colv[wb];
+  for (int e = lane; e < 4 * CW; e += 64) cw[e / CW][e % CW] = 0.0;  // padding stays zero
   __builtin_amdgcn_wave_barrier();
   const double inv_sig = com->inv_sigma_t;
   constexpr int NTILE = NB * (NB + 1) / 2;
   v4d acc[NTILE];
 #pragma unroll
   for (int q = 0; q < NTILE; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  constexpr int TVA = TV > 0 ? TV : 1;
+  double xacc[TVA][NB + 1];
+#pragma unroll
+  for (int j = 0; j < TVA; ++j)
+#pragma unroll
+    for (int b = 0; b <= NB; ++b) xacc[j][b] = 0.0;
   const int64_t N = com->N;
   for (int64_t t0 = 0; t0 < N; t0 += TSZ) {
     const int ns = N - t0 < TSZ ? static_cast<int>(N - t0) : TSZ;
@@ -99,8 +135,8 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
       stage[2][k] = in ? wt[t0 + k] : 0.0;
     }
     __syncthreads();
-    if (!live) continue;
-    for (int s0 = 0; s0 < ns; s0 += 4) {
+    // the block's waves take every fourth step of four samples
+    for (int s0 = 4 * wb; s0 < ns; s0 += 4 * NW) {
       const int il = s0 + kq;  // beyond ns the staged weight is 0
       const double ta = stage[0][il];
       const double xi = stage[1][il];
@@ -113,18 +149,18 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
           double sv, cv;
           sincos_tab(fk[r] * ta, tab, sv, cv);
           if (kk < n) {
-            cw[kq][1 + 2 * kk] = cv;
-            cw[kq][2 + 2 * kk] = sv;
+            cw[kq][sl[r]] = cv;
+            cw[kq][sl[r] + 1] = sv;
             if (gn) {
-              cw[kq][K + 1 + 2 * kk] = cv * tt;
-              cw[kq][K + 2 + 2 * kk] = sv * tt;
+              cw[kq][st[r]] = cv * tt;
+              cw[kq][st[r] + 1] = sv * tt;
             }
           }
         }
       }
       if (c16 == 0) {
-        cw[kq][0] = 1.0;
-        cw[kq][K] = xi;
+        cw[kq][slot1] = 1.0;
+        cw[kq][slotx] = xi;
       }
       __builtin_amdgcn_wave_barrier();
       double a[NB], bw[NB];
@@ -132,6 +168,16 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
       for (int b = 0; b < NB; ++b) {
         a[b] = cw[kq][16 * b + c16];
         bw[b] = wi * a[b];
+      }
+      if constexpr (TV > 0) {
+        const double ax = cw[kq][XO + c16];
+#pragma unroll
+        for (int j = 0; j < TV; ++j) {
+          const double ej = wi * cw[kq][XO + j];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) xacc[j][b] = __builtin_fma(ej, a[b], xacc[j][b]);
+          xacc[j][NB] = __builtin_fma(ej, ax, xacc[j][NB]);
+        }
       }
       __builtin_amdgcn_wave_barrier();
       int q = 0;
@@ -144,7 +190,43 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
         }
     }
   }
-  if (!live) return;
+  // the waves' partial sums added in wave order through LDS (the staging
+  // tile holds NW - 1 waves' four values per lane), then written by wave 0
+  double* red = &stage[0][0];
+  static_assert(3 * TSZ >= (NW - 1) * 4 * 64, "reduction scratch");
+  auto reduce4 = [&](v4d& v) {
+    __syncthreads();
+    if (wb > 0) {
+      double* r = red + (wb - 1) * 256 + lane;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) r[64 * k] = v[k];
+    }
+    __syncthreads();
+    if (wb == 0) {
+#pragma unroll
+      for (int w = 1; w < NW; ++w) {
+        const double* r = red + (w - 1) * 256 + lane;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += r[64 * k];
+      }
+    }
+  };
+#pragma unroll
+  for (int q = 0; q < NTILE; ++q) reduce4(acc[q]);
+  if constexpr (TV > 0) {
+    constexpr int NX = TV * (NB + 1);
+#pragma unroll
+    for (int e = 0; e < NX; e += 4) {
+      v4d v;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = e + k < NX ? xacc[(e + k) / (NB + 1)][(e + k) % (NB + 1)] : 0.0;
+      reduce4(v);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (e + k < NX) xacc[(e + k) / (NB + 1)][(e + k) % (NB + 1)] = v[k];
+    }
+  }
+  if (wb != 0) return;
   // D[i][j] of block (b1, b2) sits in lane j + 16 (i % 4), register i / 4
   double* G = gram + d.goff;
   int q = 0;
@@ -156,10 +238,41 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * b1 + kq + 4 * v;
         const int c = 16 * b2 + c16;
-        if (r < C && c <= r) G[r * (r + 1) / 2 + c] = acc[q][v];
+        if (TV == 0) {
+          if (r < C && c <= r) G[r * (r + 1) / 2 + c] = acc[q][v];
+        } else if (r < T && c <= r) {
+          const int gr = gcol(r), gc = gcol(c);
+          G[gr * (gr + 1) / 2 + gc] = acc[q][v];
+        }
       }
       ++q;
     }
+  if constexpr (TV > 0) {
+    // the extra columns' sums over the four sample lanes; lane c16 < 16 then
+    // holds <w~ e_j col> for the block column 16 b + c16 and extra column c16
+    auto xcol = [&](int j) { return j == 0 ? 0 : j == 1 ? K : gcol(XO + j - 2); };
+#pragma unroll
+    for (int j = 0; j < TV; ++j) {
+      const int gj = xcol(j);
+#pragma unroll
+      for (int b = 0; b <= NB; ++b) {
+        double v = xacc[j][b];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        int gc = -1;
+        if (b < NB) {
+          if (16 * b + c16 < T && 16 * b + c16 < XO) gc = gcol(16 * b + c16);
+        } else if (c16 < TV) {
+          gc = xcol(c16);
+          if (gc > gj) gc = -1;  // each extra pair once
+        }
+        if (kq == 0 && gc >= 0) {
+          const int r = gj > gc ? gj : gc, c = gj > gc ? gc : gj;
+          G[r * (r + 1) / 2 + c] = v;
+        }
+      }
+    }
+  }
 }
 
 
@@ -655,13 +768,44 @@ __global__ void copy_f64_kernel(const double* __restrict__ src, double* __restri
   if (i < n) dst[i] = src[i];
 }
 
-template <int NB>
+template <int NB, int TV>
 hipError_t gram_nb(hipStream_t st, const TupleDesc* desc, const int32_t* order, int n_order, const TupleCommon* com,
                    const double* tau, const double* xt, const double* wt, const double* ftry, const TupleState* state,
                    double* gram, int mode) {
-  const int blocks = (n_order + 3) / 4;
-  tuple_gram_kernel<NB><<<blocks, BLOCK, 0, st>>>(desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+  tuple_gram_kernel<NB, TV><<<n_order, BLOCK, 0, st>>>(desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
   return hipGetLastError();
+}
+
+// Column layout of the MFMA Gram kernel for tuples of n frequencies: all C
+// columns in ceil(C / 16) blocks (TV = 0), or the T = C - 2 trigonometric
+// columns in floor(T / 16) blocks and TV = 2 + T % 16 <= 6 extra columns on
+// the VALU, whichever costs fewer issue cycles (a float64 16x16x4 MFMA
+// 64, a float64 multiply-add 4, per step of four samples).
+void gram_layout(int n, int mode, int& NB, int& TV) {
+  const int C = mode == TUPLE_GN ? 4 * n + 2 : 2 * n + 2;
+  const int T = C - 2;
+  NB = (C + 15) / 16;
+  TV = 0;
+  const int nbm = T / 16, tail = T % 16;
+  if (nbm < 1 || nbm > 4 || tail > 4) return;
+  const int cost0 = 64 * NB * (NB + 1) / 2;
+  const int cost1 = 64 * nbm * (nbm + 1) / 2 + 4 * (2 + tail) * (nbm + 1);
+  if (cost1 < cost0) {
+    NB = nbm;
+    TV = 2 + tail;
+  }
+}
+
+template <int NB>
+hipError_t gram_tv(int TV, hipStream_t st, const TupleDesc* desc, const int32_t* order, int n_order,
+                   const TupleCommon* com, const double* tau, const double* xt, const double* wt, const double* ftry,
+                   const TupleState* state, double* gram, int mode) {
+  switch (TV) {
+    case 2: return gram_nb<NB, 2>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    case 4: return gram_nb<NB, 4>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    case 6: return gram_nb<NB, 6>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // Lanes per tuple for a group of n_order tuples of N samples: enough groups
@@ -727,7 +871,7 @@ hipError_t adjoint_nf(hipStream_t st, int L, const TupleDesc* desc, const int32_
 
 bool tuple_lanes_supported(int n, int mode) { return mode == TUPLE_FWD && n >= 1 && n <= LANES_MAX_N; }
 
-hipError_t launch_tuple_gram(hipStream_t st, int NB, int nf, int n_cu, const TupleDesc* desc, const int32_t* order,
+hipError_t launch_tuple_gram(hipStream_t st, int nf, int n_cu, const TupleDesc* desc, const int32_t* order,
                              int n_order, int64_t N, const TupleCommon* com, const double* tau, const double* xt,
                              const double* wt, const double* ftry, const TupleState* state, double* gram,
                              int mode, bool f32) {
@@ -755,14 +899,25 @@ hipError_t launch_tuple_gram(hipStream_t st, int NB, int nf, int n_cu, const Tup
       default: return hipErrorInvalidValue;
     }
   }
-  switch (NB) {
-    case 1: return gram_nb<1>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
-    case 2: return gram_nb<2>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
-    case 3: return gram_nb<3>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
-    case 4: return gram_nb<4>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
-    case 5: return gram_nb<5>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
-    case 6: return gram_nb<6>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
-    case 7: return gram_nb<7>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+  int nb = 0, tv = 0;
+  gram_layout(nf, mode, nb, tv);
+  if (tv > 0) {
+    switch (nb) {
+      case 1: return gram_tv<1>(tv, st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+      case 2: return gram_tv<2>(tv, st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+      case 3: return gram_tv<3>(tv, st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+      case 4: return gram_tv<4>(tv, st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (nb) {
+    case 1: return gram_nb<1, 0>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    case 2: return gram_nb<2, 0>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    case 3: return gram_nb<3, 0>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    case 4: return gram_nb<4, 0>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    case 5: return gram_nb<5, 0>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    case 6: return gram_nb<6, 0>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
+    case 7: return gram_nb<7, 0>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, mode);
     default: return hipErrorInvalidValue;
   }
 }

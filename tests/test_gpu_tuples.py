@@ -96,6 +96,52 @@ def test_refined_subsets_match_oracle_gn(ctx):
         assert bool(fl[mask - 1] & 16) == r.converged
 
 
+def _many_sines(seed, N, n_sin):
+    """Weighted series with n_sin well separated sinusoids (spacing 0.037,
+    about 18 / span) and Gaussian noise."""
+    rng = np.random.default_rng(seed)
+    t = np.sort(rng.uniform(0.0, 500.0, size=N))
+    fr = 0.05 + 0.037 * np.arange(n_sin)
+    amp = rng.uniform(1.0, 3.0, size=n_sin)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=n_sin)
+    sig = rng.uniform(0.5, 1.5, size=N)
+    x = (amp[None, :] * np.sin(2.0 * np.pi * fr[None, :] * t[:, None] + ph[None, :])).sum(axis=1)
+    x = x + 0.3 * sig * rng.standard_normal(N)
+    return t, x, 1.0 / sig**2, fr
+
+
+@pytest.mark.parametrize("refine", [0, 3])
+def test_gram_column_layouts(ctx, refine):
+    """Tuples of every size 1..24 (forward) and 1..24 (Gauss-Newton): every
+    column layout of the MFMA Gram kernel (all columns in 16-column blocks, or
+    the trigonometric columns in blocks and 1, x~ and a short tail of them
+    accumulated on the VALU)."""
+    n_pool = 24
+    t, x, w, fr = _many_sines(741, 1200, n_pool)
+    nrm = O.normalize(t, x, w)
+    rng = np.random.default_rng(742)
+    pool = fr + rng.uniform(-0.1, 0.1, size=n_pool) / nrm.T_eff
+    masks = [(1 << k) - 1 for k in range(1, n_pool + 1)]
+    for k in (5, 8, 9, 12, 13, 16, 17):
+        masks.append(int(sum(1 << int(i) for i in rng.choice(n_pool, size=k, replace=False))))
+    masks = np.array(masks, np.uint64)
+    print(f"case: gram layouts refine={refine}", flush=True)
+    l, z, f, fl = (a.cpu().numpy() for a in ctx.tuples(t, x, w, pool, masks=masks, refine_steps=refine))
+    for k, m in enumerate(masks):
+        mem = members(int(m), n_pool)
+        if refine == 0:
+            zr, lr, _, flr = O.tuple_fit(nrm, pool[mem])
+            assert fl[k] == flr
+            assert zerr(z[k], zr) <= TOL64, (len(mem), z[k], zr)
+            assert abs(l[k] - lr) <= 1e-9 * lr, (len(mem), l[k], lr)
+        else:
+            r = O.gn_refine(nrm, pool[mem], refine)
+            assert abs(l[k] - r.l) <= 1e-9 * r.l, (len(mem), l[k], r.l)
+            assert np.max(np.abs(f[k][mem] - r.f)) * nrm.T_eff < 1e-7, len(mem)
+            assert zerr(z[k], r.z) <= TOL64, (len(mem), z[k], r.z)
+            assert bool(fl[k] & 16) == r.converged
+
+
 def _ragged(rng, pool, n_tuples, n_max, T):
     sizes = rng.integers(1, n_max + 1, size=n_tuples)
     toff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
