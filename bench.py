@@ -73,7 +73,8 @@ def f32_kernel(KP):
 
 # HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (KiB per dispatch), scaled by
 # what the same counters read for a plain device copy of known size (FETCH x2.0, WRITE x1.0).  A
-# figure is only used while the kernel source still has the hash it was measured with.
+# figure is only used while the kernel source and its compile flags still have the hash it was
+# measured with (source_hash).
 COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = {
     "scan_f64_kernel": {"src": "scan_f64.hip", "sha1": "2f187ae1836dd72a375fe29397e974041ee9c147",
@@ -88,16 +89,23 @@ TRAFFIC = {
 }
 
 
+def source_hash(src):
+    """sha1 of a kernel source file followed by its per-file compile flags."""
+    import hashlib
+    from paper_1309_0100_amd import build
+    with open(os.path.join(build.CSRC, src), "rb") as fh:
+        h = hashlib.sha1(fh.read())
+    h.update(" ".join(build.FILE_FLAGS.get(src, [])).encode())
+    return h.hexdigest()
+
+
 def traffic_bytes(kernel):
     """Measured HBM bytes per launch of `kernel`, or None when not measured for the current source."""
-    import hashlib
     t = TRAFFIC.get(kernel)
     if not t or t["fetch_kib"] is None:
         return None
-    path = os.path.join(ROOT, "paper_1309_0100_amd", "csrc", t["src"])
-    with open(path, "rb") as fh:
-        if hashlib.sha1(fh.read()).hexdigest() != t["sha1"]:
-            return None
+    if source_hash(t["src"]) != t["sha1"]:
+        return None
     return 1024.0 * (COUNTER_SCALE["fetch"] * t["fetch_kib"] + COUNTER_SCALE["write"] * t["write_kib"])
 
 

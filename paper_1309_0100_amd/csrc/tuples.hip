@@ -42,14 +42,15 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // One workgroup per tuple; its four wavefronts take every fourth step of four
 // samples and add their partial Gram matrices in wave order at the end (short
 // workgroups, so that the last round of a launch leaves little of the GPU
-// idle).  Per step, lane (c16, kq) first
-// evaluates cos and sin of the frequencies c16, c16 + 16, ... at sample kq
-// (one float64 sin/cos pair per frequency and sample) and writes the columns
-// they make (cos, sin, and in the Gauss-Newton mode t' cos, t' sin) into a
-// wave-private LDS table of the four samples' column values (the columns 1
-// and x~ by lane c16 = 0, the padding columns zero), then reads the value of
-// its own column for each 16-column block, and the wave accumulates the
-// lower-triangle blocks of the Gram on float64 MFMA.
+// idle).  Per step of eight samples, lane (c8, s8) first evaluates cos and
+// sin of the frequencies c8, c8 + 8, ... at sample s8 (one float64 sin/cos
+// pair per frequency and sample) and writes the columns they make (cos, sin,
+// and in the Gauss-Newton mode t' cos, t' sin) into a wave-private LDS table
+// of the eight samples' column values (the columns 1 and x~ by lane c8 = 0,
+// the padding columns zero); then, for each half of four samples, lane
+// (c16, kq) reads the value of its column 16 b + c16 at sample kq for every
+// 16-column block b, and the wave accumulates the lower-triangle blocks of
+// the Gram on float64 MFMA.
 //
 // Column layout.  TV = 0: the blocks hold the Gram's own column order
 // (1, cos/sin pairs, x~, t' cos/sin pairs), padded to 16 NB.  TV > 0: the
@@ -68,13 +69,15 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
                                                            const double* __restrict__ ftry,
                                                            const TupleState* __restrict__ state,
                                                            double* __restrict__ gram, int mode) {
-  // frequencies per lane: n <= 8 NB - 1 (TV = 0) or 2 n <= 16 NB + 4
-  constexpr int NRMAX = TV == 0 ? (NB + 1) / 2 : (8 * NB + 2 + 15) / 16;
+  // frequencies per lane (eight per pass): n <= 8 NB - 1 (TV = 0) or
+  // 2 n <= 16 NB + 4
+  constexpr int NRMAX = TV == 0 ? NB : NB + 1;
   constexpr int XO = 16 * NB;             // first extra slot (TV > 0)
   constexpr int CW = XO + (TV > 0 ? 16 : 0);
-  constexpr int TSZ = 1024;               // samples per block-wide staging tile
+  constexpr int TSZ = 512;                // samples per block-wide staging tile
   constexpr int NW = BLOCK / 64;
-  __shared__ double colv[NW][4][CW];      // per wave: the column values of the step's samples
+  constexpr int SP = 8;                   // samples per step
+  __shared__ double colv[NW][SP][CW];     // per wave: the column values of the step's samples
   __shared__ double stage[3][TSZ];        // tau, x~, w~ of the tile
   __shared__ double2 tab[TRIG_TAB];
   // one tuple per block (the launch has n_order blocks)
@@ -90,9 +93,11 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
   const int T = C - 2;       // trigonometric columns
   const int K = 2 * n + 1;   // the x~ column; the t' columns follow it
   const double* f = ftry + d.foff;
-  const int c16 = lane & 15;
-  const int kq = lane >> 4;
-  const int nr = (n + 15) >> 4;
+  const int c16 = lane & 15;  // MFMA operands: column within the block
+  const int kq = lane >> 4;   // and sample within the four of an MFMA
+  const int c8 = lane & 7;    // trigonometry: frequency c8 + 8 r
+  const int s8 = lane >> 3;   // at sample s8 of the step
+  const int nr = (n + 7) >> 3;
   // Gram column of trigonometric column q (cos/sin pairs, then t' pairs)
   auto gcol = [&](int q) { return q < 2 * n ? q + 1 : q + 2; };
   // table slot of trigonometric column q
@@ -103,7 +108,7 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
   int sl[NRMAX], st[NRMAX];
 #pragma unroll
   for (int r = 0; r < NRMAX; ++r) {
-    const int kk = c16 + 16 * r;
+    const int kk = c8 + 8 * r;
     fk[r] = kk < n ? f[kk] : 0.0;
     sl[r] = kk < n ? tslot(2 * kk) : 0;
     st[r] = kk < n ? tslot(2 * n + 2 * kk) : 0;
@@ -111,7 +116,7 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
   const int slot1 = TV == 0 ? 0 : XO;
   const int slotx = TV == 0 ? K : XO + 1;
   double(*cw)[CW] = colv[wb];
-  for (int e = lane; e < 4 * CW; e += 64) cw[e / CW][e % CW] = 0.0;  // padding stays zero
+  for (int e = lane; e < SP * CW; e += 64) cw[e / CW][e % CW] = 0.0;  // padding stays zero
   __builtin_amdgcn_wave_barrier();
   const double inv_sig = com->inv_sigma_t;
   constexpr int NTILE = NB * (NB + 1) / 2;
@@ -135,138 +140,140 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
       stage[2][k] = in ? wt[t0 + k] : 0.0;
     }
     __syncthreads();
-    // the block's waves take every fourth step of four samples
-    for (int s0 = 4 * wb; s0 < ns; s0 += 4 * NW) {
-      const int il = s0 + kq;  // beyond ns the staged weight is 0
-      const double ta = stage[0][il];
-      const double xi = stage[1][il];
-      const double wi = stage[2][il];
-      const double tt = ta * inv_sig;
+    // the block's waves take every fourth step of eight samples: one sin/cos
+    // pass over eight frequencies x eight samples, then two MFMA steps of four
+    for (int s0 = SP * wb; s0 < ns; s0 += SP * NW) {
+      {
+        const int il = s0 + s8;  // beyond ns the staged values are 0
+        const double ta = stage[0][il];
+        const double tt = ta * inv_sig;
 #pragma unroll
-      for (int r = 0; r < NRMAX; ++r) {
-        if (r < nr) {
-          const int kk = c16 + 16 * r;
-          double sv, cv;
-          sincos_tab(fk[r] * ta, tab, sv, cv);
-          if (kk < n) {
-            cw[kq][sl[r]] = cv;
-            cw[kq][sl[r] + 1] = sv;
-            if (gn) {
-              cw[kq][st[r]] = cv * tt;
-              cw[kq][st[r] + 1] = sv * tt;
+        for (int r = 0; r < NRMAX; ++r) {
+          if (r < nr) {
+            const int kk = c8 + 8 * r;
+            double sv, cv;
+            sincos_tab(fk[r] * ta, tab, sv, cv);
+            if (kk < n) {
+              cw[s8][sl[r]] = cv;
+              cw[s8][sl[r] + 1] = sv;
+              if (gn) {
+                cw[s8][st[r]] = cv * tt;
+                cw[s8][st[r] + 1] = sv * tt;
+              }
             }
           }
         }
-      }
-      if (c16 == 0) {
-        cw[kq][slot1] = 1.0;
-        cw[kq][slotx] = xi;
-      }
-      __builtin_amdgcn_wave_barrier();
-      double a[NB], bw[NB];
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        a[b] = cw[kq][16 * b + c16];
-        bw[b] = wi * a[b];
-      }
-      if constexpr (TV > 0) {
-        const double ax = cw[kq][XO + c16];
-#pragma unroll
-        for (int j = 0; j < TV; ++j) {
-          const double ej = wi * cw[kq][XO + j];
-#pragma unroll
-          for (int b = 0; b < NB; ++b) xacc[j][b] = __builtin_fma(ej, a[b], xacc[j][b]);
-          xacc[j][NB] = __builtin_fma(ej, ax, xacc[j][NB]);
+        if (c8 == 0) {
+          cw[s8][slot1] = 1.0;
+          cw[s8][slotx] = stage[1][il];
         }
       }
       __builtin_amdgcn_wave_barrier();
-      int q = 0;
+      double a[2][NB], ax[2], ex[2][TVA], wi[2];
 #pragma unroll
-      for (int b1 = 0; b1 < NB; ++b1)
+      for (int u = 0; u < 2; ++u) {
+        const int row = 4 * u + kq;
+        wi[u] = stage[2][s0 + row];
 #pragma unroll
-        for (int b2 = 0; b2 <= b1; ++b2) {
-          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[b1], bw[b2], acc[q], 0, 0, 0);
-          ++q;
+        for (int b = 0; b < NB; ++b) a[u][b] = cw[row][16 * b + c16];
+        if constexpr (TV > 0) {
+          ax[u] = cw[row][XO + c16];
+#pragma unroll
+          for (int j = 0; j < TV; ++j) ex[u][j] = cw[row][XO + j];
         }
-    }
-  }
-  // the waves' partial sums added in wave order through LDS (the staging
-  // tile holds NW - 1 waves' four values per lane), then written by wave 0
-  double* red = &stage[0][0];
-  static_assert(3 * TSZ >= (NW - 1) * 4 * 64, "reduction scratch");
-  auto reduce4 = [&](v4d& v) {
-    __syncthreads();
-    if (wb > 0) {
-      double* r = red + (wb - 1) * 256 + lane;
+      }
+      __builtin_amdgcn_wave_barrier();
 #pragma unroll
-      for (int k = 0; k < 4; ++k) r[64 * k] = v[k];
-    }
-    __syncthreads();
-    if (wb == 0) {
+      for (int u = 0; u < 2; ++u) {
+        double bw[NB];
 #pragma unroll
-      for (int w = 1; w < NW; ++w) {
-        const double* r = red + (w - 1) * 256 + lane;
+        for (int b = 0; b < NB; ++b) bw[b] = wi[u] * a[u][b];
+        if constexpr (TV > 0) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] += r[64 * k];
+          for (int j = 0; j < TV; ++j) {
+            const double ej = wi[u] * ex[u][j];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) xacc[j][b] = __builtin_fma(ej, a[u][b], xacc[j][b]);
+            xacc[j][NB] = __builtin_fma(ej, ax[u], xacc[j][NB]);
+          }
+        }
+        int q = 0;
+#pragma unroll
+        for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+          for (int b2 = 0; b2 <= b1; ++b2) {
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][b1], bw[b2], acc[q], 0, 0, 0);
+            ++q;
+          }
       }
     }
-  };
-#pragma unroll
-  for (int q = 0; q < NTILE; ++q) reduce4(acc[q]);
-  if constexpr (TV > 0) {
-    constexpr int NX = TV * (NB + 1);
-#pragma unroll
-    for (int e = 0; e < NX; e += 4) {
-      v4d v;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) v[k] = e + k < NX ? xacc[(e + k) / (NB + 1)][(e + k) % (NB + 1)] : 0.0;
-      reduce4(v);
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (e + k < NX) xacc[(e + k) / (NB + 1)][(e + k) % (NB + 1)] = v[k];
-    }
   }
-  if (wb != 0) return;
-  // D[i][j] of block (b1, b2) sits in lane j + 16 (i % 4), register i / 4
+  // The waves' partial sums, added in wave order through LDS one 16x16 block
+  // at a time (the accumulators are only stored, which keeps them in the
+  // registers the MFMA writes): thread (rk, rl) sums register rk of lane rl
+  // over the waves and writes that Gram entry.
+  // D[i][j] of block (b1, b2) sits in lane j + 16 (i % 4), register i / 4.
+  double* red = &stage[0][0];  // [NW][4][64]
+  static_assert(3 * TSZ >= NW * 4 * 64, "reduction scratch");
   double* G = gram + d.goff;
+  const int rk = threadIdx.x >> 6, rl = threadIdx.x & 63;
+  const int rc16 = rl & 15, rkq = rl >> 4;
+  auto sum_waves = [&]() {
+    double v = red[rk * 64 + rl];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += red[(w * 4 + rk) * 64 + rl];
+    return v;
+  };
   int q = 0;
 #pragma unroll
   for (int b1 = 0; b1 < NB; ++b1)
 #pragma unroll
     for (int b2 = 0; b2 <= b1; ++b2) {
+      __syncthreads();
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * b1 + kq + 4 * v;
-        const int c = 16 * b2 + c16;
-        if (TV == 0) {
-          if (r < C && c <= r) G[r * (r + 1) / 2 + c] = acc[q][v];
-        } else if (r < T && c <= r) {
-          const int gr = gcol(r), gc = gcol(c);
-          G[gr * (gr + 1) / 2 + gc] = acc[q][v];
-        }
+      for (int k = 0; k < 4; ++k) red[(wb * 4 + k) * 64 + lane] = acc[q][k];
+      __syncthreads();
+      const double v = sum_waves();
+      const int r = 16 * b1 + rkq + 4 * rk;
+      const int c = 16 * b2 + rc16;
+      if (TV == 0) {
+        if (r < C && c <= r) G[r * (r + 1) / 2 + c] = v;
+      } else if (r < T && c <= r) {
+        const int gr = gcol(r), gc = gcol(c);
+        G[gr * (gr + 1) / 2 + gc] = v;
       }
       ++q;
     }
   if constexpr (TV > 0) {
-    // the extra columns' sums over the four sample lanes; lane c16 < 16 then
-    // holds <w~ e_j col> for the block column 16 b + c16 and extra column c16
+    // <w~ e_j col> for extra column j against the block column 16 b + c16
+    // (b < NB) or extra column c16 (b = NB): summed over the waves and the
+    // four sample lanes, four (j, b) pairs at a time
     auto xcol = [&](int j) { return j == 0 ? 0 : j == 1 ? K : gcol(XO + j - 2); };
+    constexpr int NX = TV * (NB + 1);
 #pragma unroll
-    for (int j = 0; j < TV; ++j) {
-      const int gj = xcol(j);
+    for (int e = 0; e < NX; e += 4) {
+      __syncthreads();
 #pragma unroll
-      for (int b = 0; b <= NB; ++b) {
-        double v = xacc[j][b];
-        v += __shfl_xor(v, 16);
-        v += __shfl_xor(v, 32);
+      for (int k = 0; k < 4; ++k)
+        red[(wb * 4 + k) * 64 + lane] = e + k < NX ? xacc[(e + k) / (NB + 1)][(e + k) % (NB + 1)] : 0.0;
+      __syncthreads();
+      const int ex = e + rk;
+      if (ex < NX && rl < 16) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+#pragma unroll
+          for (int g = 0; g < 4; ++g) v += red[(w * 4 + rk) * 64 + 16 * g + rl];
+        const int j = ex / (NB + 1), b = ex % (NB + 1);
+        const int gj = xcol(j);
         int gc = -1;
         if (b < NB) {
-          if (16 * b + c16 < T && 16 * b + c16 < XO) gc = gcol(16 * b + c16);
-        } else if (c16 < TV) {
-          gc = xcol(c16);
+          if (16 * b + rl < T) gc = gcol(16 * b + rl);
+        } else if (rl < TV) {
+          gc = xcol(rl);
           if (gc > gj) gc = -1;  // each extra pair once
         }
-        if (kq == 0 && gc >= 0) {
+        if (gc >= 0) {
           const int r = gj > gc ? gj : gc, c = gj > gc ? gc : gj;
           G[r * (r + 1) / 2 + c] = v;
         }
