@@ -27,7 +27,11 @@
  *  - Per-element numeric conditions are not call errors: they are reported in
  *    `flags_out` bits (see FREDEC_FLAG_*).
  *  - A context is bound to one device and is not thread-safe: use one context
- *    per host thread.  Outputs are always float64 whatever the precision.
+ *    per host thread.  It owns three side streams (default priority) onto
+ *    which a call may fork independent kernels; they are joined back to the
+ *    caller's stream (events) before the call's later work, so the call stays
+ *    ordered on that stream and can be captured into a HIP graph from it.
+ *    Outputs are always float64 whatever the precision.
  *  - Time t is in the caller's unit (e.g. days); frequencies are in cycles per
  *    that unit.  Data are normalised internally as in Sect. 4.1 (eq. idn):
  *    weights to unit sum, x to zero weighted mean and unit weighted variance,

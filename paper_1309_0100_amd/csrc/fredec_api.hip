@@ -382,9 +382,14 @@ int fredec_create(fredec_ctx** out, int device) {
   ctx->device = device;
   DeviceGuard g(device);
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming) != hipSuccess) {
-    delete ctx;
+  bool ok = hipGetDeviceProperties(&prop, device) == hipSuccess &&
+            hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; ok && i < fredec_ctx::NSIDE; ++i)
+    ok = hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&ctx->join_ev[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    fredec_destroy(ctx);
     return FREDEC_EDEVICE;
   }
   ctx->n_cu = prop.multiProcessorCount;
@@ -450,6 +455,11 @@ void fredec_destroy(fredec_ctx* ctx) {
   if (ctx->staging_pending) (void)hipEventSynchronize(ctx->staging_done);
   if (ctx->staging) (void)hipHostFree(ctx->staging);
   if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
+  for (int i = 0; i < fredec_ctx::NSIDE; ++i) {
+    if (ctx->side[i]) (void)hipStreamDestroy(ctx->side[i]);
+    if (ctx->join_ev[i]) (void)hipEventDestroy(ctx->join_ev[i]);
+  }
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
   delete ctx;
 }
 

@@ -21,6 +21,12 @@ struct fredec_ctx {
   int mfma_ft[5] = {0, 0, 0, 0, 0};  // MFMA scan: 16-frequency tiles per wave, by column tiles (0 = default)
   int f32_form = FREDEC_F32_FORM_AUTO;   // kernel family of the reduced-precision scan (FREDEC_F32_FORM_*)
   int f32_auto_valu_max_kp = 6;      // automatic form: VALU kernel up to this KP = 2m + 2 (m <= 2)
+  // side streams (default priority) for launches of independent kernel
+  // groups, joined back to the caller's stream with events
+  static constexpr int NSIDE = 3;
+  hipStream_t side[NSIDE] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[NSIDE] = {};
   // optional timing of the dominant kernel of each call (HIP events)
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;

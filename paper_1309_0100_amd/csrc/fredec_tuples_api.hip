@@ -171,14 +171,50 @@ int normalise(hipStream_t st, const TuplePlan& P, const TupleDev& D, const doubl
   return FREDEC_OK;
 }
 
+// One Gram pass.  The size groups write disjoint Gram matrices, so they run
+// concurrently on the caller's stream and the context's side streams (each
+// group, largest estimated work first, onto the least loaded stream), which
+// lets the small groups and the last, partly filled rounds of the large ones
+// overlap; the side streams are joined back before the pass ends.
 int gram_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, int mode) {
   ProfScope prof(ctx, st);
-  for (const auto& g : P.groups) {
-    if (launch_tuple_gram(st, g.nf, ctx->n_cu, D.desc, D.order + g.begin, g.count, P.N, D.com, D.tau, D.xt,
-                          D.wt, D.ftry, D.state, D.gram, mode, P.precision == FREDEC_FP32) != hipSuccess)
-      return FREDEC_EDEVICE;
+  const int ng = static_cast<int>(P.groups.size());
+  const int nst = std::min(ng, 1 + fredec_ctx::NSIDE);
+  std::vector<int> idx(ng), on(ng, 0);
+  for (int k = 0; k < ng; ++k) idx[k] = k;
+  auto work = [&](int k) {
+    const int n = P.groups[k].nf;
+    const double C = mode == TUPLE_GN ? 4.0 * n + 2.0 : 2.0 * n + 2.0;
+    return static_cast<double>(P.groups[k].count) * C * C;
+  };
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return work(a) > work(b); });
+  std::vector<double> load(nst, 0.0);
+  for (int k : idx) {
+    const int s = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+    on[k] = s;
+    load[s] += work(k);
   }
-  return FREDEC_OK;
+  if (nst > 1) {
+    if (hipEventRecord(ctx->fork_ev, st) != hipSuccess) return FREDEC_EDEVICE;
+    for (int s = 1; s < nst; ++s)
+      if (hipStreamWaitEvent(ctx->side[s - 1], ctx->fork_ev, 0) != hipSuccess) return FREDEC_EDEVICE;
+  }
+  int rc = FREDEC_OK;
+  for (int k = 0; k < ng && rc == FREDEC_OK; ++k) {
+    const auto& g = P.groups[k];
+    const hipStream_t gs = on[k] == 0 ? st : ctx->side[on[k] - 1];
+    if (launch_tuple_gram(gs, g.nf, ctx->n_cu, D.desc, D.order + g.begin, g.count, P.N, D.com, D.tau, D.xt,
+                          D.wt, D.ftry, D.state, D.gram, mode, P.precision == FREDEC_FP32) != hipSuccess)
+      rc = FREDEC_EDEVICE;
+  }
+  // the join is enqueued even after a failed launch, so that no side stream
+  // is left forked from the caller's stream
+  for (int s = 1; s < nst; ++s) {
+    if (hipEventRecord(ctx->join_ev[s - 1], ctx->side[s - 1]) != hipSuccess ||
+        hipStreamWaitEvent(st, ctx->join_ev[s - 1], 0) != hipSuccess)
+      rc = FREDEC_EDEVICE;
+  }
+  return rc;
 }
 
 // Adjoint gradient of every tuple (forward state, theta* and f in the workspace).
