@@ -59,12 +59,9 @@ int make_plan(int64_t N, const std::vector<int>& sizes, bool gn, TuplePlan& P) {
     d.n = n;
     d.nb = (C + 15) / 16;
     d.foff = P.nf;
-    d.goff = P.ngram;
-    d.soff = P.nscratch;
     d.thoff = P.ntheta;
+    d.unused = 0;
     P.nf += n;
-    P.ngram += static_cast<int64_t>(C) * (C + 1) / 2;
-    P.nscratch += gn ? static_cast<int64_t>(K) * n + n * (n + 1) / 2 + n : 0;
     P.ntheta += K;
   }
   if (N - 3 * static_cast<int64_t>(P.max_n) - 1 <= 0) return FREDEC_EDOF;
@@ -79,6 +76,20 @@ int make_plan(int64_t N, const std::vector<int>& sizes, bool gn, TuplePlan& P) {
     if (P.groups.empty() || P.groups.back().nb != d.nb || P.groups.back().nf != d.n)
       P.groups.push_back(TuplePlan::Group{d.nb, d.n, k, 0});
     P.groups.back().count++;
+  }
+  // Gram matrices and solve scratch, interleaved within each size group
+  for (const auto& g : P.groups) {
+    const int n = g.nf;
+    const int C = gn ? 4 * n + 2 : 2 * n + 2;
+    const int K = 2 * n + 1;
+    for (int64_t j = 0; j < g.count; ++j) {
+      TupleDesc& d = P.desc[P.order[g.begin + j]];
+      d.goff = P.ngram + j;
+      d.soff = P.nscratch + j;
+      d.gs = static_cast<int32_t>(g.count);
+    }
+    P.ngram += static_cast<int64_t>(C) * (C + 1) / 2 * g.count;
+    P.nscratch += (gn ? static_cast<int64_t>(K) * n + n * (n + 1) / 2 + n : 0) * g.count;
   }
   size_t off = 0;
   auto take = [&](size_t bytes) {

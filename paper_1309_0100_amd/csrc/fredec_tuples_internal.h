@@ -14,6 +14,11 @@ constexpr double GN_TOL = 1e-10;       // stop once max |df_k| T_eff falls below
 constexpr double GN_CLAMP = 0.25;      // largest step max |df_k| T_eff
 constexpr int LANES_MAX_N = 6;         // largest tuple size of the lane-group VALU kernels
 
+// The packed Gram matrices and the solve scratch of a size group are stored
+// interleaved: element e of the tuple at position j of its group sits at
+// goff + e gs (soff + e gs), goff = group base + j, gs = the group's size, so
+// that the one-thread-per-tuple solve reads consecutive addresses across a
+// wavefront.
 struct TupleDesc {
   int64_t foff;   // first frequency of the tuple in the ragged arrays
   int64_t goff;   // first double of its packed Gram matrix
@@ -21,6 +26,8 @@ struct TupleDesc {
   int64_t thoff;  // first double of theta* (2n + 1 values)
   int32_t n;      // frequencies
   int32_t nb;     // 16-column blocks of its Gram
+  int32_t gs;     // element stride of its Gram matrix and scratch
+  int32_t unused;
 };
 
 struct TupleCommon {

@@ -216,6 +216,7 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
   double* red = &stage[0][0];  // [NW][4][64]
   static_assert(3 * TSZ >= NW * 4 * 64, "reduction scratch");
   double* G = gram + d.goff;
+  const int64_t gs = d.gs;
   const int rk = threadIdx.x >> 6, rl = threadIdx.x & 63;
   const int rc16 = rl & 15, rkq = rl >> 4;
   auto sum_waves = [&]() {
@@ -237,10 +238,10 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
       const int r = 16 * b1 + rkq + 4 * rk;
       const int c = 16 * b2 + rc16;
       if (TV == 0) {
-        if (r < C && c <= r) G[r * (r + 1) / 2 + c] = v;
+        if (r < C && c <= r) G[(r * (r + 1) / 2 + c) * gs] = v;
       } else if (r < T && c <= r) {
         const int gr = gcol(r), gc = gcol(c);
-        G[gr * (gr + 1) / 2 + gc] = v;
+        G[(gr * (gr + 1) / 2 + gc) * gs] = v;
       }
       ++q;
     }
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
         }
         if (gc >= 0) {
           const int r = gj > gc ? gj : gc, c = gj > gc ? gc : gj;
-          G[r * (r + 1) / 2 + c] = v;
+          G[(r * (r + 1) / 2 + c) * gs] = v;
         }
       }
     }
@@ -365,26 +366,29 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_lanes_kernel(const TupleDesc
   }
   if (live && r == 0) {
     double* G = gram + desc[ti].goff;
+    const int64_t gs = desc[ti].gs;
 #pragma unroll
-    for (int q = 0; q < NACC; ++q) G[q] = acc[q];
+    for (int q = 0; q < NACC; ++q) G[q * gs] = acc[q];
   }
 }
 
-__device__ __forceinline__ double& P_(double* G, int r, int c) { return G[r * (r + 1) / 2 + c]; }
+// Element (r, c), r >= c, of a packed lower-triangular matrix stored with
+// element stride gs.
+__device__ __forceinline__ double& P_(double* G, int r, int c, int64_t gs) { return G[(r * (r + 1) / 2 + c) * gs]; }
 
 // In-place Cholesky of the leading K x K block of the packed lower matrix G.
-__device__ bool chol_inplace(double* G, int K) {
+__device__ bool chol_inplace(double* G, int K, int64_t gs) {
   for (int j = 0; j < K; ++j) {
-    const double diag = P_(G, j, j);
+    const double diag = P_(G, j, j, gs);
     double dsum = diag;
-    for (int k = 0; k < j; ++k) dsum -= P_(G, j, k) * P_(G, j, k);
+    for (int k = 0; k < j; ++k) dsum -= P_(G, j, k, gs) * P_(G, j, k, gs);
     if (!(dsum > PIVOT_TOL * diag)) return false;
     const double ljj = sqrt(dsum);
-    P_(G, j, j) = ljj;
+    P_(G, j, j, gs) = ljj;
     for (int i = j + 1; i < K; ++i) {
-      double v = P_(G, i, j);
-      for (int k = 0; k < j; ++k) v -= P_(G, i, k) * P_(G, j, k);
-      P_(G, i, j) = v / ljj;
+      double v = P_(G, i, j, gs);
+      for (int k = 0; k < j; ++k) v -= P_(G, i, k, gs) * P_(G, j, k, gs);
+      P_(G, i, j, gs) = v / ljj;
     }
   }
   return true;
@@ -406,6 +410,7 @@ __global__ __launch_bounds__(BLOCK) void tuple_solve_kernel(const TupleDesc* __r
   const int n = d.n;
   const int K = 2 * n + 1;
   double* G = gram + d.goff;
+  const int64_t gs = d.gs;
   double* ft = ftry + d.foff;
   double* fa = facc + d.foff;
   double* st = step + d.foff;
@@ -416,18 +421,18 @@ __global__ __launch_bounds__(BLOCK) void tuple_solve_kernel(const TupleDesc* __r
   for (int k = 0; k < n; ++k)
     for (int l = k + 1; l < n; ++l) degen |= fabs(ft[k] - ft[l]) * T < MASK_WIDTH;
   // l_0 of the constant model and D from the Gram
-  const double D = P_(G, K, K);
-  const double l0 = D - P_(G, K, 0) * P_(G, K, 0) / P_(G, 0, 0);
-  bool ok = !degen && chol_inplace(G, K);
+  const double D = P_(G, K, K, gs);
+  const double l0 = D - P_(G, K, 0, gs) * P_(G, K, 0, gs) / P_(G, 0, 0, gs);
+  bool ok = !degen && chol_inplace(G, K, gs);
   double l = 0.0;
   if (ok) {
     // a = L^{-1} g in place on row K; l = D - a.a
     double aa = 0.0;
     for (int i = 0; i < K; ++i) {
-      double v = P_(G, K, i);
-      for (int k = 0; k < i; ++k) v -= P_(G, i, k) * P_(G, K, k);
-      v /= P_(G, i, i);
-      P_(G, K, i) = v;
+      double v = P_(G, K, i, gs);
+      for (int k = 0; k < i; ++k) v -= P_(G, i, k, gs) * P_(G, K, k, gs);
+      v /= P_(G, i, i, gs);
+      P_(G, K, i, gs) = v;
       aa += v * v;
     }
     l = D - aa;
@@ -449,9 +454,9 @@ __global__ __launch_bounds__(BLOCK) void tuple_solve_kernel(const TupleDesc* __r
   }
   // accepted: theta* = L^{-T} a
   for (int i = K - 1; i >= 0; --i) {
-    double v = P_(G, K, i);
-    for (int k = i + 1; k < K; ++k) v -= P_(G, k, i) * th[k];
-    th[i] = v / P_(G, i, i);
+    double v = P_(G, K, i, gs);
+    for (int k = i + 1; k < K; ++k) v -= P_(G, k, i, gs) * th[k];
+    th[i] = v / P_(G, i, i, gs);
   }
   S.has_acc = 1;
   S.l_acc = l;
@@ -466,22 +471,22 @@ __global__ __launch_bounds__(BLOCK) void tuple_solve_kernel(const TupleDesc* __r
   // P = <phi J'>, JJ = <J' J'>, rJ = <x J'> - P^T theta, V = L^{-1} P,
   // H = JJ - V^T V, dnu = H^{-1} rJ, df = dnu / (2 pi sigma_t).
   const int ts0 = K + 1;  // first t' column
-  double* V = scratch + d.soff;          // K x n
-  double* H = V + static_cast<int64_t>(K) * n;  // packed n x n
-  double* rJ = H + n * (n + 1) / 2;     // n
+  double* V = scratch + d.soff;                      // K x n
+  double* H = V + static_cast<int64_t>(K) * n * gs;  // packed n x n
+  double* rJ = H + static_cast<int64_t>(n * (n + 1) / 2) * gs;  // n
   for (int k = 0; k < n; ++k) {
     const double ak = th[1 + 2 * k], bk = th[2 + 2 * k];
     const int rc = ts0 + 2 * k, rs = ts0 + 2 * k + 1;
     // P column k, then forward substitution into V column k
     for (int j = 0; j < K; ++j) {
-      double p = -ak * P_(G, rs, j) + bk * P_(G, rc, j);
-      for (int m = 0; m < j; ++m) p -= P_(G, j, m) * V[m * n + k];
-      V[j * n + k] = p / P_(G, j, j);
+      double p = -ak * P_(G, rs, j, gs) + bk * P_(G, rc, j, gs);
+      for (int m = 0; m < j; ++m) p -= P_(G, j, m, gs) * V[(m * n + k) * gs];
+      V[(j * n + k) * gs] = p / P_(G, j, j, gs);
     }
     // <x J'_k> - sum_j theta_j P_jk, with P recomputed
-    double r = -ak * P_(G, rs, K) + bk * P_(G, rc, K);
-    for (int j = 0; j < K; ++j) r -= th[j] * (-ak * P_(G, rs, j) + bk * P_(G, rc, j));
-    rJ[k] = r;
+    double r = -ak * P_(G, rs, K, gs) + bk * P_(G, rc, K, gs);
+    for (int j = 0; j < K; ++j) r -= th[j] * (-ak * P_(G, rs, j, gs) + bk * P_(G, rc, j, gs));
+    rJ[k * gs] = r;
   }
   for (int k = 0; k < n; ++k) {
     const double ak = th[1 + 2 * k], bk = th[2 + 2 * k];
@@ -490,29 +495,29 @@ __global__ __launch_bounds__(BLOCK) void tuple_solve_kernel(const TupleDesc* __r
       const double am = th[1 + 2 * m], bm = th[2 + 2 * m];
       const int mc = ts0 + 2 * m, ms = ts0 + 2 * m + 1;
       // <J'_k J'_m> from the packed lower Gram (row index >= column index)
-      auto g = [&](int r1, int r2) { return r1 >= r2 ? P_(G, r1, r2) : P_(G, r2, r1); };
+      auto g = [&](int r1, int r2) { return r1 >= r2 ? P_(G, r1, r2, gs) : P_(G, r2, r1, gs); };
       double jj = ak * am * g(ks, ms) - ak * bm * g(ks, mc) - bk * am * g(kc, ms) + bk * bm * g(kc, mc);
-      for (int j = 0; j < K; ++j) jj -= V[j * n + k] * V[j * n + m];
-      H[k * (k + 1) / 2 + m] = jj;
+      for (int j = 0; j < K; ++j) jj -= V[(j * n + k) * gs] * V[(j * n + m) * gs];
+      H[(k * (k + 1) / 2 + m) * gs] = jj;
     }
   }
-  bool hok = chol_inplace(H, n);
+  bool hok = chol_inplace(H, n, gs);
   double big = 0.0;
   if (hok) {
     // solve H dnu = rJ (in place in rJ)
     for (int i = 0; i < n; ++i) {
-      double v = rJ[i];
-      for (int k = 0; k < i; ++k) v -= H[i * (i + 1) / 2 + k] * rJ[k];
-      rJ[i] = v / H[i * (i + 1) / 2 + i];
+      double v = rJ[i * gs];
+      for (int k = 0; k < i; ++k) v -= H[(i * (i + 1) / 2 + k) * gs] * rJ[k * gs];
+      rJ[i * gs] = v / H[(i * (i + 1) / 2 + i) * gs];
     }
     for (int i = n - 1; i >= 0; --i) {
-      double v = rJ[i];
-      for (int k = i + 1; k < n; ++k) v -= H[k * (k + 1) / 2 + i] * rJ[k];
-      rJ[i] = v / H[i * (i + 1) / 2 + i];
+      double v = rJ[i * gs];
+      for (int k = i + 1; k < n; ++k) v -= H[(k * (k + 1) / 2 + i) * gs] * rJ[k * gs];
+      rJ[i * gs] = v / H[(i * (i + 1) / 2 + i) * gs];
     }
     const double scale = com->inv_two_pi_sigma_t;
     for (int k = 0; k < n; ++k) {
-      st[k] = rJ[k] * scale;
+      st[k] = rJ[k * gs] * scale;
       big = fmax(big, fabs(st[k]) * T);
     }
   }
