@@ -377,6 +377,26 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_lanes_kernel(const TupleDesc
 __device__ __forceinline__ double& P_(double* G, int r, int c, int64_t gs) { return G[(r * (r + 1) / 2 + c) * gs]; }
 
 // In-place Cholesky of the leading K x K block of the packed lower matrix G.
+// The solve runs one thread per tuple, one wavefront per SIMD: its loops
+// are latency-bound, so independent rows (columns) are taken W at a time,
+// which keeps W load and multiply-add chains in flight; each sum keeps the
+// order of the plain loop.
+
+// Rows i .. i + W - 1 of column j of the Cholesky factor.
+template <int W>
+__device__ __forceinline__ void chol_rows(double* G, int i, int j, double inv, int64_t gs) {
+  double v[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) v[w] = P_(G, i + w, j, gs);
+  for (int k = 0; k < j; ++k) {
+    const double ljk = P_(G, j, k, gs);
+#pragma unroll
+    for (int w = 0; w < W; ++w) v[w] -= P_(G, i + w, k, gs) * ljk;
+  }
+#pragma unroll
+  for (int w = 0; w < W; ++w) P_(G, i + w, j, gs) = v[w] * inv;
+}
+
 __device__ bool chol_inplace(double* G, int K, int64_t gs) {
   for (int j = 0; j < K; ++j) {
     const double diag = P_(G, j, j, gs);
@@ -384,14 +404,65 @@ __device__ bool chol_inplace(double* G, int K, int64_t gs) {
     for (int k = 0; k < j; ++k) dsum -= P_(G, j, k, gs) * P_(G, j, k, gs);
     if (!(dsum > PIVOT_TOL * diag)) return false;
     const double ljj = sqrt(dsum);
+    const double inv = 1.0 / ljj;
     P_(G, j, j, gs) = ljj;
-    for (int i = j + 1; i < K; ++i) {
-      double v = P_(G, i, j, gs);
-      for (int k = 0; k < j; ++k) v -= P_(G, i, k, gs) * P_(G, j, k, gs);
-      P_(G, i, j, gs) = v / ljj;
-    }
+    int i = j + 1;
+    for (; i + 4 <= K; i += 4) chol_rows<4>(G, i, j, inv, gs);
+    for (; i < K; ++i) chol_rows<1>(G, i, j, inv, gs);
   }
   return true;
+}
+
+// Columns kb .. kb + W - 1 of V = L^{-1} P (P column k = -a_k <phi t' sin_k>
+// + b_k <phi t' cos_k>, from the Gram rows of the t' columns).
+template <int W>
+__device__ __forceinline__ void v_cols(double* G, double* V, const double* th, int K, int n, int kb, int ts0,
+                                       int64_t gs) {
+  double ak[W], bk[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    ak[w] = th[1 + 2 * (kb + w)];
+    bk[w] = th[2 + 2 * (kb + w)];
+  }
+  for (int j = 0; j < K; ++j) {
+    double p[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int rc = ts0 + 2 * (kb + w);
+      p[w] = -ak[w] * P_(G, rc + 1, j, gs) + bk[w] * P_(G, rc, j, gs);
+    }
+    for (int m = 0; m < j; ++m) {
+      const double g = P_(G, j, m, gs);
+#pragma unroll
+      for (int w = 0; w < W; ++w) p[w] -= g * V[(m * n + kb + w) * gs];
+    }
+    const double inv = 1.0 / P_(G, j, j, gs);
+#pragma unroll
+    for (int w = 0; w < W; ++w) V[(j * n + kb + w) * gs] = p[w] * inv;
+  }
+}
+
+// H entries (k, m .. m + W - 1) = <J'_k J'_m> - (V^T V)_km.
+template <int W>
+__device__ __forceinline__ void h_entries(double* G, const double* V, double* H, const double* th, int K, int n,
+                                          int k, int m, int ts0, int64_t gs) {
+  auto g = [&](int r1, int r2) { return r1 >= r2 ? P_(G, r1, r2, gs) : P_(G, r2, r1, gs); };
+  const double ak = th[1 + 2 * k], bk = th[2 + 2 * k];
+  const int kc = ts0 + 2 * k, ks = kc + 1;
+  double jj[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const double am = th[1 + 2 * (m + w)], bm = th[2 + 2 * (m + w)];
+    const int mc = ts0 + 2 * (m + w), ms = mc + 1;
+    jj[w] = ak * am * g(ks, ms) - ak * bm * g(ks, mc) - bk * am * g(kc, ms) + bk * bm * g(kc, mc);
+  }
+  for (int j = 0; j < K; ++j) {
+    const double vk = V[(j * n + k) * gs];
+#pragma unroll
+    for (int w = 0; w < W; ++w) jj[w] -= vk * V[(j * n + m + w) * gs];
+  }
+#pragma unroll
+  for (int w = 0; w < W; ++w) H[(k * (k + 1) / 2 + m + w) * gs] = jj[w];
 }
 
 __global__ __launch_bounds__(BLOCK) void tuple_solve_kernel(const TupleDesc* __restrict__ desc,
@@ -474,32 +545,24 @@ __global__ __launch_bounds__(BLOCK) void tuple_solve_kernel(const TupleDesc* __r
   double* V = scratch + d.soff;                      // K x n
   double* H = V + static_cast<int64_t>(K) * n * gs;  // packed n x n
   double* rJ = H + static_cast<int64_t>(n * (n + 1) / 2) * gs;  // n
+  {
+    int kb = 0;
+    for (; kb + 4 <= n; kb += 4) v_cols<4>(G, V, th, K, n, kb, ts0, gs);
+    for (; kb < n; ++kb) v_cols<1>(G, V, th, K, n, kb, ts0, gs);
+  }
   for (int k = 0; k < n; ++k) {
     const double ak = th[1 + 2 * k], bk = th[2 + 2 * k];
     const int rc = ts0 + 2 * k, rs = ts0 + 2 * k + 1;
-    // P column k, then forward substitution into V column k
-    for (int j = 0; j < K; ++j) {
-      double p = -ak * P_(G, rs, j, gs) + bk * P_(G, rc, j, gs);
-      for (int m = 0; m < j; ++m) p -= P_(G, j, m, gs) * V[(m * n + k) * gs];
-      V[(j * n + k) * gs] = p / P_(G, j, j, gs);
-    }
     // <x J'_k> - sum_j theta_j P_jk, with P recomputed
     double r = -ak * P_(G, rs, K, gs) + bk * P_(G, rc, K, gs);
     for (int j = 0; j < K; ++j) r -= th[j] * (-ak * P_(G, rs, j, gs) + bk * P_(G, rc, j, gs));
     rJ[k * gs] = r;
   }
+  // <J'_k J'_m> from the packed lower Gram (row index >= column index)
   for (int k = 0; k < n; ++k) {
-    const double ak = th[1 + 2 * k], bk = th[2 + 2 * k];
-    const int kc = ts0 + 2 * k, ks = ts0 + 2 * k + 1;
-    for (int m = 0; m <= k; ++m) {
-      const double am = th[1 + 2 * m], bm = th[2 + 2 * m];
-      const int mc = ts0 + 2 * m, ms = ts0 + 2 * m + 1;
-      // <J'_k J'_m> from the packed lower Gram (row index >= column index)
-      auto g = [&](int r1, int r2) { return r1 >= r2 ? P_(G, r1, r2, gs) : P_(G, r2, r1, gs); };
-      double jj = ak * am * g(ks, ms) - ak * bm * g(ks, mc) - bk * am * g(kc, ms) + bk * bm * g(kc, mc);
-      for (int j = 0; j < K; ++j) jj -= V[(j * n + k) * gs] * V[(j * n + m) * gs];
-      H[(k * (k + 1) / 2 + m) * gs] = jj;
-    }
+    int m = 0;
+    for (; m + 4 <= k + 1; m += 4) h_entries<4>(G, V, H, th, K, n, k, m, ts0, gs);
+    for (; m <= k; ++m) h_entries<1>(G, V, H, th, K, n, k, m, ts0, gs);
   }
   bool hok = chol_inplace(H, n, gs);
   double big = 0.0;
