@@ -79,13 +79,13 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = {
     "scan_f64_kernel": {"src": "scan_f64.hip", "sha1": "2f187ae1836dd72a375fe29397e974041ee9c147",
                         "fetch_kib": 1173.6, "write_kib": 8789.1},
-    "scan_f16x3_kernel": {"src": "scan_f16x3.hip", "sha1": "26613eaed51dfddcd8334a1ff05c1e759acb02f3",
-                          "fetch_kib": 1372.7, "write_kib": 8798.7},
+    "scan_f16x3_kernel": {"src": "scan_f16x3.hip", "sha1": "d768b09d0d39957d4c68daa23fd38339037fcb5d",
+                          "fetch_kib": 1370.2, "write_kib": 8798.7},
     "scan_mfma_kernel": {"src": "scan_mfma.hip", "sha1": None, "fetch_kib": None, "write_kib": None},
     "scan_f32_kernel": {"src": "scan_f32.hip", "sha1": None, "fetch_kib": None, "write_kib": None},
     # one Gram pass: the six tuple-size kernels (n = 1..6) of the pass added
-    "tuple_gram_lanes_kernel": {"src": "tuples.hip", "sha1": "e52cadd88091a71778393b179fe1ae864569b6b3",
-                                "fetch_kib": 12036.7, "write_kib": 27295.3},
+    "tuple_gram_lanes_kernel": {"src": "tuples.hip", "sha1": "958dfa3c2361f6c5f4c712c8b1c2f3fa49b43aa8",
+                                "fetch_kib": 12739.0, "write_kib": 31592.5},
 }
 
 
