@@ -84,7 +84,7 @@ TRAFFIC = {
     "scan_mfma_kernel": {"src": "scan_mfma.hip", "sha1": None, "fetch_kib": None, "write_kib": None},
     "scan_f32_kernel": {"src": "scan_f32.hip", "sha1": None, "fetch_kib": None, "write_kib": None},
     # one Gram pass: the six tuple-size kernels (n = 1..6) of the pass added
-    "tuple_gram_lanes_kernel": {"src": "tuples.hip", "sha1": "958dfa3c2361f6c5f4c712c8b1c2f3fa49b43aa8",
+    "tuple_gram_lanes_kernel": {"src": "tuples.hip", "sha1": "763b83864ed78348f6985e233ec891c904c8a37b",
                                 "fetch_kib": 12739.0, "write_kib": 31592.5},
 }
 

@@ -39,7 +39,7 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// One workgroup per tuple; its four wavefronts take every fourth step of four
+// One workgroup per tuple; its four wavefronts take every fourth step of eight
 // samples and add their partial Gram matrices in wave order at the end (short
 // workgroups, so that the last round of a launch leaves little of the GPU
 // idle).  Per step of eight samples, lane (c8, s8) first evaluates cos and
@@ -57,9 +57,9 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // blocks hold only the trigonometric columns (the cos/sin pairs, then the
 // t' pairs) and TV extra columns, 1, x~ and the trigonometric columns past
 // 16 NB, are accumulated against every column on the VALU (TV multiply-adds
-// per block and sample, summed over the four sample lanes at the end).  The
-// host picks TV > 0 where it saves a block: a 16x16x4 float64 MFMA costs the
-// issue time of 16 float64 multiply-adds.
+// per block and sample, summed over the sample lanes and the waves at the
+// end).  The host picks TV > 0 where it saves issue time: a 16x16x4 float64
+// MFMA costs that of 16 float64 multiply-adds.
 template <int NB, int TV>
 __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __restrict__ desc,
                                                            const int32_t* __restrict__ order, int n_order,
