@@ -142,6 +142,26 @@ def test_gram_column_layouts(ctx, refine):
             assert bool(fl[k] & 16) == r.converged
 
 
+def test_gram_short_ragged_series(ctx):
+    """A series shorter than one staging tile and not a multiple of the
+    eight-sample step (N = 157): Gauss-Newton refinement of tuples of 1..10
+    frequencies through every column layout of the MFMA Gram kernel."""
+    n_pool = 10
+    t, x, w, fr = _many_sines(743, 157, n_pool)
+    nrm = O.normalize(t, x, w)
+    rng = np.random.default_rng(744)
+    pool = fr + rng.uniform(-0.05, 0.05, size=n_pool) / nrm.T_eff
+    masks = np.array([(1 << k) - 1 for k in range(1, n_pool + 1)], np.uint64)
+    print("case: gram short ragged series N=157", flush=True)
+    l, z, f, fl = (a.cpu().numpy() for a in ctx.tuples(t, x, w, pool, masks=masks, refine_steps=2))
+    for k, m in enumerate(masks):
+        mem = members(int(m), n_pool)
+        r = O.gn_refine(nrm, pool[mem], 2)
+        assert abs(l[k] - r.l) <= 1e-9 * r.l, (len(mem), l[k], r.l)
+        assert np.max(np.abs(f[k][mem] - r.f)) * nrm.T_eff < 1e-7, len(mem)
+        assert zerr(z[k], r.z) <= TOL64, (len(mem), z[k], r.z)
+
+
 def _ragged(rng, pool, n_tuples, n_max, T):
     sizes = rng.integers(1, n_max + 1, size=n_tuples)
     toff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
