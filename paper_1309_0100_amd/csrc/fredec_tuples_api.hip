@@ -182,13 +182,15 @@ int normalise(hipStream_t st, const TuplePlan& P, const TupleDev& D, const doubl
   return FREDEC_OK;
 }
 
-// One Gram pass.  The size groups write disjoint Gram matrices, so they run
-// concurrently on the caller's stream and the context's side streams (each
-// group, largest estimated work first, onto the least loaded stream), which
-// lets the small groups and the last, partly filled rounds of the large ones
-// overlap; the side streams are joined back before the pass ends.
-int gram_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, int mode) {
-  ProfScope prof(ctx, st);
+// Launches fn(group, stream) for every size group of the plan.  The groups
+// write disjoint outputs, so they run concurrently on the caller's stream and
+// the context's side streams (each group, largest estimated work first, onto
+// the least loaded stream), which lets the small groups and the last, partly
+// filled rounds of the large ones overlap; the side streams are joined back
+// to the caller's stream before this returns (also after a failed launch, so
+// that no side stream is left forked).
+template <class Launch>
+int launch_groups(const fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, int mode, Launch&& fn) {
   const int ng = static_cast<int>(P.groups.size());
   const int nst = std::min(ng, 1 + fredec_ctx::NSIDE);
   std::vector<int> idx(ng), on(ng, 0);
@@ -211,15 +213,8 @@ int gram_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDe
       if (hipStreamWaitEvent(ctx->side[s - 1], ctx->fork_ev, 0) != hipSuccess) return FREDEC_EDEVICE;
   }
   int rc = FREDEC_OK;
-  for (int k = 0; k < ng && rc == FREDEC_OK; ++k) {
-    const auto& g = P.groups[k];
-    const hipStream_t gs = on[k] == 0 ? st : ctx->side[on[k] - 1];
-    if (launch_tuple_gram(gs, g.nf, ctx->n_cu, D.desc, D.order + g.begin, g.count, P.N, D.com, D.tau, D.xt,
-                          D.wt, D.ftry, D.state, D.gram, mode, P.precision == FREDEC_FP32) != hipSuccess)
-      rc = FREDEC_EDEVICE;
-  }
-  // the join is enqueued even after a failed launch, so that no side stream
-  // is left forked from the caller's stream
+  for (int k = 0; k < ng && rc == FREDEC_OK; ++k)
+    if (!fn(P.groups[k], on[k] == 0 ? st : ctx->side[on[k] - 1])) rc = FREDEC_EDEVICE;
   for (int s = 1; s < nst; ++s) {
     if (hipEventRecord(ctx->join_ev[s - 1], ctx->side[s - 1]) != hipSuccess ||
         hipStreamWaitEvent(st, ctx->join_ev[s - 1], 0) != hipSuccess)
@@ -228,14 +223,23 @@ int gram_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDe
   return rc;
 }
 
-// Adjoint gradient of every tuple (forward state, theta* and f in the workspace).
+// One Gram pass (the size groups concurrently).
+int gram_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, int mode) {
+  ProfScope prof(ctx, st);
+  return launch_groups(ctx, st, P, mode, [&](const TuplePlan::Group& g, hipStream_t gs) {
+    return launch_tuple_gram(gs, g.nf, ctx->n_cu, D.desc, D.order + g.begin, g.count, P.N, D.com, D.tau, D.xt,
+                             D.wt, D.ftry, D.state, D.gram, mode, P.precision == FREDEC_FP32) == hipSuccess;
+  });
+}
+
+// Adjoint gradient of every tuple (forward state, theta* and f in the
+// workspace), the size groups concurrently.
 int adjoint_pass(const fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, const double* f,
                  double* dzdf, double* hout) {
-  for (const auto& g : P.groups)
-    if (launch_tuple_adjoint(st, g.nf, ctx->n_cu, D.desc, D.order + g.begin, g.count, P.N, D.com, D.tau, D.xt, D.wt,
-                             f, D.theta, D.state, dzdf, hout, P.precision == FREDEC_FP32) != hipSuccess)
-      return FREDEC_EDEVICE;
-  return FREDEC_OK;
+  return launch_groups(ctx, st, P, TUPLE_FWD, [&](const TuplePlan::Group& g, hipStream_t gs) {
+    return launch_tuple_adjoint(gs, g.nf, ctx->n_cu, D.desc, D.order + g.begin, g.count, P.N, D.com, D.tau, D.xt,
+                                D.wt, f, D.theta, D.state, dzdf, hout, P.precision == FREDEC_FP32) == hipSuccess;
+  });
 }
 
 // Forward evaluation (and optional Gauss-Newton refinement) of every tuple.
