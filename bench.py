@@ -80,7 +80,7 @@ TRAFFIC = {
     "scan_f64_kernel": {"src": "scan_f64.hip", "sha1": "2f187ae1836dd72a375fe29397e974041ee9c147",
                         "fetch_kib": 1173.6, "write_kib": 8789.1},
     "scan_f16x3_kernel": {"src": "scan_f16x3.hip", "sha1": "d768b09d0d39957d4c68daa23fd38339037fcb5d",
-                          "fetch_kib": 1370.2, "write_kib": 8798.7},
+                          "fetch_kib": 1370.3, "write_kib": 8798.7},
     "scan_mfma_kernel": {"src": "scan_mfma.hip", "sha1": None, "fetch_kib": None, "write_kib": None},
     "scan_f32_kernel": {"src": "scan_f32.hip", "sha1": None, "fetch_kib": None, "write_kib": None},
     # one Gram pass: the six tuple-size kernels (n = 1..6) of the pass added
