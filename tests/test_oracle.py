@@ -198,6 +198,60 @@ def test_golden_dft_worked_example():
         assert flag == 0 and abs(z - _golden_val(e)) < 1e-12
 
 
+def test_goodness_golden():
+    """G of Sect. 6 (item 2) at the hand-derived l values of the worked DFT
+    example, and the same G from the oracle's own least-squares fit."""
+    with open(os.path.join(GOLDEN, "dft_worked.json")) as fh:
+        g = json.load(fh)
+    N = g["N"]
+    t = np.asarray(g["t"], float)
+    x = np.zeros_like(t)
+    for amp, kind, k in g["components"]:
+        ph = 2 * np.pi * k * t / N
+        x += amp * (np.cos(ph) if kind == "cos" else np.sin(ph))
+    nrm = O.normalize(t, x, np.asarray(g["w"], float))
+    for ks, l_expr, G_expr in g["goodness"]["cases"]:
+        m = len(ks)
+        G = _golden_val(G_expr)
+        assert abs(O.goodness(_golden_val(l_expr), N, m) - G) < 1e-15
+        assert abs(O.goodness(O.lsq(nrm, np.asarray(ks) / N).l, N, m) - G) < 1e-13
+
+
+@pytest.mark.parametrize("seed,freqs", [(5, [0.013]), (6, [0.021, 0.047]), (7, [0.011, 0.03, 0.071])])
+def test_goodness_is_ratio_of_reduced_chi2(seed, freqs):
+    """Sect. 6: G is the ratio of the reduced chi^2 of the best fit of H_m to
+    the reduced chi^2 of H_0 (the weighted variance of the raw x with N - 1
+    degrees of freedom) - computed here on the raw data by an SVD solver."""
+    s = _series(seed, 90, span=300.0, n_sin=2)
+    sw = np.sqrt(s.w)
+
+    def chi2(fs):
+        cols = [np.ones_like(s.t)]
+        for f in fs:
+            cols += [np.cos(2 * np.pi * f * s.t), np.sin(2 * np.pi * f * s.t)]
+        A = np.stack(cols, 1) * sw[:, None]
+        th, *_ = np.linalg.lstsq(A, s.x * sw, rcond=None)
+        r = s.x * sw - A @ th
+        return float(r @ r)
+
+    m = len(freqs)
+    G_ref = (chi2(freqs) / (s.N - 3 * m - 1)) / (chi2([]) / (s.N - 1))
+    l = O.lsq(O.normalize(s.t, s.x, s.w), freqs).l
+    assert abs(O.goodness(l, s.N, m) - G_ref) < 1e-12 * G_ref
+
+
+def test_local_maxima_golden():
+    """The peak rule of Phase 1 on a hand-made array with plateaus, a flagged
+    point and maxima at both ends."""
+    with open(os.path.join(GOLDEN, "local_maxima.json")) as fh:
+        g = json.load(fh)
+    z = np.asarray(g["z"], float)
+    fl = np.asarray(g["flags"], np.uint8)
+    assert list(O.local_maxima(z, fl)) == g["peaks"]
+    # without the flag the flagged maximum is a peak too
+    assert list(O.local_maxima(z, np.zeros_like(fl))) == sorted(g["peaks"] + [9])
+
+
 # ------------------------------------------------------------- invariants
 def _scan_small(t, x, w, base=(), df=3e-4, F=2500, idx=None):
     return O.scan(t, x, w, list(base), df, F, idx=idx)

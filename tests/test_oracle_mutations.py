@@ -4,6 +4,7 @@ at least one of the independent pins fail."""
 import numpy as np
 import pytest
 
+import oracle
 import oracle.fredec_ref as R
 import tests.test_oracle as P
 
@@ -18,6 +19,9 @@ PINS = [
     P.test_gn_converges_to_truth_on_noiseless_data,
     P.test_phase3_multiplicative_table,
     P.test_tuple_permutation_and_lstsq,
+    P.test_goodness_golden,
+    lambda: P.test_goodness_is_ratio_of_reduced_chi2(6, [0.021, 0.047]),
+    P.test_local_maxima_golden,
 ]
 
 
@@ -67,6 +71,25 @@ def _normalize_unweighted_mean(t, x, w):
     return R.Normalized(n.tau, d / sx, n.wt, n.tbar, xbar, sx, n.var_t, n.T_eff)
 
 
+def _local_maxima_nonstrict_left(z, flags):
+    j = np.arange(1, z.size - 1)
+    ok = (z[j] >= z[j - 1]) & (z[j] >= z[j + 1]) & (flags[j] == 0)
+    return j[ok]
+
+
+def _local_maxima_no_flags(z, flags):
+    j = np.arange(1, z.size - 1)
+    ok = (z[j] > z[j - 1]) & (z[j] >= z[j + 1])
+    return j[ok]
+
+
+def _local_maxima_with_ends(z, flags):
+    zp = np.concatenate([[-np.inf], z, [-np.inf]])
+    j = np.arange(1, zp.size - 1)
+    ok = (zp[j] > zp[j - 1]) & (zp[j] >= zp[j + 1]) & (flags[j - 1] == 0)
+    return j[ok] - 1
+
+
 MUTATIONS = {
     "phase without 2 pi": ("design", _design_no_2pi),
     "dropped constant column": ("design", _design_no_constant),
@@ -76,6 +99,12 @@ MUTATIONS = {
     "wrong sign in the frequency derivative": ("model_jacobian", _jacobian_sign),
     "unweighted mean of x": ("normalize", _normalize_unweighted_mean),
     "popcount off by one": ("popcount", lambda m: bin(m).count("1") + (1 if m > 2 else 0)),
+    "goodness with N instead of N - 1": ("goodness", lambda l, N, m: l * N / R.n_dof(N, m)),
+    "goodness with m instead of 3m": ("goodness", lambda l, N, m: l * (N - 1) / (N - m - 1)),
+    "goodness inverted": ("goodness", lambda l, N, m: l * R.n_dof(N, m) / (N - 1)),
+    "peaks non-strict on the left": ("local_maxima", _local_maxima_nonstrict_left),
+    "peaks ignoring flags": ("local_maxima", _local_maxima_no_flags),
+    "peaks at the grid ends": ("local_maxima", _local_maxima_with_ends),
 }
 
 
@@ -83,6 +112,8 @@ MUTATIONS = {
 def test_planted_mistake_is_caught(name, monkeypatch):
     attr, fn = MUTATIONS[name]
     monkeypatch.setattr(R, attr, fn)
+    if hasattr(oracle, attr):   # the package re-exports the functions the pins call directly
+        monkeypatch.setattr(oracle, attr, fn)
     failures = 0
     for pin in PINS:
         try:
