@@ -84,7 +84,9 @@ enum {
 };
 
 #define FREDEC_MAX_BASE 24   /* largest base model m of a scan */
-#define FREDEC_MAX_POOL 24   /* largest pool size n for tuples and the cascade */
+#define FREDEC_MAX_POOL 27   /* largest tuple size n (explicit masks, ragged tuples) and pool size of the
+                                cascade; Sect. 5 names n = 25-27 as the practical limit of the method.  With
+                                masks == NULL (all 2^n - 1 subsets) the caller's workspace bounds n. */
 
 /* Context --------------------------------------------------------------- */
 int fredec_create(fredec_ctx** ctx, int device);
@@ -99,23 +101,38 @@ int fredec_version(void); /* 100 * major + minor */
  * event pairs since the last read or enable, then resets the count. */
 int fredec_profile(fredec_ctx* ctx, int32_t enable);
 int fredec_profile_read(fredec_ctx* ctx, double* total_ms, int64_t* launches);
+/* The same timing by kind of kernel group: ms_out[k] and launches_out[k]
+ * (host arrays of n_kinds) receive the summed time (ms) and the number of
+ * timed groups of kind k < n_kinds since the last read or enable, then every
+ * count is reset.  fredec_profile_read reports kinds SCAN and GRAM. */
+enum {
+  FREDEC_PROF_SCAN = 0,     /* trig-sum kernels of a scan (every kernel family) */
+  FREDEC_PROF_GRAM = 1,     /* tuple Gram passes (all size groups of a pass) */
+  FREDEC_PROF_SOLVE = 2,    /* tuple solves (Cholesky, theta*, Gauss-Newton step) */
+  FREDEC_PROF_PREP = 3,     /* normalisation and base-model precomputation of a scan */
+  FREDEC_PROF_RESCORE = 4,  /* float64 re-scoring of reduced-precision scan points */
+  FREDEC_PROF_ADJOINT = 5,  /* adjoint passes (dz/df) */
+  FREDEC_PROF_NKIND = 6
+};
+int fredec_profile_read_kinds(fredec_ctx* ctx, int32_t n_kinds, double* ms_out, int64_t* launches_out);
 
 /* Kernel and tile choices made by the autotuner (paper_1309_0100_amd/autotune.py).
- * FREDEC_TILE_SCAN_MFMA: key = column tiles of the float32 MFMA scan operand
- * (1..4, i.e. ceil((2m+2)/16)), value = 16-frequency tiles per wavefront
- * (2, 4, 6 or 8 for key 1; 2 or 4 for key 2; 2 for keys 3, 4; 0 = default).
+ * FREDEC_TILE_SCAN_F16X3: key = column tiles NT of the split-float16 scan
+ * operand (1..4, i.e. ceil((2m+1)/16)), value = 16-frequency tiles per wave
+ * FT (1, 2 or 4 with NT * FT <= 4; 0 = default: 4, 2, 1, 1 for NT = 1..4).
  * FREDEC_TILE_SCAN_F32_FORM: key = 0, value = kernel family of the
  * FREDEC_FP32 scan (FREDEC_F32_FORM_*): VALU = float32 vector sums (base
- * models with m <= 12; the float32 MFMA kernel above), MFMA32 = float32
- * matrix cores for every m, F16X3 = float16 matrix cores on split operands
- * (three products per step) for every m, AUTO (default) = VALU for
- * 2m + 2 <= the key-1 setting and F16X3 above.  All give results within the
- * float32 bound.  Key = 1: value = largest 2m + 2 (0..26, default 6) that
- * the AUTO form gives to the VALU kernel.
+ * models with m <= 12; the split-float16 kernel above), F16X3 = float16
+ * matrix cores on split operands (three products per step) for every m,
+ * AUTO (default) = VALU for 2m + 2 <= the key-1 setting and F16X3 above.
+ * All give results within the float32 bound.  Key = 1: value = largest
+ * 2m + 2 (0..26, default 6) that the AUTO form gives to the VALU kernel.
+ * FREDEC_TILE_SCAN_F32_FORM value 1 (a float32-MFMA kernel family) is no
+ * longer provided and is rejected.
  * Errors: EINVAL for an unsupported combination.  The workspace size of a
  * scan does not depend on these settings. */
-enum { FREDEC_TILE_SCAN_MFMA = 1, FREDEC_TILE_SCAN_F32_FORM = 2 };
-enum { FREDEC_F32_FORM_VALU = 0, FREDEC_F32_FORM_MFMA32 = 1, FREDEC_F32_FORM_F16X3 = 2, FREDEC_F32_FORM_AUTO = 3 };
+enum { FREDEC_TILE_SCAN_F16X3 = 1, FREDEC_TILE_SCAN_F32_FORM = 2 };
+enum { FREDEC_F32_FORM_VALU = 0, FREDEC_F32_FORM_F16X3 = 2, FREDEC_F32_FORM_AUTO = 3 };
 int fredec_set_tile(fredec_ctx* ctx, int32_t kernel, int32_t key, int32_t value);
 
 /* Normalisation (Sect. 4.1, eq. idn; T_eff of Sect. 2) -------------------
@@ -223,19 +240,39 @@ int fredec_tuples(fredec_ctx* ctx, void* stream, const double* t, const double* 
 
 /* z and its gradient for ragged tuples: tuple k owns the frequencies
  * f[toff[k] .. toff[k+1]) (f device float64, toff host int64, toff[0] = 0,
- * 1 <= toff[k+1] - toff[k] <= FREDEC_MAX_POOL).  By the envelope theorem on
- * l = min_theta chi^2: dz/df_k = (N_H / l) <r J_k>, with r = x~ - Phi theta*
- * and J_k = d mu / d f_k = 2 pi t (-a_k sin 2 pi f_k t + b_k cos 2 pi f_k t);
- * h_k = (N_H / l) <J_k^2> is the diagonal Gauss-Newton curvature.  The
+ * 1 <= toff[k+1] - toff[k] <= FREDEC_MAX_POOL).  z is the absolute statistic
+ * of eq. zpow at the given frequencies, l the least-squares minimum of eq. lsq
+ * (Sect. 3).  The gradient follows the frequency part of the gradient g_f of
+ * eq. lsqf at theta = theta*(f) (Sect. 3: its theta part vanishes there):
+ * dl/df_k = -2 <r J_k>, hence dz/df_k = (N_H / l) <r J_k>, with
+ * r = x~ - Phi theta*, J_k = d mu / d f_k = 2 pi t (-a_k sin 2 pi f_k t +
+ * b_k cos 2 pi f_k t) and N_H = N - 3n - 1; h_k = (N_H / l) <J_k^2> is the
+ * diagonal of the frequency block of the Fisher matrix Q_f of eq. lsqf in the
+ * same units (the curvature of a one-frequency Gauss-Newton step).  The
  * adjoint recomputes the trig terms sample by sample (nothing of size N x n
  * is stored).  Outputs (device, nullable): z_out, l_out, flags_out
  * [n_tuples]; theta_out [sum(2 n_k + 1)], tuple k at offset 2 toff[k] + k
- * (c, a_1, b_1, ..., a_n, b_n); dz_df, h_out [toff[n_tuples]]. */
+ * (c, a_1, b_1, ..., a_n, b_n); dz_df, h_out [toff[n_tuples]].  With dz_df
+ * and h_out both NULL no adjoint pass is made.  Degenerate tuples (flags)
+ * get NaN gradients.  Errors: EINVAL, ENOTSUP (a tuple above
+ * FREDEC_MAX_POOL), EDOF (N - 3 n_max - 1 <= 0), ENOMEM. */
 int fredec_grad_workspace(int64_t N, const int64_t* toff_host, int64_t n_tuples, size_t* bytes);
 int fredec_grad(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
                 const double* f, const int64_t* toff_host, int64_t n_tuples, int32_t precision,
                 void* workspace, size_t ws_bytes, double* z_out, double* l_out, double* theta_out,
                 double* dz_df, double* h_out, uint8_t* flags_out);
+
+/* The adjoint pass of fredec_grad alone, for a forward evaluation made
+ * earlier (the backward pass of an automatic-differentiation framework):
+ * given the frequencies f, toff as for fredec_grad, and that call's theta_out
+ * (theta, device) and l_out (l, device), writes dz_df and h_out (device,
+ * nullable, [toff[n_tuples]]) by the formulas of fredec_grad.  A tuple whose
+ * l is not finite and positive gets NaN.  Workspace from
+ * fredec_grad_workspace.  Errors as for fredec_grad. */
+int fredec_adjoint(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                   const double* f, const int64_t* toff_host, int64_t n_tuples, const double* theta,
+                   const double* l, int32_t precision, void* workspace, size_t ws_bytes, double* dz_df,
+                   double* h_out);
 
 /* Fixed-step preconditioned ascent of z for ragged tuples (workspace as for
  * fredec_grad): `steps` times f_k += clamp(<r J_k> / <J_k^2>, +-clamp / T_eff),

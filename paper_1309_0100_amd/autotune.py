@@ -1,14 +1,19 @@
-"""Kernel and tile-shape autotuner for the float32 residual scan.
+"""Kernel and tile-shape autotuner of the reduced-precision residual scan.
 
-For each operand width bucket NT (16-column tiles: 1 for m <= 7, 2 for
-m <= 15, ...) it times every supported frequency-tile count FT of the MFMA
-kernel on a synthetic series of the benchmark's shape (N samples, m base
-frequencies, F grid points) and keeps the fastest; then it finds the base
-model sizes where the float32 VALU kernel beats the split-float16 MFMA kernel
-(the boundary of the automatic form), and times every kernel family of the
-float32 form over m = 0, 2, 4, 8 and keeps the fastest.  The choice is written to
-tuning.json next to this file; Context(tuning=True) applies it through
-fredec_set_tile.  Usage: python -m paper_1309_0100_amd.autotune [--N 2000 --F 1000000]
+It times, with the library's own HIP-event timing of the scan kernels, on a
+synthetic series of the benchmark's shape (N samples, F grid points):
+
+* for every column-tile bucket NT of the split-float16 kernel (NT = 1 for
+  m <= 7, 2 for m <= 15, ...), every supported count FT of 16-frequency tiles
+  per wave, and keeps the fastest;
+* for m = 0 .. 6, the float32 VALU kernel against the split-float16 kernel,
+  which fixes the boundary of the automatic form (the largest 2m + 2 up to
+  which the VALU kernel is faster);
+* every kernel family over m = 0, 2, 4, 8, keeping the fastest as the form.
+
+The choice is written to tuning.json next to this file; Context(tuning=True)
+applies it through fredec_set_tile.
+Usage: python -m paper_1309_0100_amd.autotune [--N 2000 --F 1000000]
 """
 from __future__ import annotations
 
@@ -22,11 +27,13 @@ from . import fredec, synth
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING = os.path.join(HERE, "tuning.json")
-CANDIDATES = {1: (2, 4, 6, 8), 2: (2, 4), 3: (2,), 4: (2,)}
+# supported FT per column-tile bucket (FT in {1, 2, 4}, NT FT <= 4) and the base size timed for each
+F16X3_FT = {1: (1, 2, 4), 2: (1, 2), 3: (1,), 4: (1,)}
 BUCKET_M = {1: 4, 2: 10, 3: 18, 4: 24}
 
 
 def time_scan(ctx, s, base, df, F, reps=5):
+    """Mean HIP-event time (ms) of the scan kernels of one float32 scan."""
     import torch
     ctx.scan_series(s.t, s.x, s.w, base, df, F, precision=fredec.FP32)
     torch.cuda.synchronize()
@@ -41,48 +48,45 @@ def time_scan(ctx, s, base, df, F, reps=5):
 def tune(N=2000, F=1_000_000, buckets=(1, 2), reps=5, verbose=True, out_path=TUNING):
     ctx = fredec.Context(0, tuning=False)
     s = synth.random_series(7, N, span=4000.0, n_sin=4)
-    out = {"N": N, "F": F, "scan_mfma": {}}
-    ctx.set_tile(fredec.TILE_SCAN_F32_FORM, 0, 1)  # time the MFMA kernel's tiles first
+    df = 2.0 / F
+    out = {"N": N, "F": F, "scan_f16x3": {}}
+    ctx.set_tile(fredec.TILE_SCAN_F32_FORM, 0, fredec.F32_FORM_F16X3)
     for nt in buckets:
         m = BUCKET_M[nt]
         base = np.random.default_rng(nt).uniform(0.01, 1.5, size=m)
         best = None
-        for ft in CANDIDATES[nt]:
-            ctx.set_tile(fredec.TILE_SCAN_MFMA, nt, ft)
-            ms = time_scan(ctx, s, base, 2.0 / F, F, reps)
+        for ft in F16X3_FT[nt]:
+            ctx.set_tile(fredec.TILE_SCAN_F16X3, nt, ft)
+            ms = time_scan(ctx, s, base, df, F, reps)
             if verbose:
-                print(f"NT={nt} (m={m}) FT={ft}: {ms:.3f} ms", flush=True)
+                print(f"split-float16 NT={nt} (m={m}) FT={ft}: {ms:.3f} ms", flush=True)
             if best is None or ms < best[1]:
                 best = (ft, ms)
-        out["scan_mfma"][str(nt)] = {"FT": best[0], "ms": best[1]}
-        ctx.set_tile(fredec.TILE_SCAN_MFMA, nt, best[0])
-    # automatic float32 form: the VALU kernel serves base models up to the
-    # largest 2m + 2 where it beats the split-float16 MFMA kernel
-    ms_by_m = {}
+        out["scan_f16x3"][str(nt)] = {"FT": best[0], "ms": best[1]}
+        ctx.set_tile(fredec.TILE_SCAN_F16X3, nt, best[0])
+    # automatic form: the VALU kernel up to the largest 2m + 2 where it wins
     valu_max_kp = 0
     for m in range(0, 7):
         base = np.random.default_rng(100 + m).uniform(0.01, 1.5, size=m)
         t = {}
         for form in (fredec.F32_FORM_VALU, fredec.F32_FORM_F16X3):
             ctx.set_tile(fredec.TILE_SCAN_F32_FORM, 0, form)
-            t[form] = time_scan(ctx, s, base, 2.0 / F, F, reps)
-        ms_by_m[m] = t
+            t[form] = time_scan(ctx, s, base, df, F, reps)
         if verbose:
-            print(f"m={m}: VALU {t[fredec.F32_FORM_VALU]:.3f} ms, split-float16 MFMA {t[fredec.F32_FORM_F16X3]:.3f} ms",
+            print(f"m={m}: VALU {t[fredec.F32_FORM_VALU]:.3f} ms, split-float16 {t[fredec.F32_FORM_F16X3]:.3f} ms",
                   flush=True)
         if t[fredec.F32_FORM_VALU] < t[fredec.F32_FORM_F16X3] and valu_max_kp == 2 * m:
             valu_max_kp = 2 * m + 2
     ctx.set_tile(fredec.TILE_SCAN_F32_FORM, 1, valu_max_kp)
     out["scan_f32_auto"] = {"valu_max_kp": valu_max_kp}
-    # float32 form: every kernel family on a spread of base-model sizes
     ms_form = {}
-    names = {0: "VALU", 1: "MFMA32", 2: "F16X3", 3: "AUTO"}
+    names = {fredec.F32_FORM_VALU: "VALU", fredec.F32_FORM_F16X3: "F16X3", fredec.F32_FORM_AUTO: "AUTO"}
     for form in names:
         ctx.set_tile(fredec.TILE_SCAN_F32_FORM, 0, form)
         tot = 0.0
         for m in (0, 2, 4, 8):
             base = np.random.default_rng(200 + m).uniform(0.01, 1.5, size=m)
-            tot += time_scan(ctx, s, base, 2.0 / F, F, reps)
+            tot += time_scan(ctx, s, base, df, F, reps)
         ms_form[form] = tot
         if verbose:
             print(f"float32 form {names[form]}: {tot:.3f} ms over m = 0, 2, 4, 8", flush=True)
@@ -99,8 +103,8 @@ def apply(ctx, path=TUNING):
         return False
     with open(path) as fh:
         tab = json.load(fh)
-    for nt, v in tab.get("scan_mfma", {}).items():
-        ctx.set_tile(fredec.TILE_SCAN_MFMA, int(nt), int(v["FT"]))
+    for nt, v in tab.get("scan_f16x3", {}).items():
+        ctx.set_tile(fredec.TILE_SCAN_F16X3, int(nt), int(v["FT"]))
     if "scan_f32_form" in tab:
         ctx.set_tile(fredec.TILE_SCAN_F32_FORM, 0, int(tab["scan_f32_form"]["form"]))
     if "scan_f32_auto" in tab:

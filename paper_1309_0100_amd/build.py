@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfredec.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["fredec_api.hip", "fredec_tuples_api.hip", "prep.hip", "scan_f64.hip", "scan_mfma.hip", "scan_f32.hip", "scan_f16x3.hip", "tuples.hip", "select.hip",
+SOURCES = ["fredec_api.hip", "fredec_tuples_api.hip", "prep.hip", "scan_f64.hip", "rescore.hip", "scan_f32.hip", "scan_f16x3.hip", "tuples.hip", "select.hip",
            "fredec_select_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

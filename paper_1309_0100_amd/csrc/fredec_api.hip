@@ -54,18 +54,19 @@ int upload_wait(fredec_ctx* ctx) {
 
 size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
-ProfScope::ProfScope(fredec_ctx* ctx, hipStream_t st) : ctx_(ctx), st_(st) {
+ProfScope::ProfScope(fredec_ctx* ctx, hipStream_t st, int kind) : ctx_(ctx), st_(st) {
   if (!ctx_->profiling) return;
   if (ctx_->prof_used == ctx_->prof_events.size()) {
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
-    ctx_->prof_events.push_back({a, b});
+    ctx_->prof_events.push_back({a, b, kind});
   }
   idx_ = static_cast<long>(ctx_->prof_used++);
-  (void)hipEventRecord(ctx_->prof_events[idx_].first, st_);
+  ctx_->prof_events[idx_].kind = kind;
+  (void)hipEventRecord(ctx_->prof_events[idx_].begin, st_);
 }
 ProfScope::~ProfScope() {
-  if (idx_ >= 0) (void)hipEventRecord(ctx_->prof_events[idx_].second, st_);
+  if (idx_ >= 0) (void)hipEventRecord(ctx_->prof_events[idx_].end, st_);
 }
 
 }  // namespace fredec
@@ -83,19 +84,18 @@ struct ScanLayout {
   int max_nt = 1;
 };
 
-constexpr int MFMA_FT_MIN = 2;
-
 // Frequencies per workgroup of the scan kernel used for a series (for the
-// reduced-precision forms the smallest tile of any of their kernels, which
+// reduced-precision form the smallest tile of any of its kernels, which
 // bounds the work list of any setting).
 int64_t scan_tile(int KP, int32_t precision) {
   if (precision == FREDEC_FP32) return 64;
   return static_cast<int64_t>(BLOCK) * scan_freqs_per_thread(KP);
 }
 
-int mfma_ft_for(const fredec_ctx* ctx, int NT) {
-  const int ft = (ctx && NT >= 1 && NT <= 4 && ctx->mfma_ft[NT]) ? ctx->mfma_ft[NT] : mfma_freq_tiles(NT);
-  return ft;
+// 16-frequency tiles per wave of the split-float16 scan for NT column tiles
+// (the context's setting, else the default).
+int f16x3_ft_for(const fredec_ctx* ctx, int NT) {
+  return (ctx && NT >= 1 && NT <= 4 && ctx->f16x3_ft[NT]) ? ctx->f16x3_ft[NT] : f16x3_freq_tiles(NT);
 }
 
 // Checks the host descriptors of a scan batch and computes the workspace layout.
@@ -172,11 +172,11 @@ struct ScanPlan : fredec_plan {
   int32_t kp_max = 2;    // largest KP of the series
   std::vector<SeriesIn> sin;
   std::vector<ScanWork> work;
-  enum Kind { F64 = 0, MFMA = 1, F32 = 2, F16X3 = 3 };
+  enum Kind { F64 = 0, F32 = 2, F16X3 = 3 };
   struct Group {
     int kind;        // kernel family
-    int key;         // KP (float64, float32 VALU) or column tiles NT (MFMA forms)
-    int ft;          // MFMA: 16-frequency tiles per wave the work list was cut for
+    int key;         // KP (float64, float32 VALU) or column tiles NT (split float16)
+    int ft;          // split float16: 16-frequency tiles per wave the work list was cut for
     int64_t begin, end;
   };
   std::vector<Group> groups;
@@ -237,7 +237,7 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
     }
   }
   // Work list: tiles grouped by kernel instance (KP for the float64 and the
-  // float32 VALU kernels, column tiles NT for MFMA), longest series first
+  // float32 VALU kernels, column tiles NT for the split-float16 kernel), longest series first
   // inside a group.
   const int form = ctx ? ctx->f32_form : FREDEC_F32_FORM_AUTO;
   const int auto_kp = ctx ? ctx->f32_auto_valu_max_kp : F32_AUTO_VALU_MAX_KP;
@@ -245,13 +245,10 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
     if (precision == FREDEC_FP64) return static_cast<int>(ScanPlan::F64);
     if (form == FREDEC_F32_FORM_F16X3 || (form == FREDEC_F32_FORM_AUTO && sin[s].KP > auto_kp))
       return static_cast<int>(ScanPlan::F16X3);
-    if (form == FREDEC_F32_FORM_AUTO) return static_cast<int>(ScanPlan::F32);
-    if (form == FREDEC_F32_FORM_VALU && sin[s].KP <= F32_VALU_MAX_KP) return static_cast<int>(ScanPlan::F32);
-    return static_cast<int>(ScanPlan::MFMA);
+    if (sin[s].KP <= F32_VALU_MAX_KP) return static_cast<int>(ScanPlan::F32);
+    return static_cast<int>(ScanPlan::F16X3);
   };
-  auto key = [&](int32_t s) {
-    return (kind(s) == ScanPlan::MFMA || kind(s) == ScanPlan::F16X3) ? sin[s].NT : sin[s].KP;
-  };
+  auto key = [&](int32_t s) { return kind(s) == ScanPlan::F16X3 ? sin[s].NT : sin[s].KP; };
   std::vector<int32_t> order(n_series);
   for (int32_t s = 0; s < n_series; ++s) order[s] = s;
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
@@ -262,7 +259,6 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
   for (int32_t s = 0; s < n_series; ++s) {
     const int kd = kind(s);
     sin[s].outputs = kd == ScanPlan::F32     ? PREP_G32
-                     : kd == ScanPlan::MFMA  ? PREP_G32 | PREP_AUX
                      : kd == ScanPlan::F16X3 ? PREP_AUX | PREP_F16
                                              : 0;
   }
@@ -271,11 +267,10 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
   P.groups.clear();
   for (int32_t s : order) {
     const int kd = kind(s);
-    const int ft = kd == ScanPlan::MFMA ? mfma_ft_for(ctx, sin[s].NT) : 0;
-    const int64_t tile = kd == ScanPlan::MFMA    ? 64 * static_cast<int64_t>(ft)
-                         : kd == ScanPlan::F16X3 ? 64 * static_cast<int64_t>(f16x3_freq_tiles(sin[s].NT))
-                         : kd == ScanPlan::F32   ? static_cast<int64_t>(BLOCK) * scan_f32_freqs_per_thread(sin[s].KP)
-                                                 : scan_tile(sin[s].KP, precision);
+    const int ft = kd == ScanPlan::F16X3 ? f16x3_ft_for(ctx, sin[s].NT) : 0;
+    const int64_t tile = kd == ScanPlan::F16X3 ? 64 * static_cast<int64_t>(ft)
+                         : kd == ScanPlan::F32 ? static_cast<int64_t>(BLOCK) * scan_f32_freqs_per_thread(sin[s].KP)
+                                               : scan_tile(sin[s].KP, precision);
     if (P.groups.empty() || P.groups.back().kind != kd || P.groups.back().key != key(s))
       P.groups.push_back(ScanPlan::Group{kd, key(s), ft, static_cast<int64_t>(P.work.size()), 0});
     for (int64_t j0 = 0; j0 < sin[s].F; j0 += tile) P.work.push_back(ScanWork{s, 0, j0});
@@ -319,20 +314,20 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const double
   // per series, the prep kernel writes only what its scan kernel reads (SeriesIn::outputs)
   const int flags = PREP_BASE | PREP_REC64 | PREP_G32 | PREP_AUX | PREP_F16;
   if (f32 && launch_zero_u64(st, d_count, P.n_series) != hipSuccess) return FREDEC_EDEVICE;
-  if (launch_prep(st, P.n_series, P.kp_max, L.ptiles, d_sin, d_hdr, t, x, w, d_tau - base_off, d_xt - base_off,
-                  d_wt - base_off, d_rec, d_phi, d_g32, d_aux, d_b16, at<double>(ws, L.off_ppart),
-                  at<double>(ws, L.off_pm), flags) != hipSuccess)
-    return FREDEC_EDEVICE;
   {
-    ProfScope prof(ctx, st);
+    ProfScope prof(ctx, st, FREDEC_PROF_PREP);
+    if (launch_prep(st, P.n_series, P.kp_max, L.ptiles, d_sin, d_hdr, t, x, w, d_tau - base_off, d_xt - base_off,
+                    d_wt - base_off, d_rec, d_phi, d_g32, d_aux, d_b16, at<double>(ws, L.off_ppart),
+                    at<double>(ws, L.off_pm), flags) != hipSuccess)
+      return FREDEC_EDEVICE;
+  }
+  {
+    ProfScope prof(ctx, st, FREDEC_PROF_SCAN);
     for (const auto& gr : P.groups) {
       const int n = static_cast<int>(gr.end - gr.begin);
       hipError_t err;
-      if (gr.kind == ScanPlan::MFMA)
-        err = launch_scan_mfma(st, gr.key, gr.ft, n, d_work + gr.begin, d_sin, d_hdr, d_g32, d_aux, z_out, flags_out,
-                               d_list, d_count);
-      else if (gr.kind == ScanPlan::F16X3)
-        err = launch_scan_f16x3(st, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_aux, d_b16, z_out, flags_out,
+      if (gr.kind == ScanPlan::F16X3)
+        err = launch_scan_f16x3(st, gr.key, gr.ft, n, d_work + gr.begin, d_sin, d_hdr, d_aux, d_b16, z_out, flags_out,
                                 d_list, d_count);
       else if (gr.kind == ScanPlan::F32)
         err = launch_scan_f32(st, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_rec, d_g32, z_out, flags_out, d_list,
@@ -342,10 +337,12 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const double
       if (err != hipSuccess) return FREDEC_EDEVICE;
     }
   }
-  if (f32 && launch_rescore(st, L.max_nt, 4 * std::max(ctx->n_cu, 1), P.n_series, d_sin, d_hdr, d_rec, d_list,
-                            d_count, d_chunk, z_out,
-                            flags_out) != hipSuccess)
-    return FREDEC_EDEVICE;
+  if (f32) {
+    ProfScope prof(ctx, st, FREDEC_PROF_RESCORE);
+    if (launch_rescore(st, L.max_nt, 4 * std::max(ctx->n_cu, 1), P.n_series, d_sin, d_hdr, d_rec, d_list, d_count,
+                       d_chunk, z_out, flags_out) != hipSuccess)
+      return FREDEC_EDEVICE;
+  }
   if (launch_copy_stats(st, P.n_series, d_hdr, d_sin, l_base_out, status_out, nullptr) != hipSuccess)
     return FREDEC_EDEVICE;
   return FREDEC_OK;
@@ -399,15 +396,16 @@ int fredec_create(fredec_ctx** out, int device) {
 
 int fredec_set_tile(fredec_ctx* ctx, int32_t kernel, int32_t key, int32_t value) {
   if (!ctx) return FREDEC_EINVAL;
-  if (kernel == FREDEC_TILE_SCAN_MFMA) {
+  if (kernel == FREDEC_TILE_SCAN_F16X3) {
     if (key < 1 || key > 4) return FREDEC_EINVAL;
-    if (value != 0 && !mfma_tile_supported(key, value)) return FREDEC_EINVAL;
-    ctx->mfma_ft[key] = value;
+    if (value != 0 && !f16x3_tile_supported(key, value)) return FREDEC_EINVAL;
+    ctx->f16x3_ft[key] = value;
     return FREDEC_OK;
   }
   if (kernel == FREDEC_TILE_SCAN_F32_FORM) {
     if (key == 0) {
-      if (value < FREDEC_F32_FORM_VALU || value > FREDEC_F32_FORM_AUTO) return FREDEC_EINVAL;
+      if (value != FREDEC_F32_FORM_VALU && value != FREDEC_F32_FORM_F16X3 && value != FREDEC_F32_FORM_AUTO)
+        return FREDEC_EINVAL;
       ctx->f32_form = value;
       return FREDEC_OK;
     }
@@ -428,20 +426,38 @@ int fredec_profile(fredec_ctx* ctx, int32_t enable) {
   return FREDEC_OK;
 }
 
+int fredec_profile_read_kinds(fredec_ctx* ctx, int32_t n_kinds, double* ms_out, int64_t* launches_out) {
+  if (!ctx || n_kinds < 1 || !ms_out || !launches_out) return FREDEC_EINVAL;
+  DeviceGuard g(ctx->device);
+  for (int k = 0; k < n_kinds; ++k) {
+    ms_out[k] = 0.0;
+    launches_out[k] = 0;
+  }
+  int rc = FREDEC_OK;
+  for (size_t k = 0; k < ctx->prof_used; ++k) {
+    const auto& e = ctx->prof_events[k];
+    float ms = 0.0f;
+    if (hipEventSynchronize(e.end) != hipSuccess || hipEventElapsedTime(&ms, e.begin, e.end) != hipSuccess) {
+      rc = FREDEC_EDEVICE;
+      break;
+    }
+    if (e.kind >= 0 && e.kind < n_kinds) {
+      ms_out[e.kind] += ms;
+      launches_out[e.kind] += 1;
+    }
+  }
+  ctx->prof_used = 0;
+  return rc;
+}
+
 int fredec_profile_read(fredec_ctx* ctx, double* total_ms, int64_t* launches) {
   if (!ctx || !total_ms || !launches) return FREDEC_EINVAL;
-  DeviceGuard g(ctx->device);
-  double sum = 0.0;
-  for (size_t k = 0; k < ctx->prof_used; ++k) {
-    float ms = 0.0f;
-    if (hipEventSynchronize(ctx->prof_events[k].second) != hipSuccess ||
-        hipEventElapsedTime(&ms, ctx->prof_events[k].first, ctx->prof_events[k].second) != hipSuccess)
-      return FREDEC_EDEVICE;
-    sum += ms;
-  }
-  *total_ms = sum;
-  *launches = static_cast<int64_t>(ctx->prof_used);
-  ctx->prof_used = 0;
+  double ms[FREDEC_PROF_NKIND];
+  int64_t n[FREDEC_PROF_NKIND];
+  const int rc = fredec_profile_read_kinds(ctx, FREDEC_PROF_NKIND, ms, n);
+  if (rc) return rc;
+  *total_ms = ms[FREDEC_PROF_SCAN] + ms[FREDEC_PROF_GRAM];
+  *launches = n[FREDEC_PROF_SCAN] + n[FREDEC_PROF_GRAM];
   return FREDEC_OK;
 }
 
@@ -449,8 +465,8 @@ void fredec_destroy(fredec_ctx* ctx) {
   if (!ctx) return;
   DeviceGuard g(ctx->device);
   for (auto& e : ctx->prof_events) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
+    (void)hipEventDestroy(e.begin);
+    (void)hipEventDestroy(e.end);
   }
   if (ctx->staging_pending) (void)hipEventSynchronize(ctx->staging_done);
   if (ctx->staging) (void)hipHostFree(ctx->staging);

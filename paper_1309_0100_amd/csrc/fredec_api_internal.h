@@ -18,7 +18,7 @@ struct fredec_ctx {
   size_t staging_bytes = 0;
   hipEvent_t staging_done = nullptr;
   bool staging_pending = false;
-  int mfma_ft[5] = {0, 0, 0, 0, 0};  // MFMA scan: 16-frequency tiles per wave, by column tiles (0 = default)
+  int f16x3_ft[5] = {0, 0, 0, 0, 0};  // split-float16 scan: 16-frequency tiles per wave, by column tiles (0 = default)
   int f32_form = FREDEC_F32_FORM_AUTO;   // kernel family of the reduced-precision scan (FREDEC_F32_FORM_*)
   int f32_auto_valu_max_kp = 6;      // automatic form: VALU kernel up to this KP = 2m + 2 (m <= 2)
   // side streams (default priority) for launches of independent kernel
@@ -29,7 +29,11 @@ struct fredec_ctx {
   hipEvent_t join_ev[NSIDE] = {};
   // optional timing of the dominant kernel of each call (HIP events)
   bool profiling = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+  struct ProfEvent {
+    hipEvent_t begin, end;
+    int kind;  // FREDEC_PROF_*
+  };
+  std::vector<ProfEvent> prof_events;
   size_t prof_used = 0;
 };
 
@@ -65,11 +69,11 @@ int upload(fredec_ctx* ctx, hipStream_t st, void* dst, const void* src, size_t b
 // Waits until every upload enqueued so far has reached the device.
 int upload_wait(fredec_ctx* ctx);
 
-// Records a pair of HIP events on `st` around the dominant kernel launches of
-// a call when the context has profiling enabled.
+// Records a pair of HIP events on `st` around a group of kernel launches of
+// one kind (FREDEC_PROF_*) when the context has profiling enabled.
 class ProfScope {
  public:
-  ProfScope(fredec_ctx* ctx, hipStream_t st);
+  ProfScope(fredec_ctx* ctx, hipStream_t st, int kind = FREDEC_PROF_SCAN);
   ~ProfScope();
 
  private:

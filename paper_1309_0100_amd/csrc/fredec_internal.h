@@ -275,18 +275,12 @@ hipError_t launch_prep(hipStream_t st, int n_series, int kp_max, int64_t n_tiles
                        SeriesHdr* hdr, const double* t, const double* x, const double* w, double* tau, double* xt,
                        double* wt, double* rec, double* phi, float* g32, double* aux, void* b16, double* ppart,
                        double* pm, int flags);
-hipError_t launch_scan_mfma(hipStream_t st, int NT, int FT, int n_work, const ScanWork* work,
-                            const SeriesIn* sin, const SeriesHdr* hdr, const float* g32,
-                            const double* aux, double* z, uint8_t* flags, Rescore* list,
-                            unsigned long long* count);
 // float64 re-scoring of the listed points (per-series lists at list[goff_s ..],
 // count[s] entries each; off: 2 n_series + 3 int64 of workspace for the plan)
 hipError_t launch_rescore(hipStream_t st, int NT, int grid, int n_series, const SeriesIn* sin, const SeriesHdr* hdr,
                           const double* rec, const Rescore* list, const unsigned long long* count, int64_t* off,
                           double* z, uint8_t* flags);
 hipError_t launch_zero_u64(hipStream_t st, unsigned long long* p, int n);
-int mfma_freq_tiles(int NT);  // default FT of the MFMA scan kernel (16-frequency tiles per wave)
-bool mfma_tile_supported(int NT, int FT);
 hipError_t launch_scan_f64(hipStream_t st, int KP, int n_work, const ScanWork* work,
                            const SeriesIn* sin, const SeriesHdr* hdr, const double* rec,
                            double* z, uint8_t* flags);
@@ -302,12 +296,16 @@ hipError_t launch_scan_f32(hipStream_t st, int KP, int n_work, const ScanWork* w
                            const SeriesHdr* hdr, const double* rec, const float* g32, double* z, uint8_t* flags,
                            Rescore* list, unsigned long long* count);
 int scan_f32_freqs_per_thread(int KP);  // R of the float32 VALU scan kernel
-constexpr int F32_VALU_MAX_KP = 26;     // larger base models use the MFMA form
+constexpr int F32_VALU_MAX_KP = 26;     // larger base models use the split-float16 MFMA form
 constexpr int F32_AUTO_VALU_MAX_KP = 6;  // automatic form: VALU kernel for m <= 2, split float16 MFMA above
 // Reduced-precision MFMA scan on split float16 operands (aux records and the
 // preparation kernel's float16 operand array b16, 8-half vectors).
-constexpr int f16x3_freq_tiles(int NT) { return NT <= 1 ? 4 : NT <= 2 ? 2 : 1; }  // 16-frequency tiles per wave
-hipError_t launch_scan_f16x3(hipStream_t st, int NT, int n_work, const ScanWork* work, const SeriesIn* sin,
+constexpr int f16x3_freq_tiles(int NT) { return NT <= 1 ? 4 : NT <= 2 ? 2 : 1; }  // default 16-frequency tiles per wave
+// supported (column tiles, frequency tiles per wave): FT in {1, 2, 4} with NT FT <= 4
+constexpr bool f16x3_tile_supported(int NT, int FT) {
+  return NT >= 1 && NT <= 4 && (FT == 1 || FT == 2 || FT == 4) && NT * FT <= 4;
+}
+hipError_t launch_scan_f16x3(hipStream_t st, int NT, int FT, int n_work, const ScanWork* work, const SeriesIn* sin,
                              const SeriesHdr* hdr, const double* aux, const void* b16, double* z, uint8_t* flags,
                              Rescore* list, unsigned long long* count);
 // 8-half vectors of the float16 operand of a series of N samples and NT column tiles:

@@ -71,7 +71,9 @@ int phase1_layout(int64_t N, int64_t F, int32_t max_scans, int32_t precision, Ph
   }
   if (rc) return rc;
   if ((rc = fredec_scan_at_workspace(N, mmax, &L.at_ws))) return rc;
-  L.peak_cap = std::min<int64_t>(F, 1 << 20);
+  // interior maxima with z_{j-1} < z_j cannot be adjacent: at most
+  // ceil((F - 2) / 2) of them, so every peak above the threshold is kept
+  L.peak_cap = std::max<int64_t>((F - 1) / 2, 1);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -244,7 +246,8 @@ int fredec_phase1(fredec_ctx* ctx, void* stream, const double* t, const double* 
     if (launch_peaks(st, d_z, d_fl, F, zmin, d_pk, d_cnt, L.peak_cap) != hipSuccess) return FREDEC_EDEVICE;
     unsigned long long cnt = 0;
     if ((rc = sync_read(st, &cnt, d_cnt, sizeof(cnt)))) return rc;
-    const int64_t np = std::min<int64_t>(static_cast<int64_t>(cnt), L.peak_cap);
+    if (static_cast<int64_t>(cnt) > L.peak_cap) return FREDEC_EDEVICE;  // cannot happen (see phase1_layout)
+    const int64_t np = static_cast<int64_t>(cnt);
     std::vector<Peak> pk(np);
     if ((rc = sync_read(st, pk.data(), d_pk, sizeof(Peak) * np))) return rc;
     if (precision == FREDEC_FP32 && np > 0) {

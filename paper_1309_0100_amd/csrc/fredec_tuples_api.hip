@@ -1,6 +1,7 @@
 // C ABI of the tuple statistics: fredec_tuples (all subsets of a pool, fixed
-// or refined frequencies), fredec_grad / fredec_adjoint (z and dz/df of
-// ragged tuples) and fredec_ascent (fixed-step preconditioned ascent).
+// or refined frequencies), fredec_grad (z and dz/df of ragged tuples),
+// fredec_adjoint (dz/df of an earlier forward evaluation) and fredec_ascent
+// (fixed-step preconditioned ascent).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -225,7 +226,7 @@ int launch_groups(const fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, int
 
 // One Gram pass (the size groups concurrently).
 int gram_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, int mode) {
-  ProfScope prof(ctx, st);
+  ProfScope prof(ctx, st, FREDEC_PROF_GRAM);
   return launch_groups(ctx, st, P, mode, [&](const TuplePlan::Group& g, hipStream_t gs) {
     return launch_tuple_gram(gs, g.nf, ctx->n_cu, D.desc, D.order + g.begin, g.count, P.N, D.com, D.tau, D.xt,
                              D.wt, D.ftry, D.state, D.gram, mode, P.precision == FREDEC_FP32) == hipSuccess;
@@ -234,8 +235,9 @@ int gram_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDe
 
 // Adjoint gradient of every tuple (forward state, theta* and f in the
 // workspace), the size groups concurrently.
-int adjoint_pass(const fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, const double* f,
+int adjoint_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, const double* f,
                  double* dzdf, double* hout) {
+  ProfScope prof(ctx, st, FREDEC_PROF_ADJOINT);
   return launch_groups(ctx, st, P, TUPLE_FWD, [&](const TuplePlan::Group& g, hipStream_t gs) {
     return launch_tuple_adjoint(gs, g.nf, ctx->n_cu, D.desc, D.order + g.begin, g.count, P.N, D.com, D.tau, D.xt,
                                 D.wt, f, D.theta, D.state, dzdf, hout, P.precision == FREDEC_FP32) == hipSuccess;
@@ -249,6 +251,7 @@ int run_fit(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev&
   for (int it = 0; it <= refine_steps; ++it) {
     int rc = gram_pass(ctx, st, P, D, mode);
     if (rc) return rc;
+    ProfScope prof(ctx, st, FREDEC_PROF_SOLVE);
     if (launch_tuple_solve(st, D.desc, D.order, nt, D.com, D.gram, D.scr, D.ftry, D.facc, D.step, D.theta, D.state,
                            mode, it == refine_steps ? 1 : 0) != hipSuccess)
       return FREDEC_EDEVICE;
@@ -510,6 +513,31 @@ int fredec_grad(fredec_ctx* ctx, void* stream, const double* t, const double* x,
   if (theta_out && launch_copy_f64(st, D.theta, theta_out, P.ntheta) != hipSuccess) return FREDEC_EDEVICE;
   if ((dz_df || h_out) && (rc = adjoint_pass(ctx, st, P, D, D.ftry, dz_df, h_out))) return rc;
   return FREDEC_OK;
+}
+
+int fredec_adjoint(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                   const double* f, const int64_t* toff, int64_t n_tuples, const double* theta, const double* l,
+                   int32_t precision, void* ws, size_t ws_bytes, double* dz_df, double* h_out) {
+  int rc = check_series_args(t, x, w, N);
+  if (rc) return rc;
+  if (!f || !theta || !l) return FREDEC_EINVAL;
+  if (precision != FREDEC_FP64 && precision != FREDEC_FP32) return FREDEC_EINVAL;
+  std::vector<int> sizes;
+  if ((rc = sizes_from_toff(toff, n_tuples, sizes))) return rc;
+  TuplePlan P;
+  if ((rc = make_plan(N, sizes, false, P))) return rc;
+  P.precision = precision;
+  if (!ws || ws_bytes < P.total) return FREDEC_ENOMEM;
+  if (!ctx) return FREDEC_EINVAL;
+  if (!dz_df && !h_out) return FREDEC_OK;
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TupleDev D = dev_ptrs(ws, P);
+  if ((rc = upload_descriptors(ctx, st, P, D, N))) return rc;
+  if ((rc = normalise(st, P, D, t, x, w, N))) return rc;
+  if (launch_tuple_state_from_l(st, static_cast<int>(n_tuples), l, D.state) != hipSuccess) return FREDEC_EDEVICE;
+  if (launch_copy_f64(st, theta, D.theta, P.ntheta) != hipSuccess) return FREDEC_EDEVICE;
+  return adjoint_pass(ctx, st, P, D, f, dz_df, h_out);
 }
 
 int fredec_ascent(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,

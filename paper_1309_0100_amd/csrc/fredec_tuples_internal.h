@@ -71,6 +71,7 @@ hipError_t launch_tuple_adjoint(hipStream_t st, int nf, int n_cu, const TupleDes
 hipError_t launch_tuple_ascent_update(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
                                       const double* g, const double* h, double* f, double clamp, TupleState* state);
 hipError_t launch_tuple_init(hipStream_t st, int n_tuples, TupleState* state);
+hipError_t launch_tuple_state_from_l(hipStream_t st, int n_tuples, const double* l, TupleState* state);
 hipError_t launch_tuple_l0(hipStream_t st, const TupleState* state, double* l0_out);
 hipError_t launch_tuple_common(hipStream_t st, const SeriesHdr* hdr, int64_t N, TupleCommon* com);
 hipError_t launch_copy_f64(hipStream_t st, const double* src, double* dst, int64_t n);

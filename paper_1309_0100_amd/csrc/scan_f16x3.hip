@@ -378,28 +378,26 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
   }
 }
 
-template <int NT>
+template <int NT, int FT>
 hipError_t launch_nt(hipStream_t st, int n_work, const ScanWork* work, const SeriesIn* sin, const SeriesHdr* hdr,
                      const double* aux, const void* b16, double* z, uint8_t* flags, Rescore* list,
                      unsigned long long* count) {
-  scan_f16x3_kernel<NT, f16x3_freq_tiles(NT), F16X3_TS><<<n_work, BLOCK, 0, st>>>(
-      work, sin, hdr, aux, static_cast<const v8h*>(b16), z, flags, list, count);
+  scan_f16x3_kernel<NT, FT, F16X3_TS><<<n_work, BLOCK, 0, st>>>(work, sin, hdr, aux, static_cast<const v8h*>(b16), z,
+                                                               flags, list, count);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_scan_f16x3(hipStream_t st, int NT, int n_work, const ScanWork* work, const SeriesIn* sin,
+hipError_t launch_scan_f16x3(hipStream_t st, int NT, int FT, int n_work, const ScanWork* work, const SeriesIn* sin,
                              const SeriesHdr* hdr, const double* aux, const void* b16, double* z, uint8_t* flags,
                              Rescore* list, unsigned long long* count) {
   if (n_work <= 0) return hipSuccess;
-  switch (NT) {
-    case 1: return launch_nt<1>(st, n_work, work, sin, hdr, aux, b16, z, flags, list, count);
-    case 2: return launch_nt<2>(st, n_work, work, sin, hdr, aux, b16, z, flags, list, count);
-    case 3: return launch_nt<3>(st, n_work, work, sin, hdr, aux, b16, z, flags, list, count);
-    case 4: return launch_nt<4>(st, n_work, work, sin, hdr, aux, b16, z, flags, list, count);
-    default: return hipErrorInvalidValue;
-  }
+#define X(nt, ft) \
+  if (NT == nt && FT == ft) return launch_nt<nt, ft>(st, n_work, work, sin, hdr, aux, b16, z, flags, list, count);
+  X(1, 1) X(1, 2) X(1, 4) X(2, 1) X(2, 2) X(3, 1) X(4, 1)
+#undef X
+  return hipErrorInvalidValue;
 }
 
 }  // namespace fredec

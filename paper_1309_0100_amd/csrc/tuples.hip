@@ -811,6 +811,18 @@ __global__ void tuple_ascent_update_kernel(const TupleDesc* __restrict__ desc, i
   S.l_acc = __builtin_inf();
 }
 
+// State of a forward evaluation made by an earlier call, from its l: the
+// adjoint kernels need the accepted l and whether there is one.
+__global__ void tuple_state_from_l_kernel(int n_tuples, const double* __restrict__ l,
+                                          TupleState* __restrict__ state) {
+  const int ti = blockIdx.x * BLOCK + threadIdx.x;
+  if (ti >= n_tuples) return;
+  const double v = l[ti];
+  TupleState& S = state[ti];
+  S.has_acc = isfinite(v) ? 1 : 0;
+  S.l_acc = isfinite(v) ? v : __builtin_inf();
+}
+
 __global__ void tuple_init_kernel(int n_tuples, TupleState* __restrict__ state) {
   const int ti = blockIdx.x * BLOCK + threadIdx.x;
   if (ti >= n_tuples) return;
@@ -1055,6 +1067,12 @@ hipError_t launch_tuple_ascent_update(hipStream_t st, const TupleDesc* desc, int
   if (n_tuples <= 0) return hipSuccess;
   tuple_ascent_update_kernel<<<(n_tuples + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(desc, n_tuples, com, g, h, f, clamp,
                                                                                state);
+  return hipGetLastError();
+}
+
+hipError_t launch_tuple_state_from_l(hipStream_t st, int n_tuples, const double* l, TupleState* state) {
+  if (n_tuples <= 0) return hipSuccess;
+  tuple_state_from_l_kernel<<<(n_tuples + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(n_tuples, l, state);
   return hipGetLastError();
 }
 

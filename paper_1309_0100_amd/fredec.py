@@ -22,11 +22,14 @@ FP64 = 0
 FP32 = 1
 
 OK, EINVAL, EDOF, EWEIGHT, EDEGEN, ESINGULAR, ENOMEM, EDEVICE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7, -8
-TILE_SCAN_MFMA = 1
+TILE_SCAN_F16X3 = 1
 TILE_SCAN_F32_FORM = 2
-F32_FORM_VALU, F32_FORM_MFMA32, F32_FORM_F16X3, F32_FORM_AUTO = 0, 1, 2, 3
+F32_FORM_VALU, F32_FORM_F16X3, F32_FORM_AUTO = 0, 2, 3
+MAX_BASE = 24
+MAX_POOL = 27
 FLAG_MASKED, FLAG_SINGULAR, FLAG_PERFECT, FLAG_DEGENERATE, FLAG_BADSERIES = 1, 2, 4, 8, 128
 FLAG_CONVERGED, FLAG_RESCORED = 16, 64
+PROF_KINDS = ("scan", "gram", "solve", "prep", "rescore", "adjoint")
 
 c_i32, c_i64, c_sz, c_p, c_d = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
 c_pp = ctypes.POINTER(ctypes.c_void_p)
@@ -40,6 +43,7 @@ _SIGS = {
     "fredec_set_tile": (c_i32, [c_p, c_i32, c_i32, c_i32]),
     "fredec_profile": (c_i32, [c_p, c_i32]),
     "fredec_profile_read": (c_i32, [c_p, ctypes.POINTER(c_d), ctypes.POINTER(c_i64)]),
+    "fredec_profile_read_kinds": (c_i32, [c_p, c_i32, c_p, c_p]),
     "fredec_normalize_workspace": (c_i32, [c_i32, c_szp]),
     "fredec_normalize": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_sz, c_p, c_p, c_p, c_p, c_p]),
     "fredec_scan_workspace": (c_i32, [c_i32, c_p, c_p, c_p, c_i32, c_szp]),
@@ -51,6 +55,8 @@ _SIGS = {
     "fredec_grad_workspace": (c_i32, [c_i64, c_p, c_i64, c_szp]),
     "fredec_grad": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_i64, c_i32, c_p, c_sz, c_p, c_p, c_p, c_p,
                             c_p, c_p]),
+    "fredec_adjoint": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_i64, c_p, c_p, c_i32, c_p, c_sz, c_p,
+                               c_p]),
     "fredec_ascent": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_i64, c_i32, c_d, c_i32, c_p, c_sz, c_p,
                               c_p, c_p]),
     "fredec_zcrit": (c_i32, [c_d, c_i32, c_d, c_p, c_p]),
@@ -212,6 +218,14 @@ class Context:
     def profile(self, enable: bool = True):
         _check(load().fredec_profile(self.handle, int(enable)), "fredec_profile")
 
+    def profile_read_kinds(self):
+        """{kind: (ms, timed groups)} for every kind of kernel group since the last read."""
+        n = len(PROF_KINDS)
+        ms = np.zeros(n, np.float64)
+        cnt = np.zeros(n, np.int64)
+        _check(load().fredec_profile_read_kinds(self.handle, n, _ptr(ms), _ptr(cnt)), "fredec_profile_read_kinds")
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PROF_KINDS)}
+
     def profile_read(self):
         """(total ms, event pairs) of the dominant kernels since the last read."""
         ms = ctypes.c_double()
@@ -354,6 +368,24 @@ class Context:
                                   _ptr(toff), nt, precision, _ptr(ws), need.value, _ptr(z), _ptr(l), _ptr(th),
                                   _ptr(g), _ptr(h), _ptr(fl)), "fredec_grad")
         return z, l, th, g, h, fl
+
+    def adjoint(self, t, x, w, f, toff, theta, l, want_h=False, precision=FP64):
+        """dz/df (and h) of ragged tuples from an earlier forward evaluation's
+        theta and l (device tensors, as returned by grad)."""
+        torch = _torch()
+        t, x, w, f = self._f64(t), self._f64(x), self._f64(w), self._f64(f)
+        theta, l = self._f64(theta), self._f64(l)
+        toff = np.ascontiguousarray(toff, np.int64)
+        nt = toff.size - 1
+        need = ctypes.c_size_t()
+        _check(load().fredec_grad_workspace(t.numel(), _ptr(toff), nt, ctypes.byref(need)), "fredec_grad_workspace")
+        ws = self._workspace(need.value)
+        g = self._empty(int(toff[-1]), torch.float64)
+        h = self._empty(int(toff[-1]), torch.float64) if want_h else None
+        _check(load().fredec_adjoint(self.handle, _stream(self.device), _ptr(t), _ptr(x), _ptr(w), t.numel(), _ptr(f),
+                                     _ptr(toff), nt, _ptr(theta), _ptr(l), precision, _ptr(ws), need.value, _ptr(g),
+                                     _ptr(h)), "fredec_adjoint")
+        return g, h
 
     def ascent(self, t, x, w, f, toff, steps=20, clamp=0.1, precision=FP64):
         """Preconditioned ascent; returns (f, z, l, flags) with f a new device tensor."""

@@ -38,7 +38,7 @@ def test_backward_is_adjoint_gradient(ctx):
     dev = torch.device("cuda", 0)
     print("case: autograd backward vs oracle gradient, 48 tuples", flush=True)
     fd = torch.tensor(f, device=dev, requires_grad=True)
-    z, l, h, fl = tuple_z(ctx, s.t, s.x, s.w, fd, toff)
+    z, l, h, fl = tuple_z(ctx, s.t, s.x, s.w, fd, toff, want_h=True)
     rng = np.random.default_rng(1)
     up = torch.tensor(rng.uniform(0.5, 2.0, size=toff.size - 1), device=dev)
     (z * up).sum().backward()
@@ -85,6 +85,27 @@ def test_autograd_matches_central_differences(ctx):
             assert abs(fdv - g[j]) <= 1e-6 * max(abs(g[j]), nrm.T_eff), (j, fdv, g[j])
 
 
+def test_forward_only_has_no_curvature_and_backward_matches_grad(ctx):
+    """Without want_h the forward pass makes no adjoint pass (h is NaN); the
+    backward pass (fredec_adjoint on the saved theta* and l) gives the
+    gradient that one fredec_grad call computes with its own adjoint pass."""
+    import torch
+    from paper_1309_0100_amd.autograd import tuple_z
+    s, nrm, f, toff = _case(seed=733, N=500, n_tuples=32)
+    dev = torch.device("cuda", 0)
+    print("case: forward-only autograd and backward vs fredec_grad, 32 tuples", flush=True)
+    fd = torch.tensor(f, device=dev, requires_grad=True)
+    z, l, h, fl = tuple_z(ctx, s.t, s.x, s.w, fd, toff)
+    assert torch.isnan(h).all()
+    z.sum().backward()
+    zg, lg, thg, gg, hg, flg = ctx.grad(s.t, s.x, s.w, f, toff, want_grad=True)
+    a, b = fd.grad.cpu().numpy(), gg.cpu().numpy()
+    assert np.array_equal(np.isnan(a), np.isnan(b))
+    ok = ~np.isnan(b)
+    assert np.array_equal(a[ok], b[ok])
+    assert np.array_equal(z.detach().cpu().numpy(), zg.cpu().numpy())
+
+
 def test_autograd_loop_reproduces_library_ascent(ctx):
     """Twenty preconditioned steps f += clamp(g / h, +-0.1 / T_eff) driven
     through autograd give the library's fixed-step ascent."""
@@ -103,7 +124,7 @@ def test_autograd_loop_reproduces_library_ascent(ctx):
     lim = 0.1 / nrm.T_eff
     for _ in range(20):
         fv = f.clone().requires_grad_(True)
-        z, l, h, fl = tuple_z(ctx, s.t, s.x, s.w, fv, toff, seg=seg)
+        z, l, h, fl = tuple_z(ctx, s.t, s.x, s.w, fv, toff, seg=seg, want_h=True)
         z.sum().backward()
         with torch.no_grad():
             g = fv.grad
