@@ -554,6 +554,53 @@ def survives(ltab, S: int, N: int, zc) -> bool:
     return bool(np.all(zrel > zc[d]))
 
 
+def supersets(R: int, n: int) -> np.ndarray:
+    """Every subset S of {0..n-1} that contains the mask R: R joined with each
+    subset of the remaining bits."""
+    free = [b for b in range(n) if not R >> b & 1]
+    T = np.zeros(1 << len(free), np.int64)
+    k = np.arange(1 << len(free), dtype=np.int64)
+    for j, b in enumerate(free):
+        T |= ((k >> j) & 1) << b
+    return T | R
+
+
+def survive_table(ltab, n: int, N: int, zc) -> np.ndarray:
+    """The rule of survives() for every subset at once (Sect. 4.4, Sect. 2):
+    for each non-empty removed set R and each S containing it, the test of S
+    against S' = S minus R at depth |R|.  survive[S] is True iff S passes all
+    of them; survive[0] is False."""
+    ltab = np.asarray(ltab, np.float64)
+    M = 1 << n
+    pc = np.array([popcount(S) for S in range(M)], np.int64)
+    NH = N - 3 * pc - 1
+    with np.errstate(invalid="ignore"):
+        ok = np.isfinite(ltab) & (ltab > 0) & (NH > 0)
+    ok[0] = False
+    for R in range(1, M):
+        S = supersets(R, n)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            zrel = 0.5 * NH[S] * np.log(ltab[S ^ R] / ltab[S])
+        ok[S] &= zrel > zc[pc[R]]
+    return ok
+
+
+def maximal_sets(surv: np.ndarray, n: int) -> list[int]:
+    """Survivors with no surviving strict superset (Sect. 4.4): the output
+    sets, in increasing mask order.  A set has a surviving strict superset
+    iff one of its one-element extensions survives or has one."""
+    M = 1 << n
+    has_sup = np.zeros(M, bool)
+    for S in range(M - 1, 0, -1):
+        for k in range(n):
+            if not S >> k & 1:
+                T = S | (1 << k)
+                if surv[T] or has_sup[T]:
+                    has_sup[S] = True
+                    break
+    return [S for S in range(1, M) if surv[S] and not has_sup[S]]
+
+
 def phase3(ltab, n: int, N: int, zc) -> tuple[np.ndarray, np.ndarray, int]:
     """Backward cascade of Sect. 4.4 / the 2^m - 1 joint tests of Sect. 2:
     subset S survives iff for every proper subset S' (including the empty
@@ -566,16 +613,7 @@ def phase3(ltab, n: int, N: int, zc) -> tuple[np.ndarray, np.ndarray, int]:
     for S in range(1, 1 << n):
         tests += (1 << popcount(S)) - 1
         surv[S] = survives(ltab, S, N, zc)
-    # inclusion-maximal survivors: no surviving strict superset
-    has_sup = np.zeros(1 << n, bool)
-    for S in range((1 << n) - 1, 0, -1):
-        for k in range(n):
-            if not S >> k & 1:
-                T = S | (1 << k)
-                if surv[T] or has_sup[T]:
-                    has_sup[S] = True
-                    break
-    maximal = [S for S in range(1, 1 << n) if surv[S] and not has_sup[S]]
+    maximal = maximal_sets(surv, n)
     G = {S: ltab[S] * (N - 1) / n_dof(N, popcount(S)) for S in maximal}
     maximal.sort(key=lambda S: (popcount(S), G[S], S))
     return surv, np.asarray(maximal, np.int64), tests

@@ -401,6 +401,46 @@ def test_phase3_multiplicative_table():
     assert list(maximal) == [strong]
 
 
+@pytest.mark.parametrize("n", [1, 2, 4, 6])
+def test_survive_table_equals_per_subset_rule(n):
+    """The whole-table form of the Phase 3 rule gives, subset by subset, what
+    the per-subset rule gives (random tables with some non-finite entries and
+    thresholds large enough that both outcomes occur)."""
+    rng = np.random.default_rng(40 + n)
+    ltab = np.concatenate([[1.0], rng.uniform(0.2, 1.0, size=(1 << n) - 1)])
+    ltab[rng.integers(1, 1 << n, size=max(1, n // 2))] = np.nan
+    zc = O.zcrit_table(n, 50.0, 0.05)
+    tab = O.survive_table(ltab, n, 80, zc)
+    for S in range(1, 1 << n):
+        assert bool(tab[S]) == O.survives(ltab, S, 80, zc), S
+    assert not tab[0]
+    surv, maximal, _ = O.phase3(ltab, n, 80, zc)
+    assert np.array_equal(surv, tab)
+    assert sorted(int(S) for S in maximal) == O.maximal_sets(tab, n)
+
+
+def test_survive_table_multiplicative():
+    """Multiplicative table of the strong/weak components (see above) through
+    the whole-table rule: survivors = non-empty subsets of the strong set."""
+    n = 8
+    q = np.where(np.arange(n) % 3 == 0, 0.5, 0.999)
+    ltab = np.array([np.prod(q[[k for k in range(n) if S >> k & 1]]) for S in range(1 << n)])
+    tab = O.survive_table(ltab, n, 1000, O.zcrit_table(n, 300.0, 0.05))
+    strong = sum(1 << k for k in range(n) if k % 3 == 0)
+    for S in range(1 << n):
+        assert tab[S] == (S != 0 and (S & ~strong) == 0)
+    assert O.maximal_sets(tab, n) == [strong]
+
+
+def test_supersets_enumeration():
+    n = 7
+    for R in [0, 1, 0b1010, 0b1111111]:
+        sup = O.supersets(R, n)
+        assert sup.size == 1 << (n - O.popcount(R))
+        assert len(set(sup.tolist())) == sup.size
+        assert all((int(S) & R) == R and 0 <= S < (1 << n) for S in sup)
+
+
 def test_phase1_noiseless_pool_contains_injected():
     s = synth.random_series(91, 400, span=400.0, n_sin=3, noise=0.05)
     df, F = 1e-4, 5000
