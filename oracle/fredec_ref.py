@@ -622,3 +622,71 @@ def phase3(ltab, n: int, N: int, zc) -> tuple[np.ndarray, np.ndarray, int]:
 def goodness(l: float, N: int, m: int) -> float:
     """G = l_{m,loc} N_H0 / N_Hm, Sect. 6 item 2."""
     return l * (N - 1) / n_dof(N, m)
+
+
+# ------------------------------------------- Phase 4 and the report of Sect. 6
+def residual_fap(t, x, w, freqs, df: float, F: int, A1: float = 1.0):
+    """Single-frequency FAP of the highest peak left in the residual
+    periodogram of a solution (Sect. 6, last item of the per-solution output):
+    the residual scan on the grid with the solution's frequencies as the base
+    model, its highest interior local maximum z_max (ties -> lowest index),
+    and FAP_1(z_max) of eq. zFAP with W = f_max T_eff, capped at 1.  Returns
+    (fap, z_max, grid index of that peak); (1, nan, -1) when the periodogram
+    has no peak."""
+    res = scan(t, x, w, np.atleast_1d(np.asarray(freqs, np.float64)), df, F)
+    pk = local_maxima(res.z, res.flags)
+    if pk.size == 0:
+        return 1.0, float("nan"), -1
+    j = int(pk[np.argmax(res.z[pk])])
+    z = float(res.z[j])
+    W = F * df * res.T_eff
+    return min(1.0, math.exp(log_fap(z, 1, W, A1))), z, j
+
+
+def loglik_terms(nrm: Normalized, freqs) -> np.ndarray:
+    """Per-sample Gaussian log-likelihood of the least-squares fit of model
+    H_n at the given frequencies, with the relative weights known and the
+    noise scale fitted by maximum likelihood (the noise model of Sect. 2):
+    sample i has variance l / (N w~_i), so
+        ll_i = -1/2 ln(2 pi l / (N w~_i)) - N w~_i r_i^2 / (2 l),
+    r = x~ - Phi theta*, l = <r^2> (normalised data)."""
+    fit = lsq(nrm, freqs)
+    r = nrm.xt - design(nrm.tau, freqs) @ fit.theta
+    l = float(np.sum(nrm.wt * r * r))
+    N = nrm.N
+    return -0.5 * np.log(TWO_PI * l / (N * nrm.wt)) - N * nrm.wt * r * r / (2.0 * l)
+
+
+def vuong(nrm: Normalized, f_ref, f_alt) -> float:
+    """Vuong's statistic for two non-nested fits (Phase 4 of Sect. 4 and
+    Sect. 6): with d_i = ll_i(ref) - ll_i(alt) the per-sample log-likelihood
+    differences, V = sum d / (sqrt(N) omega), omega^2 = mean(d^2) - mean(d)^2;
+    positive when the reference fits better.  The paper does not print the
+    formula: this is the plain statistic, without a correction for the
+    numbers of parameters.  0 when omega = 0 (identical fits)."""
+    d = loglik_terms(nrm, f_ref) - loglik_terms(nrm, f_alt)
+    N = d.size
+    om2 = float(np.mean(d * d) - np.mean(d) ** 2)
+    if om2 <= 0.0:
+        return 0.0
+    return float(np.sum(d) / (math.sqrt(N) * math.sqrt(om2)))
+
+
+def phase4(nrm: Normalized, solutions, vuong_max: float = 5.0):
+    """Phase 4 of Sect. 4 with the report of Sect. 6: the solutions (lists of
+    frequencies) in chi^2-increase order grouped by their number of
+    frequencies (within a group G and chi^2 have the same order), G of each
+    (Sect. 6), the Vuong statistic of the smallest-G solution against each,
+    and whether the solution is kept by the filter V < vuong_max (default 5).
+    Returns a list of dicts in output order."""
+    rows = []
+    for k, f in enumerate(solutions):
+        f = np.sort(np.atleast_1d(np.asarray(f, np.float64)))
+        l = lsq(nrm, f).l
+        rows.append({"index": k, "freqs": f, "m": f.size, "l": l, "G": goodness(l, nrm.N, f.size)})
+    best = min(rows, key=lambda r: (r["G"], r["index"]))
+    for r in rows:
+        r["vuong"] = 0.0 if r is best else vuong(nrm, best["freqs"], r["freqs"])
+        r["keep"] = r["vuong"] < vuong_max
+    rows.sort(key=lambda r: (r["m"], r["l"], r["index"]))
+    return rows

@@ -7,6 +7,7 @@ import pytest
 import oracle
 import oracle.fredec_ref as R
 import tests.test_oracle as P
+import tests.test_oracle_phase4 as P4
 
 PINS = [
     P.test_scan_m0_matches_scipy_lombscargle_plain_workload,
@@ -22,6 +23,10 @@ PINS = [
     P.test_goodness_golden,
     lambda: P.test_goodness_is_ratio_of_reduced_chi2(6, [0.021, 0.047]),
     P.test_local_maxima_golden,
+    lambda: P4.test_loglik_differences_match_scipy(1),
+    P4.test_vuong_identities,
+    P4.test_phase4_orders_and_filters,
+    P4.test_residual_fap_known_content,
 ]
 
 
@@ -90,7 +95,30 @@ def _local_maxima_with_ends(z, flags):
     return j[ok] - 1
 
 
+def _loglik_no_scale_term(nrm, freqs):
+    fit = R.lsq(nrm, freqs)
+    r = nrm.xt - R.design(nrm.tau, freqs) @ fit.theta
+    l = float(np.sum(nrm.wt * r * r))
+    return -nrm.N * nrm.wt * r * r / (2.0 * l)
+
+
+def _vuong_no_sqrt_n(nrm, f_ref, f_alt):
+    d = R.loglik_terms(nrm, f_ref) - R.loglik_terms(nrm, f_alt)
+    om2 = float(np.mean(d * d) - np.mean(d) ** 2)
+    return 0.0 if om2 <= 0 else float(np.sum(d) / np.sqrt(om2))
+
+
+_orig_scan = R.scan
+
+
+def _residual_scan_without_base(t, x, w, base_f, df, F, idx=None, block=256):
+    return _orig_scan(t, x, w, np.zeros(0), df, F, idx=idx, block=block)
+
+
 MUTATIONS = {
+    "log-likelihood without the fitted-scale term": ("loglik_terms", _loglik_no_scale_term),
+    "Vuong statistic without sqrt(N)": ("vuong", _vuong_no_sqrt_n),
+    "residual periodogram without the solution as base": ("scan", _residual_scan_without_base),
     "phase without 2 pi": ("design", _design_no_2pi),
     "dropped constant column": ("design", _design_no_constant),
     "N_H off by one": ("n_dof", lambda N, n: N - 3 * n),
