@@ -11,4 +11,5 @@ from .fredec_ref import *  # noqa: F401,F403
 from .fredec_ref import (Normalized, normalize, design, cholesky_checked, lsq, n_dof, grid, scan,  # noqa: F401
                          tuple_fit, tuple_grad, gn_step, gn_refine, ascent, zcrit, zcrit_table, log_fap,
                          local_maxima, phase1, phase2, phase3, goodness, popcount, survive_table,
-                         maximal_sets, supersets, residual_fap, loglik_terms, vuong, phase4)
+                         maximal_sets, supersets, residual_fap, loglik_terms, vuong, phase4,
+                         global_local_scan)

@@ -286,23 +286,27 @@ def tuple_grad(nrm: Normalized, freqs):
     return z, l, NH / l * g, NH / l * h
 
 
-def gn_step(nrm: Normalized, freqs, theta):
+def gn_step(nrm: Normalized, freqs, theta, frozen=()):
     """One Gauss-Newton step of Sect. 3 (eq. lsqf): with xi = (theta, f) and
     J~ = [Phi, J_1..J_n], Q_f = <J~ J~^T> and g_f = <r J~> (its theta part
-    vanishes at theta*); the step is Q_f^{-1} g_f and its f part is returned."""
+    vanishes at theta*); the step is Q_f^{-1} g_f and its f part is returned.
+    Frequencies whose index is in `frozen` are held fixed: their columns J_k
+    are left out of J~ and their step is 0."""
     freqs = np.atleast_1d(np.asarray(freqs, np.float64))
+    free = [k for k in range(freqs.size) if k not in set(frozen)]
     Phi = design(nrm.tau, freqs)
-    J = model_jacobian(nrm, freqs, theta)
+    J = model_jacobian(nrm, freqs, theta)[:, free]
     Jt = np.concatenate([Phi, J], axis=1)
     r = nrm.xt - Phi @ theta
     WJ = Jt * nrm.wt[:, None]
     Qf = WJ.T @ Jt
     gf = WJ.T @ r
     L, ok = cholesky_checked(Qf)
+    step = np.zeros(freqs.size)
     if not ok:
-        return np.zeros(freqs.size), False
-    step = back_subst(L, forward_subst(L, gf))
-    return step[Phi.shape[1]:], True
+        return step, False
+    step[free] = back_subst(L, forward_subst(L, gf))[Phi.shape[1]:]
+    return step, True
 
 
 @dataclass
@@ -316,7 +320,7 @@ class Refined:
 
 
 def gn_refine(nrm: Normalized, f0, steps: int, clamp: float = 0.25, max_halvings: int = 5,
-              tol: float = 1e-10, accept_rtol: float = 1e-12) -> Refined:
+              tol: float = 1e-10, accept_rtol: float = 1e-12, frozen=()) -> Refined:
     """Local refinement l_{n,loc} of Sect. 3 (and the local statistic of
     Sect. 2): Gauss-Newton steps on f with theta re-solved at every iterate.
     Step control (not given in the paper): the step is scaled so that
@@ -324,7 +328,8 @@ def gn_refine(nrm: Normalized, f0, steps: int, clamp: float = 0.25, max_halvings
     more than accept_rtol is rejected and the step halved (at most
     max_halvings times in a row); the iteration stops once
     max |df_k| T_eff < tol.  `steps` trial evaluations follow the evaluation
-    at f0, so 1 + steps least-squares fits are made in total."""
+    at f0, so 1 + steps least-squares fits are made in total.  The
+    frequencies with an index in `frozen` stay at their start values."""
     f0 = np.atleast_1d(np.asarray(f0, np.float64))
     n = f0.size
     T = nrm.T_eff
@@ -348,7 +353,7 @@ def gn_refine(nrm: Normalized, f0, steps: int, clamp: float = 0.25, max_halvings
         fit = None if degenerate else lsq(nrm, f_try)
         if fit is not None and fit.ok and fit.l <= l_acc * (1.0 + accept_rtol):
             f_acc, l_acc, th_acc = f_try.copy(), fit.l, fit.theta
-            step, ok = gn_step(nrm, f_acc, th_acc)
+            step, ok = gn_step(nrm, f_acc, th_acc, frozen)
             halvings = 0
             big = np.max(np.abs(step)) * T
             if not ok or big < tol:
@@ -690,3 +695,52 @@ def phase4(nrm: Normalized, solutions, vuong_max: float = 5.0):
         r["keep"] = r["vuong"] < vuong_max
     rows.sort(key=lambda r: (r["m"], r["l"], r["index"]))
     return rows
+
+
+# --------------------------------------- global-local residual periodogram, Sect. 2
+@dataclass
+class GlobalLocalResult:
+    z: np.ndarray           # z*_{1|m,loc}(f_j | f'_loc)
+    flags: np.ndarray
+    l_base: float           # l_{m,loc}(f'_loc)
+    base: np.ndarray        # the base frequencies at that local minimum
+    freqs: np.ndarray
+
+
+def global_local_scan(t, x, w, base_loc, df: float, F: int, refine_steps: int = 8, idx=None) -> GlobalLocalResult:
+    """The residual periodogram with a locally re-optimised base model
+    (Sect. 2, after eq. zpowrel): for every grid frequency f_j,
+        z*_{1|m,loc}(f_j | f'_loc) = (N - 3m - 4)/2 ln(l_{m,loc}(f'_loc) / l_{1|m,loc}(f_j | f'_loc)),
+    l_{m,loc}: the base model's chi^2 minimum near f'_loc (Gauss-Newton from
+    f'_loc); l_{1|m,loc}(f_j): the minimum of the model with the m base
+    frequencies and f_j near f'_loc with f_j held fixed (Gauss-Newton over the
+    base frequencies, started at the refined base).  Both refinements make
+    1 + refine_steps least-squares fits at most (gn_refine).  Flags as for
+    scan(): f_j within MASK_WIDTH / T_eff of a refined base frequency gives
+    z := 0 and FLAG_MASKED; a degenerate start gives z := 0 and
+    FLAG_SINGULAR; l <= 0 gives z := +inf and FLAG_PERFECT.  The maximum of
+    z* over the grid is the global-local statistic z*_{1|m,loc}(*|f'_loc)."""
+    nrm = normalize(t, x, w)
+    base_loc = np.atleast_1d(np.asarray(base_loc, np.float64))
+    m = base_loc.size
+    NH = n_dof(nrm.N, m + 1)
+    if m:
+        rb = gn_refine(nrm, base_loc, refine_steps)
+        lb, fb = rb.l, rb.f
+    else:
+        lb, fb = lsq(nrm, []).l, base_loc
+    f = grid(df, F, idx)
+    z = np.zeros(f.size)
+    flags = np.zeros(f.size, np.uint8)
+    for q, fj in enumerate(f):
+        if m and np.any(np.abs(fj - fb) * nrm.T_eff < MASK_WIDTH):
+            flags[q] = FLAG_MASKED
+            continue
+        r = gn_refine(nrm, np.concatenate([fb, [fj]]), refine_steps, frozen=(m,))
+        if r.flag & FLAG_DEGENERATE:
+            flags[q] = FLAG_SINGULAR
+        elif r.flag & FLAG_PERFECT:
+            z[q], flags[q] = np.inf, FLAG_PERFECT
+        else:
+            z[q] = 0.5 * NH * math.log(lb / r.l)
+    return GlobalLocalResult(z, flags, lb, fb, f)

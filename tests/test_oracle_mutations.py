@@ -27,6 +27,8 @@ PINS = [
     P4.test_vuong_identities,
     P4.test_phase4_orders_and_filters,
     P4.test_residual_fap_known_content,
+    P4.test_global_local_dominates_fixed_base_scan,
+    P4.test_global_local_matches_brute_force_minimisation,
 ]
 
 
@@ -115,7 +117,20 @@ def _residual_scan_without_base(t, x, w, base_f, df, F, idx=None, block=256):
     return _orig_scan(t, x, w, np.zeros(0), df, F, idx=idx, block=block)
 
 
+_orig_gn_step = R.gn_step
+
+
+def _gn_step_ignoring_frozen(nrm, freqs, theta, frozen=()):
+    return _orig_gn_step(nrm, freqs, theta)
+
+
+def _gn_step_zero(nrm, freqs, theta, frozen=()):
+    return np.zeros(np.atleast_1d(freqs).size), True
+
+
 MUTATIONS = {
+    "global-local periodogram moving the trial frequency": ("gn_step", _gn_step_ignoring_frozen),
+    "global-local periodogram without re-optimised base": ("gn_step", _gn_step_zero),
     "log-likelihood without the fitted-scale term": ("loglik_terms", _loglik_no_scale_term),
     "Vuong statistic without sqrt(N)": ("vuong", _vuong_no_sqrt_n),
     "residual periodogram without the solution as base": ("scan", _residual_scan_without_base),

@@ -105,3 +105,57 @@ def test_residual_fap_known_content():
     assert math.isclose(fap2, 2.0 * fap_one, rel_tol=1e-12)
     W = F * df * T
     assert math.isclose(fap_one, W * math.exp(-z_one) * math.sqrt(z_one), rel_tol=1e-12)
+
+
+# ------------------------------------------- global-local residual periodogram
+def test_global_local_without_base_is_the_plain_periodogram():
+    """With no base model there is nothing to re-optimise: z*_{1|0,loc} = z_1."""
+    s = synth.random_series(341, 120, span=60.0, n_sin=2, noise=0.5)
+    df, F = 5e-3, 300
+    g = O.global_local_scan(s.t, s.x, s.w, [], df, F)
+    r = O.scan(s.t, s.x, s.w, [], df, F)
+    assert np.array_equal(g.flags, r.flags)
+    assert np.allclose(g.z, r.z, rtol=1e-12, atol=1e-12)
+
+
+def test_global_local_dominates_fixed_base_scan():
+    """Re-optimising the base frequencies can only lower chi^2: z* is at least
+    the residual periodogram on the refined base held fixed."""
+    s = synth.random_series(342, 150, span=80.0, n_sin=3, noise=0.6)
+    df, F = 4e-3, 200
+    base = s.true_f[:2] * (1.0 + 1e-3)
+    g = O.global_local_scan(s.t, s.x, s.w, base, df, F, refine_steps=6)
+    r = O.scan(s.t, s.x, s.w, g.base, df, F)
+    ok = (g.flags == 0) & (r.flags == 0)
+    assert ok.sum() > 0.9 * F
+    assert np.all(g.z[ok] >= r.z[ok] - 1e-9 * np.maximum(r.z[ok], 1.0))
+    assert np.max(g.z[ok] - r.z[ok]) > 1e-3      # the re-optimisation does something
+
+
+def test_global_local_matches_brute_force_minimisation():
+    """m = 1: l_{1|1,loc}(f_j) is the minimum over the base frequency f' near
+    the refined base of l_2({f', f_j}); a bounded scalar minimiser (scipy) on a
+    dense bracket finds the same minimum."""
+    from scipy.optimize import minimize_scalar
+    s = synth.random_series(343, 100, span=50.0, n_sin=2, noise=0.4)
+    nrm = O.normalize(s.t, s.x, s.w)
+    T = nrm.T_eff
+    base = np.array([s.true_f[0] + 0.05 / T])
+    df, F = 6e-3, 120
+    idx = np.array([7, 31, 55, 90], np.int64)
+    g = O.global_local_scan(s.t, s.x, s.w, base, df, F, refine_steps=30, idx=idx)
+    fb = float(g.base[0])
+    checked = 0
+    for q, j in enumerate(idx):
+        fj = (j + 1) * df
+        if g.flags[q] or abs(fj - fb) * T < 1.0:
+            continue
+        grid = np.linspace(fb - 0.3 / T, fb + 0.3 / T, 601)
+        ls = [O.lsq(nrm, [u, fj]).l for u in grid]
+        u0 = grid[int(np.argmin(ls))]
+        res = minimize_scalar(lambda u: O.lsq(nrm, [u, fj]).l, bounds=(u0 - 1e-3 / T, u0 + 1e-3 / T),
+                              method="bounded", options={"xatol": 1e-13 / T})
+        l_loc = g.l_base * math.exp(-2.0 * g.z[q] / O.n_dof(nrm.N, 2))
+        assert abs(l_loc - res.fun) <= 1e-9 * res.fun, (j, l_loc, res.fun)
+        checked += 1
+    assert checked >= 3
