@@ -170,6 +170,35 @@ int fredec_scan(fredec_ctx* ctx, void* stream, int32_t n_series,
                 int32_t precision, void* workspace, size_t ws_bytes,
                 double* z_out, uint8_t* flags_out, double* l_base_out, int32_t* status_out);
 
+/* Allocation-free residual scan ---------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP-graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The result
+ * of fredec_scan for ONE series (t, x, w device [N]; base_f host [m], nullable
+ * when m = 0; grid f_j = (j+1) df, j < F; outputs as for fredec_scan with
+ * n_series = 1), computed by the same kernels, with its scratch memory taken
+ * from a static device array of the library instead of a workspace.  The call
+ * makes no allocation and no copy of any kind (no hipMalloc, hipFree,
+ * hipHostMalloc, memset or host-to-device copy): the series descriptor and the
+ * work list are written by kernels from launch arguments.  No timing events
+ * are recorded (fredec_profile does not apply).
+ *  - Limit: the scan's scratch (fredec_scan_workspace of this one series) must
+ *    fit FREDEC_STATIC_SCRATCH_BYTES (32 MiB: e.g. N = 2000, m = 4,
+ *    F = 10^6 in both precisions; N = 10^4, m = 12, F = 4e6 in FREDEC_FP64
+ *    only); larger scans return FREDEC_ENOTSUP before anything is enqueued.
+ *  - Each GPU holds its own copy of the array (32 MiB) from library load
+ *    until the process ends; its address is resolved by fredec_create.
+ *  - Every call on one GPU shares that GPU's array and leaves its contents
+ *    behind (each call re-initialises what it reads).  Calls that overlap in
+ *    time on one GPU (several streams, threads or contexts) race on it:
+ *    serialise them.
+ * Errors: EINVAL (null pointer, N <= 0, F <= 0, m < 0, bad precision or df,
+ * null or unusable context), EDOF, ENOTSUP (m > FREDEC_MAX_BASE or scratch
+ * above the limit), EDEVICE. */
+#define FREDEC_STATIC_SCRATCH_BYTES (32 * 1024 * 1024)
+int fredec_scan_static(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                       const double* base_f_host, int32_t m, double df, int64_t F, int32_t precision, double* z_out,
+                       uint8_t* flags_out, double* l_base_out, int32_t* status_out);
+
 /* The same statistic for one series at an explicit list of grid indices
  * (device int64 idx[n_idx], each in [0, F)), always in float64.  Used to
  * re-score reduced-precision peaks.  z_out/flags_out: device [n_idx]. */

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -55,7 +56,7 @@ int upload_wait(fredec_ctx* ctx) {
 size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
 ProfScope::ProfScope(fredec_ctx* ctx, hipStream_t st, int kind) : ctx_(ctx), st_(st) {
-  if (!ctx_->profiling) return;
+  if (!ctx_ || !ctx_->profiling) return;
   if (ctx_->prof_used == ctx_->prof_events.size()) {
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
@@ -70,6 +71,13 @@ ProfScope::~ProfScope() {
 }
 
 }  // namespace fredec
+
+// Scratch memory of the allocation-free scan (fredec_scan_static).  Each GPU
+// the library runs on holds its own copy from module load until the process
+// ends.  In host code this name is only a stand-in for the symbol: the device
+// address of a GPU's copy comes from hipGetSymbolAddress on that device
+// (static_scratch_address) and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[FREDEC_STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -182,6 +190,71 @@ struct ScanPlan : fredec_plan {
   std::vector<Group> groups;
 };
 
+// Running offsets of the per-series arrays of a scan workspace.
+struct SeriesOffsets {
+  int64_t goff = 0, rec = 0, phi = 0, g32 = 0, aux = 0, b16 = 0, ptile = 0, ppart = 0, pm = 0;
+};
+
+// Descriptor of one series (samples [soff, soff + N) of the caller's arrays,
+// base frequencies bf[0..m), grid of F points with step df) at the running
+// offsets `o`, which it advances.
+int series_desc(SeriesIn& d, int64_t soff, int64_t N, const double* bf, int32_t m, double df, int64_t F,
+                int32_t precision, SeriesOffsets& o) {
+  d.soff = soff;
+  d.N = N;
+  d.goff = o.goff;
+  d.F = F;
+  d.df = df;
+  if (!std::isfinite(df) || df == 0.0) return FREDEC_EINVAL;
+  d.rot_step = static_cast<double>(BLOCK) * df;
+  d.rot_tile = 16.0 * df;
+  d.m = m;
+  d.KP = 2 * m + 2;
+  prep_assign(d, o.ptile, o.ppart, o.pm);
+  d.NT = col_tiles(d.KP);
+  for (int k = 0; k < m; ++k) {
+    d.base_f[k] = bf[k];
+    if (!std::isfinite(d.base_f[k])) return FREDEC_EINVAL;
+  }
+  d.rec_off = o.rec;
+  d.phi_off = o.phi;
+  d.g32_off = o.g32;
+  d.aux_off = o.aux;
+  d.b16_off = o.b16;
+  o.goff += F;
+  o.phi += N * d.KP;
+  o.rec += N * rec_stride(d.KP);
+  if (precision == FREDEC_FP32) {
+    o.g32 += N * 16 * d.NT;
+    o.aux += N * AUX_STRIDE;
+    o.b16 += b16_vectors(N, d.NT);
+  }
+  return FREDEC_OK;
+}
+
+// Kernel family that scans a series with KP = 2m + 2 columns.
+int scan_kind(const fredec_ctx* ctx, int32_t precision, int KP) {
+  const int form = ctx ? ctx->f32_form : FREDEC_F32_FORM_AUTO;
+  const int auto_kp = ctx ? ctx->f32_auto_valu_max_kp : F32_AUTO_VALU_MAX_KP;
+  if (precision == FREDEC_FP64) return ScanPlan::F64;
+  if (form == FREDEC_F32_FORM_F16X3 || (form == FREDEC_F32_FORM_AUTO && KP > auto_kp)) return ScanPlan::F16X3;
+  if (KP <= F32_VALU_MAX_KP) return ScanPlan::F32;
+  return ScanPlan::F16X3;
+}
+
+// Operand sets the preparation writes for a series scanned by kernel family `kind`.
+int kind_outputs(int kind) {
+  return kind == ScanPlan::F32 ? PREP_G32 : kind == ScanPlan::F16X3 ? PREP_AUX | PREP_F16 : 0;
+}
+
+// Grid points per work-list tile of kernel family `kind` (ft: split-float16
+// 16-frequency tiles per wave).
+int64_t kind_tile(int kind, int KP, int ft, int32_t precision) {
+  return kind == ScanPlan::F16X3 ? 64 * static_cast<int64_t>(ft)
+         : kind == ScanPlan::F32 ? static_cast<int64_t>(BLOCK) * scan_f32_freqs_per_thread(KP)
+                                 : scan_tile(KP, precision);
+}
+
 // Host part of a scan: checks, workspace layout, descriptors and work list.
 int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, const double* base_f,
                const int64_t* boff, const double* df, const int64_t* F, int32_t precision, void* ws, size_t ws_bytes,
@@ -201,53 +274,18 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
   std::vector<SeriesIn>& sin = P.sin;
   sin.assign(n_series, SeriesIn{});
   std::memset(sin.data(), 0, sizeof(SeriesIn) * n_series);
-  int64_t goff = 0, rec_off = 0, phi_off = 0, g32_off = 0, aux_off = 0, b16_off = 0;
-  int64_t ptile = 0, ppart = 0, pmo = 0;
+  SeriesOffsets o;
   for (int32_t s = 0; s < n_series; ++s) {
-    SeriesIn& d = sin[s];
-    d.soff = soff[s];
-    d.N = soff[s + 1] - soff[s];
-    d.goff = goff;
-    d.F = F[s];
-    d.df = df[s];
-    if (!std::isfinite(df[s]) || df[s] == 0.0) return FREDEC_EINVAL;
-    d.rot_step = static_cast<double>(BLOCK) * df[s];
-    d.rot_tile = 16.0 * df[s];
-    d.m = static_cast<int32_t>(boff[s + 1] - boff[s]);
-    d.KP = 2 * d.m + 2;
-    if (d.KP > P.kp_max) P.kp_max = d.KP;
-    prep_assign(d, ptile, ppart, pmo);
-    d.NT = col_tiles(d.KP);
-    for (int k = 0; k < d.m; ++k) {
-      d.base_f[k] = base_f[boff[s] - boff[0] + k];
-      if (!std::isfinite(d.base_f[k])) return FREDEC_EINVAL;
-    }
-    d.rec_off = rec_off;
-    d.phi_off = phi_off;
-    d.g32_off = g32_off;
-    d.aux_off = aux_off;
-    d.b16_off = b16_off;
-    goff += F[s];
-    phi_off += d.N * d.KP;
-    rec_off += d.N * rec_stride(d.KP);
-    if (precision == FREDEC_FP32) {
-      g32_off += d.N * 16 * d.NT;
-      aux_off += d.N * AUX_STRIDE;
-      b16_off += b16_vectors(d.N, d.NT);
-    }
+    const int32_t m = static_cast<int32_t>(boff[s + 1] - boff[s]);
+    if ((rc = series_desc(sin[s], soff[s], soff[s + 1] - soff[s], base_f + (boff[s] - boff[0]), m, df[s], F[s],
+                          precision, o)))
+      return rc;
+    if (sin[s].KP > P.kp_max) P.kp_max = sin[s].KP;
   }
   // Work list: tiles grouped by kernel instance (KP for the float64 and the
   // float32 VALU kernels, column tiles NT for the split-float16 kernel), longest series first
   // inside a group.
-  const int form = ctx ? ctx->f32_form : FREDEC_F32_FORM_AUTO;
-  const int auto_kp = ctx ? ctx->f32_auto_valu_max_kp : F32_AUTO_VALU_MAX_KP;
-  auto kind = [&](int32_t s) {
-    if (precision == FREDEC_FP64) return static_cast<int>(ScanPlan::F64);
-    if (form == FREDEC_F32_FORM_F16X3 || (form == FREDEC_F32_FORM_AUTO && sin[s].KP > auto_kp))
-      return static_cast<int>(ScanPlan::F16X3);
-    if (sin[s].KP <= F32_VALU_MAX_KP) return static_cast<int>(ScanPlan::F32);
-    return static_cast<int>(ScanPlan::F16X3);
-  };
+  auto kind = [&](int32_t s) { return scan_kind(ctx, precision, sin[s].KP); };
   auto key = [&](int32_t s) { return kind(s) == ScanPlan::F16X3 ? sin[s].NT : sin[s].KP; };
   std::vector<int32_t> order(n_series);
   for (int32_t s = 0; s < n_series; ++s) order[s] = s;
@@ -256,21 +294,14 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
     if (key(a) != key(b)) return key(a) < key(b);
     return sin[a].N > sin[b].N;
   });
-  for (int32_t s = 0; s < n_series; ++s) {
-    const int kd = kind(s);
-    sin[s].outputs = kd == ScanPlan::F32     ? PREP_G32
-                     : kd == ScanPlan::F16X3 ? PREP_AUX | PREP_F16
-                                             : 0;
-  }
+  for (int32_t s = 0; s < n_series; ++s) sin[s].outputs = kind_outputs(kind(s));
   P.work.clear();
   P.work.reserve(L.n_work);
   P.groups.clear();
   for (int32_t s : order) {
     const int kd = kind(s);
     const int ft = kd == ScanPlan::F16X3 ? f16x3_ft_for(ctx, sin[s].NT) : 0;
-    const int64_t tile = kd == ScanPlan::F16X3 ? 64 * static_cast<int64_t>(ft)
-                         : kd == ScanPlan::F32 ? static_cast<int64_t>(BLOCK) * scan_f32_freqs_per_thread(sin[s].KP)
-                                               : scan_tile(sin[s].KP, precision);
+    const int64_t tile = kind_tile(kd, sin[s].KP, ft, precision);
     if (P.groups.empty() || P.groups.back().kind != kd || P.groups.back().key != key(s))
       P.groups.push_back(ScanPlan::Group{kd, key(s), ft, static_cast<int64_t>(P.work.size()), 0});
     for (int64_t j0 = 0; j0 < sin[s].F; j0 += tile) P.work.push_back(ScanWork{s, 0, j0});
@@ -289,8 +320,10 @@ int scan_upload(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P) {
 
 // Kernel launches of a scan whose descriptors are in the workspace: no host
 // to device copies, allocations or synchronisation (capturable).
-int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const double* t, const double* x, const double* w,
-                double* z_out, uint8_t* flags_out, double* l_base_out, int32_t* status_out) {
+int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const ScanPlan::Group* groups, size_t n_groups,
+                const double* t, const double* x, const double* w, double* z_out, uint8_t* flags_out,
+                double* l_base_out, int32_t* status_out, bool timed = true) {
+  fredec_ctx* prof_ctx = timed ? ctx : nullptr;
   const ScanLayout& L = P.L;
   void* ws = P.ws;
   SeriesIn* d_sin = at<SeriesIn>(ws, L.off_sin);
@@ -315,15 +348,16 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const double
   const int flags = PREP_BASE | PREP_REC64 | PREP_G32 | PREP_AUX | PREP_F16;
   if (f32 && launch_zero_u64(st, d_count, P.n_series) != hipSuccess) return FREDEC_EDEVICE;
   {
-    ProfScope prof(ctx, st, FREDEC_PROF_PREP);
+    ProfScope prof(prof_ctx, st, FREDEC_PROF_PREP);
     if (launch_prep(st, P.n_series, P.kp_max, L.ptiles, d_sin, d_hdr, t, x, w, d_tau - base_off, d_xt - base_off,
                     d_wt - base_off, d_rec, d_phi, d_g32, d_aux, d_b16, at<double>(ws, L.off_ppart),
                     at<double>(ws, L.off_pm), flags) != hipSuccess)
       return FREDEC_EDEVICE;
   }
   {
-    ProfScope prof(ctx, st, FREDEC_PROF_SCAN);
-    for (const auto& gr : P.groups) {
+    ProfScope prof(prof_ctx, st, FREDEC_PROF_SCAN);
+    for (size_t g = 0; g < n_groups; ++g) {
+      const ScanPlan::Group& gr = groups[g];
       const int n = static_cast<int>(gr.end - gr.begin);
       hipError_t err;
       if (gr.kind == ScanPlan::F16X3)
@@ -338,7 +372,7 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const double
     }
   }
   if (f32) {
-    ProfScope prof(ctx, st, FREDEC_PROF_RESCORE);
+    ProfScope prof(prof_ctx, st, FREDEC_PROF_RESCORE);
     if (launch_rescore(st, L.max_nt, 4 * std::max(ctx->n_cu, 1), P.n_series, d_sin, d_hdr, d_rec, d_list, d_count,
                        d_chunk, z_out, flags_out) != hipSuccess)
       return FREDEC_EDEVICE;
@@ -346,6 +380,43 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const double
   if (launch_copy_stats(st, P.n_series, d_hdr, d_sin, l_base_out, status_out, nullptr) != hipSuccess)
     return FREDEC_EDEVICE;
   return FREDEC_OK;
+}
+
+// ------------------------------------------------------------ static scratch
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[MAX_DEVICES] = {};
+
+// Device address of the calling device's copy of `scratch`; `dev` must be
+// the current device.  Looked up once per device.
+int static_scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return FREDEC_ENOTSUP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FREDEC_EDEVICE;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return FREDEC_OK;
+}
+
+// The descriptor of the single series of fredec_scan_static, written by the
+// device (kernel argument) instead of a host-to-device copy.
+__global__ void store_series_kernel(SeriesIn d, SeriesIn* dst) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *dst = d;
+}
+
+// Work list of a single series: tile k starts at grid index k * tile.
+__global__ void fill_work_kernel(ScanWork* work, int64_t n, int64_t tile) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k < n) {
+    ScanWork wk;
+    wk.series = 0;
+    wk.pad = 0;
+    wk.j0 = k * tile;
+    work[k] = wk;
+  }
 }
 
 }  // namespace
@@ -390,6 +461,11 @@ int fredec_create(fredec_ctx** out, int device) {
     return FREDEC_EDEVICE;
   }
   ctx->n_cu = prop.multiProcessorCount;
+  // the device address of this device's static scratch array (fredec_scan_static)
+  if (static_scratch_address(device, &ctx->static_scratch) != FREDEC_OK) {
+    fredec_destroy(ctx);
+    return FREDEC_EDEVICE;
+  }
   *out = ctx;
   return FREDEC_OK;
 }
@@ -542,7 +618,8 @@ int fredec_scan(fredec_ctx* ctx, void* stream, int32_t n_series, const double* t
   DeviceGuard g(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((rc = scan_upload(ctx, st, P))) return rc;
-  return scan_launch(ctx, st, P, t, x, w, z_out, flags_out, l_base_out, status_out);
+  return scan_launch(ctx, st, P, P.groups.data(), P.groups.size(), t, x, w, z_out, flags_out, l_base_out,
+                     status_out);
 }
 
 int fredec_scan_plan(fredec_ctx* ctx, void* stream, int32_t n_series, const int64_t* soff, const double* base_f,
@@ -576,11 +653,50 @@ int fredec_plan_scan(fredec_ctx* ctx, fredec_plan* plan, void* stream, const dou
   if (!ctx || !plan || plan->kind != fredec_plan::SCAN || !t || !x || !w || !z_out) return FREDEC_EINVAL;
   if (plan->device != ctx->device) return FREDEC_EINVAL;
   DeviceGuard g(ctx->device);
-  return scan_launch(ctx, static_cast<hipStream_t>(stream), *static_cast<ScanPlan*>(plan), t, x, w, z_out, flags_out,
-                     l_base_out, status_out);
+  const ScanPlan& P = *static_cast<ScanPlan*>(plan);
+  return scan_launch(ctx, static_cast<hipStream_t>(stream), P, P.groups.data(), P.groups.size(), t, x, w, z_out,
+                     flags_out, l_base_out, status_out);
 }
 
 void fredec_plan_destroy(fredec_plan* plan) { delete plan; }
+
+// ------------------------------------------------------------ allocation-free scan
+int fredec_scan_static(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                       const double* base_f, int32_t m, double df, int64_t F, int32_t precision, double* z_out,
+                       uint8_t* flags_out, double* l_base_out, int32_t* status_out) {
+  if (!t || !x || !w || !z_out || N <= 0 || m < 0 || F <= 0) return FREDEC_EINVAL;
+  if (m > 0 && !base_f) return FREDEC_EINVAL;
+  const int64_t soff[2] = {0, N}, boff[2] = {0, m}, Fs[1] = {F};
+  ScanPlan P;  // no host allocation: its vectors stay empty
+  int rc = scan_layout(1, soff, boff, Fs, precision, P.L);
+  if (rc) return rc;
+  if (P.L.total > static_cast<size_t>(FREDEC_STATIC_SCRATCH_BYTES)) return FREDEC_ENOTSUP;
+  SeriesIn d;
+  std::memset(&d, 0, sizeof(d));
+  SeriesOffsets o;
+  if ((rc = series_desc(d, 0, N, base_f, m, df, F, precision, o))) return rc;
+  if (!ctx || !ctx->static_scratch) return FREDEC_EINVAL;
+  const int kd = scan_kind(ctx, precision, d.KP);
+  d.outputs = kind_outputs(kd);
+  const int ft = kd == ScanPlan::F16X3 ? f16x3_ft_for(ctx, d.NT) : 0;
+  const int64_t tile = kind_tile(kd, d.KP, ft, precision);
+  const int64_t n_work = (F + tile - 1) / tile;  // <= P.L.n_work (laid out for the smallest tile)
+  P.ws = ctx->static_scratch;
+  P.ws_bytes = FREDEC_STATIC_SCRATCH_BYTES;
+  P.n_series = 1;
+  P.precision = precision;
+  P.kp_max = d.KP;
+  P.base_off = 0;
+  const ScanPlan::Group gr{kd, kd == ScanPlan::F16X3 ? d.NT : d.KP, ft, 0, n_work};
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(store_series_kernel, dim3(1), dim3(64), 0, st, d, at<SeriesIn>(P.ws, P.L.off_sin));
+  if (hipGetLastError() != hipSuccess) return FREDEC_EDEVICE;
+  hipLaunchKernelGGL(fill_work_kernel, dim3(static_cast<unsigned>((n_work + 255) / 256)), dim3(256), 0, st,
+                     at<ScanWork>(P.ws, P.L.off_work), n_work, tile);
+  if (hipGetLastError() != hipSuccess) return FREDEC_EDEVICE;
+  return scan_launch(ctx, st, P, &gr, 1, t, x, w, z_out, flags_out, l_base_out, status_out, /*timed=*/false);
+}
 
 int fredec_scan_at_workspace(int64_t N, int32_t m, size_t* bytes) {
   if (!bytes || N <= 0 || m < 0) return FREDEC_EINVAL;

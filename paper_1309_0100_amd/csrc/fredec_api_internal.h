@@ -35,6 +35,9 @@ struct fredec_ctx {
   };
   std::vector<ProfEvent> prof_events;
   size_t prof_used = 0;
+  // device address of this device's copy of the static scratch array of
+  // fredec_scan_static (resolved when the context is created)
+  void* static_scratch = nullptr;
 };
 
 // A prepared call (fredec_*_plan): the host-side launch schedule of a batch
@@ -70,7 +73,8 @@ int upload(fredec_ctx* ctx, hipStream_t st, void* dst, const void* src, size_t b
 int upload_wait(fredec_ctx* ctx);
 
 // Records a pair of HIP events on `st` around a group of kernel launches of
-// one kind (FREDEC_PROF_*) when the context has profiling enabled.
+// one kind (FREDEC_PROF_*) when the context has profiling enabled (nothing
+// for a null context).
 class ProfScope {
  public:
   ProfScope(fredec_ctx* ctx, hipStream_t st, int kind = FREDEC_PROF_SCAN);

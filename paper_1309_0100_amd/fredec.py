@@ -27,6 +27,7 @@ TILE_SCAN_F32_FORM = 2
 F32_FORM_VALU, F32_FORM_F16X3, F32_FORM_AUTO = 0, 2, 3
 MAX_BASE = 24
 MAX_POOL = 27
+STATIC_SCRATCH_BYTES = 32 * 1024 * 1024
 FLAG_MASKED, FLAG_SINGULAR, FLAG_PERFECT, FLAG_DEGENERATE, FLAG_BADSERIES = 1, 2, 4, 8, 128
 FLAG_CONVERGED, FLAG_RESCORED = 16, 64
 PROF_KINDS = ("scan", "gram", "solve", "prep", "rescore", "adjoint")
@@ -67,6 +68,8 @@ _SIGS = {
     "fredec_phase1_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_szp]),
     "fredec_phase1": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_d, c_i64, c_d, c_d, c_d, c_i32, c_i32, c_i32, c_p,
                               c_sz, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
+    "fredec_scan_static": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_i32, c_d, c_i64, c_i32, c_p, c_p, c_p,
+                                   c_p]),
     "fredec_scan_at_workspace": (c_i32, [c_i64, c_i32, c_szp]),
     "fredec_scan_at": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_i32, c_d, c_p, c_i64, c_p, c_sz, c_p, c_p]),
     "fredec_plan_destroy": (None, [c_p]),
@@ -307,6 +310,24 @@ class Context:
         n = len(t) if not hasattr(t, "numel") else t.numel()
         base_f = np.atleast_1d(np.asarray(base_f, np.float64))
         return self.scan(t, x, w, [0, n], base_f, [0, base_f.size], [df], [F], precision)
+
+    def scan_static(self, t, x, w, base_f, df, F, precision=FP64, out=None):
+        """One series through the allocation-free entry point
+        (fredec_scan_static: scratch in the library's static device array;
+        `out` = preallocated (z, flags, l_base, status) tensors, else they are
+        allocated here, outside the call).  Returns (z, flags, l_base, status)."""
+        torch = _torch()
+        t, x, w = self._f64(t), self._f64(x), self._f64(w)
+        base_f = np.ascontiguousarray(np.atleast_1d(np.asarray(base_f, np.float64)))
+        if out is None:
+            out = (self._empty(F, torch.float64), self._empty(F, torch.uint8), self._empty(1, torch.float64),
+                   self._empty(1, torch.int32))
+        z, flags, lbase, status = out
+        _check(load().fredec_scan_static(self.handle, _stream(self.device), _ptr(t), _ptr(x), _ptr(w), t.numel(),
+                                         _ptr(base_f) if base_f.size else None, base_f.size, float(df), int(F),
+                                         precision, _ptr(z), _ptr(flags), _ptr(lbase), _ptr(status)),
+               "fredec_scan_static")
+        return z, flags, lbase, status
 
     def scan_at(self, t, x, w, base_f, df, idx):
         """float64 statistic of one series at grid indices idx (device int64)."""

@@ -205,3 +205,29 @@ def test_plan_entry_points_validate_host_arguments(lib):
                                   ctypes.byref(plan)) == F.EINVAL           # empty tuple
     assert lib.fredec_plan_ascent(None, None, None, d, d, d, d, None, None, None) == F.EINVAL
     lib.fredec_plan_destroy(None)
+
+
+def test_scan_static_rejects_host_errors_without_device(lib):
+    """fredec_scan_static checks its host arguments and the static scratch
+    limit before it needs a context or a device."""
+    dummy = ctypes.c_void_p(16)   # never dereferenced: every call below fails a host check
+    base = np.array([0.1] * 25)
+
+    def call(N=100, m=1, df=1e-3, Fg=500, prec=0, z=dummy):
+        return lib.fredec_scan_static(None, None, dummy, dummy, dummy, N, _p(base) if m else None, m, df, Fg, prec,
+                                      z, None, None, None)
+
+    assert call() == F.EINVAL                     # valid arguments, null context
+    assert call(z=None) == F.EINVAL
+    assert call(N=0) == F.EINVAL
+    assert call(Fg=0) == F.EINVAL
+    assert call(prec=5) == F.EINVAL
+    assert call(df=0.0) == F.EINVAL
+    assert call(N=10, m=2) == F.EDOF              # N - 3m - 4 = 0
+    assert call(m=25) == F.ENOTSUP                # m > FREDEC_MAX_BASE
+    # float32 re-scoring lists for F = 4e6 exceed FREDEC_STATIC_SCRATCH_BYTES
+    assert call(N=10_000, m=12, Fg=4_000_000, prec=1) == F.ENOTSUP
+    # the same scan in float64 fits
+    assert call(N=10_000, m=12, Fg=4_000_000, prec=0) == F.EINVAL
+    assert _scan_ws(lib, [0, 10_000], [0, 12], [4_000_000], prec=1)[1] > F.STATIC_SCRATCH_BYTES
+    assert _scan_ws(lib, [0, 10_000], [0, 12], [4_000_000], prec=0)[1] <= F.STATIC_SCRATCH_BYTES
