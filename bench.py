@@ -1,27 +1,37 @@
 """Benchmark of the FREDEC multifrequency-periodogram hot path on one MI355X.
 
-Default workload (the metric's configuration): the residual scan - one series
-of N=2000 irregular times over 4000 d with seasonal gaps (8 months on / 4 off),
-4 injected sinusoids, base model = constant + the 4 injected frequencies
-(m = 4), F = 10^6 grid frequencies up to 2 cycles/day.  One step = the scan
-path: normalisation, base-model precomputation (orthonormal basis), trig
-generation and sums, 2x2 Schur solves and z for every grid frequency, float64
-re-scoring of ill-conditioned points (float32 form), and the list of
-periodogram peaks above the FAP_1 threshold (fredec_scan + fredec_peaks).
-Both forms are timed; the headline is the faster one, the other is
-reported beside it.  Inputs are resident in HBM before the
-timed region starts.
+Default workload: the whole method on one series shaped like the paper's
+largest analyses - N = 10^4 irregular times over 20000 d with nightly and
+seasonal gaps, 12 injected sinusoids + noise.  One step = one full pass:
+Phase 1 residual scans on F = 4e6 grid frequencies up to 5 c/d (base model
+grown until the FAP_0 stop), a pool capped at 16 candidates, all 65535
+subsets of the pool refined (8 Gauss-Newton steps each) in Phase 2, and the
+Phase 3 cascade.  Inputs are resident in HBM before the timed region.  The
+headline is the float32 form (float32 trig and sums, the base-column sums on
+the float16 matrix cores with split operands, float64 phase reduction,
+solves and re-scoring); the float64 form is timed beside it.
 
-The JSON line also carries the tuple workload (N=1000 over 3000 d, 65536
-tuples of 1..6 perturbed periodogram peaks, forward z + adjoint dz/df + update
-for 20 ascent steps: fredec_ascent) as tuples/s, the roofline of each dominant
-kernel (its average duration measured live with HIP events on the call's
-stream), the error against the float64 oracle on a sample, and the oracle
-itself timed on a bounded sample of the same workload on the host cores.
+value = scan points (N x F per Phase 1 scan) per second of the whole pass;
+tuples/s = refined subsets per second of the same pass.
 
---workload batched: 4096 series of uneven N and m (CSR batch), F = 65536.
---workload full: the whole method on N = 10^4 (Phase 1 scans on F = 4e6, a
-16-frequency pool, 65535 refined subtuples, Phase 3).
+Roofline (dominant kernel group: the Phase 1 scan kernels, one launch per
+scan, HIP events on the call's stream): T_roof = max(VALU model, MFMA model,
+HBM bytes) per scan, summed over the scans, against the HIP-event time:
+  VALU model (lane-op slots per (frequency, sample) pair; chip issue peak
+  256 CU x 64 lanes x 2.4 GHz = 39.3 Tops/s):
+    trig generation, one complex rotation per pair       4
+    second-order terms w~c, <w~ c c>, <w~ c s>            3
+    data-column sums <w~ r_b c>, <w~ r_b s>               2
+    base-column sums 2(2m+1), where they run on the VALU  4m + 2
+  MFMA model: the base-column sums as split-float16 products (three per sum,
+  2 flops each) against the float16 dense peak of 2.5 PFLOP/s.
+The sums themselves are 2 S = 8m + 12 flops per pair (S = 4m + 6 sums).
+
+Extra keys: the residual scan (N = 2000, m = 4, F = 10^6), the tuple ascent
+(65536 tuples of 1..6 frequencies, N = 1000, 20 steps) in both forms, and the
+float64 oracle timed on the host cores (one process, then one per core).
+
+--workload residual | batched | tuples: that workload alone as the headline.
 """
 from __future__ import annotations
 
@@ -38,54 +48,23 @@ sys.path.insert(0, ROOT)
 
 METRIC = "periodogram points/s (N×F) + tuples/s at stated rel-err vs FP64 oracle"
 
-# MI355X published peaks
-PEAK_FP64_VALU = 78.6e12      # flop/s, FMA = 2 flops
-PEAK_FP32_MFMA = 157.3e12     # flop/s, dense
-PEAK_FP32_VALU = 157.3e12     # flop/s, float32 vector (the published peak counts packed FMA; a
-                              # non-packed FMA per lane and cycle reaches half of it)
-PEAK_FP64_MFMA = 78.6e12      # flop/s, float64 matrix cores
-
-
-def f32_form():
-    """Kernel family of the float32 scan chosen by the autotuner and the VALU
-    boundary of the automatic form: (form, largest 2m + 2 on the VALU kernel);
-    the library defaults (automatic, 6) when no table is stored."""
-    path = os.path.join(ROOT, "paper_1309_0100_amd", "tuning.json")
-    try:
-        with open(path) as fh:
-            tab = json.load(fh)
-        return (int(tab.get("scan_f32_form", {}).get("form", 3)),
-                int(tab.get("scan_f32_auto", {}).get("valu_max_kp", 6)))
-    except (OSError, ValueError):
-        return 3, 6
-
-
-def f32_kernel(KP):
-    """Name of the kernel the float32 scan of a base model with 2m + 2 = KP uses."""
-    form, valu_max = f32_form()
-    if form == 0:
-        return "scan_f32_kernel" if KP <= 26 else "scan_mfma_kernel"
-    if form == 1:
-        return "scan_mfma_kernel"
-    if form == 2 or KP > valu_max:
-        return "scan_f16x3_kernel"
-    return "scan_f32_kernel"
+# MI355X: issue and published peaks
+PEAK_VALU_OPS = 256 * 64 * 2.4e9   # VALU lane-op slots per second (one instruction per lane and cycle)
+PEAK_F16_MFMA = 2.5e15             # flop/s, dense float16 matrix cores
+PEAK_F64_MFMA = 78.6e12            # flop/s, float64 matrix cores
+PEAK_HBM = 8.0e12                  # B/s
 
 # HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (KiB per dispatch), scaled by
 # what the same counters read for a plain device copy of known size (FETCH x2.0, WRITE x1.0).  A
 # figure is only used while the kernel source and its compile flags still have the hash it was
-# measured with (source_hash).
+# measured with (source_hash); keyed by (kernel, workload).
 COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = {
-    "scan_f64_kernel": {"src": "scan_f64.hip", "sha1": "2f187ae1836dd72a375fe29397e974041ee9c147",
-                        "fetch_kib": 1173.6, "write_kib": 8789.1},
-    "scan_f16x3_kernel": {"src": "scan_f16x3.hip", "sha1": "d768b09d0d39957d4c68daa23fd38339037fcb5d",
-                          "fetch_kib": 1370.3, "write_kib": 8798.7},
-    "scan_mfma_kernel": {"src": "scan_mfma.hip", "sha1": None, "fetch_kib": None, "write_kib": None},
-    "scan_f32_kernel": {"src": "scan_f32.hip", "sha1": None, "fetch_kib": None, "write_kib": None},
-    # one Gram pass: the six tuple-size kernels (n = 1..6) of the pass added
-    "tuple_gram_lanes_kernel": {"src": "tuples.hip", "sha1": "763b83864ed78348f6985e233ec891c904c8a37b",
-                                "fetch_kib": 12739.0, "write_kib": 31592.5},
+    # float32 Phase 1 scans of the full pass, averaged over its 18 launches (scan_f16x3_kernel x17,
+    # scan_f32_kernel x1)
+    "full_fp32_phase1_scans": {"src": {"scan_f16x3.hip": "b96ce106c763caf4f985e385766738f7d20e5725",
+                                        "scan_f32.hip": "ce2bad490820f493b1da42222c1e35694aabec42"},
+                               "fetch_kib": 8609.0, "write_kib": 35176.0},
 }
 
 
@@ -99,28 +78,76 @@ def source_hash(src):
     return h.hexdigest()
 
 
-def traffic_bytes(kernel):
-    """Measured HBM bytes per launch of `kernel`, or None when not measured for the current source."""
-    t = TRAFFIC.get(kernel)
-    if not t or t["fetch_kib"] is None:
-        return None
-    if source_hash(t["src"]) != t["sha1"]:
+def traffic_bytes(key):
+    """Measured HBM bytes per launch, or None when not measured for the current sources."""
+    t = TRAFFIC.get(key)
+    if not t or any(source_hash(src) != sha for src, sha in t["src"].items()):
         return None
     return 1024.0 * (COUNTER_SCALE["fetch"] * t["fetch_kib"] + COUNTER_SCALE["write"] * t["write_kib"])
+
+
+def f32_auto_valu_max_kp():
+    """Largest 2m + 2 that the float32 form gives to its VALU kernel (tuning table, else the default)."""
+    try:
+        with open(os.path.join(ROOT, "paper_1309_0100_amd", "tuning.json")) as fh:
+            return int(json.load(fh).get("scan_f32_auto", {}).get("valu_max_kp", 6))
+    except (OSError, ValueError):
+        return 6
+
+
+def scan_kernel(m, fp32):
+    if not fp32:
+        return "scan_f64_kernel"
+    return "scan_f32_kernel" if 2 * m + 2 <= f32_auto_valu_max_kp() else "scan_f16x3_kernel"
+
+
+def scan_model(m, fp32):
+    """Per (frequency, sample) pair: VALU slots, MFMA flops and the MFMA peak of the kernel that scans a
+    base of m frequencies (see the module docstring)."""
+    kern = scan_kernel(m, fp32)
+    K = 2 * m + 1
+    if kern == "scan_f16x3_kernel":
+        return kern, 9.0, 12.0 * K, PEAK_F16_MFMA
+    return kern, 9.0 + 2.0 * K, 0.0, PEAK_F16_MFMA
+
+
+def scan_roofline(ms_list, N, F, t_meas, fp32, traffic=None):
+    """Roofline of a list of scans (base sizes ms_list, one launch each) measured at t_meas seconds."""
+    P = float(N) * float(F)
+    t_roof, slots, mflops, kerns = 0.0, 0.0, 0.0, {}
+    for m in ms_list:
+        kern, v, mf, mpk = scan_model(m, fp32)
+        kerns[kern] = kerns.get(kern, 0) + 1
+        tv, tm = v * P / PEAK_VALU_OPS, mf * P / mpk
+        th = (traffic or 0.0) / PEAK_HBM
+        t_roof += max(tv, tm, th)
+        slots += v * P
+        mflops += mf * P
+    achieved = slots / t_meas
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12, "unit": "Tops/s",
+            "frac": t_roof / t_meas, "traffic": traffic,
+            "kernel": " + ".join(f"{k} x{n}" for k, n in sorted(kerns.items())),
+            "kernel_ms": t_meas * 1e3, "launches": len(ms_list),
+            "mfma_frac": (mflops / t_meas / PEAK_F16_MFMA) if mflops else 0.0,
+            "sum_flops_per_pair": [8 * m + 12 for m in ms_list],
+            "algorithmic": "VALU lane-op slots per (frequency, sample) pair: 9 (complex rotation 4, second-order "
+                           "terms 3, data-column sums 2) + 2(2m+1) base-column sums where they run on the VALU; "
+                           "split-float16 kernel: base-column sums on the float16 matrix cores (12(2m+1) flops per "
+                           "pair vs 2.5 PFLOP/s); T_roof = sum over scans of max(VALU, MFMA, HBM), frac = "
+                           "T_roof / HIP-event time; achieved = model slots / HIP-event time"}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["residual", "batched", "full"], default="residual")
-    ap.add_argument("--precision", choices=["fp32", "fp64", "both"], default="both")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time of the CPU baseline")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["full", "residual", "batched", "tuples"], default="full")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time of each CPU baseline leg")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-tuples", action="store_true")
-    ap.add_argument("--tuple-steps", type=int, default=3, help="timed fredec_ascent calls of the tuple workload")
-    ap.add_argument("--tile", type=int, default=0, help="MFMA frequency tiles per wave (0 = tuned/default)")
+    ap.add_argument("--no-extra", action="store_true", help="headline workload only")
+    ap.add_argument("--fp64-steps", type=int, default=3,
+                    help="timed passes of the float64 form beside the headline (0: not run)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes 5 times (the reference kernel "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -143,7 +170,7 @@ def copy_reference(nbytes):
 
 def timed(ctx, step, steps, warmup):
     """Wall time per step over `steps` timed steps (after `warmup`), and the
-    HIP-event time of the library's profiled kernels per step."""
+    HIP-event time (seconds per step) of the library's kernel groups by kind."""
     import torch
     for _ in range(warmup):
         step()
@@ -155,340 +182,372 @@ def timed(ctx, step, steps, warmup):
         step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    kms, nl = ctx.profile_read()
+    kinds = ctx.profile_read_kinds()
     ctx.profile(False)
-    return el / steps, kms / 1e3 / max(steps, 1), nl
+    per = {k: (ms / 1e3 / max(steps, 1), n / max(steps, 1)) for k, (ms, n) in kinds.items()}
+    return el / steps, per
 
 
-def fap_pool_threshold(s):
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ full pass
+def full_leg(ctx, s, dev, fp32, steps, warmup):
+    import torch
+    from paper_1309_0100_amd import fredec, pipeline
+    prec = fredec.FP32 if fp32 else fredec.FP64
+    t, x, w = (torch.as_tensor(a, device=dev) for a in (s.t, s.x, s.w))
+    out = {}
+
+    def step():
+        out["r"] = pipeline.run(ctx, t, x, w, s.df, s.F, pool_cap=16, refine_steps=8, precision=prec)
+
+    sec, per = timed(ctx, step, steps, warmup)
+    res = out["r"]
+    n = res.pool.size
+    t_scan = per["scan"][0]
+    roof = scan_roofline(list(range(res.n_scans)), s.N, s.F, t_scan, fp32,
+                         traffic_bytes("full_fp32_phase1_scans") if fp32 else None)
+    # Phase 2 Gauss-Newton Gram passes (float64 matrix cores): C(C+1) flops per (tuple, sample) and pass,
+    # C = 4n + 2 columns; passes per pass of the method = the timed Gram groups per step
+    from math import comb
+    C = np.array([4 * k + 2 for k in range(1, n + 1)], np.float64)
+    cnt = np.array([comb(n, k) for k in range(1, n + 1)], np.float64)
+    gram_flops = float(np.sum(cnt * C * (C + 1))) * s.N
+    t_gram, n_gram = per["gram"]
+    leg = {"seconds_per_pass": sec, "points_per_s": s.N * s.F * res.n_scans / sec,
+           "tuples_per_s": ((1 << n) - 1) / sec, "n_scans": res.n_scans, "pool_size": n,
+           "n_solutions": len(res.solutions), "truncated": res.truncated,
+           "kernel_seconds_per_pass": {k: v[0] for k, v in per.items()},
+           "launch_groups_per_pass": {k: v[1] for k, v in per.items()},
+           "roofline": roof,
+           "phase2_gram_roofline": {"bound": "mfma", "kernel": "tuple_gram_kernel",
+                                    "achieved": gram_flops * n_gram / t_gram / 1e12 if t_gram else None,
+                                    "peak": PEAK_F64_MFMA / 1e12, "unit": "TFLOP/s",
+                                    "frac": gram_flops * n_gram / t_gram / PEAK_F64_MFMA if t_gram else None,
+                                    "passes": n_gram, "ms_per_gram_pass": t_gram / max(n_gram, 1) * 1e3,
+                                    "algorithmic": "C(C+1) flop per (tuple, sample) per Gauss-Newton Gram pass, "
+                                                   "C = 4n+2 columns, every subset of the pool"}}
+    return leg, res
+
+
+def full_errors(ctx, s, dev, res32, res64):
+    """Error of the float32 pass: its decisions against the float64 pass, its refined l-table against
+    the float64 pass and against the oracle's Gauss-Newton refinement on sampled subsets, and the
+    float32 statistic of the final Phase 1 scan against the float64 one at every grid point."""
+    import torch
+    import oracle as O
     from paper_1309_0100_amd import fredec
-    span = float(s.t.max() - s.t.min())
-    return float(fredec.zcrit(s.F * s.df * span, 1, 0.1)[1])
+    e = {"pool_identical": bool(np.array_equal(res32.pool, res64.pool)),
+         "n_scans_identical": res32.n_scans == res64.n_scans,
+         "solutions_identical": [sl.mask for sl in res32.solutions] == [sl.mask for sl in res64.solutions]}
+    if res32.ltab is not None and res64.ltab is not None and res32.ltab.size == res64.ltab.size:
+        a, b = res32.ltab, res64.ltab
+        ok = np.isfinite(a) & np.isfinite(b) & (b > 0)
+        e["ltab_rel_err_fp32_vs_fp64"] = float(np.max(np.abs(a[ok] - b[ok]) / b[ok]))
+    nrm = O.normalize(s.t, s.x, s.w)
+    n = res64.pool.size
+    rng = np.random.default_rng(7)
+    masks = [1 << k for k in range(min(n, 3))] + [(1 << n) - 1] + rng.integers(1, 1 << n, size=4).tolist()
+    err = {"fp32": 0.0, "fp64": 0.0}
+    for S in masks:
+        mem = [k for k in range(n) if S >> k & 1]
+        r = O.gn_refine(nrm, res64.pool[mem], 8)
+        if r.flag:
+            continue
+        for k, res in (("fp32", res32), ("fp64", res64)):
+            err[k] = max(err[k], abs(res.ltab[S] - r.l) / r.l)
+    e["refined_l_rel_err_vs_oracle"] = err
+    e["refined_subsets_checked"] = len(masks)
+    # the last Phase 1 scan (base = every SLICK frequency of the pass) in both forms
+    base = res64.base
+    t, x, w = (torch.as_tensor(a, device=dev) for a in (s.t, s.x, s.w))
+    z32, f32_, _, _ = ctx.scan_series(t, x, w, base, s.df, s.F, precision=fredec.FP32)
+    z64, f64_, _, _ = ctx.scan_series(t, x, w, base, s.df, s.F, precision=fredec.FP64)
+    good = (f32_ == 0) & (f64_ == 0) & torch.isfinite(z64)
+    rel = (z32 - z64).abs() / torch.clamp(z64.abs(), min=1.0)
+    e["last_scan_m"] = int(base.size)
+    e["last_scan_z_rel_err_fp32_vs_fp64"] = float(rel[good].max().item())
+    e["last_scan_points_compared"] = int(good.sum().item())
+    e["last_scan_points_rescored_fp32"] = int(((f32_ & 64) != 0).sum().item())
+    return e
 
 
-# ------------------------------------------------------------------ residual
-def residual_leg(ctx, args, prec_name, s):
+# ------------------------------------------------------------------ residual scan
+def residual_leg(ctx, s, dev, fp32, steps, warmup):
     import torch
     from paper_1309_0100_amd import fredec
-    prec = fredec.FP64 if prec_name == "fp64" else fredec.FP32
-    dev = torch.device("cuda", 0)
+    prec = fredec.FP32 if fp32 else fredec.FP64
     t, x, w = (torch.as_tensor(a, device=dev) for a in (s.t, s.x, s.w))
-    soff = np.array([0, s.N], np.int64)
-    boff = np.array([0, s.base_f.size], np.int64)
-    ws = torch.empty(ctx.scan_workspace(soff, boff, [s.F], prec), dtype=torch.uint8, device=dev)
-    out = (torch.empty(s.F, dtype=torch.float64, device=dev), torch.empty(s.F, dtype=torch.uint8, device=dev),
-           torch.empty(1, dtype=torch.float64, device=dev), torch.empty(1, dtype=torch.int32, device=dev))
-    zc1 = fap_pool_threshold(s)
+    plan, pout = ctx.scan_plan(np.array([0, s.N], np.int64), s.base_f, np.array([0, s.base_f.size], np.int64),
+                               [s.df], [s.F], prec)
+    # FAP_1 listing threshold, W = f_max T_eff (Sect. 2), T_eff from the library's normalisation
+    T_eff = float(ctx.normalize(t, x, w)[3][0, 4].item())
+    zc1 = float(fredec.zcrit(s.F * s.df * T_eff, 1, 0.1)[1])
     peaks = {}
-    # the scan prepared once (descriptors and work list resident in the
-    # workspace); a step launches its kernels and lists the peaks
-    plan, pout = ctx.scan_plan(soff, s.base_f, boff, [s.df], [s.F], prec)
 
     def step():
         plan.run(t, x, w, pout)
         peaks["p"] = ctx.peaks(pout[0], pout[1], zc1)
 
-    def step_unprepared():
-        ctx.scan(t, x, w, soff, s.base_f, boff, [s.df], [s.F], prec, workspace=ws, out=out)
-        peaks["p"] = ctx.peaks(out[0], out[1], zc1)
-
-    sec_u, _, _ = timed(ctx, step_unprepared, args.steps, args.warmup)
-    sec, ksec, nl = timed(ctx, step, args.steps, args.warmup)
-    out = pout
-    points = s.N * s.F
-    m = s.base_f.size
-    KP, K = 2 * m + 2, 2 * m + 1
-    if prec == fredec.FP64:
-        fpp = 2 * (2 * KP + 3)
-        roof = {"bound": "alu", "peak": PEAK_FP64_VALU, "kernel": "scan_f64_kernel",
-                "algorithmic": f"{fpp} flop per (frequency, sample) pair: {2 * KP + 3} float64 multiply-adds "
-                               f"(cos and sin against {KP} columns, cos^2, cos sin, sin^2)"}
-    elif f32_kernel(KP) == "scan_mfma_kernel":
-        fpp = 4 * K
-        roof = {"bound": "mfma", "peak": PEAK_FP32_MFMA, "kernel": "scan_mfma_kernel",
-                "algorithmic": f"{fpp} flop per (frequency, sample) pair: cos and sin against the {K} "
-                               "orthonormal base columns, one float32 multiply-add each, on MFMA (unpadded)"}
-    else:
-        fpp = 2 * (2 * KP + 3)
-        kern = f32_kernel(KP)
-        roof = {"bound": "alu", "peak": PEAK_FP32_VALU, "kernel": kern,
-                "algorithmic": f"{fpp} flop per (frequency, sample) pair: {2 * KP + 3} multiply-adds (cos and sin "
-                               f"against {K} base columns, cos^2, cos sin; the data column in float64), against the "
-                               "float32 vector peak" + (" (the base-column sums run on the float16 matrix cores with "
-                                                        "split operands, the rest on the VALU)"
-                                                        if kern == "scan_f16x3_kernel" else "")}
-    achieved = fpp * points / ksec
-    z = out[0].cpu().numpy()
-    fl = out[1].cpu().numpy()
-    leg = {"value": points / sec, "ms_per_step": sec * 1e3, "ms_per_step_unprepared": sec_u * 1e3,
-           "roofline": {"bound": roof["bound"], "achieved": achieved / 1e12, "peak": roof["peak"] / 1e12,
-                        "unit": "TFLOP/s", "frac": achieved / roof["peak"], "traffic": traffic_bytes(roof["kernel"]),
-                        "kernel": roof["kernel"], "kernel_ms": ksec * 1e3, "launches_per_step": nl / args.steps,
-                        "algorithmic": roof["algorithmic"]},
-           "rescored_points": int(((fl & 64) != 0).sum()), "n_peaks_above_fap1": int(len(peaks["p"][0]))}
-    return leg, z
+    sec, per = timed(ctx, step, steps, warmup)
+    t_scan = per["scan"][0]
+    fl = pout[1]
+    return {"value": s.N * s.F / sec, "unit": "points/s", "ms_per_step": sec * 1e3,
+            "roofline": scan_roofline([s.base_f.size], s.N, s.F, t_scan, fp32),
+            "kernel_ms": {k: v[0] * 1e3 for k, v in per.items()},
+            "rescored_points": int(((fl & 64) != 0).sum().item()),
+            "n_peaks_above_fap1": int(len(peaks["p"][0]))}, pout[0].cpu().numpy(), pout[1].cpu().numpy()
 
 
-def oracle_sample(s, z_gpu, seconds):
-    """The float64 oracle on a bounded strided sample of the grid, one thread,
-    and the error of each GPU form there."""
-    try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(limits=1)
-    except Exception:  # pragma: no cover
-        limiter = None
+def residual_error(s, z, fl, n_idx=1500):
     import oracle as O
-    stride = 7
-    idx_all = np.arange(0, s.F, stride)
-    done = 0
-    err = {k: 0.0 for k in z_gpu}
-    t0 = time.perf_counter()
-    for b in range(0, idx_all.size, 256):
-        idx = idx_all[b:b + 256]
-        ref = O.scan(s.t, s.x, s.w, s.base_f, s.df, s.F, idx=idx)
-        good = ref.flags == 0
-        for k, v in z_gpu.items():
-            e = np.abs(v[idx][good] - ref.z[good]) / np.maximum(np.abs(ref.z[good]), 1.0)
-            err[k] = max(err[k], float(np.max(e, initial=0.0)))
-        done += idx.size
-        if time.perf_counter() - t0 > seconds:
-            break
-    el = time.perf_counter() - t0
-    del limiter
-    return {"value": s.N * done / el, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} grid frequencies (every {stride}th from the low end of F={s.F}) of the same series, "
-                      f"N={s.N}, m={s.base_f.size}; {el:.1f} s single-threaded"}, err
+    rng = np.random.default_rng(3)
+    idx = np.unique(np.concatenate([rng.integers(0, s.F, size=n_idx),
+                                    np.argsort(-np.nan_to_num(z["fp64"], nan=-1.0))[:50]])).astype(np.int64)
+    r = O.scan(s.t, s.x, s.w, s.base_f, s.df, s.F, idx=idx)
+    good = r.flags == 0
+    out = {}
+    for k, v in z.items():
+        e = np.abs(v[idx][good] - r.z[good]) / np.maximum(np.abs(r.z[good]), 1.0)
+        out[k] = float(e.max())
+        out[k + "_flags_equal"] = bool(np.array_equal(fl[k][idx] & ~np.uint8(64), r.flags))
+    out["points_checked"] = int(good.sum())
+    return out
 
 
 # ------------------------------------------------------------------ tuples
-def tuples_leg(ctx, args, n_steps=20):
+def tuples_leg(ctx, dev, fp32, steps, n_steps=20):
     import torch
-    from paper_1309_0100_amd import synth
+    from paper_1309_0100_amd import fredec, synth
+    prec = fredec.FP32 if fp32 else fredec.FP64
     s = synth.tuples_series()
-    dev = torch.device("cuda", 0)
     t, x, w = (torch.as_tensor(a, device=dev) for a in (s.t, s.x, s.w))
     z, fl, _, _ = ctx.scan_series(t, x, w, [], s.df, s.F)
     idx, zp = ctx.peaks(z, fl, 0.0)
     top = idx[np.lexsort((idx, -zp))[:12]]
     peaks = (top + 1).astype(np.float64) * s.df
     f0, toff = synth.tuples_draw(peaks, n_tuples=65536)
-    f0d = torch.as_tensor(f0, device=dev)
     nt = toff.size - 1
     res = {}
 
     def step():
-        res["r"] = ctx.ascent(t, x, w, f0d, toff, steps=n_steps, clamp=0.1)
+        f = torch.as_tensor(f0, device=dev)
+        res["r"] = ctx.ascent(t, x, w, f, toff, steps=n_steps, clamp=0.1, precision=prec)
 
-    sec, ksec, nl = timed(ctx, step, args.tuple_steps, 1)
-    # Gram pass: C(C+1)/2 multiply-adds per (tuple, sample), C = 2n + 2 columns
-    C = 2 * np.diff(toff).astype(np.float64) + 2
-    gram_flops = float(np.sum(C * (C + 1))) * s.N * (n_steps + 1)
-    achieved = gram_flops / ksec
+    sec, per = timed(ctx, step, steps, 1)
+    nn = np.diff(toff).astype(np.float64)
+    C = 2 * nn + 2
+    # per (tuple, sample) and pass: the Gram lower triangle C(C+1)/2 multiply-adds + 12 slots of trig per
+    # member (offset rotation 8 + complex product 4)
+    slots = float(np.sum(C * (C + 1) / 2 + 12 * nn)) * s.N * (n_steps + 1)
+    t_gram = per["gram"][0]
     fa, zz, ll, ff = res["r"]
-    leg = {"value": nt / sec, "unit": "tuples/s", "tuple_steps_per_s": nt * n_steps / sec,
-           "ms_per_call": sec * 1e3, "dtype": "f64",
-           "workload": f"N={s.N} over 3000 d, {nt} tuples of 1..6 perturbed peaks of the m=0 scan, "
-                       f"{n_steps} ascent steps (forward z + adjoint dz/df + update) per call",
-           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
-                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
-                        "traffic": traffic_bytes("tuple_gram_lanes_kernel"),
-                        "kernel": "tuple_gram_lanes_kernel", "kernel_ms_per_call": ksec * 1e3,
-                        "launches_per_call": nl / args.tuple_steps,
-                        "algorithmic": "C(C+1) flop per (tuple, sample) per pass, C = 2n+2 Gram columns "
-                                       f"(float64 multiply-adds of the lower triangle incl. the data column; "
-                                       f"the n sin/cos are overhead), {n_steps + 1} passes per call"}}
-    return leg, (s, f0, toff, fa.cpu().numpy(), zz.cpu().numpy(), ff.cpu().numpy())
+    return {"value": nt / sec, "unit": "tuples/s", "tuple_steps_per_s": nt * n_steps / sec,
+            "ms_per_call": sec * 1e3, "kernel_ms": {k: v[0] * 1e3 for k, v in per.items()},
+            "roofline": {"bound": "alu", "kernel": "tuple_gram_lanes_kernel", "achieved": slots / t_gram / 1e12,
+                         "peak": PEAK_VALU_OPS / 1e12, "unit": "Tops/s", "frac": slots / t_gram / PEAK_VALU_OPS,
+                         "algorithmic": "VALU lane-op slots per (tuple, sample) and pass: C(C+1)/2 Gram multiply-adds "
+                                        "(C = 2n+2) + 12 per member for its trig; 21 passes per call"}}, \
+        (s, f0, toff, fa.cpu().numpy(), zz.cpu().numpy())
 
 
-def tuples_error(data, n_check=48):
+def tuples_error(data, n_check=24):
     import oracle as O
-    s, f0, toff, fa, zz, ff = data
+    s, f0, toff, fa, zz = data
     nrm = O.normalize(s.t, s.x, s.w)
     err_f, err_z = 0.0, 0.0
     nt = toff.size - 1
-    for k in range(0, nt, max(1, nt // n_check)):
+    ks = range(0, nt, max(1, nt // n_check))
+    for k in ks:
         fr, zr, lr = O.ascent(nrm, f0[toff[k]:toff[k + 1]], steps=20, clamp=0.1)
         if not np.isfinite(zr):
             continue
         err_f = max(err_f, float(np.max(np.abs(fa[toff[k]:toff[k + 1]] - fr)) * nrm.T_eff))
         err_z = max(err_z, float(abs(zz[k] - zr) / max(abs(zr), 1.0)))
-    return {"z": err_z, "f_times_T_eff": err_f, "tuples_checked": len(range(0, nt, max(1, nt // n_check)))}
+    return {"z": err_z, "f_times_T_eff": err_f, "tuples_checked": len(ks)}
 
 
 # ------------------------------------------------------------------ batched
-def batched_leg(ctx, args, prec_name, b):
+def batched_leg(ctx, b, dev, fp32, steps, warmup):
     import torch
     from paper_1309_0100_amd import fredec
-    prec = fredec.FP64 if prec_name == "fp64" else fredec.FP32
-    dev = torch.device("cuda", 0)
+    prec = fredec.FP32 if fp32 else fredec.FP64
     t, x, w = (torch.as_tensor(a, device=dev) for a in (b.t, b.x, b.w))
-    # prepared once: a step launches the scan's kernels
     plan, out = ctx.scan_plan(b.soff, b.base_f, b.boff, b.df, b.F, prec)
 
     def step():
         plan.run(t, x, w, out)
 
-    steps = max(2, args.steps // 4)
-    sec, ksec, _ = timed(ctx, step, steps, 1)
+    sec, per = timed(ctx, step, steps, warmup)
     Ns = np.diff(b.soff).astype(np.float64)
-    KP = 2 * np.diff(b.boff).astype(np.float64) + 2
+    ms = np.diff(b.boff)
     points = float(np.sum(Ns * np.asarray(b.F)))
-    # the scans' sums: 2 KP + 3 multiply-adds per (frequency, sample) pair
-    flops = float(np.sum(Ns * np.asarray(b.F) * 2 * (2 * KP + 3)))
-    achieved = flops / ksec
-    peak = PEAK_FP64_VALU if prec == fredec.FP64 else PEAK_FP32_VALU
-    leg = {"value": points / sec, "ms_per_step": sec * 1e3, "kernel_ms": ksec * 1e3, "pairs": points,
-           "rescored_points": int(((out[1] & 64) != 0).sum().item()),
-           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                        "frac": achieved / peak, "traffic": None,
-                        "kernel": "scan_f64_kernel" if prec == fredec.FP64 else "scan_f16x3_kernel + scan_f32_kernel",
-                        "algorithmic": "2 (2 KP + 3) flop per (frequency, sample) pair summed over the series "
-                                       "(KP = 2 m_s + 2), over the HIP-event time of all scan kernel launches"}}
-    return leg, out[0].clone(), out[1].clone()
+    t_scan = per["scan"][0]
+    t_roof = 0.0
+    for m in np.unique(ms):
+        P = float(np.sum(Ns[ms == m] * np.asarray(b.F)[ms == m]))
+        _, v, mf, mpk = scan_model(int(m), fp32)
+        t_roof += max(v * P / PEAK_VALU_OPS, mf * P / mpk)
+    return {"value": points / sec, "ms_per_step": sec * 1e3, "pairs": points,
+            "kernel_ms": {k: v[0] * 1e3 for k, v in per.items()},
+            "roofline": {"bound": "alu", "frac": t_roof / t_scan, "kernel": "all scan kernel launches",
+                         "unit": "Tops/s", "peak": PEAK_VALU_OPS / 1e12, "kernel_ms": t_scan * 1e3},
+            "rescored_points": int(((out[1] & 64) != 0).sum().item())}, out[0].clone(), out[1].clone()
 
 
-# ------------------------------------------------------------------ full
-def full_leg(ctx, args, prec_name, s):
-    import torch
-    from paper_1309_0100_amd import fredec, pipeline
-    prec = fredec.FP64 if prec_name == "fp64" else fredec.FP32
-    dev = torch.device("cuda", 0)
-    t, x, w = (torch.as_tensor(a, device=dev) for a in (s.t, s.x, s.w))
-    torch.cuda.synchronize()
+# ------------------------------------------------------------------ CPU baseline
+def _oracle_block(args):
+    """One block of the oracle's scan (worker of the CPU baseline)."""
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover
+        lim = None
+    import oracle as O
+    t, x, w, base, df, F, idx = args
+    O.scan(t, x, w, base, df, F, idx=idx)
+    del lim
+    return idx.size
+
+
+def cpu_baseline(s, seconds):
+    """The float64 oracle on a bounded sample of the full pass's scans: base models of m = 0 .. 12
+    frequencies (the injected frequencies, strongest first, as stand-ins for the SLICK frequencies), 64
+    random grid points per scan per block; first one process, then one process per core (at most 16).
+    Runs before anything touches the GPU (the worker processes are forked)."""
+    import multiprocessing as mp
+    order = np.argsort(-s.true_A)
+    bases = [s.true_f[order[:m]] for m in range(s.true_f.size + 1)]
+    rng = np.random.default_rng(1)
+    blocks = []
+    for rep in range(200):
+        for base in bases:
+            idx = np.sort(rng.choice(s.F, size=64, replace=False)).astype(np.int64)
+            blocks.append((s.t, s.x, s.w, base, s.df, s.F, idx))
+    # one process
     t0 = time.perf_counter()
-    res = pipeline.run(ctx, t, x, w, s.df, s.F, pool_cap=16, refine_steps=8, precision=prec)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    n = res.pool.size
-    # Phase-2 Gram kernel at the pass's shape: one Gauss-Newton step of every subtuple of the final
-    # pool (two Gram passes, every tuple live in both), timed by HIP events around the Gram launches
-    ctx.profile(True)
-    torch.cuda.synchronize()
-    ctx.tuples(t, x, w, res.pool, refine_steps=1, precision=prec)
-    torch.cuda.synchronize()
-    kms, nl = ctx.profile_read()
-    ctx.profile(False)
-    # Phase-1 scan kernels of the pass: the preliminary scans again (scan k has a base model of k
-    # frequencies), timed by HIP events around their scan kernel launches
-    ctx.profile(True)
-    torch.cuda.synchronize()
-    p1 = ctx.phase1(t, x, w, s.df, s.F, pool_cap=16, precision=prec)
-    torch.cuda.synchronize()
-    kms1, nl1 = ctx.profile_read()
-    ctx.profile(False)
-    KP = 2.0 * np.arange(p1["n_scans"], dtype=np.float64) + 2.0
-    flops1 = float(np.sum(2.0 * (2.0 * KP + 3.0))) * s.N * s.F
-    ach1 = flops1 / (kms1 / 1e3)
-    peak1 = PEAK_FP64_VALU if prec == fredec.FP64 else PEAK_FP32_VALU
-    from math import comb
-    C = np.array([4 * k + 2 for k in range(1, n + 1)], np.float64)
-    cnt = np.array([comb(n, k) for k in range(1, n + 1)], np.float64)
-    flops = 2.0 * float(np.sum(cnt * C * (C + 1))) * s.N
-    achieved = flops / (kms / 1e3)
-    return {"seconds": el, "n_scans": res.n_scans, "pool": [float(f) for f in res.pool],
-            "n_tuples": (1 << n) - 1, "n_solutions": len(res.solutions),
-            "solutions": [[float(f) for f in sol.freqs] for sol in res.solutions[:5]],
-            "scan_pairs": float(s.N) * s.F * res.n_scans,
-            "phase1_roofline": {"bound": "alu", "achieved": ach1 / 1e12, "peak": peak1 / 1e12, "unit": "TFLOP/s",
-                                "frac": ach1 / peak1, "traffic": None,
-                                "kernel": "scan_f64_kernel" if prec == fredec.FP64 else
-                                          "scan_f16x3_kernel + scan_f32_kernel",
-                                "kernel_ms_per_pass": kms1, "scans": int(p1["n_scans"]), "launches": int(nl1),
-                                "algorithmic": "2 (2 KP + 3) flop per (frequency, sample) pair, KP = 2k + 2 for "
-                                               "the scan on a base of k frequencies, over the HIP-event time of the "
-                                               "Phase 1 scan kernel launches" + (
-                                                   "" if prec == fredec.FP64 else
-                                                   "; counted against the float32 vector peak although the "
-                                                   "base-column sums (most of the flops at large k) run on the "
-                                                   "float16 matrix cores with split operands")},
-            "phase2_roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64_MFMA / 1e12,
-                                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
-                                "kernel": "tuple_gram_kernel", "kernel_ms_per_pass": kms / max(nl, 1),
-                                "passes": int(nl),
-                                "algorithmic": "C(C+1) flop per (tuple, sample) per Gauss-Newton Gram pass, C = 4n+2 "
-                                               "columns (1, cos, sin, x~, t' cos, t' sin; lower triangle), float64 "
-                                               "matrix cores"}}
+    done1 = 0
+    for b in blocks:
+        done1 += _oracle_block(b)
+        if time.perf_counter() - t0 > seconds:
+            break
+    el1 = time.perf_counter() - t0
+    # one process per core
+    P = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    doneP = 0
+    with mp.get_context("fork").Pool(P) as pool:
+        for k in pool.imap_unordered(_oracle_block, blocks, chunksize=1):
+            doneP += k
+            if time.perf_counter() - t0 > seconds:
+                pool.terminate()
+                break
+    elP = time.perf_counter() - t0
+    return {"value": s.N * done1 / el1, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done1} grid points of the full-pass series (N={s.N}, F={s.F}) in blocks of 64 random "
+                      f"points, cycling over base models of m = 0..{len(bases) - 1} injected frequencies; "
+                      f"{el1:.1f} s in one process (BLAS threads = 1)",
+            "all_cores": {"value": s.N * doneP / elP, "unit": "points/s", "cores": P,
+                          "sample": f"{doneP} grid points, same blocks, {P} processes, {elP:.1f} s"}}
 
 
+# ------------------------------------------------------------------ main
 def main():
     args = parse()
     if args.copy_bytes:
         copy_reference(args.copy_bytes)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
+                                   "(multi-GPU sharding is a design note, not built)"}))
         sys.exit(2)
-    from paper_1309_0100_amd import fredec, synth
+    from paper_1309_0100_amd import synth
+    cpu = None
+    if args.workload == "full" and not args.no_cpu:
+        progress("oracle on the host cores")
+        cpu = cpu_baseline(synth.full(), args.cpu_seconds)
+    import torch
+    from paper_1309_0100_amd import fredec
+    dev = torch.device("cuda", 0)
     ctx = fredec.Context(0)
-    if args.tile:
-        ctx.set_tile(fredec.TILE_SCAN_MFMA, 1, args.tile)
-    forms = ["fp32", "fp64"] if args.precision == "both" else [args.precision]
     res = {"metric": METRIC, "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
+    extra = not args.no_extra
 
-    if args.workload == "residual":
-        s = synth.residual()
-        legs, zs = {}, {}
-        for fm in forms:
-            legs[fm], zs[fm] = residual_leg(ctx, args, fm, s)
-        head = max(forms, key=lambda k: legs[k]["value"])
-        res.update({"value": legs[head]["value"], "ms_per_step": legs[head]["ms_per_step"],
-                    "dtype": "f32" if head == "fp32" else "f64",
-                    "config": {"workload": "residual scan: N=2000 over 4000 d, seasonal gaps, m=4 base sinusoids, "
-                                           "F=10^6 grid to 2 c/d; scan (prepared plan: normalisation, base precomputation, "
-                                           "scan kernels, float64 re-scoring) + peak list per step",
-                               "N": s.N, "F": s.F, "m": int(s.base_f.size), "form": head},
-                    "ms_per_step_unprepared": legs[head]["ms_per_step_unprepared"],
-                    "roofline": legs[head]["roofline"],
-                    "rescored_points": legs[head]["rescored_points"]})
-        for fm in forms:
-            if fm != head:
-                res[f"{fm}_form"] = legs[fm]
-        if len(forms) == 2:
-            res["speedup_fp32_over_fp64"] = legs["fp32"]["value"] / legs["fp64"]["value"]
-        data = None
-        if not args.no_tuples:
-            res["tuples"], data = tuples_leg(ctx, args)
-        if not args.no_cpu:
-            cb, err = oracle_sample(s, zs, args.cpu_seconds)
-            res["cpu_baseline"] = cb
-            res["max_rel_err_vs_oracle"] = err
-            if data is not None:
-                res["tuples"]["max_err_vs_oracle"] = tuples_error(data)
+    if args.workload == "full":
+        s = synth.full()
+        progress("full pass, float32 form")
+        leg32, r32 = full_leg(ctx, s, dev, True, args.steps, args.warmup)
+        leg64 = r64 = None
+        if args.fp64_steps > 0:
+            progress("full pass, float64 form")
+            leg64, r64 = full_leg(ctx, s, dev, False, min(args.steps, args.fp64_steps), min(args.warmup, 1))
+        res.update({"value": leg32["points_per_s"], "ms_per_step": leg32["seconds_per_pass"] * 1e3,
+                    "tuples_per_s": leg32["tuples_per_s"], "dtype": "f32 (f16x3 MFMA)",
+                    "config": {"workload": "full FREDEC pass: N=10^4 over 20000 d (nightly + seasonal gaps), 12 "
+                                           "sinusoids; Phase 1 scans on F=4e6 to 5 c/d until the FAP_0 stop, pool "
+                                           "cap 16, all 65535 subsets refined (8 Gauss-Newton steps), Phase 3",
+                               "N": s.N, "F": s.F, "pool_cap": 16, "form": "fp32"},
+                    "roofline": leg32["roofline"], "fp32_form": leg32})
+        if leg64 is not None:
+            res["fp64_form"] = dict(leg64, steps=min(args.steps, args.fp64_steps))
+            res["speedup_fp32_over_fp64"] = leg64["seconds_per_pass"] / leg32["seconds_per_pass"]
+            progress("errors of the float32 pass")
+            res["errors"] = full_errors(ctx, s, dev, r32, r64)
+        if extra:
+            progress("residual scan (N=2000, m=4, F=1e6)")
+            sr = synth.residual()
+            legs, zs, fls = {}, {}, {}
+            for k, fp32 in (("fp32", True), ("fp64", False)):
+                legs[k], zs[k], fls[k] = residual_leg(ctx, sr, dev, fp32, 20, 5)
+            legs["speedup_fp32_over_fp64"] = legs["fp64"]["ms_per_step"] / legs["fp32"]["ms_per_step"]
+            legs["max_rel_err_vs_oracle"] = residual_error(sr, zs, fls)
+            res["residual_scan"] = legs
+            progress("tuple ascent (65536 tuples, 20 steps)")
+            tl = {}
+            for k, fp32 in (("fp64", False), ("fp32", True)):
+                tl[k], data = tuples_leg(ctx, dev, fp32, 3)
+                tl[k]["max_err_vs_oracle"] = tuples_error(data)
+            tl["speedup_fp32_over_fp64"] = tl["fp64"]["ms_per_call"] / tl["fp32"]["ms_per_call"]
+            res["tuples"] = tl
+        if cpu is not None:
+            res["cpu_baseline"] = cpu
+    elif args.workload == "residual":
+        sr = synth.residual()
+        legs, zs, fls = {}, {}, {}
+        for k, fp32 in (("fp32", True), ("fp64", False)):
+            legs[k], zs[k], fls[k] = residual_leg(ctx, sr, dev, fp32, args.steps, args.warmup)
+        res.update({"value": legs["fp32"]["value"], "ms_per_step": legs["fp32"]["ms_per_step"],
+                    "dtype": "f32 (f16x3 MFMA)", "roofline": legs["fp32"]["roofline"],
+                    "config": {"workload": "residual scan: N=2000 over 4000 d, seasonal gaps, m=4, F=10^6 to 2 c/d",
+                               "N": sr.N, "F": sr.F, "m": int(sr.base_f.size), "form": "fp32"},
+                    "forms": legs, "speedup_fp32_over_fp64": legs["fp64"]["ms_per_step"] / legs["fp32"]["ms_per_step"],
+                    "max_rel_err_vs_oracle": residual_error(sr, zs, fls)})
     elif args.workload == "batched":
         b = synth.batched()
-        import torch
-        runs = {fm: batched_leg(ctx, args, fm, b) for fm in forms}
-        legs = {fm: r[0] for fm, r in runs.items()}
-        if len(forms) == 2:
-            # float32 arithmetic against the float64 form (itself checked against the oracle to 1e-9 by
-            # the tests) on every grid point that the float32 form scored itself (not re-scored in
-            # float64) and that neither form flags
-            z32, f32_, z64, f64_ = runs["fp32"][1], runs["fp32"][2], runs["fp64"][1], runs["fp64"][2]
-            good = (f32_ == 0) & (f64_ == 0) & torch.isfinite(z64)
-            err = (z32 - z64).abs() / torch.clamp(z64.abs(), min=1.0)
-            legs["fp32"]["max_rel_err_vs_fp64"] = float(err[good].max().item())
-            legs["fp32"]["points_compared"] = int(good.sum().item())
-        head = max(forms, key=lambda k: legs[k]["value"])
-        res.update({"value": legs[head]["value"], "ms_per_step": legs[head]["ms_per_step"],
-                    "dtype": "f32" if head == "fp32" else "f64",
-                    "config": {"workload": "batched scan: 4096 series, N log-uniform in [50, 5000], "
-                                           "m uniform in 0..6, F=65536", "series": int(b.soff.size - 1),
-                               "samples": int(b.soff[-1]), "form": head},
-                    "roofline": legs[head]["roofline"],
-                    "forms": legs})
+        runs = {k: batched_leg(ctx, b, dev, fp32, args.steps, args.warmup) for k, fp32 in (("fp32", True),
+                                                                                          ("fp64", False))}
+        legs = {k: r[0] for k, r in runs.items()}
+        z32, f32_, z64, f64_ = runs["fp32"][1], runs["fp32"][2], runs["fp64"][1], runs["fp64"][2]
+        good = (f32_ == 0) & (f64_ == 0) & torch.isfinite(z64)
+        err = (z32 - z64).abs() / torch.clamp(z64.abs(), min=1.0)
+        legs["fp32"]["max_rel_err_vs_fp64"] = float(err[good].max().item())
+        res.update({"value": legs["fp32"]["value"], "ms_per_step": legs["fp32"]["ms_per_step"],
+                    "dtype": "f32 (f16x3 MFMA)", "roofline": legs["fp32"]["roofline"],
+                    "config": {"workload": "batched scan: 4096 series, N log-uniform in [50, 5000], m uniform in "
+                                           "0..6, F=65536", "series": int(b.soff.size - 1),
+                               "samples": int(b.soff[-1]), "form": "fp32"}, "forms": legs})
     else:
-        s = synth.full()
-        legs = {fm: full_leg(ctx, args, fm, s) for fm in forms}
-        head = min(forms, key=lambda k: legs[k]["seconds"])
-        res.update({"value": legs[head]["scan_pairs"] / legs[head]["seconds"],
-                    "ms_per_step": legs[head]["seconds"] * 1e3, "steps": 1, "warmup": 0,
-                    "dtype": "f32" if head == "fp32" else "f64",
-                    "config": {"workload": "full method: N=10^4 over 20000 d, Phase 1 scans on F=4e6, pool cap 16, "
-                                           "every subtuple refined (8 Gauss-Newton steps), Phase 3", "form": head},
-                    # the Phase 1 scans take most of the pass; the Phase 2 Gram's roofline is in the legs
-                    "roofline": legs[head]["phase1_roofline"],
-                    "forms": legs})
+        tl = {}
+        for k, fp32 in (("fp64", False), ("fp32", True)):
+            tl[k], data = tuples_leg(ctx, dev, fp32, args.steps)
+            tl[k]["max_err_vs_oracle"] = tuples_error(data)
+        res.update({"value": tl["fp32"]["value"], "unit": "tuples/s", "ms_per_step": tl["fp32"]["ms_per_call"],
+                    "dtype": "f32", "roofline": tl["fp32"]["roofline"],
+                    "config": {"workload": "tuple ascent: N=1000 over 3000 d, 65536 tuples of 1..6 perturbed peaks, "
+                                           "20 steps", "form": "fp32"}, "forms": tl})
     print(json.dumps(res), flush=True)
 
 
