@@ -303,6 +303,27 @@ int fredec_adjoint(fredec_ctx* ctx, void* stream, const double* t, const double*
                    const double* l, int32_t precision, void* workspace, size_t ws_bytes, double* dz_df,
                    double* h_out);
 
+/* Vuong's statistic between fits (Phase 4 of Sect. 4 and the per-solution
+ * output of Sect. 6, which compare each alternative solution with the best
+ * one; the paper does not print the formula).  For ragged tuples as in
+ * fredec_grad (f device, toff host) with their least-squares coefficients
+ * theta (device, the theta_out layout of fredec_grad, from a fredec_grad call
+ * at the same f), the residuals r = x~ - Phi theta* are recomputed sample by
+ * sample, l_k = <r^2> (device l_out [n_tuples], nullable), and for the
+ * Gaussian noise model of Sect. 2 with known relative weights and a fitted
+ * scale (sample i has variance l / (N w~_i)) the per-sample log-likelihood
+ * differences of tuple `ref` against tuple k,
+ *   d_i = -1/2 ln(l_ref / l_k) - (N w~_i / 2)(r_ref,i^2 / l_ref - r_k,i^2 / l_k),
+ * give V_out[k] = sum d / (sqrt(N) omega), omega^2 = mean(d^2) - mean(d)^2
+ * (device [n_tuples]; positive when `ref` fits better; V_ref = 0; 0 for
+ * identical fits; NaN if an l is not finite and positive).  Workspace from
+ * fredec_vuong_workspace (includes N x n_tuples residuals).  Errors: EINVAL
+ * (also ref outside [0, n_tuples)), ENOTSUP, EDOF, ENOMEM. */
+int fredec_vuong_workspace(int64_t N, const int64_t* toff_host, int64_t n_tuples, size_t* bytes);
+int fredec_vuong(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                 const double* f, const int64_t* toff_host, int64_t n_tuples, const double* theta, int64_t ref,
+                 void* workspace, size_t ws_bytes, double* l_out, double* V_out);
+
 /* Fixed-step preconditioned ascent of z for ragged tuples (workspace as for
  * fredec_grad): `steps` times f_k += clamp(<r J_k> / <J_k^2>, +-clamp / T_eff),
  * then a final evaluation.  f (device) is updated in place; outputs as for
@@ -332,6 +353,32 @@ int fredec_ascent_plan(fredec_ctx* ctx, void* stream, int64_t N, const int64_t* 
 int fredec_plan_ascent(fredec_ctx* ctx, fredec_plan* plan, void* stream,
                        const double* t, const double* x, const double* w, double* f,
                        double* z_out, double* l_out, uint8_t* flags_out);
+
+/* Global-local residual periodogram (Sect. 2, the statistic with a locally
+ * re-optimised base model defined after eq. zpowrel) -------------------------
+ * One series t, x, w (device, N samples) and base frequencies f'
+ * (host base_f[m], m <= FREDEC_MAX_BASE).  The base model is first refined
+ * by Gauss-Newton from f' (the step control of fredec_tuples, refine_steps
+ * trial points): l_b = l_{m,loc}(f'_loc).  Then for every grid frequency
+ * f_j = (j+1) df, j < F, the model with the m base frequencies and f_j is
+ * refined the same way from (f'_loc, f_j) with f_j held fixed (its
+ * Gauss-Newton step is zero; the base frequencies move):
+ *     z_j = (N - 3m - 4)/2 ln(l_b / l_{1|m,loc}(f_j | f'_loc)),
+ * whose maximum over the grid is the global-local statistic.  Flags as for
+ * fredec_scan: f_j within 0.05 / T_eff of a refined base frequency: z = 0,
+ * FREDEC_FLAG_MASKED; a degenerate start: z = 0, FREDEC_FLAG_SINGULAR; l <= 0:
+ * z = +inf, FREDEC_FLAG_PERFECT.  float64 throughout (Gram passes on the
+ * float64 matrix cores); the grid runs in chunks of at most 65536 points.
+ * Outputs: z_out (device [F]), flags_out (device [F], nullable), l_base_out
+ * (device [1], nullable), base_out (device [m], nullable: f'_loc).
+ * Synchronises `stream` once (after the base refinement).  Errors: EINVAL,
+ * ENOTSUP (m > FREDEC_MAX_BASE), EDOF (N - 3m - 4 <= 0), ENOMEM, ESINGULAR
+ * (the base model cannot be fitted). */
+int fredec_global_local_workspace(int64_t N, int32_t m, int64_t F, size_t* bytes);
+int fredec_global_local(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                        const double* base_f_host, int32_t m, double df, int64_t F, int32_t refine_steps,
+                        void* workspace, size_t ws_bytes, double* z_out, uint8_t* flags_out, double* l_base_out,
+                        double* base_out);
 
 /* FAP thresholds (eq. zFAP) ------------------------------------------------
  * zc[d], d = 1..n (zc[0] = 0): the z with A_d W^d e^{-z} z^{3d/2-1} = fap on
@@ -386,6 +433,29 @@ int fredec_phase1(fredec_ctx* ctx, void* stream, const double* t, const double* 
                   int32_t precision, void* workspace, size_t ws_bytes, double* pool_out, double* pool_z_out,
                   int32_t* n_pool, double* base_out, int32_t* n_base, int32_t* n_scans, int32_t* truncated,
                   double* W_out);
+
+/* Residual single-frequency FAP of each solution (Sect. 6: the per-solution
+ * output lists the FAP of the largest peak left in the residual periodogram;
+ * eq. zFAP with n = 1).  Solution k has the frequencies
+ * sol_f[sol_off[k] .. sol_off[k+1]) (host arrays, sol_off[0] = 0, at most
+ * FREDEC_MAX_BASE each).  For each, the residual scan of fredec_scan on the
+ * grid f_j = (j+1) df, j < F, with those frequencies as the base model; its
+ * highest interior local maximum by the rule of fredec_peaks (largest z,
+ * ties -> lowest index) z_max at grid index j_max; and
+ *     FAP = min(1, A1 W e^{-z_max} z_max^{1/2}),   W = F df T_eff.
+ * With FREDEC_FP32 the scans use the reduced-precision sums; the peaks within
+ * 1e-4 max(z, 1) of the float32 maximum are followed uphill in float64
+ * (fredec_scan_at) and the maximum is taken over the float64 values.
+ * Synchronises `stream` after every scan.  Host outputs [n_sol]: fap_out,
+ * zmax_out, jmax_out (a periodogram without peak: FAP 1, z NaN, j -1).
+ * Errors: EINVAL, ENOTSUP (a solution above FREDEC_MAX_BASE), EDOF
+ * (N - 3(m_max + 1) - 1 <= 0), ENOMEM, a series status code (EWEIGHT,
+ * EDEGEN, ESINGULAR for a singular solution). */
+int fredec_residual_fap_workspace(int64_t N, int64_t F, int32_t m_max, int32_t precision, size_t* bytes);
+int fredec_residual_fap(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                        const double* sol_f_host, const int64_t* sol_off_host, int32_t n_sol, double df, int64_t F,
+                        double A1, int32_t precision, void* workspace, size_t ws_bytes, double* fap_out,
+                        double* zmax_out, int64_t* jmax_out);
 
 #ifdef __cplusplus
 }

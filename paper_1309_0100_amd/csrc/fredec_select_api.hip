@@ -50,6 +50,80 @@ int sync_read(hipStream_t st, void* dst, const void* src, size_t bytes) {
 
 __global__ void zero_count_kernel(unsigned long long* c) { *c = 0ull; }
 
+// Device buffers of the float64 hill climb: grid indices, their z and flags
+// (3 per peak) and the fredec_scan_at workspace.
+struct ClimbBuffers {
+  int64_t* idx;
+  double* z;
+  uint8_t* fl;
+  void* at_ws;
+  size_t at_bytes;
+};
+
+// Float64 hill climb from each reduced-precision peak in `pk` to the float64
+// local maximum of the scan with base model `base` (fredec_scan_at on the
+// point and its neighbours until neither neighbour is higher).  Replaces `pk`
+// by the float64 maxima reached that are interior, carry no flag other than
+// FREDEC_FLAG_RESCORED and have z > zmin, sorted by index without repeats.
+// The buffers hold 3 entries per peak.
+int climb_f64(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+              const std::vector<double>& base, double df, int64_t F, const ClimbBuffers& cb, double zmin,
+              std::vector<Peak>& pk) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t np = static_cast<int64_t>(pk.size());
+  int rc;
+  std::vector<int64_t> cur(np);
+  for (int64_t k = 0; k < np; ++k) cur[k] = pk[k].j;
+  std::vector<char> active(np, 1);
+  std::vector<double> zc(np, 0.0);
+  std::vector<uint8_t> fc(np, 0);
+  for (int iter = 0; iter < 64; ++iter) {
+    std::vector<int64_t> idx;
+    std::vector<int64_t> who;
+    for (int64_t k = 0; k < np; ++k)
+      if (active[k]) {
+        for (int o = -1; o <= 1; ++o) idx.push_back(std::min<int64_t>(std::max<int64_t>(cur[k] + o, 0), F - 1));
+        who.push_back(k);
+      }
+    if (who.empty()) break;
+    if ((rc = upload(ctx, st, cb.idx, idx.data(), sizeof(int64_t) * idx.size()))) return rc;
+    if ((rc = fredec_scan_at(ctx, stream, t, x, w, N, base.empty() ? nullptr : base.data(),
+                             static_cast<int32_t>(base.size()), df, cb.idx, static_cast<int64_t>(idx.size()),
+                             cb.at_ws, cb.at_bytes, cb.z, cb.fl)))
+      return rc;
+    std::vector<double> zv(idx.size());
+    std::vector<uint8_t> fv(idx.size());
+    if ((rc = sync_read(st, zv.data(), cb.z, sizeof(double) * zv.size()))) return rc;
+    if ((rc = sync_read(st, fv.data(), cb.fl, fv.size()))) return rc;
+    for (size_t q = 0; q < who.size(); ++q) {
+      const int64_t k = who[q];
+      const double zl = zv[3 * q], zm = zv[3 * q + 1], zr = zv[3 * q + 2];
+      const int64_t j = cur[k];
+      if (j <= 0 || j >= F - 1) {
+        active[k] = 0;
+        zc[k] = -1.0;  // not an interior point
+        continue;
+      }
+      if (zl >= zm) {
+        cur[k] = j - 1;
+      } else if (zr > zm) {
+        cur[k] = j + 1;
+      } else {
+        active[k] = 0;
+        zc[k] = zm;
+        fc[k] = fv[3 * q + 1];
+      }
+    }
+  }
+  std::vector<Peak> out;
+  for (int64_t k = 0; k < np; ++k)
+    if (!active[k] && zc[k] > zmin && (fc[k] & ~FREDEC_FLAG_RESCORED) == 0) out.push_back(Peak{cur[k], zc[k]});
+  std::sort(out.begin(), out.end(), [](const Peak& a, const Peak& b) { return a.j < b.j; });
+  out.erase(std::unique(out.begin(), out.end(), [](const Peak& a, const Peak& b) { return a.j == b.j; }), out.end());
+  pk.swap(out);
+  return FREDEC_OK;
+}
+
 struct Phase1Layout {
   size_t scan_ws = 0, at_ws = 0;
   size_t off_scan = 0, off_at = 0, off_z = 0, off_fl = 0, off_lb = 0, off_st = 0, off_peaks = 0, off_count = 0,
@@ -92,6 +166,64 @@ int phase1_layout(int64_t N, int64_t F, int32_t max_scans, int32_t precision, Ph
   L.off_zat = take(sizeof(double) * 3 * L.peak_cap);
   L.off_flat = take(3 * L.peak_cap);
   L.total = off;
+  return FREDEC_OK;
+}
+
+
+struct FapLayout {
+  size_t scan_ws = 0, at_ws = 0;
+  size_t off_scan = 0, off_at = 0, off_z = 0, off_fl = 0, off_lb = 0, off_st = 0, off_part = 0, off_best = 0,
+         off_peaks = 0, off_count = 0, off_idx = 0, off_zat = 0, off_flat = 0, total = 0;
+  int64_t peak_cap = 0;
+};
+
+int fap_layout(int64_t N, int64_t F, int32_t m_max, int32_t precision, FapLayout& L) {
+  if (N <= 0 || F < 3 || m_max < 0) return FREDEC_EINVAL;
+  if (m_max > FREDEC_MAX_BASE) return FREDEC_ENOTSUP;
+  const int64_t soff[2] = {0, N};
+  const int64_t boff[2] = {0, m_max};
+  const int64_t Fs[1] = {F};
+  int rc = fredec_scan_workspace(1, soff, boff, Fs, precision, &L.scan_ws);
+  if (rc) return rc;
+  if ((rc = fredec_scan_at_workspace(N, m_max, &L.at_ws))) return rc;
+  L.peak_cap = std::max<int64_t>((F - 1) / 2, 1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.off_scan = take(L.scan_ws);
+  L.off_at = take(L.at_ws);
+  L.off_z = take(sizeof(double) * F);
+  L.off_fl = take(F);
+  L.off_lb = take(sizeof(double));
+  L.off_st = take(sizeof(int32_t));
+  L.off_part = take(sizeof(Peak) * peak_max_parts(F));
+  L.off_best = take(sizeof(Peak));
+  L.off_peaks = take(precision == FREDEC_FP32 ? sizeof(Peak) * L.peak_cap : 0);
+  L.off_count = take(sizeof(unsigned long long));
+  L.off_idx = take(precision == FREDEC_FP32 ? sizeof(int64_t) * 3 * L.peak_cap : 0);
+  L.off_zat = take(precision == FREDEC_FP32 ? sizeof(double) * 3 * L.peak_cap : 0);
+  L.off_flat = take(precision == FREDEC_FP32 ? 3 * L.peak_cap : 0);
+  L.total = off;
+  return FREDEC_OK;
+}
+
+// Largest base model among the solutions, or a negative code.
+int fap_check(const double* sol_f, const int64_t* sol_off, int32_t n_sol, int32_t* m_max) {
+  if (!sol_off || n_sol < 1 || sol_off[0] != 0) return FREDEC_EINVAL;
+  int64_t mm = 0;
+  for (int32_t k = 0; k < n_sol; ++k) {
+    const int64_t m = sol_off[k + 1] - sol_off[k];
+    if (m < 0) return FREDEC_EINVAL;
+    if (m > FREDEC_MAX_BASE) return FREDEC_ENOTSUP;
+    mm = std::max(mm, m);
+  }
+  if (sol_off[n_sol] > 0 && !sol_f) return FREDEC_EINVAL;
+  for (int64_t q = 0; q < sol_off[n_sol]; ++q)
+    if (!std::isfinite(sol_f[q])) return FREDEC_EINVAL;
+  *m_max = static_cast<int32_t>(mm);
   return FREDEC_OK;
 }
 
@@ -251,57 +383,8 @@ int fredec_phase1(fredec_ctx* ctx, void* stream, const double* t, const double* 
     std::vector<Peak> pk(np);
     if ((rc = sync_read(st, pk.data(), d_pk, sizeof(Peak) * np))) return rc;
     if (precision == FREDEC_FP32 && np > 0) {
-      // float64 hill climb from each float32 peak to the float64 local maximum
-      std::vector<int64_t> cur(np);
-      for (int64_t k = 0; k < np; ++k) cur[k] = pk[k].j;
-      std::vector<char> active(np, 1);
-      std::vector<double> zc(np, 0.0);
-      std::vector<uint8_t> fc(np, 0);
-      for (int iter = 0; iter < 64; ++iter) {
-        std::vector<int64_t> idx;
-        std::vector<int64_t> who;
-        for (int64_t k = 0; k < np; ++k)
-          if (active[k]) {
-            for (int o = -1; o <= 1; ++o) idx.push_back(std::min<int64_t>(std::max<int64_t>(cur[k] + o, 0), F - 1));
-            who.push_back(k);
-          }
-        if (who.empty()) break;
-        if ((rc = upload(ctx, st, d_idx, idx.data(), sizeof(int64_t) * idx.size()))) return rc;
-        if ((rc = fredec_scan_at(ctx, stream, t, x, w, N, base.empty() ? nullptr : base.data(),
-                                 static_cast<int32_t>(base.size()), df, d_idx, static_cast<int64_t>(idx.size()),
-                                 at<void>(ws, L.off_at), L.at_ws, d_zat, d_flat)))
-          return rc;
-        std::vector<double> zv(idx.size());
-        std::vector<uint8_t> fv(idx.size());
-        if ((rc = sync_read(st, zv.data(), d_zat, sizeof(double) * zv.size()))) return rc;
-        if ((rc = sync_read(st, fv.data(), d_flat, fv.size()))) return rc;
-        for (size_t q = 0; q < who.size(); ++q) {
-          const int64_t k = who[q];
-          const double zl = zv[3 * q], zm = zv[3 * q + 1], zr = zv[3 * q + 2];
-          const int64_t j = cur[k];
-          if (j <= 0 || j >= F - 1) {
-            active[k] = 0;
-            zc[k] = -1.0;  // not an interior point
-            continue;
-          }
-          if (zl >= zm) {
-            cur[k] = j - 1;
-          } else if (zr > zm) {
-            cur[k] = j + 1;
-          } else {
-            active[k] = 0;
-            zc[k] = zm;
-            fc[k] = fv[3 * q + 1];
-          }
-        }
-      }
-      std::vector<Peak> out;
-      for (int64_t k = 0; k < np; ++k)
-        if (!active[k] && zc[k] > zc1 && (fc[k] & ~FREDEC_FLAG_RESCORED) == 0) out.push_back(Peak{cur[k], zc[k]});
-      std::sort(out.begin(), out.end(), [](const Peak& a, const Peak& b) { return a.j < b.j; });
-      out.erase(std::unique(out.begin(), out.end(), [](const Peak& a, const Peak& b) { return a.j == b.j; }),
-                out.end());
-      pk.swap(out);
+      ClimbBuffers cb{d_idx, d_zat, d_flat, at<void>(ws, L.off_at), L.at_ws};
+      if ((rc = climb_f64(ctx, stream, t, x, w, N, base, df, F, cb, zc1, pk))) return rc;
     }
     if (pk.empty()) break;
     // descending z, ties -> lower index
@@ -340,6 +423,95 @@ int fredec_phase1(fredec_ctx* ctx, void* stream, const double* t, const double* 
   for (size_t k = 0; k < base.size(); ++k) base_out[k] = base[k];
   *n_base = static_cast<int32_t>(base.size());
   *n_scans = scans;
+  return FREDEC_OK;
+}
+
+// ------------------------------------------------------------ residual FAP
+int fredec_residual_fap_workspace(int64_t N, int64_t F, int32_t m_max, int32_t precision, size_t* bytes) {
+  if (!bytes) return FREDEC_EINVAL;
+  if (precision != FREDEC_FP64 && precision != FREDEC_FP32) return FREDEC_EINVAL;
+  FapLayout L;
+  int rc = fap_layout(N, F, m_max, precision, L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return FREDEC_OK;
+}
+
+int fredec_residual_fap(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                        const double* sol_f, const int64_t* sol_off, int32_t n_sol, double df, int64_t F, double A1,
+                        int32_t precision, void* ws, size_t ws_bytes, double* fap_out, double* zmax_out,
+                        int64_t* jmax_out) {
+  if (!t || !x || !w || N <= 0 || F < 3 || !fap_out || !zmax_out || !jmax_out) return FREDEC_EINVAL;
+  if (!(A1 > 0.0) || !std::isfinite(A1) || !std::isfinite(df) || df == 0.0) return FREDEC_EINVAL;
+  if (precision != FREDEC_FP64 && precision != FREDEC_FP32) return FREDEC_EINVAL;
+  int32_t m_max = 0;
+  int rc = fap_check(sol_f, sol_off, n_sol, &m_max);
+  if (rc) return rc;
+  if (N - 3 * (static_cast<int64_t>(m_max) + 1) - 1 <= 0) return FREDEC_EDOF;
+  FapLayout L;
+  if ((rc = fap_layout(N, F, m_max, precision, L))) return rc;
+  if (!ws || ws_bytes < L.total) return FREDEC_ENOMEM;
+  if (!ctx) return FREDEC_EINVAL;
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* d_z = at<double>(ws, L.off_z);
+  uint8_t* d_fl = at<uint8_t>(ws, L.off_fl);
+  double* d_lb = at<double>(ws, L.off_lb);
+  int32_t* d_st = at<int32_t>(ws, L.off_st);
+  Peak* d_part = at<Peak>(ws, L.off_part);
+  Peak* d_best = at<Peak>(ws, L.off_best);
+  Peak* d_pk = at<Peak>(ws, L.off_peaks);
+  unsigned long long* d_cnt = at<unsigned long long>(ws, L.off_count);
+  const int64_t soff[2] = {0, N};
+  double W = 0.0;
+  for (int32_t k = 0; k < n_sol; ++k) {
+    std::vector<double> base(sol_f + sol_off[k], sol_f + sol_off[k + 1]);
+    const int64_t boff[2] = {0, static_cast<int64_t>(base.size())};
+    if ((rc = fredec_scan(ctx, stream, 1, t, x, w, soff, base.empty() ? nullptr : base.data(), boff, &df, &F,
+                          precision, at<void>(ws, L.off_scan), L.scan_ws, d_z, d_fl, d_lb, d_st)))
+      return rc;
+    int32_t status = 0;
+    if ((rc = sync_read(st, &status, d_st, sizeof(status)))) return rc;
+    if (status) return status;
+    if (k == 0) {
+      double stats[6];
+      // the scan workspace begins with SeriesIn[1] then SeriesHdr[1]
+      const SeriesHdr* hdr = at<const SeriesHdr>(ws, L.off_scan + align_up(sizeof(SeriesIn)));
+      if ((rc = sync_read(st, stats, hdr->stats, sizeof(stats)))) return rc;
+      W = std::fabs(static_cast<double>(F) * df * stats[4]);
+    }
+    if (launch_peak_max(st, d_z, d_fl, F, d_part, d_best) != hipSuccess) return FREDEC_EDEVICE;
+    Peak best{-1, 0.0};
+    if ((rc = sync_read(st, &best, d_best, sizeof(best)))) return rc;
+    if (best.j >= 0 && precision == FREDEC_FP32) {
+      // the float32 peaks that can be the highest (within the float32 error
+      // bound of its maximum), followed uphill in float64
+      const double zmin = best.z - 1e-4 * std::max(std::fabs(best.z), 1.0);
+      zero_count_kernel<<<1, 1, 0, st>>>(d_cnt);
+      if (hipGetLastError() != hipSuccess) return FREDEC_EDEVICE;
+      if (launch_peaks(st, d_z, d_fl, F, zmin, d_pk, d_cnt, L.peak_cap) != hipSuccess) return FREDEC_EDEVICE;
+      unsigned long long cnt = 0;
+      if ((rc = sync_read(st, &cnt, d_cnt, sizeof(cnt)))) return rc;
+      if (static_cast<int64_t>(cnt) > L.peak_cap) return FREDEC_EDEVICE;  // cannot happen: peaks are not adjacent
+      std::vector<Peak> pk(static_cast<size_t>(cnt));
+      if ((rc = sync_read(st, pk.data(), d_pk, sizeof(Peak) * pk.size()))) return rc;
+      ClimbBuffers cb{at<int64_t>(ws, L.off_idx), at<double>(ws, L.off_zat), at<uint8_t>(ws, L.off_flat),
+                      at<void>(ws, L.off_at), L.at_ws};
+      if ((rc = climb_f64(ctx, stream, t, x, w, N, base, df, F, cb, -HUGE_VAL, pk))) return rc;
+      best = Peak{-1, 0.0};
+      for (const Peak& p : pk)  // sorted by index: ties keep the lower one
+        if (best.j < 0 || p.z > best.z) best = p;
+    }
+    if (best.j < 0) {
+      fap_out[k] = 1.0;
+      zmax_out[k] = std::nan("");
+      jmax_out[k] = -1;
+    } else {
+      fap_out[k] = std::min(1.0, std::exp(log_fap(best.z, 1, W, A1)));
+      zmax_out[k] = best.z;
+      jmax_out[k] = best.j;
+    }
+  }
   return FREDEC_OK;
 }
 

@@ -61,7 +61,7 @@ int make_plan(int64_t N, const std::vector<int>& sizes, bool gn, TuplePlan& P) {
     d.nb = (C + 15) / 16;
     d.foff = P.nf;
     d.thoff = P.ntheta;
-    d.unused = 0;
+    d.frozen = 0;
     P.nf += n;
     P.ntheta += K;
   }
@@ -406,6 +406,42 @@ int ascent_launch(fredec_ctx* ctx, hipStream_t st, const AscentPlan& P, const do
   return FREDEC_OK;
 }
 
+
+// Workspace of the global-local residual periodogram: the base model's
+// refinement (one tuple of m frequencies, m > 0), then the trial tuples of one
+// chunk of the grid (cg tuples of m + 1 frequencies, the last frozen) and of
+// the shorter last chunk, which reuses the same memory.
+struct GlobalLocalLayout {
+  TuplePlan base, chunk, tail;
+  int64_t cg = 0, tail_count = 0;
+  size_t off_chunk = 0, total = 0;
+};
+
+constexpr size_t GL_CHUNK_BYTES = size_t(256) << 20;  // largest chunk workspace (below 65536 tuples)
+
+int gl_layout(int64_t N, int32_t m, int64_t F, GlobalLocalLayout& L) {
+  if (N <= 0 || m < 0 || F < 1) return FREDEC_EINVAL;
+  if (m > FREDEC_MAX_BASE) return FREDEC_ENOTSUP;
+  if (N - 3 * (static_cast<int64_t>(m) + 1) - 1 <= 0) return FREDEC_EDOF;
+  int rc;
+  if (m > 0 && (rc = make_plan(N, std::vector<int>(1, m), true, L.base))) return rc;
+  L.cg = std::min<int64_t>(F, 65536);
+  for (;;) {
+    L.chunk = TuplePlan();
+    if ((rc = make_plan(N, std::vector<int>(static_cast<size_t>(L.cg), m + 1), true, L.chunk))) return rc;
+    if (L.chunk.total <= GL_CHUNK_BYTES || L.cg <= 1024) break;
+    L.cg = std::max<int64_t>(L.cg / 2, 1024);
+  }
+  L.tail_count = F % L.cg;
+  if (L.tail_count && (rc = make_plan(N, std::vector<int>(static_cast<size_t>(L.tail_count), m + 1), true, L.tail)))
+    return rc;
+  for (TupleDesc& d : L.chunk.desc) d.frozen = 1 << m;
+  for (TupleDesc& d : L.tail.desc) d.frozen = 1 << m;
+  L.off_chunk = m > 0 ? align_up(L.base.total) : 0;
+  L.total = L.off_chunk + L.chunk.total;
+  return FREDEC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -538,6 +574,108 @@ int fredec_adjoint(fredec_ctx* ctx, void* stream, const double* t, const double*
   if (launch_tuple_state_from_l(st, static_cast<int>(n_tuples), l, D.state) != hipSuccess) return FREDEC_EDEVICE;
   if (launch_copy_f64(st, theta, D.theta, P.ntheta) != hipSuccess) return FREDEC_EDEVICE;
   return adjoint_pass(ctx, st, P, D, f, dz_df, h_out);
+}
+
+int fredec_vuong_workspace(int64_t N, const int64_t* toff, int64_t n_tuples, size_t* bytes) {
+  if (!bytes || N <= 0) return FREDEC_EINVAL;
+  std::vector<int> sizes;
+  int rc = sizes_from_toff(toff, n_tuples, sizes);
+  if (rc) return rc;
+  TuplePlan P;
+  if ((rc = make_plan(N, sizes, false, P))) return rc;
+  *bytes = P.total + align_up(sizeof(double) * static_cast<size_t>(n_tuples) * N) +
+           align_up(sizeof(double) * static_cast<size_t>(n_tuples));
+  return FREDEC_OK;
+}
+
+int fredec_vuong(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                 const double* f, const int64_t* toff, int64_t n_tuples, const double* theta, int64_t ref, void* ws,
+                 size_t ws_bytes, double* l_out, double* V_out) {
+  int rc = check_series_args(t, x, w, N);
+  if (rc) return rc;
+  if (!f || !theta || !V_out) return FREDEC_EINVAL;
+  std::vector<int> sizes;
+  if ((rc = sizes_from_toff(toff, n_tuples, sizes))) return rc;
+  if (ref < 0 || ref >= n_tuples || n_tuples > (int64_t(1) << 30)) return FREDEC_EINVAL;
+  TuplePlan P;
+  if ((rc = make_plan(N, sizes, false, P))) return rc;
+  size_t need = 0;
+  fredec_vuong_workspace(N, toff, n_tuples, &need);
+  if (!ws || ws_bytes < need) return FREDEC_ENOMEM;
+  if (!ctx) return FREDEC_EINVAL;
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TupleDev D = dev_ptrs(ws, P);
+  double* d_r = at<double>(ws, P.total);
+  double* d_l = l_out ? l_out : at<double>(ws, P.total + align_up(sizeof(double) * static_cast<size_t>(n_tuples) * N));
+  if ((rc = upload_descriptors(ctx, st, P, D, N))) return rc;
+  if ((rc = normalise(st, P, D, t, x, w, N))) return rc;
+  if (launch_tuple_vuong(st, D.desc, static_cast<int>(n_tuples), D.com, D.tau, D.xt, D.wt, f, theta,
+                         static_cast<int>(ref), d_r, d_l, V_out) != hipSuccess)
+    return FREDEC_EDEVICE;
+  return FREDEC_OK;
+}
+
+int fredec_global_local_workspace(int64_t N, int32_t m, int64_t F, size_t* bytes) {
+  if (!bytes) return FREDEC_EINVAL;
+  GlobalLocalLayout L;
+  int rc = gl_layout(N, m, F, L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return FREDEC_OK;
+}
+
+int fredec_global_local(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
+                        const double* base_f, int32_t m, double df, int64_t F, int32_t refine_steps, void* ws,
+                        size_t ws_bytes, double* z_out, uint8_t* flags_out, double* l_base_out, double* base_out) {
+  int rc = check_series_args(t, x, w, N);
+  if (rc) return rc;
+  if (!z_out || refine_steps < 0 || !std::isfinite(df) || df == 0.0) return FREDEC_EINVAL;
+  if (m > 0 && !base_f) return FREDEC_EINVAL;
+  for (int q = 0; q < m; ++q)
+    if (!std::isfinite(base_f[q])) return FREDEC_EINVAL;
+  GlobalLocalLayout L;
+  if ((rc = gl_layout(N, m, F, L))) return rc;
+  if (!ws || ws_bytes < L.total) return FREDEC_ENOMEM;
+  if (!ctx) return FREDEC_EINVAL;
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const double* fb = nullptr;
+  const double* lb = nullptr;
+  if (m > 0) {
+    // the base model refined by Gauss-Newton from base_f: l_{m,loc} and f'_loc
+    TupleDev B = dev_ptrs(ws, L.base);
+    if ((rc = upload_descriptors(ctx, st, L.base, B, N))) return rc;
+    if ((rc = normalise(st, L.base, B, t, x, w, N))) return rc;
+    if ((rc = upload(ctx, st, B.ftry, base_f, sizeof(double) * m))) return rc;
+    if ((rc = run_fit(ctx, st, L.base, B, refine_steps))) return rc;
+    TupleState s0;
+    if (hipMemcpyAsync(&s0, B.state, sizeof(s0), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return FREDEC_EDEVICE;
+    if (!s0.has_acc) return FREDEC_ESINGULAR;
+    fb = B.facc;
+    lb = &B.state[0].l_acc;
+    if (base_out && launch_copy_f64(st, fb, base_out, m) != hipSuccess) return FREDEC_EDEVICE;
+  }
+  void* cws = static_cast<char*>(ws) + L.off_chunk;
+  const TuplePlan* uploaded = nullptr;
+  for (int64_t j0 = 0; j0 < F; j0 += L.cg) {
+    const int count = static_cast<int>(std::min<int64_t>(L.cg, F - j0));
+    const TuplePlan& P = count == L.cg ? L.chunk : L.tail;
+    TupleDev D = dev_ptrs(cws, P);
+    if (uploaded != &P) {
+      if ((rc = upload_descriptors(ctx, st, P, D, N))) return rc;
+      uploaded = &P;
+    }
+    if ((rc = normalise(st, P, D, t, x, w, N))) return rc;
+    if (launch_gl_fill(st, fb, m, df, j0, count, D.ftry) != hipSuccess) return FREDEC_EDEVICE;
+    if ((rc = run_fit(ctx, st, P, D, refine_steps))) return rc;
+    if (launch_gl_finish(st, D.state, count, fb, m, df, j0, D.com, lb, z_out, flags_out,
+                         j0 == 0 ? l_base_out : nullptr) != hipSuccess)
+      return FREDEC_EDEVICE;
+  }
+  return FREDEC_OK;
 }
 
 int fredec_ascent(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,

@@ -27,7 +27,7 @@ struct TupleDesc {
   int32_t n;      // frequencies
   int32_t nb;     // 16-column blocks of its Gram
   int32_t gs;     // element stride of its Gram matrix and scratch
-  int32_t unused;
+  int32_t frozen; // bit k set: the Gauss-Newton step keeps frequency k fixed
 };
 
 struct TupleCommon {
@@ -74,6 +74,19 @@ hipError_t launch_tuple_init(hipStream_t st, int n_tuples, TupleState* state);
 hipError_t launch_tuple_state_from_l(hipStream_t st, int n_tuples, const double* l, TupleState* state);
 hipError_t launch_tuple_l0(hipStream_t st, const TupleState* state, double* l0_out);
 hipError_t launch_tuple_common(hipStream_t st, const SeriesHdr* hdr, int64_t N, TupleCommon* com);
+// Residuals r [n_tuples x N] and l = <r^2> (lres) of every tuple's fit with
+// coefficients theta, then Vuong's statistic of tuple `ref` against each (V).
+hipError_t launch_tuple_vuong(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
+                              const double* tau, const double* xt, const double* wt, const double* f,
+                              const double* theta, int ref, double* r, double* lres, double* V);
+// Global-local residual periodogram: the chunk's tuples (refined base fb
+// [device, m], then the trial frequency) and their statistic z / flags at
+// grid indices j0 .. j0 + count (lb: device l of the refined base, null for
+// m = 0; lb_out nullable).
+hipError_t launch_gl_fill(hipStream_t st, const double* fb, int m, double df, int64_t j0, int count, double* ftry);
+hipError_t launch_gl_finish(hipStream_t st, const TupleState* state, int count, const double* fb, int m, double df,
+                            int64_t j0, const TupleCommon* com, const double* lb, double* z, uint8_t* flags,
+                            double* lb_out);
 hipError_t launch_copy_f64(hipStream_t st, const double* src, double* dst, int64_t n);
 
 }  // namespace fredec

@@ -81,12 +81,64 @@ __global__ void copy_u8_kernel(const uint8_t* __restrict__ a, uint8_t* __restric
 
 unsigned grid_of(uint64_t n) { return static_cast<unsigned>((n + BLOCK - 1) / BLOCK); }
 
+// The better of two peaks: the larger z, then the lower index; j < 0 marks none.
+__device__ __forceinline__ Peak better(const Peak& a, const Peak& b) {
+  if (a.j < 0) return b;
+  if (b.j < 0) return a;
+  return (a.z > b.z || (a.z == b.z && a.j < b.j)) ? a : b;
+}
+
+// Block tree reduction of one peak per thread (BLOCK threads).
+__device__ Peak block_best(Peak p, Peak* sh) {
+  sh[threadIdx.x] = p;
+  __syncthreads();
+  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = better(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// Highest interior local maximum of z (the peak rule of peaks_kernel) within
+// each block's grid points: part[blockIdx.x] (j = -1 if none).
+__global__ void peak_max_partial_kernel(const double* __restrict__ z, const uint8_t* __restrict__ flags, int64_t F,
+                                        Peak* __restrict__ part) {
+  __shared__ Peak sh[BLOCK];
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x + 1;
+  Peak p{-1, 0.0};
+  if (j < F - 1) {
+    const double zj = z[j];
+    const bool fl = flags ? (flags[j] & ~FREDEC_FLAG_RESCORED) != 0 : false;
+    if (!fl && zj > z[j - 1] && zj >= z[j + 1]) p = Peak{j, zj};
+  }
+  const Peak b = block_best(p, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+// The best of n partial results (one block).
+__global__ void peak_max_final_kernel(const Peak* __restrict__ part, int64_t n, Peak* __restrict__ out) {
+  __shared__ Peak sh[BLOCK];
+  Peak p{-1, 0.0};
+  for (int64_t k = threadIdx.x; k < n; k += BLOCK) p = better(p, part[k]);
+  const Peak b = block_best(p, sh);
+  if (threadIdx.x == 0) *out = b;
+}
+
 }  // namespace
 
 hipError_t launch_peaks(hipStream_t st, const double* z, const uint8_t* flags, int64_t F, double zmin, Peak* out,
                         unsigned long long* count, int64_t cap) {
   if (F < 3) return hipSuccess;
   peaks_kernel<<<grid_of(static_cast<uint64_t>(F - 2)), BLOCK, 0, st>>>(z, flags, F, zmin, out, count, cap);
+  return hipGetLastError();
+}
+
+int64_t peak_max_parts(int64_t F) { return F < 3 ? 1 : static_cast<int64_t>(grid_of(static_cast<uint64_t>(F - 2))); }
+
+hipError_t launch_peak_max(hipStream_t st, const double* z, const uint8_t* flags, int64_t F, Peak* part, Peak* out) {
+  const int64_t np = peak_max_parts(F);
+  if (F >= 3) peak_max_partial_kernel<<<static_cast<unsigned>(np), BLOCK, 0, st>>>(z, flags, F, part);
+  peak_max_final_kernel<<<1, BLOCK, 0, st>>>(part, F >= 3 ? np : 0, out);
   return hipGetLastError();
 }
 

@@ -564,6 +564,19 @@ __global__ __launch_bounds__(BLOCK) void tuple_solve_kernel(const TupleDesc* __r
     for (; m + 4 <= k + 1; m += 4) h_entries<4>(G, V, H, th, K, n, k, m, ts0, gs);
     for (; m <= k; ++m) h_entries<1>(G, V, H, th, K, n, k, m, ts0, gs);
   }
+  if (d.frozen) {
+    // frozen frequencies: their J' columns leave the system (row and column
+    // of H replaced by the identity's, right-hand side 0, so their step is 0
+    // and the others solve the reduced system exactly)
+    for (int k = 0; k < n; ++k) {
+      if (!(d.frozen >> k & 1)) continue;
+      rJ[k * gs] = 0.0;
+      for (int m = 0; m < n; ++m) {
+        const int i = k > m ? k : m, j = k > m ? m : k;
+        H[(i * (i + 1) / 2 + j) * gs] = k == m ? 1.0 : 0.0;
+      }
+    }
+  }
   bool hok = chol_inplace(H, n, gs);
   double big = 0.0;
   if (hok) {
@@ -954,6 +967,148 @@ hipError_t adjoint_nf(hipStream_t st, int L, const TupleDesc* desc, const int32_
   }
 }
 
+// Residual of each tuple's least-squares fit, r_i = x~_i - Phi(t_i) theta*
+// (theta* of tuple k at theta[thoff]: c, a_1, b_1, ...), into r[k N + i],
+// and l_k = <r^2> (the weighted sum) into lres[k].  One wavefront per tuple,
+// samples over its lanes, trig recomputed per sample.
+__global__ __launch_bounds__(BLOCK) void tuple_residual_kernel(const TupleDesc* __restrict__ desc, int n_tuples,
+                                                               const TupleCommon* __restrict__ com,
+                                                               const double* __restrict__ tau,
+                                                               const double* __restrict__ xt,
+                                                               const double* __restrict__ wt,
+                                                               const double* __restrict__ f,
+                                                               const double* __restrict__ theta, double* __restrict__ r,
+                                                               double* __restrict__ lres) {
+  __shared__ double2 tab[TRIG_TAB];
+  trig_table_fill(tab);
+  __syncthreads();
+  const int k = (blockIdx.x * BLOCK + threadIdx.x) >> 6;
+  if (k >= n_tuples) return;
+  const int lane = threadIdx.x & 63;
+  const TupleDesc& d = desc[k];
+  const int n = d.n;
+  const double* fk = f + d.foff;
+  const double* th = theta + d.thoff;
+  const int64_t N = com->N;
+  double* rk = r + static_cast<int64_t>(k) * N;
+  double acc = 0.0;
+  for (int64_t i = lane; i < N; i += 64) {
+    const double ta = tau[i];
+    double ri = xt[i] - th[0];
+    for (int q = 0; q < n; ++q) {
+      double sv, cv;
+      sincos_tab(fk[q] * ta, tab, sv, cv);
+      ri -= th[1 + 2 * q] * cv + th[2 + 2 * q] * sv;
+    }
+    rk[i] = ri;
+    acc = __builtin_fma(wt[i] * ri, ri, acc);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0) lres[k] = acc;
+}
+
+// Vuong's statistic of the fit `ref` against the fit of every tuple k, for the
+// Gaussian noise model with known relative weights and a fitted scale (sample
+// i has variance l / (N w~_i)): with the per-sample log-likelihood
+// differences d_i = ll_i(ref) - ll_i(k)
+//   = -1/2 ln(l_ref / l_k) - (N w~_i / 2)(r_ref,i^2 / l_ref - r_k,i^2 / l_k),
+// V_k = sum d / (sqrt(N) omega), omega^2 = mean(d^2) - mean(d)^2.  V_ref = 0;
+// V = 0 where omega^2 <= 0 (identical fits); NaN where a fit's l is not
+// finite and positive.  One workgroup per tuple; the sums over the samples are
+// combined in a fixed tree.
+__global__ __launch_bounds__(BLOCK) void tuple_vuong_kernel(int ref, const TupleCommon* __restrict__ com,
+                                                            const double* __restrict__ wt,
+                                                            const double* __restrict__ r,
+                                                            const double* __restrict__ lres, double* __restrict__ V) {
+  __shared__ double s1[BLOCK], s2[BLOCK];
+  const int k = blockIdx.x;
+  const int64_t N = com->N;
+  const double lr = lres[ref], lk = lres[k];
+  if (k == ref) {
+    if (threadIdx.x == 0) V[k] = 0.0;
+    return;
+  }
+  if (!(lr > 0.0 && lk > 0.0 && isfinite(lr) && isfinite(lk))) {
+    if (threadIdx.x == 0) V[k] = __builtin_nan("");
+    return;
+  }
+  const double c0 = -0.5 * log(lr / lk);
+  const double hN = 0.5 * static_cast<double>(N);
+  const double ir = 1.0 / lr, ik = 1.0 / lk;
+  const double* rr = r + static_cast<int64_t>(ref) * N;
+  const double* rk = r + static_cast<int64_t>(k) * N;
+  double a1 = 0.0, a2 = 0.0;
+  for (int64_t i = threadIdx.x; i < N; i += BLOCK) {
+    const double a = rr[i], b = rk[i];
+    const double di = c0 - hN * wt[i] * (a * a * ir - b * b * ik);
+    a1 += di;
+    a2 = __builtin_fma(di, di, a2);
+  }
+  s1[threadIdx.x] = a1;
+  s2[threadIdx.x] = a2;
+  __syncthreads();
+  for (int h = BLOCK / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      s1[threadIdx.x] += s1[threadIdx.x + h];
+      s2[threadIdx.x] += s2[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double Nd = static_cast<double>(N);
+    const double m1 = s1[0] / Nd;
+    const double om2 = s2[0] / Nd - m1 * m1;
+    V[k] = om2 > 0.0 ? s1[0] / (sqrt(Nd) * sqrt(om2)) : 0.0;
+  }
+}
+
+// Global-local residual periodogram (Sect. 2): trial frequencies of a chunk of
+// the grid, f_j = (j0 + k + 1) df, appended to the refined base frequencies fb
+// (tuple k = fb_0 .. fb_{m-1}, f_j, its last member frozen).
+__global__ void gl_fill_kernel(const double* __restrict__ fb, int m, double df, int64_t j0, int count,
+                               double* __restrict__ ftry) {
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= count) return;
+  double* f = ftry + static_cast<int64_t>(k) * (m + 1);
+  for (int q = 0; q < m; ++q) f[q] = fb[q];
+  f[m] = static_cast<double>(j0 + k + 1) * df;
+}
+
+// z_j = (N - 3m - 4)/2 ln(l_b / l_j) of the chunk from the refined tuples'
+// accepted l (l_b: *lb, or each tuple's constant-model l_0 when lb is null,
+// m = 0).  f_j within MASK_WIDTH / T_eff of a refined base frequency: z = 0,
+// FLAG_MASKED; a tuple whose start point is degenerate: z = 0, FLAG_SINGULAR;
+// l <= 0: z = +inf, FLAG_PERFECT.  Block 0's first thread also writes l_b.
+__global__ void gl_finish_kernel(const TupleState* __restrict__ state, int count, const double* __restrict__ fb, int m,
+                                 double df, int64_t j0, const TupleCommon* __restrict__ com,
+                                 const double* __restrict__ lb, double* __restrict__ z, uint8_t* __restrict__ flags,
+                                 double* __restrict__ lb_out) {
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  if (k == 0 && lb_out) *lb_out = lb ? *lb : state[0].l0;
+  if (k >= count) return;
+  const double T = com->T_eff;
+  const double f = static_cast<double>(j0 + k + 1) * df;
+  const double NH = static_cast<double>(com->N - 3 * (m + 1) - 1);
+  bool masked = false;
+  for (int q = 0; q < m; ++q) masked |= fabs(f - fb[q]) * T < MASK_WIDTH;
+  const TupleState& S = state[k];
+  double zj = 0.0;
+  uint8_t fl = 0;
+  if (masked) {
+    fl = FREDEC_FLAG_MASKED;
+  } else if (!S.has_acc) {
+    fl = FREDEC_FLAG_SINGULAR;
+  } else if (!(S.l_acc > 0.0)) {
+    zj = __builtin_inf();
+    fl = FREDEC_FLAG_PERFECT;
+  } else {
+    zj = 0.5 * NH * log((lb ? *lb : S.l0) / S.l_acc);
+  }
+  z[j0 + k] = zj;
+  if (flags) flags[j0 + k] = fl;
+}
+
 }  // namespace
 
 bool tuple_lanes_supported(int n, int mode) { return mode == TUPLE_FWD && n >= 1 && n <= LANES_MAX_N; }
@@ -1087,8 +1242,30 @@ hipError_t launch_tuple_common(hipStream_t st, const SeriesHdr* hdr, int64_t N, 
   return hipGetLastError();
 }
 
+hipError_t launch_gl_fill(hipStream_t st, const double* fb, int m, double df, int64_t j0, int count, double* ftry) {
+  gl_fill_kernel<<<(count + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(fb, m, df, j0, count, ftry);
+  return hipGetLastError();
+}
+
+hipError_t launch_gl_finish(hipStream_t st, const TupleState* state, int count, const double* fb, int m, double df,
+                            int64_t j0, const TupleCommon* com, const double* lb, double* z, uint8_t* flags,
+                            double* lb_out) {
+  gl_finish_kernel<<<(count + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(state, count, fb, m, df, j0, com, lb, z, flags,
+                                                                  lb_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_tuple_l0(hipStream_t st, const TupleState* state, double* l0_out) {
   tuple_l0_kernel<<<1, 64, 0, st>>>(state, l0_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_tuple_vuong(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
+                              const double* tau, const double* xt, const double* wt, const double* f,
+                              const double* theta, int ref, double* r, double* lres, double* V) {
+  if (n_tuples <= 0) return hipSuccess;
+  tuple_residual_kernel<<<(n_tuples + 3) / 4, BLOCK, 0, st>>>(desc, n_tuples, com, tau, xt, wt, f, theta, r, lres);
+  tuple_vuong_kernel<<<n_tuples, BLOCK, 0, st>>>(ref, com, wt, r, lres, V);
   return hipGetLastError();
 }
 

@@ -60,6 +60,11 @@ _SIGS = {
                                c_p]),
     "fredec_ascent": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_i64, c_i32, c_d, c_i32, c_p, c_sz, c_p,
                               c_p, c_p]),
+    "fredec_vuong_workspace": (c_i32, [c_i64, c_p, c_i64, c_szp]),
+    "fredec_vuong": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_i64, c_p, c_i64, c_p, c_sz, c_p, c_p]),
+    "fredec_global_local_workspace": (c_i32, [c_i64, c_i32, c_i64, c_szp]),
+    "fredec_global_local": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_i32, c_d, c_i64, c_i32, c_p, c_sz, c_p, c_p,
+                                    c_p, c_p]),
     "fredec_zcrit": (c_i32, [c_d, c_i32, c_d, c_p, c_p]),
     "fredec_peaks_workspace": (c_i32, [c_i64, c_szp]),
     "fredec_peaks": (c_i32, [c_p, c_p, c_p, c_p, c_i64, c_d, c_p, c_sz, c_i64, c_p, c_p, c_p]),
@@ -70,6 +75,9 @@ _SIGS = {
                               c_sz, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
     "fredec_scan_static": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_i32, c_d, c_i64, c_i32, c_p, c_p, c_p,
                                    c_p]),
+    "fredec_residual_fap_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_szp]),
+    "fredec_residual_fap": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_i32, c_d, c_i64, c_d, c_i32, c_p,
+                                    c_sz, c_p, c_p, c_p]),
     "fredec_scan_at_workspace": (c_i32, [c_i64, c_i32, c_szp]),
     "fredec_scan_at": (c_i32, [c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_i32, c_d, c_p, c_i64, c_p, c_sz, c_p, c_p]),
     "fredec_plan_destroy": (None, [c_p]),
@@ -498,6 +506,64 @@ class Context:
         n = min(nf.value, cap)
         return idx[:n].copy(), zp[:n].copy()
 
+    def global_local(self, t, x, w, base_f, df, F, refine_steps=8):
+        """Global-local residual periodogram: device tensors (z, flags, l_b,
+        refined base frequencies)."""
+        torch = _torch()
+        t, x, w = self._f64(t), self._f64(x), self._f64(w)
+        base_f = np.ascontiguousarray(np.atleast_1d(np.asarray(base_f, np.float64)))
+        m = base_f.size
+        need = ctypes.c_size_t()
+        _check(load().fredec_global_local_workspace(t.numel(), m, int(F), ctypes.byref(need)),
+               "fredec_global_local_workspace")
+        ws = self._workspace(need.value)
+        z, fl = self._empty(F, torch.float64), self._empty(F, torch.uint8)
+        lb, fb = self._empty(1, torch.float64), self._empty(max(m, 1), torch.float64)
+        _check(load().fredec_global_local(self.handle, _stream(self.device), _ptr(t), _ptr(x), _ptr(w), t.numel(),
+                                          _ptr(base_f) if m else None, m, float(df), int(F), int(refine_steps),
+                                          _ptr(ws), need.value, _ptr(z), _ptr(fl), _ptr(lb), _ptr(fb) if m else None),
+               "fredec_global_local")
+        return z, fl, lb, fb[:m]
+
+    def vuong(self, t, x, w, solutions, ref):
+        """Vuong's statistic of solution `ref` against every solution (a list
+        of frequency lists), at the least-squares fits of their frequencies:
+        device tensors (V, l)."""
+        torch = _torch()
+        t, x, w = self._f64(t), self._f64(x), self._f64(w)
+        flat, toff = _ragged(solutions)
+        nt = toff.size - 1
+        f = self._f64(flat[:toff[-1]])
+        _, _, theta, _, _, _ = self.grad(t, x, w, f, toff, want_grad=False)
+        need = ctypes.c_size_t()
+        _check(load().fredec_vuong_workspace(t.numel(), _ptr(toff), nt, ctypes.byref(need)), "fredec_vuong_workspace")
+        ws = self._workspace(need.value)
+        V = self._empty(nt, torch.float64)
+        l = self._empty(nt, torch.float64)
+        _check(load().fredec_vuong(self.handle, _stream(self.device), _ptr(t), _ptr(x), _ptr(w), t.numel(), _ptr(f),
+                                   _ptr(toff), nt, _ptr(theta), int(ref), _ptr(ws), need.value, _ptr(l), _ptr(V)),
+               "fredec_vuong")
+        return V, l
+
+    def residual_fap(self, t, x, w, solutions, df, F, A1=1.0, precision=FP64):
+        """Residual single-frequency FAP of each solution (a list of frequency
+        lists): host arrays (fap, z_max, j_max)."""
+        t, x, w = self._f64(t), self._f64(x), self._f64(w)
+        flat, off = _ragged(solutions)
+        n_sol = off.size - 1
+        m_max = int(np.max(np.diff(off))) if n_sol else 0
+        need = ctypes.c_size_t()
+        _check(load().fredec_residual_fap_workspace(t.numel(), int(F), m_max, precision, ctypes.byref(need)),
+               "fredec_residual_fap_workspace")
+        ws = self._workspace(need.value)
+        fap, zmax = np.zeros(n_sol), np.zeros(n_sol)
+        jmax = np.zeros(n_sol, np.int64)
+        _check(load().fredec_residual_fap(self.handle, _stream(self.device), _ptr(t), _ptr(x), _ptr(w), t.numel(),
+                                          _ptr(flat), _ptr(off), n_sol, float(df), int(F), float(A1), precision,
+                                          _ptr(ws), need.value, _ptr(fap), _ptr(zmax), _ptr(jmax)),
+               "fredec_residual_fap")
+        return fap, zmax, jmax
+
     def cascade(self, ltab, n, N, zcrit):
         """Phase 3: (survive, maximal, G) device tensors of length 2^n."""
         torch = _torch()
@@ -533,6 +599,15 @@ class Context:
         return {"pool": pool[:n_pool.value].copy(), "pool_z": pz[:n_pool.value].copy(),
                 "base": base[:n_base.value].copy(), "n_scans": n_scans.value, "truncated": trunc.value,
                 "W": W.value}
+
+
+def _ragged(lists):
+    """Concatenated float64 values and int64 offsets of a list of sequences."""
+    vals = [np.atleast_1d(np.asarray(v, np.float64)) for v in lists]
+    off = np.zeros(len(vals) + 1, np.int64)
+    off[1:] = np.cumsum([v.size for v in vals])
+    flat = np.ascontiguousarray(np.concatenate(vals) if off[-1] else np.zeros(1), np.float64)
+    return flat, off
 
 
 def zcrit(W, n, fap, A=None):
