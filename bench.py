@@ -124,8 +124,14 @@ def scan_roofline(ms_list, N, F, t_meas, fp32, traffic=None):
         slots += v * P
         mflops += mf * P
     achieved = slots / t_meas
+    extra = {}
+    if fp32:
+        # the slot model fixed for the float32 form before the first measurement: float64 phase (3),
+        # hardware sin and cos at quarter rate (2 x 4), double angle (3) = 14 per pair, every sum on
+        # the matrix cores
+        extra["frac_fixed_14_slot_model"] = 14.0 * P * len(ms_list) / PEAK_VALU_OPS / t_meas
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12, "unit": "Tops/s",
-            "frac": t_roof / t_meas, "traffic": traffic,
+            "frac": t_roof / t_meas, **extra, "traffic": traffic,
             "kernel": " + ".join(f"{k} x{n}" for k, n in sorted(kerns.items())),
             "kernel_ms": t_meas * 1e3, "launches": len(ms_list),
             "mfma_frac": (mflops / t_meas / PEAK_F16_MFMA) if mflops else 0.0,

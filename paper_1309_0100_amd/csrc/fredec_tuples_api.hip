@@ -244,12 +244,28 @@ int adjoint_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const Tupl
   });
 }
 
+// The first pass of a batch of pool subsets evaluated at the pool
+// frequencies: their Gram matrices are gathered from the pool's Gram.
+struct PoolPass {
+  const double* pool_gram;  // packed lower Gram of the whole pool (element stride 1)
+  int n_pool;
+};
+
 // Forward evaluation (and optional Gauss-Newton refinement) of every tuple.
-int run_fit(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, int refine_steps) {
+int run_fit(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, int refine_steps,
+            const PoolPass* first = nullptr) {
   const int nt = static_cast<int>(P.desc.size());
   const int mode = refine_steps > 0 ? TUPLE_GN : TUPLE_FWD;
   for (int it = 0; it <= refine_steps; ++it) {
-    int rc = gram_pass(ctx, st, P, D, mode);
+    int rc = FREDEC_OK;
+    if (it == 0 && first) {
+      ProfScope prof(ctx, st, FREDEC_PROF_GRAM);
+      if (launch_tuple_gather(st, D.desc, D.order, nt, D.members, first->pool_gram, first->n_pool, mode, D.gram) !=
+          hipSuccess)
+        return FREDEC_EDEVICE;
+    } else {
+      rc = gram_pass(ctx, st, P, D, mode);
+    }
     if (rc) return rc;
     ProfScope prof(ctx, st, FREDEC_PROF_SOLVE);
     if (launch_tuple_solve(st, D.desc, D.order, nt, D.com, D.gram, D.scr, D.ftry, D.facc, D.step, D.theta, D.state,
@@ -299,7 +315,24 @@ struct SubsetPlan : fredec_plan {
   int32_t n_pool = 0, refine_steps = 0;
   std::vector<double> f0;   // starting frequencies of the members, in bit order
   std::vector<int8_t> mem;  // pool index of each member
+  // the whole pool as one tuple, whose Gram gives every subset's first-pass
+  // Gram (used when the pool fits the model: N - 3 n_pool - 1 > 0)
+  bool use_pool = false;
+  TuplePlan Pp;
+  size_t off_pool = 0;
+  std::vector<double> pool;
 };
+
+// Workspace of a batch of pool subsets: the subsets' plan, then the pool's.
+int subset_layout(int64_t N, int32_t n_pool, const std::vector<int>& sizes, bool gn, TuplePlan& T, TuplePlan& Pp,
+                  bool& use_pool, size_t& off_pool, size_t& total) {
+  int rc = make_plan(N, sizes, gn, T);
+  if (rc) return rc;
+  use_pool = make_plan(N, std::vector<int>(1, n_pool), gn, Pp) == FREDEC_OK;
+  off_pool = align_up(T.total);
+  total = use_pool ? off_pool + Pp.total : T.total;
+  return FREDEC_OK;
+}
 
 int subset_build(int64_t N, const double* pool, int32_t n_pool, const uint64_t* masks, int64_t n_tuples,
                  int32_t refine_steps, int32_t precision, void* ws, size_t ws_bytes, SubsetPlan& P) {
@@ -310,13 +343,16 @@ int subset_build(int64_t N, const double* pool, int32_t n_pool, const uint64_t* 
   if ((rc = sizes_from_masks(n_pool, masks, n_tuples, sizes))) return rc;
   for (int k = 0; k < n_pool; ++k)
     if (!std::isfinite(pool[k])) return FREDEC_EINVAL;
-  if ((rc = make_plan(N, sizes, refine_steps > 0, P.T))) return rc;
+  size_t total = 0;
+  if ((rc = subset_layout(N, n_pool, sizes, refine_steps > 0, P.T, P.Pp, P.use_pool, P.off_pool, total))) return rc;
   P.T.precision = precision;
-  if (!ws || ws_bytes < P.T.total) return FREDEC_ENOMEM;
+  P.Pp.precision = precision;
+  if (!ws || ws_bytes < total) return FREDEC_ENOMEM;
   P.ws = ws;
   P.ws_bytes = ws_bytes;
   P.N = N;
   P.n_pool = n_pool;
+  P.pool.assign(pool, pool + n_pool);
   P.refine_steps = refine_steps;
   P.f0.resize(P.T.nf);
   P.mem.resize(P.T.nf);
@@ -338,7 +374,11 @@ int subset_upload(fredec_ctx* ctx, hipStream_t st, const SubsetPlan& P) {
   int rc;
   if ((rc = upload_descriptors(ctx, st, P.T, D, P.N))) return rc;
   if ((rc = upload(ctx, st, D.f0, P.f0.data(), sizeof(double) * P.T.nf))) return rc;
-  return upload(ctx, st, D.members, P.mem.data(), P.T.nf);
+  if ((rc = upload(ctx, st, D.members, P.mem.data(), P.T.nf))) return rc;
+  if (!P.use_pool) return FREDEC_OK;
+  const TupleDev Dp = dev_ptrs(static_cast<char*>(P.ws) + P.off_pool, P.Pp);
+  if ((rc = upload_descriptors(ctx, st, P.Pp, Dp, P.N))) return rc;
+  return upload(ctx, st, Dp.f0, P.pool.data(), sizeof(double) * P.n_pool);
 }
 
 // Kernels only (capturable).
@@ -348,7 +388,16 @@ int subset_launch(fredec_ctx* ctx, hipStream_t st, const SubsetPlan& P, const do
   int rc;
   if ((rc = normalise(st, P.T, D, t, x, w, P.N))) return rc;
   if (launch_copy_f64(st, D.f0, D.ftry, P.T.nf) != hipSuccess) return FREDEC_EDEVICE;
-  if ((rc = run_fit(ctx, st, P.T, D, P.refine_steps))) return rc;
+  PoolPass first{nullptr, P.n_pool};
+  if (P.use_pool) {
+    // the Gram of the whole pool at its frequencies (one tuple)
+    const TupleDev Dp = dev_ptrs(static_cast<char*>(P.ws) + P.off_pool, P.Pp);
+    if ((rc = normalise(st, P.Pp, Dp, t, x, w, P.N))) return rc;
+    if (launch_copy_f64(st, Dp.f0, Dp.ftry, P.n_pool) != hipSuccess) return FREDEC_EDEVICE;
+    if ((rc = gram_pass(ctx, st, P.Pp, Dp, P.refine_steps > 0 ? TUPLE_GN : TUPLE_FWD))) return rc;
+    first.pool_gram = Dp.gram;
+  }
+  if ((rc = run_fit(ctx, st, P.T, D, P.refine_steps, P.use_pool ? &first : nullptr))) return rc;
   if (launch_tuple_finish(st, D.desc, static_cast<int>(P.T.desc.size()), D.com, D.state, D.facc, l_out, z_out,
                           flags_out, f_out, D.members, P.n_pool) != hipSuccess)
     return FREDEC_EDEVICE;
@@ -452,9 +501,11 @@ int fredec_tuples_workspace(int64_t N, int32_t n_pool, const uint64_t* masks, in
   std::vector<int> sizes;
   int rc = sizes_from_masks(n_pool, masks, n_tuples, sizes);
   if (rc) return rc;
-  TuplePlan P;
-  if ((rc = make_plan(N, sizes, refine_steps > 0, P))) return rc;
-  *bytes = P.total;
+  TuplePlan T, Pp;
+  bool use_pool = false;
+  size_t off_pool = 0, total = 0;
+  if ((rc = subset_layout(N, n_pool, sizes, refine_steps > 0, T, Pp, use_pool, off_pool, total))) return rc;
+  *bytes = total;
   return FREDEC_OK;
 }
 
@@ -490,6 +541,7 @@ int fredec_tuples_plan(fredec_ctx* ctx, void* stream, int64_t N, const double* p
     if (!rc) rc = upload_wait(ctx);
     std::vector<double>().swap(P->f0);
     std::vector<int8_t>().swap(P->mem);
+    std::vector<double>().swap(P->pool);
   }
   if (rc) {
     delete P;

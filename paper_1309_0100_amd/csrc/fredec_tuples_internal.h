@@ -79,6 +79,11 @@ hipError_t launch_tuple_common(hipStream_t st, const SeriesHdr* hdr, int64_t N, 
 hipError_t launch_tuple_vuong(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
                               const double* tau, const double* xt, const double* wt, const double* f,
                               const double* theta, int ref, double* r, double* lres, double* V);
+// Gram matrices of the pool subsets order[0 .. n_tuples) at the pool
+// frequencies, gathered from the pool's Gram (packed lower, its own column
+// order, element stride 1).
+hipError_t launch_tuple_gather(hipStream_t st, const TupleDesc* desc, const int32_t* order, int n_tuples,
+                               const int8_t* members, const double* pool_gram, int n_pool, int mode, double* gram);
 // Global-local residual periodogram: the chunk's tuples (refined base fb
 // [device, m], then the trial frequency) and their statistic z / flags at
 // grid indices j0 .. j0 + count (lb: device l of the refined base, null for

@@ -1109,6 +1109,51 @@ __global__ void gl_finish_kernel(const TupleState* __restrict__ state, int count
   if (flags) flags[j0 + k] = fl;
 }
 
+// Gram matrices of pool subsets at the pool frequencies as sub-blocks of the
+// pool's own Gram (Sect. 3: the normal matrix of a subset is the block of the
+// pool's normal matrix on the subset's columns).  pg: the pool's packed lower
+// Gram in its column order (1, cos/sin of each pool frequency, x~, then in the
+// Gauss-Newton mode t' cos/sin of each); tuple ti = order[o] with members
+// members[foff ..] (pool indices, increasing) receives the entries of its
+// columns in its own order.  One thread per tuple, in launch order (the
+// interleaved storage then makes the writes of a group coalesce); the pool
+// Gram is staged in LDS.
+__global__ __launch_bounds__(BLOCK) void tuple_gather_kernel(const TupleDesc* __restrict__ desc,
+                                                             const int32_t* __restrict__ order, int n_tuples,
+                                                             const int8_t* __restrict__ members,
+                                                             const double* __restrict__ pg, int n_pool, int mode,
+                                                             double* __restrict__ gram) {
+  extern __shared__ double spg[];
+  const bool gn = mode == TUPLE_GN;
+  const int CP = gn ? 4 * n_pool + 2 : 2 * n_pool + 2;
+  const int npg = CP * (CP + 1) / 2;
+  for (int e = threadIdx.x; e < npg; e += BLOCK) spg[e] = pg[e];
+  __syncthreads();
+  const int o = blockIdx.x * BLOCK + threadIdx.x;
+  if (o >= n_tuples) return;
+  const TupleDesc& d = desc[order[o]];
+  const int n = d.n;
+  const int C = gn ? 4 * n + 2 : 2 * n + 2;
+  const int K = 2 * n + 1;
+  const int8_t* mem = members + d.foff;
+  double* G = gram + d.goff;
+  const int64_t gs = d.gs;
+  auto pcol = [&](int c) {
+    if (c == 0) return 0;
+    if (c < K) return 1 + 2 * mem[(c - 1) >> 1] + ((c - 1) & 1);
+    if (c == K) return 2 * n_pool + 1;
+    return 2 * n_pool + 2 + 2 * mem[(c - K - 1) >> 1] + ((c - K - 1) & 1);
+  };
+  for (int r = 0; r < C; ++r) {
+    const int pr = pcol(r);
+    for (int c = 0; c <= r; ++c) {
+      const int pc = pcol(c);
+      const int a = pr > pc ? pr : pc, b = pr > pc ? pc : pr;
+      G[(r * (r + 1) / 2 + c) * gs] = spg[a * (a + 1) / 2 + b];
+    }
+  }
+}
+
 }  // namespace
 
 bool tuple_lanes_supported(int n, int mode) { return mode == TUPLE_FWD && n >= 1 && n <= LANES_MAX_N; }
@@ -1239,6 +1284,16 @@ hipError_t launch_tuple_init(hipStream_t st, int n_tuples, TupleState* state) {
 
 hipError_t launch_tuple_common(hipStream_t st, const SeriesHdr* hdr, int64_t N, TupleCommon* com) {
   tuple_common_kernel<<<1, 64, 0, st>>>(hdr, N, com);
+  return hipGetLastError();
+}
+
+hipError_t launch_tuple_gather(hipStream_t st, const TupleDesc* desc, const int32_t* order, int n_tuples,
+                               const int8_t* members, const double* pool_gram, int n_pool, int mode, double* gram) {
+  if (n_tuples <= 0) return hipSuccess;
+  const int CP = mode == TUPLE_GN ? 4 * n_pool + 2 : 2 * n_pool + 2;
+  const size_t lds = sizeof(double) * static_cast<size_t>(CP) * (CP + 1) / 2;
+  tuple_gather_kernel<<<(n_tuples + BLOCK - 1) / BLOCK, BLOCK, lds, st>>>(desc, order, n_tuples, members, pool_gram,
+                                                                          n_pool, mode, gram);
   return hipGetLastError();
 }
 
