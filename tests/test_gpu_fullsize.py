@@ -121,17 +121,27 @@ def test_tuple_ascent_full_size(ctx):
         assert _rel(za[k], zr) <= 1e-8
 
 
-@pytest.mark.parametrize("prec", [1], ids=["fp32"])
-def test_full_pipeline_full_size(ctx, prec):
-    """N = 10^4 over 20000 d, F = 4e6, pool capped at 16 (65535 refined
-    subtuples), Phase 3.  Checks: refined l of sampled subsets against the
-    oracle's Gauss-Newton refinement; Phase 3 survival of sampled subsets
-    against the oracle's rule on the same l-table; maximal sets consistent
-    with the survival table; solutions ordered as the method prescribes."""
-    from paper_1309_0100_amd import fredec as F, pipeline
+@pytest.fixture(scope="module")
+def full_runs(ctx):
+    """The full pass (N = 10^4 over 20000 d, F = 4e6, pool cap 16, 65535 subsets
+    refined by 8 Gauss-Newton steps, Phase 3) in both precisions."""
+    from paper_1309_0100_amd import pipeline
     s = synth.full()
-    print(f"case: full pipeline prec={prec}", flush=True)
-    res = pipeline.run(ctx, s.t, s.x, s.w, s.df, s.F, pool_cap=16, refine_steps=8, precision=prec)
+    runs = {}
+    for prec in (0, 1):
+        print(f"case: full pipeline prec={prec}", flush=True)
+        runs[prec] = pipeline.run(ctx, s.t, s.x, s.w, s.df, s.F, pool_cap=16, refine_steps=8, precision=prec)
+    return s, runs
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_full_pipeline_full_size(ctx, full_runs, prec):
+    """Refined l of sampled subsets against the oracle's Gauss-Newton
+    refinement; Phase 3 on the returned l-table against the oracle's survival
+    rule and inclusion-maximal sets; solutions ordered by size, then G."""
+    from paper_1309_0100_amd import fredec as F
+    s, runs = full_runs
+    res = runs[prec]
     n = res.pool.size
     assert 1 <= n <= 16 and res.n_scans >= 1
     assert np.all(np.diff(res.pool) > 0) or n == 1
@@ -148,17 +158,151 @@ def test_full_pipeline_full_size(ctx, prec):
             continue
         assert abs(lt[S] - r.l) <= 1e-9 * r.l, (S, lt[S], r.l)
     zc = F.zcrit(res.W, n, 0.05)
-    for S in rng.integers(1, 1 << n, size=300).tolist() + [int(m) for m in np.flatnonzero(res.survive)[:50]]:
-        assert bool(res.survive[S]) == O.survives(lt, int(S), s.N, zc), S
-    # maximal = surviving with no surviving strict superset (host check on the GPU table)
-    surv = res.survive.astype(bool)
-    sup = surv.copy()
-    for b in range(n):
-        for S in range(1 << n):
-            if not S >> b & 1:
-                sup[S] |= sup[S | (1 << b)]
-    maximal = [S for S in range(1, 1 << n) if surv[S] and not any(
-        sup[S | (1 << b)] for b in range(n) if not S >> b & 1)]
+    assert np.allclose(zc[1:], O.zcrit_table(n, res.W, 0.05)[1:], rtol=1e-12, atol=0)
+    surv_ref = O.survive_table(lt, n, s.N, zc)
+    assert np.array_equal(res.survive.astype(bool), surv_ref)
+    maximal = O.maximal_sets(surv_ref, n)
     assert sorted(sol.mask for sol in res.solutions) == maximal
     keys = [(bin(sol.mask).count("1"), sol.G, sol.mask) for sol in res.solutions]
     assert keys == sorted(keys)
+    for sol in res.solutions:
+        assert abs(sol.G - O.goodness(lt[sol.mask], s.N, bin(sol.mask).count("1"))) <= 1e-14 * sol.G
+
+
+def test_full_pipeline_forms_agree(full_runs):
+    """The float32 form takes every decision of the float64 form: same scans,
+    base, pool, l-table (Phase 2 is float64 in both), survivors and
+    solutions."""
+    _, runs = full_runs
+    a, b = runs[0], runs[1]
+    assert a.n_scans == b.n_scans and a.truncated == b.truncated
+    assert np.array_equal(a.base, b.base)
+    assert np.array_equal(a.pool, b.pool)
+    assert np.allclose(a.pool_z, b.pool_z, rtol=1e-12, atol=0)
+    assert np.array_equal(a.ltab, b.ltab, equal_nan=True)
+    assert np.array_equal(a.survive, b.survive)
+    assert [s.mask for s in a.solutions] == [s.mask for s in b.solutions]
+
+
+def test_full_phase1_decisions(ctx, full_runs):
+    """Every Phase 1 decision of the full pass checked against the oracle at
+    the grid points it rests on: in each scan (base = the SLICK frequencies
+    chosen before it) the oracle's z at the GPU's 12 highest peaks and their
+    neighbours (values to 1e-9, the peak property, the argmax among them,
+    which must be the next SLICK frequency while its z exceeds the FAP_0
+    threshold and end the phase otherwise); every pool member is a peak of
+    some scan with the recorded z and passes the FAP_1 and half-height rules
+    by the oracle's values."""
+    import torch
+    from paper_1309_0100_amd import fredec as F
+    s, runs = full_runs
+    res = runs[0]
+    nrm = O.normalize(s.t, s.x, s.w)
+    W = s.F * s.df * nrm.T_eff
+    assert abs(res.W - W) <= 1e-9 * W
+    zc0, zc1 = O.zcrit(1, W, 0.05), O.zcrit(1, W, 0.1)
+    pool_idx = np.rint(res.pool / s.df).astype(np.int64) - 1
+    assert np.array_equal((pool_idx + 1) * s.df, res.pool)
+    found = np.zeros(res.pool.size, bool)
+    for k in range(res.n_scans):
+        base = res.base[:k]
+        print(f"case: full phase 1 scan {k}", flush=True)
+        z, fl, _, st = ctx.scan_series(s.t, s.x, s.w, base, s.df, s.F, precision=F.FP64)
+        assert int(st.item()) == 0
+        idx, zp = ctx.peaks(z, fl, 0.0, cap=s.F)
+        top = idx[np.lexsort((idx, -zp))[:12]]
+        idxset = set(idx.tolist())
+        pts = np.unique(np.concatenate([top - 1, top, top + 1, pool_idx]))
+        pts = pts[(pts >= 0) & (pts < s.F)]
+        sel = torch.as_tensor(pts, device=z.device)
+        zg = z.index_select(0, sel).cpu().numpy()
+        fg = fl.index_select(0, sel).cpu().numpy()
+        r = O.scan(s.t, s.x, s.w, base, s.df, s.F, idx=pts)
+        assert np.array_equal(fg, r.flags), k
+        good = r.flags == 0
+        assert np.all(_rel(zg[good], r.z[good]) <= _tol(0, r.rho[good])), k
+        zo = dict(zip(pts.tolist(), r.z.tolist()))
+        for j in top:
+            assert zo[j] > zo[j - 1] and zo[j] >= zo[j + 1], (k, j)
+        jmax = int(top[0])
+        assert all(zo[jmax] > zo[int(j)] or (zo[jmax] == zo[int(j)] and jmax < j) for j in top[1:]), k
+        if k < res.base.size:
+            assert res.base[k] == (jmax + 1) * s.df, k
+            assert zo[jmax] > zc0
+        else:
+            assert zo[jmax] <= zc0
+        zg_at = dict(zip(pts.tolist(), zg.tolist()))
+        for q, j in enumerate(pool_idx.tolist()):
+            if found[q] or j not in idxset:
+                continue
+            if abs(zg_at[j] - res.pool_z[q]) <= 1e-12 * max(1.0, res.pool_z[q]):
+                found[q] = True
+                assert _rel(zo[j], res.pool_z[q]) <= 1e-9
+                assert zo[j] > zc1 and zo[j] >= 0.5 * zo[jmax] * (1 - 1e-12)
+    assert found.all(), res.pool[~found]
+
+
+def test_phase1_reduced_full_shape_matches_oracle(ctx):
+    """Phase 1 and Phase 3 of a reduced series of the full-pass shape (N =
+    2000 over 4000 d, F = 2e5 to 5 c/d) against the oracle's own run of both
+    phases (tests/golden/phase1_full_reduced.json, written by
+    make_phase1_golden.py): the SLICK base, the pool and the number of scans
+    bit-exact in both precisions; pool z to 1e-9; the Phase 3 survivors and
+    maximal sets on the GPU's fixed-frequency l-table bit-exact."""
+    import json
+    import os
+    from paper_1309_0100_amd import fredec as F
+    path = os.path.join(os.path.dirname(__file__), "golden", "phase1_full_reduced.json")
+    with open(path) as fh:
+        g = json.load(fh)
+    c = g["case"]
+    s = synth.full(N=c["N"], span=c["span"], F=c["F"], fmax=c["fmax"])
+    for prec in (F.FP64, F.FP32):
+        print(f"case: reduced full-shape phase 1 prec={prec}", flush=True)
+        p1 = ctx.phase1(s.t, s.x, s.w, s.df, s.F, pool_cap=16, precision=prec)
+        assert p1["n_scans"] == g["n_scans"] and p1["truncated"] == g["truncated"]
+        assert np.array_equal(p1["base"], (np.asarray(g["base_index"]) + 1) * s.df)
+        assert np.array_equal(p1["pool"], (np.asarray(g["pool_index"]) + 1) * s.df)
+        assert np.all(_rel(p1["pool_z"], np.asarray(g["pool_z"])) <= 1e-9)
+        assert abs(p1["W"] - g["W"]) <= 1e-12 * g["W"]
+    import torch
+    n = len(g["pool"])
+    l0 = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    l, _, _, fl = ctx.tuples(s.t, s.x, s.w, np.asarray(g["pool"]), refine_steps=0, l0_out=l0)
+    lt = np.concatenate([l0.cpu().numpy(), l.cpu().numpy()])
+    degenerate = np.concatenate([[False], (fl.cpu().numpy() & F.FLAG_DEGENERATE) != 0])
+    for key, ref in g["ltab_sample"].items():
+        S = int(key)
+        if not np.isfinite(ref):
+            assert degenerate[S]
+            continue
+        assert not degenerate[S] and abs(lt[S] - ref) <= 1e-9 * ref, (S, lt[S], ref)
+    zc = F.zcrit(g["W"], n, 0.05)
+    surv, maxi, _ = (a.cpu().numpy() for a in ctx.cascade(lt, n, s.N, zc))
+    bits = np.unpackbits(np.frombuffer(bytes.fromhex(g["survive_bits"]), np.uint8), bitorder="little")
+    assert np.array_equal(surv.astype(np.uint8), bits[:1 << n])
+    assert sorted(np.flatnonzero(maxi).tolist()) == g["maximal"]
+
+
+def test_residual_scan_fp32_peaks(ctx):
+    """The float32 form's 50 highest periodogram peaks of the residual scan
+    (N = 2000, m = 4, F = 10^6) are the float64 form's, each a peak of the
+    oracle's values with z to 1e-6."""
+    import torch
+    from paper_1309_0100_amd import fredec as F
+    s = synth.residual()
+    print("case: residual full size fp32 peaks", flush=True)
+    tops = {}
+    for prec in (F.FP64, F.FP32):
+        z, fl, _, _ = ctx.scan_series(s.t, s.x, s.w, s.base_f, s.df, s.F, precision=prec)
+        idx, zp = ctx.peaks(z, fl, 0.0, cap=s.F)
+        o = np.lexsort((idx, -zp))[:50]
+        tops[prec] = (idx[o], zp[o])
+    assert np.array_equal(np.sort(tops[F.FP64][0]), np.sort(tops[F.FP32][0]))
+    j, z32 = tops[F.FP32]
+    pts = np.unique(np.concatenate([j - 1, j, j + 1]))
+    r = O.scan(s.t, s.x, s.w, s.base_f, s.df, s.F, idx=pts)
+    zo = dict(zip(pts.tolist(), r.z.tolist()))
+    for jj, zz in zip(j.tolist(), z32.tolist()):
+        assert zo[jj] > zo[jj - 1] and zo[jj] >= zo[jj + 1]
+        assert abs(zz - zo[jj]) / max(1.0, zo[jj]) <= 1e-6
