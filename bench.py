@@ -216,12 +216,14 @@ def full_leg(ctx, s, dev, fp32, steps, warmup):
     roof = scan_roofline(list(range(res.n_scans)), s.N, s.F, t_scan, fp32,
                          traffic_bytes("full_fp32_phase1_scans") if fp32 else None)
     # Phase 2 Gauss-Newton Gram passes (float64 matrix cores): C(C+1) flops per (tuple, sample) and pass,
-    # C = 4n + 2 columns; passes per pass of the method = the timed Gram groups per step
+    # C = 4n + 2 columns, over the 8 per-subset passes of the 9 (the first is gathered from the pool's
+    # Gram: its two timed groups, the pool Gram and the gather, take under a millisecond)
     from math import comb
     C = np.array([4 * k + 2 for k in range(1, n + 1)], np.float64)
     cnt = np.array([comb(n, k) for k in range(1, n + 1)], np.float64)
     gram_flops = float(np.sum(cnt * C * (C + 1))) * s.N
-    t_gram, n_gram = per["gram"]
+    t_gram = per["gram"][0]
+    n_gram = 8
     leg = {"seconds_per_pass": sec, "points_per_s": s.N * s.F * res.n_scans / sec,
            "tuples_per_s": ((1 << n) - 1) / sec, "n_scans": res.n_scans, "pool_size": n,
            "n_solutions": len(res.solutions), "truncated": res.truncated,
@@ -234,7 +236,8 @@ def full_leg(ctx, s, dev, fp32, steps, warmup):
                                     "frac": gram_flops * n_gram / t_gram / PEAK_F64_MFMA if t_gram else None,
                                     "passes": n_gram, "ms_per_gram_pass": t_gram / max(n_gram, 1) * 1e3,
                                     "algorithmic": "C(C+1) flop per (tuple, sample) per Gauss-Newton Gram pass, "
-                                                   "C = 4n+2 columns, every subset of the pool"}}
+                                                   "C = 4n+2 columns, every subset of the pool, 8 passes "
+                                                   "(the first of 9 gathered from the pool Gram)"}}
     return leg, res
 
 
@@ -278,6 +281,60 @@ def full_errors(ctx, s, dev, res32, res64):
     e["last_scan_points_compared"] = int(good.sum().item())
     e["last_scan_points_rescored_fp32"] = int(((f32_ & 64) != 0).sum().item())
     return e
+
+
+def convergence_leg(ctx, s, dev, res, n_masks=4096):
+    """Gauss-Newton (fredec_tuples, refine_steps R) against the fixed-step
+    preconditioned ascent (fredec_ascent, S steps) on pool subsets of the full
+    pass, both from the pool frequencies: the share of subsets whose
+    Gauss-Newton iteration stopped on the step tolerance (max |df| T_eff <
+    1e-10) within R passes, and each method's largest distance (times T_eff)
+    from the R = 16 Gauss-Newton frequencies over the subsets that stay in
+    that basin (within 0.1 / T_eff)."""
+    import torch
+    from paper_1309_0100_amd import fredec
+    pool = res.pool
+    n = pool.size
+    rng = np.random.default_rng(17)
+    masks = np.unique(rng.integers(1, 1 << n, size=n_masks).astype(np.uint64))
+    t, x, w = (torch.as_tensor(a, device=dev) for a in (s.t, s.x, s.w))
+    T = float(ctx.normalize(t, x, w)[3][0, 4].item())
+    mem = [[k for k in range(n) if int(m) >> k & 1] for m in masks]
+    gn = {}
+    for R in (1, 2, 4, 8, 16):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        l, z, f, fl = ctx.tuples(t, x, w, pool, masks=masks, refine_steps=R)
+        torch.cuda.synchronize()
+        gn[R] = (time.perf_counter() - t0, f.cpu().numpy(), fl.cpu().numpy())
+    ref = gn[16][1]
+    out = {"subsets": int(masks.size), "pool_size": int(n), "gauss_newton": {}, "ascent": {}}
+    for R, (sec, f, fl) in gn.items():
+        d = np.array([np.max(np.abs(f[k, m] - ref[k, m])) for k, m in enumerate(mem)]) * T
+        ok = np.isfinite(d) & (d < 0.1)
+        out["gauss_newton"][str(R)] = {"passes": R + 1, "ms": sec * 1e3,
+                                       "converged_share": float(np.mean((fl & fredec.FLAG_CONVERGED) != 0)),
+                                       "max_dist_to_R16_times_T_eff": float(d[ok].max(initial=0.0)),
+                                       "median_dist": float(np.median(d[ok])) if ok.any() else None,
+                                       "p90_dist": float(np.percentile(d[ok], 90)) if ok.any() else None,
+                                       "share_within_1e-8": float(np.mean(d[ok] < 1e-8))}
+    toff = np.concatenate([[0], np.cumsum([len(m) for m in mem])]).astype(np.int64)
+    f0 = np.concatenate([pool[m] for m in mem])
+    for S in (5, 10, 20, 40):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fa, za, la, fla = ctx.ascent(t, x, w, f0, toff, steps=S, clamp=0.1)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        fa = fa.cpu().numpy()
+        d = np.array([np.max(np.abs(fa[toff[k]:toff[k + 1]] - ref[k, m])) for k, m in enumerate(mem)]) * T
+        ok = np.isfinite(d) & (d < 0.1)
+        out["ascent"][str(S)] = {"steps": S, "ms": sec * 1e3, "basin_share": float(np.mean(ok)),
+                                 "max_dist_to_gn_times_T_eff": float(d[ok].max(initial=0.0)),
+                                 "median_dist": float(np.median(d[ok])) if ok.any() else None,
+                                 "p90_dist": float(np.percentile(d[ok], 90)) if ok.any() else None,
+                                 "share_within_1e-8": float(np.mean(d[ok] < 1e-8))}
+    return out
 
 
 # ------------------------------------------------------------------ residual scan
@@ -503,6 +560,8 @@ def main():
             progress("errors of the float32 pass")
             res["errors"] = full_errors(ctx, s, dev, r32, r64)
         if extra:
+            progress("Gauss-Newton against ascent on pool subsets")
+            res["gn_vs_ascent"] = convergence_leg(ctx, s, dev, r32)
             progress("residual scan (N=2000, m=4, F=1e6)")
             sr = synth.residual()
             legs, zs, fls = {}, {}, {}
