@@ -60,8 +60,8 @@ PEAK_HBM = 8.0e12                  # B/s
 # measured with (source_hash); keyed by (kernel, workload).
 COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = {
-    # float32 Phase 1 scans of the full pass, averaged over its 18 launches (scan_f16x3_kernel x17,
-    # scan_f32_kernel x1)
+    # float32 Phase 1 scans of the full pass, averaged over its 18 launches (scan_f16x3_kernel x16,
+    # scan_f32_kernel x2)
     "full_fp32_phase1_scans": {"src": {"scan_f16x3.hip": "b96ce106c763caf4f985e385766738f7d20e5725",
                                         "scan_f32.hip": "ce2bad490820f493b1da42222c1e35694aabec42"},
                                "fetch_kib": 8609.0, "write_kib": 35176.0},

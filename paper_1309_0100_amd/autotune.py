@@ -1,7 +1,8 @@
 """Kernel and tile-shape autotuner of the reduced-precision residual scan.
 
 It times, with the library's own HIP-event timing of the scan kernels, on a
-synthetic series of the benchmark's shape (N samples, F grid points):
+synthetic series of the benchmark's shape (N samples, F grid points; by
+default the full pass's scans, N = 10^4 and F = 4e6):
 
 * for every column-tile bucket NT of the split-float16 kernel (NT = 1 for
   m <= 7, 2 for m <= 15, ...), every supported count FT of 16-frequency tiles
@@ -13,7 +14,7 @@ synthetic series of the benchmark's shape (N samples, F grid points):
 
 The choice is written to tuning.json next to this file; Context(tuning=True)
 applies it through fredec_set_tile.
-Usage: python -m paper_1309_0100_amd.autotune [--N 2000 --F 1000000]
+Usage: python -m paper_1309_0100_amd.autotune [--N 10000 --F 4000000]
 """
 from __future__ import annotations
 
@@ -45,7 +46,7 @@ def time_scan(ctx, s, base, df, F, reps=5):
     return ms / max(n, 1)
 
 
-def tune(N=2000, F=1_000_000, buckets=(1, 2), reps=5, verbose=True, out_path=TUNING):
+def tune(N=10_000, F=4_000_000, buckets=(1, 2), reps=5, verbose=True, out_path=TUNING):
     ctx = fredec.Context(0, tuning=False)
     s = synth.random_series(7, N, span=4000.0, n_sin=4)
     df = 2.0 / F
@@ -114,8 +115,8 @@ def apply(ctx, path=TUNING):
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("--N", type=int, default=2000)
-    ap.add_argument("--F", type=int, default=1_000_000)
+    ap.add_argument("--N", type=int, default=10_000)
+    ap.add_argument("--F", type=int, default=4_000_000)
     ap.add_argument("--buckets", type=int, nargs="+", default=[1, 2])
     ap.add_argument("--out", default=TUNING, help="where to write the table (default: tuning.json here)")
     a = ap.parse_args()
