@@ -186,6 +186,7 @@ struct ScanPlan : fredec_plan {
     int key;         // KP (float64, float32 VALU) or column tiles NT (split float16)
     int ft;          // split float16: 16-frequency tiles per wave the work list was cut for
     int64_t begin, end;
+    double work = 0.0;  // estimated cost: sum of N F (2 KP + 3) over its series
   };
   std::vector<Group> groups;
 };
@@ -306,6 +307,8 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
       P.groups.push_back(ScanPlan::Group{kd, key(s), ft, static_cast<int64_t>(P.work.size()), 0});
     for (int64_t j0 = 0; j0 < sin[s].F; j0 += tile) P.work.push_back(ScanWork{s, 0, j0});
     P.groups.back().end = static_cast<int64_t>(P.work.size());
+    P.groups.back().work +=
+        static_cast<double>(sin[s].N) * static_cast<double>(sin[s].F) * static_cast<double>(2 * sin[s].KP + 3);
   }
   return FREDEC_OK;
 }
@@ -356,20 +359,58 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const ScanPl
   }
   {
     ProfScope prof(prof_ctx, st, FREDEC_PROF_SCAN);
-    for (size_t g = 0; g < n_groups; ++g) {
+    // The groups write disjoint outputs: with several of them, they run
+    // concurrently on the caller's stream and the context's side streams
+    // (each group, largest estimated work first, onto the least loaded
+    // stream), joined back to the caller's stream with events before the
+    // re-scoring (capturable fork/join), so that one group's last, partly
+    // filled round overlaps the others.
+    const int nst = static_cast<int>(std::min<size_t>(n_groups, 1 + fredec_ctx::NSIDE));
+    int on_small[64];
+    std::vector<int> on_big;
+    int* on = n_groups <= 64 ? on_small : (on_big.assign(n_groups, 0), on_big.data());
+    {
+      double load[1 + fredec_ctx::NSIDE] = {};
+      int order_small[64];
+      std::vector<int> order_big;
+      int* order = n_groups <= 64 ? order_small : (order_big.assign(n_groups, 0), order_big.data());
+      for (size_t g = 0; g < n_groups; ++g) order[g] = static_cast<int>(g);
+      std::sort(order, order + n_groups, [&](int a, int b) { return groups[a].work > groups[b].work; });
+      for (size_t q = 0; q < n_groups; ++q) {
+        int best = 0;
+        for (int k = 1; k < nst; ++k)
+          if (load[k] < load[best]) best = k;
+        on[order[q]] = best;
+        load[best] += groups[order[q]].work;
+      }
+    }
+    if (nst > 1) {
+      if (hipEventRecord(ctx->fork_ev, st) != hipSuccess) return FREDEC_EDEVICE;
+      for (int k = 1; k < nst; ++k)
+        if (hipStreamWaitEvent(ctx->side[k - 1], ctx->fork_ev, 0) != hipSuccess) return FREDEC_EDEVICE;
+    }
+    int rc = FREDEC_OK;
+    for (size_t g = 0; g < n_groups && rc == FREDEC_OK; ++g) {
       const ScanPlan::Group& gr = groups[g];
+      const hipStream_t gs = on[g] == 0 ? st : ctx->side[on[g] - 1];
       const int n = static_cast<int>(gr.end - gr.begin);
       hipError_t err;
       if (gr.kind == ScanPlan::F16X3)
-        err = launch_scan_f16x3(st, gr.key, gr.ft, n, d_work + gr.begin, d_sin, d_hdr, d_aux, d_b16, z_out, flags_out,
+        err = launch_scan_f16x3(gs, gr.key, gr.ft, n, d_work + gr.begin, d_sin, d_hdr, d_aux, d_b16, z_out, flags_out,
                                 d_list, d_count);
       else if (gr.kind == ScanPlan::F32)
-        err = launch_scan_f32(st, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_rec, d_g32, z_out, flags_out, d_list,
+        err = launch_scan_f32(gs, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_rec, d_g32, z_out, flags_out, d_list,
                               d_count);
       else
-        err = launch_scan_f64(st, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_rec, z_out, flags_out);
-      if (err != hipSuccess) return FREDEC_EDEVICE;
+        err = launch_scan_f64(gs, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_rec, z_out, flags_out);
+      if (err != hipSuccess) rc = FREDEC_EDEVICE;
     }
+    // join (also after a failed launch, so that no side stream stays forked)
+    for (int k = 1; k < nst; ++k)
+      if (hipEventRecord(ctx->join_ev[k - 1], ctx->side[k - 1]) != hipSuccess ||
+          hipStreamWaitEvent(st, ctx->join_ev[k - 1], 0) != hipSuccess)
+        rc = FREDEC_EDEVICE;
+    if (rc) return rc;
   }
   if (f32) {
     ProfScope prof(prof_ctx, st, FREDEC_PROF_RESCORE);

@@ -16,7 +16,7 @@
 // of a sin/cos.  The other R-1 frequencies follow by rotation with the
 // record's (cos, sin)(2 pi s tau).  Per frequency the lane accumulates
 //   U_c[k] = <q_k cos>, U_s[k] = <q_k sin>, h = <r_b cos>, <r_b sin>,
-//   <cos^2>, <cos sin>, <sin^2>
+//   <cos^2>, <cos sin>   (<sin^2> = <1> - <cos^2>, eq. idn)
 // and the epilogue extends the base Cholesky factor by the 2x2 Schur block of
 // the trial column pair (the incremental extension of Sect. 3):
 //   S = C - U^T U, a_psi = L_S^{-1} h, l_{m+1} = l_m - |a_psi|^2,
@@ -36,15 +36,17 @@ constexpr int R_of(int KP) {
 }
 
 // Epilogue of one frequency from its sums (orthonormal base columns q_k,
-// base residual r_b; see the preparation kernel):
+// base residual r_b; see the preparation kernel), all weighted by w~ q_0:
 //   acc[0], acc[1]          <q_0 cos>, <q_0 sin>
-//   acc[2], acc[3], acc[4]  <cos^2>, <cos sin>, <sin^2>
+//   acc[2], acc[3]          <cos^2>, <cos sin>  (acc[4] is not used)
 //   acc[3+2k], acc[4+2k]    <q_k cos>, <q_k sin> (k = 1..K-1), then <r_b cos>, <r_b sin> (k = K)
+// q_0 = <1>^{-1/2} is the constant column, so <sin^2> = <1> - <cos^2> (eq.
+// idn) is sqrt(<1>) - acc[2] in these units.
 template <int KP>
 __device__ __forceinline__ void scan_epilogue(const double (&acc)[2 * KP + 3], double f, const SeriesIn& si,
                                               const SeriesHdr& h, double& z, uint8_t& flag) {
   constexpr int K = KP - 1;
-  const double cc = acc[2], ss = acc[4];
+  const double cc = acc[2], ss = sqrt(h.W1) - acc[2];
   double Scc = cc, Scs = acc[3], Sss = ss;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -126,7 +128,6 @@ __global__ __launch_bounds__(BLOCK) void scan_f64_kernel(const ScanWork* __restr
         acc[r][1] += tsn;
         acc[r][2] = __builtin_fma(tc, c, acc[r][2]);
         acc[r][3] = __builtin_fma(tc, s, acc[r][3]);
-        acc[r][4] = __builtin_fma(tsn, s, acc[r][4]);
 #pragma unroll
         for (int k = 1; k < KP; ++k) {
           const double g = q[3 + k];
@@ -189,7 +190,6 @@ __global__ __launch_bounds__(BLOCK) void scan_at_f64_kernel(const SeriesIn* __re
     acc[1] += tsn;
     acc[2] = __builtin_fma(tc, c, acc[2]);
     acc[3] = __builtin_fma(tc, s, acc[3]);
-    acc[4] = __builtin_fma(tsn, s, acc[4]);
 #pragma unroll
     for (int k = 1; k < KP; ++k) {
       const double gk = q[3 + k];

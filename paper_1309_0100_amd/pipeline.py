@@ -55,6 +55,9 @@ def run(ctx: "fredec.Context", t, x, w, df: float, F: int, fap0: float = 0.05, f
     n = res.pool.size
     if n == 0:
         return res
+    if n > fredec.MAX_POOL:
+        raise ValueError(f"Phase 1 kept {n} candidates, more than the {fredec.MAX_POOL} frequencies a pool can hold "
+                         f"(Sect. 5: 25-27 is the method's practical limit); pass pool_cap <= {fredec.MAX_POOL}")
     N = len(t) if not hasattr(t, "numel") else t.numel()
     dev = torch.device("cuda", ctx.device)
     ltab = torch.empty(1 << n, dtype=torch.float64, device=dev)

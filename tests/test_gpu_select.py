@@ -93,3 +93,13 @@ def test_pipeline_alias_example_matches_oracle(ctx, prec):
         assert abs(sol.l - ltab[sol.mask]) <= 1e-9 * ltab[sol.mask]
     pairs = [sol for sol in res.solutions if len(sol.freqs) == 2]
     assert len(pairs) == 1 and np.allclose(pairs[0].freqs, [0.9, 1.1], atol=0.05 / nrm.T_eff)
+
+
+def test_pipeline_rejects_pool_above_limit(ctx):
+    """Phase 1 of the full-pass series keeps 40 candidates with pool_cap = 40:
+    more than a pool can hold, so the pipeline stops with a clear error
+    before Phase 2 instead of a failed library call."""
+    from paper_1309_0100_amd import fredec as F, pipeline
+    s = synth.full()
+    with pytest.raises(ValueError, match="pool_cap"):
+        pipeline.run(ctx, s.t, s.x, s.w, s.df, s.F, pool_cap=F.MAX_POOL + 13)
