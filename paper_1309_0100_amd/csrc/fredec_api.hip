@@ -84,8 +84,9 @@ namespace {
 struct ScanLayout {
   size_t off_sin = 0, off_hdr = 0, off_work = 0, off_tau = 0, off_xt = 0, off_wt = 0, off_rec = 0, off_phi = 0;
   size_t off_g32 = 0, off_aux = 0, off_b16 = 0, off_list = 0, off_count = 0, off_chunk = 0;
-  size_t off_ppart = 0, off_pm = 0;
+  size_t off_ppart = 0, off_pm = 0, off_part = 0;
   size_t total = 0;
+  int nsplit = 1;  // sample chunks of a single float64 series with few frequency tiles
   int64_t Ntot = 0, rec_total = 0, phi_total = 0, g32_total = 0, aux_total = 0, b16_total = 0, n_work = 0,
           F_total = 0;
   int64_t ptiles = 0, ppart_total = 0, pm_total = 0;  // preparation tiles, Gram partials, basis changes
@@ -108,7 +109,7 @@ int f16x3_ft_for(const fredec_ctx* ctx, int NT) {
 
 // Checks the host descriptors of a scan batch and computes the workspace layout.
 int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, const int64_t* F, int32_t precision,
-                ScanLayout& L) {
+                ScanLayout& L, bool allow_split = true) {
   if (n_series <= 0 || !soff || !boff || !F) return FREDEC_EINVAL;
   if (precision != FREDEC_FP64 && precision != FREDEC_FP32) return FREDEC_EINVAL;
   if (soff[0] < 0 || boff[0] < 0) return FREDEC_EINVAL;
@@ -120,7 +121,8 @@ int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, cons
     if (N - 3 * m - 4 <= 0) return FREDEC_EDOF;
     const int KP = static_cast<int>(2 * m + 2);
     const int64_t tile = scan_tile(KP, precision);
-    L.n_work += (F[s] + tile - 1) / tile;
+    if (n_series == 1 && precision == FREDEC_FP64 && allow_split) L.nsplit = scan_f64_nsplit(N, KP, F[s]);
+    L.n_work += (F[s] + tile - 1) / tile * L.nsplit;
     L.Ntot += N;
     L.phi_total += N * KP;
     L.rec_total += N * rec_stride(KP);
@@ -160,6 +162,7 @@ int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, cons
   L.off_chunk = take(precision == FREDEC_FP32 ? sizeof(int64_t) * (2 * n_series + 3) : 0);
   L.off_ppart = take(sizeof(double) * L.ppart_total);
   L.off_pm = take(sizeof(double) * L.pm_total);
+  L.off_part = take(L.nsplit > 1 ? sizeof(double) * L.nsplit * (2 * (2 * (boff[1] - boff[0]) + 2) + 3) * F[0] : 0);
   L.total = off;
   return FREDEC_OK;
 }
@@ -178,6 +181,7 @@ struct ScanPlan : fredec_plan {
   int32_t precision = FREDEC_FP64;
   int64_t base_off = 0;  // soff[0]: t, x, w are indexed from the caller's pointers
   int32_t kp_max = 2;    // largest KP of the series
+  int64_t sin_F0 = 0;    // grid size of the first series (a split float64 scan has one series)
   std::vector<SeriesIn> sin;
   std::vector<ScanWork> work;
   enum Kind { F64 = 0, F32 = 2, F16X3 = 3 };
@@ -187,6 +191,7 @@ struct ScanPlan : fredec_plan {
     int ft;          // split float16: 16-frequency tiles per wave the work list was cut for
     int64_t begin, end;
     double work = 0.0;  // estimated cost: sum of N F (2 KP + 3) over its series
+    int nsplit = 1;     // float64, one series: sample chunks (work item pad = chunk)
   };
   std::vector<Group> groups;
 };
@@ -272,6 +277,7 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
   P.kp_max = 2;
   P.precision = precision;
   P.base_off = soff[0];
+  P.sin_F0 = F[0];
   std::vector<SeriesIn>& sin = P.sin;
   sin.assign(n_series, SeriesIn{});
   std::memset(sin.data(), 0, sizeof(SeriesIn) * n_series);
@@ -305,7 +311,10 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
     const int64_t tile = kind_tile(kd, sin[s].KP, ft, precision);
     if (P.groups.empty() || P.groups.back().kind != kd || P.groups.back().key != key(s))
       P.groups.push_back(ScanPlan::Group{kd, key(s), ft, static_cast<int64_t>(P.work.size()), 0});
-    for (int64_t j0 = 0; j0 < sin[s].F; j0 += tile) P.work.push_back(ScanWork{s, 0, j0});
+    const int ns = kd == ScanPlan::F64 ? L.nsplit : 1;
+    P.groups.back().nsplit = ns;
+    for (int c = 0; c < ns; ++c)
+      for (int64_t j0 = 0; j0 < sin[s].F; j0 += tile) P.work.push_back(ScanWork{s, c, j0});
     P.groups.back().end = static_cast<int64_t>(P.work.size());
     P.groups.back().work +=
         static_cast<double>(sin[s].N) * static_cast<double>(sin[s].F) * static_cast<double>(2 * sin[s].KP + 3);
@@ -402,7 +411,8 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const ScanPl
         err = launch_scan_f32(gs, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_rec, d_g32, z_out, flags_out, d_list,
                               d_count);
       else
-        err = launch_scan_f64(gs, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_rec, z_out, flags_out);
+        err = launch_scan_f64(gs, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_rec, z_out, flags_out,
+                              at<double>(ws, L.off_part), gr.nsplit, P.n_series == 1 ? P.sin_F0 : 0);
       if (err != hipSuccess) rc = FREDEC_EDEVICE;
     }
     // join (also after a failed launch, so that no side stream stays forked)
@@ -709,7 +719,7 @@ int fredec_scan_static(fredec_ctx* ctx, void* stream, const double* t, const dou
   if (m > 0 && !base_f) return FREDEC_EINVAL;
   const int64_t soff[2] = {0, N}, boff[2] = {0, m}, Fs[1] = {F};
   ScanPlan P;  // no host allocation: its vectors stay empty
-  int rc = scan_layout(1, soff, boff, Fs, precision, P.L);
+  int rc = scan_layout(1, soff, boff, Fs, precision, P.L, /*allow_split=*/false);
   if (rc) return rc;
   if (P.L.total > static_cast<size_t>(FREDEC_STATIC_SCRATCH_BYTES)) return FREDEC_ENOTSUP;
   SeriesIn d;

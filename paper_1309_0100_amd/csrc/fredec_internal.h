@@ -63,7 +63,7 @@ struct SeriesHdr {
 
 struct ScanWork {
   int32_t series;
-  int32_t pad;
+  int32_t pad;  // sample chunk of a split float64 scan (0 otherwise)
   int64_t j0;  // first grid index of the tile
 };
 
@@ -281,9 +281,17 @@ hipError_t launch_rescore(hipStream_t st, int NT, int grid, int n_series, const 
                           const double* rec, const Rescore* list, const unsigned long long* count, int64_t* off,
                           double* z, uint8_t* flags);
 hipError_t launch_zero_u64(hipStream_t st, unsigned long long* p, int n);
+// nsplit > 1: the work items cover sample chunks (ScanWork::pad = chunk) of
+// one series of F_split grid points, whose sums go to part (nsplit (2 KP + 3)
+// F_split doubles) and are then added in chunk order and finished.
 hipError_t launch_scan_f64(hipStream_t st, int KP, int n_work, const ScanWork* work,
                            const SeriesIn* sin, const SeriesHdr* hdr, const double* rec,
-                           double* z, uint8_t* flags);
+                           double* z, uint8_t* flags, double* part = nullptr, int nsplit = 1,
+                           int64_t F_split = 0);
+// Sample chunks of a float64 scan of one series: fewer than 128 frequency
+// tiles (wide fits on the chip) are split over up to 16 chunks of at least 256
+// samples; 1 = no split.
+int scan_f64_nsplit(int64_t N, int KP, int64_t F);
 hipError_t launch_scan_at_f64(hipStream_t st, int KP, const SeriesIn* sin, const SeriesHdr* hdr,
                               const double* rec, const int64_t* idx, int64_t n_idx,
                               double* z, uint8_t* flags);

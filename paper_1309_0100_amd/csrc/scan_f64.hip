@@ -60,12 +60,23 @@ __device__ __forceinline__ void scan_epilogue(const double (&acc)[2 * KP + 3], d
   schur_finish(Scc, Scs, Sss, cc, ss, hc, hs, f, si, h, z, flag);
 }
 
-template <int KP, int R>
+constexpr int F64_TS = 64;  // samples per table tile of the float64 scan
+
+// Samples per chunk when a scan is split over nsplit sample chunks (whole tiles).
+__host__ __device__ inline int64_t f64_chunk(int64_t N, int nsplit) {
+  return ((N + nsplit - 1) / nsplit + F64_TS - 1) / F64_TS * F64_TS;
+}
+
+// SPLIT: the work item covers the samples of chunk wk.pad (of nsplit) and
+// writes its raw sums to part[(chunk NS + k) F + j] for the reduction kernel
+// instead of finishing the frequencies.
+template <int KP, int R, bool SPLIT>
 __global__ __launch_bounds__(BLOCK) void scan_f64_kernel(const ScanWork* __restrict__ work,
                                                          const SeriesIn* __restrict__ sin_,
                                                          const SeriesHdr* __restrict__ hdr,
                                                          const double* __restrict__ rec,
-                                                         double* __restrict__ z_out, uint8_t* __restrict__ flags_out) {
+                                                         double* __restrict__ z_out, uint8_t* __restrict__ flags_out,
+                                                         double* __restrict__ part, int nsplit) {
   constexpr int NS = 2 * KP + 3;
   constexpr int P = rec_stride(KP);
   const ScanWork wk = work[blockIdx.x];
@@ -77,7 +88,14 @@ __global__ __launch_bounds__(BLOCK) void scan_f64_kernel(const ScanWork* __restr
   const int64_t jb = wk.j0 + threadIdx.x;
   double* zs = z_out + si.goff;
   uint8_t* fs = flags_out ? flags_out + si.goff : nullptr;
-  if (h.status != 0) {
+  int64_t i_lo = 0, i_hi = N;
+  if constexpr (SPLIT) {
+    const int64_t nc = f64_chunk(N, nsplit);
+    i_lo = static_cast<int64_t>(wk.pad) * nc;
+    i_hi = i_lo + nc < N ? i_lo + nc : N;
+    if (h.status != 0) return;  // the reduction writes NaN
+  }
+  if (!SPLIT && h.status != 0) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t j = jb + (int64_t)BLOCK * r;
@@ -94,14 +112,14 @@ __global__ __launch_bounds__(BLOCK) void scan_f64_kernel(const ScanWork* __restr
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[r][k] = 0.0;
 
-  constexpr int TS = 64;  // samples per table tile
+  constexpr int TS = F64_TS;  // samples per table tile
   __shared__ double2 eash[TS][16];  // E0 A_a per sample, a = t / 16
   __shared__ double2 bsh[TS][16];   // B_b per sample, b = t % 16
   const int ta_ = threadIdx.x >> 4, tb_ = threadIdx.x & 15;
   const double fb = static_cast<double>(wk.j0 + 1) * df;  // the block's first frequency
   const double* __restrict__ q0 = rec + si.rec_off;
-  for (int64_t i0 = 0; i0 < N; i0 += TS) {
-    const int nts = N - i0 < TS ? static_cast<int>(N - i0) : TS;
+  for (int64_t i0 = i_lo; i0 < i_hi; i0 += TS) {
+    const int nts = i_hi - i0 < TS ? static_cast<int>(i_hi - i0) : TS;
     __syncthreads();
     build_phasor_tables<KP>(q0 + i0 * P, P, nts, fb, eash, bsh);
     __syncthreads();
@@ -141,13 +159,54 @@ __global__ __launch_bounds__(BLOCK) void scan_f64_kernel(const ScanWork* __restr
   for (int r = 0; r < R; ++r) {
     const int64_t j = jb + (int64_t)BLOCK * r;
     if (j < F) {
-      double z;
-      uint8_t fl;
-      scan_epilogue<KP>(acc[r], static_cast<double>(j + 1) * df, si, h, z, fl);
-      zs[j] = z;
-      if (fs) fs[j] = fl;
+      if constexpr (SPLIT) {
+        double* pc = part + static_cast<int64_t>(wk.pad) * NS * F + j;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) pc[k * F] = acc[r][k];
+      } else {
+        double z;
+        uint8_t fl;
+        scan_epilogue<KP>(acc[r], static_cast<double>(j + 1) * df, si, h, z, fl);
+        zs[j] = z;
+        if (fs) fs[j] = fl;
+      }
     }
   }
+}
+
+// The chunks' sums of a split scan (one series) added in chunk order, then
+// the epilogue: one thread per grid frequency.
+template <int KP>
+__global__ __launch_bounds__(BLOCK) void scan_f64_reduce_kernel(const SeriesIn* __restrict__ sin_,
+                                                                const SeriesHdr* __restrict__ hdr,
+                                                                const double* __restrict__ part, int nsplit,
+                                                                double* __restrict__ z_out,
+                                                                uint8_t* __restrict__ flags_out) {
+  constexpr int NS = 2 * KP + 3;
+  const SeriesIn& si = sin_[0];
+  const SeriesHdr& h = hdr[0];
+  const int64_t F = si.F;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+  if (j >= F) return;
+  double* zs = z_out + si.goff;
+  uint8_t* fs = flags_out ? flags_out + si.goff : nullptr;
+  if (h.status != 0) {
+    zs[j] = __builtin_nan("");
+    if (fs) fs[j] = FREDEC_FLAG_BADSERIES;
+    return;
+  }
+  double acc[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    double v = 0.0;
+    for (int c = 0; c < nsplit; ++c) v += part[(static_cast<int64_t>(c) * NS + k) * F + j];
+    acc[k] = v;
+  }
+  double z;
+  uint8_t fl;
+  scan_epilogue<KP>(acc, static_cast<double>(j + 1) * si.df, si, h, z, fl);
+  zs[j] = z;
+  if (fs) fs[j] = fl;
 }
 
 // Same statistic at an explicit list of grid indices of one series: one
@@ -210,8 +269,14 @@ __global__ __launch_bounds__(BLOCK) void scan_at_f64_kernel(const SeriesIn* __re
 
 template <int KP>
 hipError_t launch_kp(hipStream_t st, int n_work, const ScanWork* work, const SeriesIn* sin, const SeriesHdr* hdr,
-                     const double* rec, double* z, uint8_t* flags) {
-  scan_f64_kernel<KP, R_of(KP)><<<n_work, BLOCK, 0, st>>>(work, sin, hdr, rec, z, flags);
+                     const double* rec, double* z, uint8_t* flags, double* part, int nsplit, int64_t F_split) {
+  if (nsplit > 1) {
+    scan_f64_kernel<KP, R_of(KP), true><<<n_work, BLOCK, 0, st>>>(work, sin, hdr, rec, z, flags, part, nsplit);
+    scan_f64_reduce_kernel<KP><<<static_cast<unsigned>((F_split + BLOCK - 1) / BLOCK), BLOCK, 0, st>>>(
+        sin, hdr, part, nsplit, z, flags);
+  } else {
+    scan_f64_kernel<KP, R_of(KP), false><<<n_work, BLOCK, 0, st>>>(work, sin, hdr, rec, z, flags, nullptr, 1);
+  }
   return hipGetLastError();
 }
 
@@ -227,17 +292,28 @@ hipError_t launch_at_kp(hipStream_t st, const SeriesIn* sin, const SeriesHdr* hd
 
 int scan_freqs_per_thread(int KP) { return R_of(KP); }
 
+int scan_f64_nsplit(int64_t N, int KP, int64_t F) {
+  const int64_t tile = static_cast<int64_t>(BLOCK) * R_of(KP);
+  const int64_t tiles = (F + tile - 1) / tile;
+  if (tiles >= 128) return 1;
+  int64_t ns = 256 / tiles;
+  if (ns > 16) ns = 16;
+  if (ns > N / 256) ns = N / 256;
+  return ns < 2 ? 1 : static_cast<int>(ns);
+}
+
 #define FREDEC_KP_CASES(X) \
   X(2) X(4) X(6) X(8) X(10) X(12) X(14) X(16) X(18) X(20) X(22) X(24) X(26) \
   X(28) X(30) X(32) X(34) X(36) X(38) X(40) X(42) X(44) X(46) X(48) X(50)
 
 hipError_t launch_scan_f64(hipStream_t st, int KP, int n_work, const ScanWork* work, const SeriesIn* sin,
-                           const SeriesHdr* hdr, const double* rec, double* z, uint8_t* flags) {
+                           const SeriesHdr* hdr, const double* rec, double* z, uint8_t* flags, double* part,
+                           int nsplit, int64_t F_split) {
   if (n_work <= 0) return hipSuccess;
   switch (KP) {
 #define X(kp) \
   case kp:    \
-    return launch_kp<kp>(st, n_work, work, sin, hdr, rec, z, flags);
+    return launch_kp<kp>(st, n_work, work, sin, hdr, rec, z, flags, part, nsplit, F_split);
     FREDEC_KP_CASES(X)
 #undef X
     default:

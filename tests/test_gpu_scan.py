@@ -66,6 +66,24 @@ def test_base_models_ragged(ctx, m, N, F):
     assert abs(float(lb.item()) - ref.l_base) < 1e-13
 
 
+@pytest.mark.parametrize("m,N,F", [(0, 1000, 700), (3, 5000, 4000), (6, 9001, 2500)])
+def test_split_scan_few_tiles(ctx, m, N, F):
+    """A single float64 scan whose grid gives few frequency tiles is split
+    over sample chunks (partial sums added in chunk order, then the
+    epilogue): 3 chunks with a ragged last one, 16 chunks, and a long ragged
+    series; every grid point against the oracle."""
+    s = synth.random_series(300 + m, N, span=500.0, n_sin=3)
+    rng = np.random.default_rng(30 + m)
+    base = np.concatenate([s.true_f, rng.uniform(0.01, 1.0, size=max(0, m - 3))])[:m]
+    df = 2.0 / F
+    print(f"case: split scan m={m} N={N} F={F}", flush=True)
+    z, fl, lb, st = ctx.scan_series(s.t, s.x, s.w, base, df, F)
+    ref = O.scan(s.t, s.x, s.w, base, df, F)
+    assert int(st.item()) == 0
+    check_scan(z, fl, ref)
+    assert abs(float(lb.item()) - ref.l_base) < 1e-13
+
+
 def test_batched_csr_uneven(ctx):
     """Several series of uneven N, m and F in one call (several kernel
     instances, ragged tiles, F = 1)."""
