@@ -124,6 +124,25 @@ int climb_f64(fredec_ctx* ctx, void* stream, const double* t, const double* x, c
   return FREDEC_OK;
 }
 
+// Largest scan workspace over the base models m = 0 .. mmax of one series
+// (a single float64 scan of few frequency tiles holds partial sums of its
+// sample chunks, so a smaller base can need more); bases that leave no
+// degrees of freedom are skipped.
+int scan_ws_upto(int64_t N, int64_t F, int mmax, int32_t precision, size_t* bytes) {
+  *bytes = 0;
+  const int64_t soff[2] = {0, N};
+  const int64_t Fs[1] = {F};
+  for (int m = 0; m <= mmax; ++m) {
+    const int64_t boff[2] = {0, m};
+    size_t b = 0;
+    const int rc = fredec_scan_workspace(1, soff, boff, Fs, precision, &b);
+    if (rc == FREDEC_EDOF) break;
+    if (rc) return rc;
+    *bytes = std::max(*bytes, b);
+  }
+  return *bytes ? FREDEC_OK : FREDEC_EDOF;
+}
+
 struct Phase1Layout {
   size_t scan_ws = 0, at_ws = 0;
   size_t off_scan = 0, off_at = 0, off_z = 0, off_fl = 0, off_lb = 0, off_st = 0, off_peaks = 0, off_count = 0,
@@ -134,15 +153,8 @@ struct Phase1Layout {
 int phase1_layout(int64_t N, int64_t F, int32_t max_scans, int32_t precision, Phase1Layout& L) {
   if (N <= 0 || F < 3 || max_scans < 1) return FREDEC_EINVAL;
   const int mmax = std::min<int>(max_scans - 1, FREDEC_MAX_BASE);
-  const int64_t soff[2] = {0, N};
-  const int64_t boff[2] = {0, mmax};
-  const int64_t Fs[1] = {F};
-  int rc = fredec_scan_workspace(1, soff, boff, Fs, precision, &L.scan_ws);
-  if (rc == FREDEC_EDOF) {  // fewer scans fit the data: size for the largest base that does
-    const int64_t m2 = std::max<int64_t>(0, (N - 5) / 3);
-    const int64_t boff2[2] = {0, std::min<int64_t>(m2, mmax)};
-    rc = fredec_scan_workspace(1, soff, boff2, Fs, precision, &L.scan_ws);
-  }
+  if (precision != FREDEC_FP64 && precision != FREDEC_FP32) return FREDEC_EINVAL;
+  int rc = scan_ws_upto(N, F, mmax, precision, &L.scan_ws);
   if (rc) return rc;
   if ((rc = fredec_scan_at_workspace(N, mmax, &L.at_ws))) return rc;
   // interior maxima with z_{j-1} < z_j cannot be adjacent: at most
@@ -180,10 +192,8 @@ struct FapLayout {
 int fap_layout(int64_t N, int64_t F, int32_t m_max, int32_t precision, FapLayout& L) {
   if (N <= 0 || F < 3 || m_max < 0) return FREDEC_EINVAL;
   if (m_max > FREDEC_MAX_BASE) return FREDEC_ENOTSUP;
-  const int64_t soff[2] = {0, N};
-  const int64_t boff[2] = {0, m_max};
-  const int64_t Fs[1] = {F};
-  int rc = fredec_scan_workspace(1, soff, boff, Fs, precision, &L.scan_ws);
+  if (N - 3 * (static_cast<int64_t>(m_max) + 1) - 1 <= 0) return FREDEC_EDOF;
+  int rc = scan_ws_upto(N, F, m_max, precision, &L.scan_ws);
   if (rc) return rc;
   if ((rc = fredec_scan_at_workspace(N, m_max, &L.at_ws))) return rc;
   L.peak_cap = std::max<int64_t>((F - 1) / 2, 1);

@@ -364,19 +364,12 @@ __global__ __launch_bounds__(BLOCK) void prep_factor_kernel(const SeriesIn* __re
       }
       h.D = gb[K];
       h.l_m = gb[K] - aa;
-      // Split float16 operand of the MFMA scan, B = S w~ q_k: since
-      // sum_i w~_i q_k(i)^2 = 1, every |w~_i q_k(i)| <= sqrt(max w~);
-      // S = 2^e puts twice that bound in [2^13, 2^14), so |B| < 2^13 (the
-      // float16 range ends near 2^16) and the low parts of the typical
-      // entries clear the float16 subnormals.
-      const double bound = 2.0 * sqrt(h.wmax);
-      int ex = 0;
-      double S = 1.0;
-      if (bound > 0.0 && isfinite(bound)) {
-        (void)frexp(bound, &ex);  // bound in [2^(ex-1), 2^ex)
-        S = ldexp(1.0, 14 - ex);
-      }
-      h.b16_inv = 1.0 / S;
+      // Split float16 operand of the MFMA scan, B = S sqrt(w~) q_k: since
+      // sum_i w~_i q_k(i)^2 = 1, every |sqrt(w~_i) q_k(i)| <= 1; S = 2^12
+      // puts twice that bound at 2^13, so |B| <= 2^12 (the float16 range
+      // ends near 2^16) and the low parts of the typical entries clear the
+      // float16 subnormals.
+      h.b16_inv = 1.0 / 4096.0;
     }
     h.W1 = gram[0];
     h.status = status;
@@ -569,7 +562,8 @@ __global__ __launch_bounds__(BLOCK) void prep_basis_kernel(int n_series, const S
     }
   }
   if (w_aux) {
-    // tau, e^{2 pi i 16 df tau}, w~, w~ r_b, 0, e^{2 pi i df tau}
+    // tau, e^{2 pi i 16 df tau}, sqrt(w~), sqrt(w~) r_b, 0, e^{2 pi i df tau}
+    // (the split-float16 scan folds sqrt(w~) into its trial phasors)
     double* dst = aux + si.aux_off + i0 * AUX_STRIDE;
     const int n = nts * AUX_STRIDE;
 #pragma unroll 4
@@ -577,11 +571,12 @@ __global__ __launch_bounds__(BLOCK) void prep_basis_kernel(int n_series, const S
       const int sl = e >> 3, f = e & 7;
       const int pf = f == 0 ? 0 : f == 1 ? 3 : f == 2 ? 4 : f == 3 ? 7 : f == 6 ? 5 : 6;
       const double v = tile[f == 4 ? sl * RS + KP - 1 : T * RS + sl * PREP_PSS + pf];
-      dst[e] = f == 5 ? 0.0 : v;
+      const double sw = sqrt(tile[T * RS + sl * PREP_PSS + 7]);
+      dst[e] = f == 5 ? 0.0 : f == 3 ? sw : f == 4 ? v / sw : v;
     }
   }
   if (w_f16) {
-    // B = S w~ q_k = hi + lo.  Layout: per step g of 32 samples and column
+    // B = S sqrt(w~) q_k = hi + lo.  Layout: per step g of 32 samples and column
     // tile nt, the high part then the low part, each 64 lanes x 8 halves;
     // lane L holds column 16 nt + L % 16 at samples 32 g + 8 (L / 16) + e,
     // e < 8 (zero beyond N and beyond column K).
@@ -601,7 +596,8 @@ __global__ __launch_bounds__(BLOCK) void prep_basis_kernel(int n_series, const S
       for (int k = 0; k < 8; ++k) {
         const int sl = s0 + k;
         const bool in = sl < nts && col < K;
-        double v = in ? S * tile[in ? sl * RS + col : 0] : 0.0;
+        // tile holds w~ q_k; B takes sqrt(w~) q_k
+        double v = in ? S * tile[in ? sl * RS + col : 0] / sqrt(tile[T * RS + (in ? sl : 0) * PREP_PSS + 7]) : 0.0;
         v = fmin(fmax(v, -65504.0), 65504.0);
         // hi: rounded to float32, then to float16 (the opaque copy keeps the
         // compiler from fusing the two roundings into a float64-to-float16

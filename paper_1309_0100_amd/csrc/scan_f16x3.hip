@@ -8,22 +8,25 @@
 // in two float16 parts, x = x_hi + x_lo, and three products per step:
 //   A B ~ A_hi B_hi + A_hi B_lo + A_lo B_hi,
 // which keeps about 22 significant bits of every product (the dropped
-// A_lo B_lo is below 2^-22 of it).  B = S w~ q_k with a power of two S per
-// series (the preparation kernel's float16 operand array, scaled so that its
-// low parts stay normal); U = D / S.  The float16 matrix cores have sixteen
-// times the float32 matrix rate, so the three products cost less than one
-// float32 step.
+// A_lo B_lo is below 2^-22 of it).  The weight is split between the two
+// operands: B = S sqrt(w~) q_k (the preparation kernel's float16 operand
+// array, S = 2^12 so that its low parts stay normal) and A = sqrt(w~) cos,
+// sqrt(w~) sin; U = D / S.  The float16 matrix cores have sixteen times the
+// float32 matrix rate, so the three products cost less than one float32 step.
 //
 // Per wave: 16 FT consecutive grid frequencies over all samples of the
 // series; one MFMA step covers 16 frequencies x 32 samples.  The lane
 // (row = lane % 16, kb = lane / 16) generates A for its frequency row at the
 // eight samples 8 kb .. 8 kb + 7 of the step: the float32 complex product
-// eat[a][s] * bt[row][s] of two unit phasors that the block computes in
-// float64 per tile of 128 samples and rounds once (eat = e^{2 pi i (j0 + 1 +
-// 16 a) df tau_s}, a = the wave's 16-frequency tile; bt = e^{2 pi i row df
-// tau_s}).  The same lane accumulates, for its row and its samples,
-//   <cos^2>, <cos sin>  float32 per tile of 128 samples, then float64,
-//   h = <r_b cos>, <r_b sin>  float64 (the data column enters z linearly),
+// eat[a][s] * bt[row][s] of two phasors that the block computes in float64
+// per tile of 128 samples and rounds once (eat = sqrt(w~_s) e^{2 pi i (j0 +
+// 1 + 16 a) df tau_s}, a = the wave's 16-frequency tile; bt = e^{2 pi i row
+// df tau_s}), i.e. c' = sqrt(w~) cos and s' = sqrt(w~) sin.  The same lane
+// accumulates, for its row and its samples,
+//   <cos^2> = sum c'^2, <cos sin> = sum c' s'  float32 per tile of 128
+//   samples, then float64,
+//   h = <r_b cos>, <r_b sin> = sum (sqrt(w~) r_b) c', ...  float64 (the
+//   data column enters z linearly),
 // reduced over the four kb lanes at the end; <sin^2> = <1> - <cos^2>.  MFMA
 // accumulators are added into float32 running sums at the end of every tile
 // (U enters z only through U^T U in the Schur block).  The epilogue forms
@@ -80,7 +83,7 @@ __device__ __forceinline__ float row_sum16(float v) {
 
 // The aux-record values of one sample that the tables need.
 struct SampleRec {
-  double tau, wt, gr, wc, ws;  // tau, w~, w~ r_b, cos and sin of 2 pi df tau
+  double tau, sw, gr, wc, ws;  // tau, sqrt(w~), sqrt(w~) r_b, cos and sin of 2 pi df tau
 };
 
 // Sample `sl` of the tile starting at i0 (neutral values beyond nts).
@@ -89,7 +92,7 @@ __device__ __forceinline__ SampleRec fetch_rec(const double* __restrict__ aser, 
   if (sl < nts) {
     const double* a = aser + (i0 + sl) * AUX_STRIDE;
     r.tau = a[0];
-    r.wt = a[3];
+    r.sw = a[3];
     r.gr = a[4];
     r.wc = a[6];
     r.ws = a[7];
@@ -97,15 +100,16 @@ __device__ __forceinline__ SampleRec fetch_rec(const double* __restrict__ aser, 
   return r;
 }
 
-// Tables of one tile of TS samples: eat[a][s] = e^{2 pi i fb tau_s} w_s^(16 a),
-// bt[b][s] = w_s^b (a, b < 16, w_s = e^{2 pi i df tau_s}), rounded to
-// float32; wts[s] = w~_s (float32), grs[s] = w~_s r_b(tau_s).  Samples
-// nts .. TS - 1 get zero entries, so that they contribute nothing.
+// Tables of one tile of TS samples: eat[a][s] = sqrt(w~_s) e^{2 pi i fb tau_s}
+// w_s^(16 a), bt[b][s] = w_s^b (a, b < 16, w_s = e^{2 pi i df tau_s}),
+// rounded to float32 (the weight folded into eat makes every trial value
+// c' = sqrt(w~) cos, s' = sqrt(w~) sin); grs[s] = sqrt(w~_s) r_b(tau_s).
+// Samples nts .. TS - 1 get zero entries, so that they contribute nothing.
 // BLOCK / TS threads per sample, each taking 16 TS / BLOCK values of a and of
 // b; rows a >= AMAX of eat are not used by the kernel and not written.
 template <int TS, int AMAX>
 __device__ __forceinline__ void build_tables(const SampleRec& r, int nts, double fb, float2* __restrict__ eat,
-                                             float2* __restrict__ bt, float* __restrict__ wts,
+                                             float2* __restrict__ bt,
                                              double* __restrict__ grs) {
   constexpr int TPS = BLOCK / TS;  // threads per sample
   constexpr int PER = 16 / TPS;    // values of a and of b per thread
@@ -119,10 +123,7 @@ __device__ __forceinline__ void build_tables(const SampleRec& r, int nts, double
       if (eb + k < AMAX) eat[(eb + k) * TSP + sl] = float2{0.0f, 0.0f};
       bt[(eb + k) * TSP + sl] = float2{0.0f, 0.0f};
     }
-    if (part == 0) {
-      wts[sl] = 0.0f;
-      grs[sl] = 0.0;
-    }
+    if (part == 0) grs[sl] = 0.0;
     return;
   }
   const double wc = r.wc, ws = r.ws;
@@ -156,13 +157,12 @@ __device__ __forceinline__ void build_tables(const SampleRec& r, int nts, double
     ps = __builtin_fma(ps, wc, pc * ws);
     pc = nc;
   }
-  if (part == 0) {
-    wts[sl] = static_cast<float>(r.wt);
-    grs[sl] = r.gr;
-  }
+  if (part == 0) grs[sl] = r.gr;
   if (eb >= AMAX) return;
   double es, ec;
   sincos_rev(fb * r.tau, es, ec);
+  es *= r.sw;
+  ec *= r.sw;
   double vc = __builtin_fma(ec, ac, -es * as);
   double vs = __builtin_fma(es, ac, ec * as);
 #pragma unroll
@@ -189,13 +189,12 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
   // LDS: the tables during the sample loop; the epilogue reuses the memory
   // for the per-frequency sums (EPF doubles per frequency)
   constexpr int EPF = 7;
-  constexpr int TAB_DOUBLES = (4 * FT + 16) * TSP + TS / 2 + TS;
+  constexpr int TAB_DOUBLES = (4 * FT + 16) * TSP + TS;
   constexpr int EP_DOUBLES = (BLOCK / 64) * 16 * FT * EPF;
   __shared__ double lds[TAB_DOUBLES > EP_DOUBLES ? TAB_DOUBLES : EP_DOUBLES];
   float2* eat = reinterpret_cast<float2*>(lds);
   float2* bt = eat + 4 * FT * TSP;
-  float* wts = reinterpret_cast<float*>(bt + 16 * TSP);
-  double* grs = reinterpret_cast<double*>(wts + TS);
+  double* grs = reinterpret_cast<double*>(bt + 16 * TSP);
 
   const ScanWork wk = work[blockIdx.x];
   const SeriesIn& si = sin_[wk.series];
@@ -241,7 +240,7 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
   for (int64_t i0 = 0; i0 < N; i0 += TS) {
     const int nts = N - i0 < TS ? static_cast<int>(N - i0) : TS;
     __syncthreads();
-    build_tables<TS, 4 * FT>(fetch_rec(aser, i0, nts, slb), nts, fb, eat, bt, wts, grs);
+    build_tables<TS, 4 * FT>(fetch_rec(aser, i0, nts, slb), nts, fb, eat, bt, grs);
     __syncthreads();
     const int ng = (nts + 31) >> 5;
     for (int gg = 0; gg < ng; ++gg) {
@@ -254,12 +253,10 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
       }
       const int s0 = 32 * gg + 8 * kb;  // first sample of this lane in the tile
       float2 bv[8];
-      float w8[8];
       double g8[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         bv[e] = bt[row * TSP + s0 + e];
-        w8[e] = wts[s0 + e];
         g8[e] = grs[s0 + e];
       }
 #pragma unroll
@@ -286,9 +283,8 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
         }
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const float wc = w8[e] * c[e];
-          cc32[ft] = __builtin_fmaf(wc, c[e], cc32[ft]);
-          cs32[ft] = __builtin_fmaf(wc, s[e], cs32[ft]);
+          cc32[ft] = __builtin_fmaf(c[e], c[e], cc32[ft]);
+          cs32[ft] = __builtin_fmaf(c[e], s[e], cs32[ft]);
           hc[ft] = __builtin_fma(g8[e], static_cast<double>(c[e]), hc[ft]);
           hs[ft] = __builtin_fma(g8[e], static_cast<double>(s[e]), hs[ft]);
         }
