@@ -129,9 +129,12 @@ int fredec_profile_read_kinds(fredec_ctx* ctx, int32_t n_kinds, double* ms_out, 
  * 2m + 2 (0..26, default 6) that the AUTO form gives to the VALU kernel.
  * FREDEC_TILE_SCAN_F32_FORM value 1 (a float32-MFMA kernel family) is no
  * longer provided and is rejected.
+ * FREDEC_TILE_TUPLE_LANES: key = tuple size n (1..6, the sizes the lane-group
+ * forward and adjoint kernels take), value = lanes per tuple (4, 8, 16, 32
+ * or 64; 0 = default: sized from the tuple count, N and the CU count).
  * Errors: EINVAL for an unsupported combination.  The workspace size of a
- * scan does not depend on these settings. */
-enum { FREDEC_TILE_SCAN_F16X3 = 1, FREDEC_TILE_SCAN_F32_FORM = 2 };
+ * scan or a tuple batch does not depend on these settings. */
+enum { FREDEC_TILE_SCAN_F16X3 = 1, FREDEC_TILE_SCAN_F32_FORM = 2, FREDEC_TILE_TUPLE_LANES = 3 };
 enum { FREDEC_F32_FORM_VALU = 0, FREDEC_F32_FORM_F16X3 = 2, FREDEC_F32_FORM_AUTO = 3 };
 int fredec_set_tile(fredec_ctx* ctx, int32_t kernel, int32_t key, int32_t value);
 

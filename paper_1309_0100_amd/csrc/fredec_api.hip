@@ -543,6 +543,12 @@ int fredec_set_tile(fredec_ctx* ctx, int32_t kernel, int32_t key, int32_t value)
     }
     return FREDEC_EINVAL;
   }
+  if (kernel == FREDEC_TILE_TUPLE_LANES) {
+    if (key < 1 || key > 6) return FREDEC_EINVAL;
+    if (value != 0 && value != 4 && value != 8 && value != 16 && value != 32 && value != 64) return FREDEC_EINVAL;
+    ctx->tuple_lanes[key] = value;
+    return FREDEC_OK;
+  }
   return FREDEC_EINVAL;
 }
 

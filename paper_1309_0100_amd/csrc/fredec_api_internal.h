@@ -20,6 +20,7 @@ struct fredec_ctx {
   bool staging_pending = false;
   int f16x3_ft[5] = {0, 0, 0, 0, 0};  // split-float16 scan: 16-frequency tiles per wave, by column tiles (0 = default)
   int f32_form = FREDEC_F32_FORM_AUTO;   // kernel family of the reduced-precision scan (FREDEC_F32_FORM_*)
+  int tuple_lanes[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // lane-group tuple kernels: lanes per tuple, by size (0 = default)
   int f32_auto_valu_max_kp = 6;      // automatic form: VALU kernel up to this KP = 2m + 2 (m <= 2)
   // side streams (default priority) for launches of independent kernel
   // groups, joined back to the caller's stream with events

@@ -224,12 +224,15 @@ int launch_groups(const fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, int
   return rc;
 }
 
-// One Gram pass (the size groups concurrently).
-int gram_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, int mode) {
+// One Gram pass (the size groups concurrently).  fuse_solve: the lane-group
+// kernels make the forward solve themselves (else they store the Gram).
+int gram_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev& D, int mode,
+              bool fuse_solve = true) {
   ProfScope prof(ctx, st, FREDEC_PROF_GRAM);
   return launch_groups(ctx, st, P, mode, [&](const TuplePlan::Group& g, hipStream_t gs) {
-    return launch_tuple_gram(gs, g.nf, ctx->n_cu, D.desc, D.order + g.begin, g.count, P.N, D.com, D.tau, D.xt,
-                             D.wt, D.ftry, D.state, D.gram, mode, P.precision == FREDEC_FP32) == hipSuccess;
+    return launch_tuple_gram(gs, g.nf, ctx->n_cu, g.nf < 8 ? ctx->tuple_lanes[g.nf] : 0, D.desc, D.order + g.begin,
+                             g.count, P.N, D.com, D.tau, D.xt, D.wt, D.ftry, D.state, D.gram, mode,
+                             P.precision == FREDEC_FP32, D.facc, D.theta, fuse_solve) == hipSuccess;
   });
 }
 
@@ -239,8 +242,9 @@ int adjoint_pass(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const Tupl
                  double* dzdf, double* hout) {
   ProfScope prof(ctx, st, FREDEC_PROF_ADJOINT);
   return launch_groups(ctx, st, P, TUPLE_FWD, [&](const TuplePlan::Group& g, hipStream_t gs) {
-    return launch_tuple_adjoint(gs, g.nf, ctx->n_cu, D.desc, D.order + g.begin, g.count, P.N, D.com, D.tau, D.xt,
-                                D.wt, f, D.theta, D.state, dzdf, hout, P.precision == FREDEC_FP32) == hipSuccess;
+    return launch_tuple_adjoint(gs, g.nf, ctx->n_cu, g.nf < 8 ? ctx->tuple_lanes[g.nf] : 0, D.desc, D.order + g.begin,
+                                g.count, P.N, D.com, D.tau, D.xt, D.wt, f, D.theta, D.state, dzdf, hout,
+                                P.precision == FREDEC_FP32) == hipSuccess;
   });
 }
 
@@ -394,7 +398,7 @@ int subset_launch(fredec_ctx* ctx, hipStream_t st, const SubsetPlan& P, const do
     const TupleDev Dp = dev_ptrs(static_cast<char*>(P.ws) + P.off_pool, P.Pp);
     if ((rc = normalise(st, P.Pp, Dp, t, x, w, P.N))) return rc;
     if (launch_copy_f64(st, Dp.f0, Dp.ftry, P.n_pool) != hipSuccess) return FREDEC_EDEVICE;
-    if ((rc = gram_pass(ctx, st, P.Pp, Dp, P.refine_steps > 0 ? TUPLE_GN : TUPLE_FWD))) return rc;
+    if ((rc = gram_pass(ctx, st, P.Pp, Dp, P.refine_steps > 0 ? TUPLE_GN : TUPLE_FWD, /*fuse_solve=*/false))) return rc;
     first.pool_gram = Dp.gram;
   }
   if ((rc = run_fit(ctx, st, P.T, D, P.refine_steps, P.use_pool ? &first : nullptr))) return rc;

@@ -51,12 +51,16 @@ struct TupleState {
 bool tuple_lanes_supported(int n, int mode);
 // nf: the exact size of every tuple of the group (it and the mode fix the
 // MFMA kernel's column layout otherwise); n_cu sizes the lane groups; N
-// samples; f32: the reduced-precision trig of the lane-group kernels (the MFMA
-// kernel is float64).
-hipError_t launch_tuple_gram(hipStream_t st, int nf, int n_cu, const TupleDesc* desc, const int32_t* order,
+// samples; lanes: lanes per tuple of the lane-group kernels (0 = sized from
+// the tuple count, N and n_cu); f32: the reduced-precision trig of the lane-group kernels (the MFMA
+// kernel is float64).  With fuse_solve the lane-group kernels (forward mode)
+// also make the tuples' solve from the Gram in registers (theta, facc and the
+// state; the Gram itself is not stored, and the solve kernel then skips these
+// tuples, which are done); without it they store the Gram.
+hipError_t launch_tuple_gram(hipStream_t st, int nf, int n_cu, int lanes, const TupleDesc* desc, const int32_t* order,
                              int n_order, int64_t N, const TupleCommon* com, const double* tau, const double* xt,
-                             const double* wt, const double* ftry, const TupleState* state, double* gram, int mode,
-                             bool f32);
+                             const double* wt, const double* ftry, TupleState* state, double* gram, int mode,
+                             bool f32, double* facc, double* theta, bool fuse_solve);
 // The solve for tuples order[0 .. n_tuples).
 hipError_t launch_tuple_solve(hipStream_t st, const TupleDesc* desc, const int32_t* order, int n_tuples,
                               const TupleCommon* com, double* gram, double* scratch, double* ftry, double* facc,
@@ -64,7 +68,7 @@ hipError_t launch_tuple_solve(hipStream_t st, const TupleDesc* desc, const int32
 hipError_t launch_tuple_finish(hipStream_t st, const TupleDesc* desc, int n_tuples, const TupleCommon* com,
                                const TupleState* state, const double* facc, double* l_out, double* z_out,
                                uint8_t* flags_out, double* f_out, const int8_t* members, int f_stride);
-hipError_t launch_tuple_adjoint(hipStream_t st, int nf, int n_cu, const TupleDesc* desc, const int32_t* order,
+hipError_t launch_tuple_adjoint(hipStream_t st, int nf, int n_cu, int lanes, const TupleDesc* desc, const int32_t* order,
                                 int n_order, int64_t N, const TupleCommon* com, const double* tau, const double* xt,
                                 const double* wt, const double* f, const double* theta, const TupleState* state,
                                 double* dzdf, double* hout, bool f32);

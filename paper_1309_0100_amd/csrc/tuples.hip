@@ -286,6 +286,115 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
 
 constexpr int pidx(int r, int c) { return r * (r + 1) / 2 + c; }
 
+// The forward solve of the tuples of a block from their Gram matrices in LDS
+// (gsh[q TPB + j] = packed lower element q, column order 1, cos/sin pairs,
+// x~, of the block's tuple j): the steps of tuple_solve_kernel's forward mode
+// (merged-frequency test, l_0, Cholesky with the relative pivot test,
+// a = L^{-1} g, l = D - a.a, the acceptance test, theta* = L^{-T} a), then
+// the tuple is done.  Sixteen lanes (one DPP row) take one tuple: lane i
+// holds row i of the augmented matrix [[G, g], [g^T, D]] (C = 2 NF + 2 rows),
+// whose Cholesky factor has a = L^{-1} g as its last row.  Column j: lane j
+// forms the pivot, its row is broadcast to the other lanes, each lane below
+// finishes its own element; theta* = L^{-T} a runs from the last column back,
+// each step one 16-lane sum of L_kj theta_k.  Every lane of the block runs
+// the same instruction stream (no divergence around the cross-lane steps);
+// only the stores are predicated.
+template <int NF, int TPB>
+__device__ __forceinline__ void fwd_solve_block(const double* gsh, const TupleDesc* __restrict__ desc,
+                                                const int32_t* __restrict__ order, int n_order,
+                                                const TupleCommon* __restrict__ com,
+                                                const double* __restrict__ ftry, double* __restrict__ facc,
+                                                double* __restrict__ theta, TupleState* __restrict__ state) {
+  constexpr int C = 2 * NF + 2;  // rows of the augmented matrix
+  constexpr int K = C - 1;       // the data row
+  static_assert(C <= 16, "one DPP row per tuple");
+  const int i = threadIdx.x & 15;
+  const int lane = threadIdx.x & 63;
+  for (int p = 0; p < (TPB + 15) / 16; ++p) {
+    const int tb = p * 16 + (threadIdx.x >> 4);
+    const int g2 = blockIdx.x * TPB + tb;
+    const bool valid = tb < TPB && g2 < n_order;
+    const int t2 = valid ? order[g2] : 0;
+    const bool live = valid && !state[t2].done;
+    const int tbc = tb < TPB ? tb : 0;
+    // row i (zero beyond the matrix)
+    double r[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) r[k] = (i < C && k <= i) ? gsh[((i * (i + 1)) / 2 + k) * TPB + tbc] : 0.0;
+    const double g00 = __shfl(r[0], 0, 16);
+    const double l0 = r[K] - r[0] * r[0] / g00;  // on lane K
+    bool own_ok = true;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      double piv = r[j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) piv -= r[k] * r[k];
+      if (i == j) {
+        own_ok = piv > PIVOT_TOL * r[j];
+        r[j] = sqrt(own_ok ? piv : 1.0);
+      }
+      double q[C];
+#pragma unroll
+      for (int k = 0; k <= j; ++k) q[k] = __shfl(r[k], j, 16);
+      const double inv = 1.0 / q[j];
+      if (i > j) {
+        double v = r[j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) v -= r[k] * q[k];
+        r[j] = v * inv;
+      }
+    }
+    // l = D - a.a on lane K
+    double aa = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) aa += r[k] * r[k];
+    const double l = r[K] - aa;
+    const uint64_t bal = __ballot(own_ok);
+    const bool chol_ok = ((bal >> (lane & 48)) & 0xFFFFull) == 0xFFFFull;
+    // theta* = L^{-T} a: lane i keeps theta_i
+    double th = 0.0;
+#pragma unroll
+    for (int j = K - 1; j >= 0; --j) {
+      const double c = (i > j && i < K) ? r[j] * th : 0.0;
+      const double sum = group_sum<16>(c);
+      const double aj = __shfl(r[j], K, 16);
+      if (i == j) th = (aj - sum) / r[j];
+    }
+    // decision on lane K, broadcast to the tuple's lanes
+    int accept = 0;
+    if (i == K && live) {
+      const TupleDesc& d = desc[t2];
+      TupleState& S = state[t2];
+      const double* ft = ftry + d.foff;
+      double f[NF];
+#pragma unroll
+      for (int k = 0; k < NF; ++k) f[k] = ft[k];
+      const double T = com->T_eff;
+      bool degen = false;
+#pragma unroll
+      for (int k = 0; k < NF; ++k)
+#pragma unroll
+        for (int m = k + 1; m < NF; ++m) degen |= fabs(f[k] - f[m]) * T < MASK_WIDTH;
+      const bool ok = chol_ok && !degen;
+      S.done = 1;
+      if (ok && l <= S.l_acc * (1.0 + ACCEPT_RTOL)) {
+        accept = 1;
+        double* fa = facc + d.foff;
+#pragma unroll
+        for (int k = 0; k < NF; ++k) fa[k] = f[k];
+        S.has_acc = 1;
+        S.l_acc = l;
+        S.l0 = l0;
+        S.halvings = 0;
+      } else if (!S.has_acc) {
+        S.flags = FREDEC_FLAG_DEGENERATE;  // the start point itself is degenerate
+      }
+    }
+    accept = __shfl(accept, K, 16);
+    if (accept && i < K) theta[desc[t2].thoff + i] = th;
+  }
+}
+
 // sin/cos(2 pi p) for the lane-group kernels: float64 (sincos_tab with the
 // block's table) or, in the reduced-precision form, the float64 phase
 // reduction p - rint(p) followed by the hardware float32 sin/cos of the
@@ -311,8 +420,10 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_lanes_kernel(const TupleDesc
                                                                  const double* __restrict__ xt,
                                                                  const double* __restrict__ wt,
                                                                  const double* __restrict__ ftry,
-                                                                 const TupleState* __restrict__ state,
-                                                                 double* __restrict__ gram) {
+                                                                 TupleState* __restrict__ state,
+                                                                 double* __restrict__ gram,
+                                                                 double* __restrict__ facc,
+                                                                 double* __restrict__ theta, int fuse) {
   constexpr int C = 2 * NF + 2;
   constexpr int NACC = C * (C + 1) / 2;
   __shared__ double2 tab[F32 ? 1 : TRIG_TAB];
@@ -364,12 +475,28 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_lanes_kernel(const TupleDesc
     acc[q] = group_sum<L>(acc[q]);
     asm volatile("" : "+v"(acc[q]));  // complete each sum here: keeps the register count of the loop
   }
-  if (live && r == 0) {
-    double* G = gram + desc[ti].goff;
-    const int64_t gs = desc[ti].gs;
+  if (!fuse) {
+    if (live && r == 0) {
+      double* G = gram + desc[ti].goff;
+      const int64_t gs = desc[ti].gs;
 #pragma unroll
-    for (int q = 0; q < NACC; ++q) G[q * gs] = acc[q];
+      for (int q = 0; q < NACC; ++q) G[q * gs] = acc[q];
+    }
+    return;
   }
+  // the solve of the forward mode: the block's Gram matrices go to LDS
+  // ([element][tuple of the block]) and the block solves them, sixteen lanes
+  // a tuple (nothing goes to memory but theta*, the state and the accepted
+  // frequencies)
+  constexpr int TPB = BLOCK / L;
+  __shared__ double gsh[NACC * TPB];
+  const int tb = threadIdx.x / L;
+  if (r == 0) {
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) gsh[q * TPB + tb] = acc[q];
+  }
+  __syncthreads();
+  fwd_solve_block<NF, TPB>(gsh, desc, order, n_order, com, ftry, facc, theta, state);
 }
 
 // Element (r, c), r >= c, of a packed lower-triangular matrix stored with
@@ -909,35 +1036,39 @@ hipError_t gram_tv(int TV, hipStream_t st, const TupleDesc* desc, const int32_t*
 }
 
 // Lanes per tuple for a group of n_order tuples of N samples: enough groups
-// of lanes to give every CU 16 waves, at least 16 samples per lane.
+// of lanes to give every CU 16 waves, at least 32 samples per lane (fewer
+// lanes mean fewer partial sums to add per tuple; at N = 1000 and 10^4
+// tuples per size, 16 lanes beat 32 for every size 1..6).
 int lanes_for(int n_order, int64_t N, int n_cu) {
   const int64_t want = 16LL * std::max(n_cu, 1) * 64;  // threads for 16 waves per CU
   int L = 4;
-  while (L < 64 && static_cast<int64_t>(n_order) * L < want && N / (2 * L) >= 16) L *= 2;
+  while (L < 64 && static_cast<int64_t>(n_order) * L < want && N / (2 * L) >= 32) L *= 2;
   return L;
 }
 
 template <int NF, int L, bool F32>
 hipError_t gram_lanes(hipStream_t st, const TupleDesc* desc, const int32_t* order, int n_order,
                       const TupleCommon* com, const double* tau, const double* xt, const double* wt,
-                      const double* ftry, const TupleState* state, double* gram) {
+                      const double* ftry, TupleState* state, double* gram, double* facc, double* theta,
+                      int fuse) {
   const int64_t threads = static_cast<int64_t>(n_order) * L;
   const int blocks = static_cast<int>((threads + BLOCK - 1) / BLOCK);
   tuple_gram_lanes_kernel<NF, L, F32><<<blocks, BLOCK, 0, st>>>(desc, order, n_order, com, tau, xt, wt, ftry, state,
-                                                             gram);
+                                                             gram, facc, theta, fuse);
   return hipGetLastError();
 }
 
 template <int NF, bool F32>
 hipError_t gram_nf(hipStream_t st, int L, const TupleDesc* desc, const int32_t* order, int n_order,
                    const TupleCommon* com, const double* tau, const double* xt, const double* wt,
-                   const double* ftry, const TupleState* state, double* gram) {
+                   const double* ftry, TupleState* state, double* gram, double* facc, double* theta,
+                   int fuse) {
   switch (L) {
-    case 4: return gram_lanes<NF, 4, F32>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-    case 8: return gram_lanes<NF, 8, F32>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-    case 16: return gram_lanes<NF, 16, F32>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-    case 32: return gram_lanes<NF, 32, F32>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-    case 64: return gram_lanes<NF, 64, F32>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+    case 4: return gram_lanes<NF, 4, F32>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse);
+    case 8: return gram_lanes<NF, 8, F32>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse);
+    case 16: return gram_lanes<NF, 16, F32>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse);
+    case 32: return gram_lanes<NF, 32, F32>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse);
+    case 64: return gram_lanes<NF, 64, F32>(st, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1158,31 +1289,31 @@ __global__ __launch_bounds__(BLOCK) void tuple_gather_kernel(const TupleDesc* __
 
 bool tuple_lanes_supported(int n, int mode) { return mode == TUPLE_FWD && n >= 1 && n <= LANES_MAX_N; }
 
-hipError_t launch_tuple_gram(hipStream_t st, int nf, int n_cu, const TupleDesc* desc, const int32_t* order,
+hipError_t launch_tuple_gram(hipStream_t st, int nf, int n_cu, int lanes, const TupleDesc* desc, const int32_t* order,
                              int n_order, int64_t N, const TupleCommon* com, const double* tau, const double* xt,
-                             const double* wt, const double* ftry, const TupleState* state, double* gram,
-                             int mode, bool f32) {
+                             const double* wt, const double* ftry, TupleState* state, double* gram,
+                             int mode, bool f32, double* facc, double* theta, bool fuse_solve) {
   if (n_order <= 0) return hipSuccess;
   if (tuple_lanes_supported(nf, mode)) {
-    const int L = lanes_for(n_order, N, n_cu);
+    const int L = lanes ? lanes : lanes_for(n_order, N, n_cu);
     if (f32) {
       switch (nf) {
-        case 1: return gram_nf<1, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-        case 2: return gram_nf<2, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-        case 3: return gram_nf<3, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-        case 4: return gram_nf<4, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-        case 5: return gram_nf<5, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-        case 6: return gram_nf<6, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+        case 1: return gram_nf<1, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse_solve ? 1 : 0);
+        case 2: return gram_nf<2, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse_solve ? 1 : 0);
+        case 3: return gram_nf<3, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse_solve ? 1 : 0);
+        case 4: return gram_nf<4, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse_solve ? 1 : 0);
+        case 5: return gram_nf<5, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse_solve ? 1 : 0);
+        case 6: return gram_nf<6, true>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse_solve ? 1 : 0);
         default: return hipErrorInvalidValue;
       }
     }
     switch (nf) {
-      case 1: return gram_nf<1, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-      case 2: return gram_nf<2, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-      case 3: return gram_nf<3, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-      case 4: return gram_nf<4, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-      case 5: return gram_nf<5, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
-      case 6: return gram_nf<6, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram);
+      case 1: return gram_nf<1, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse_solve ? 1 : 0);
+      case 2: return gram_nf<2, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse_solve ? 1 : 0);
+      case 3: return gram_nf<3, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse_solve ? 1 : 0);
+      case 4: return gram_nf<4, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse_solve ? 1 : 0);
+      case 5: return gram_nf<5, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse_solve ? 1 : 0);
+      case 6: return gram_nf<6, false>(st, L, desc, order, n_order, com, tau, xt, wt, ftry, state, gram, facc, theta, fuse_solve ? 1 : 0);
       default: return hipErrorInvalidValue;
     }
   }
@@ -1229,13 +1360,13 @@ hipError_t launch_tuple_finish(hipStream_t st, const TupleDesc* desc, int n_tupl
   return hipGetLastError();
 }
 
-hipError_t launch_tuple_adjoint(hipStream_t st, int nf, int n_cu, const TupleDesc* desc, const int32_t* order,
+hipError_t launch_tuple_adjoint(hipStream_t st, int nf, int n_cu, int lanes, const TupleDesc* desc, const int32_t* order,
                                 int n_order, int64_t N, const TupleCommon* com, const double* tau, const double* xt,
                                 const double* wt, const double* f, const double* theta, const TupleState* state,
                                 double* dzdf, double* hout, bool f32) {
   if (n_order <= 0) return hipSuccess;
   if (tuple_lanes_supported(nf, TUPLE_FWD)) {
-    const int L = lanes_for(n_order, N, n_cu);
+    const int L = lanes ? lanes : lanes_for(n_order, N, n_cu);
     if (f32) {
       switch (nf) {
         case 1: return adjoint_nf<1, true>(st, L, desc, order, n_order, com, tau, xt, wt, f, theta, state, dzdf, hout);

@@ -24,6 +24,7 @@ FP32 = 1
 OK, EINVAL, EDOF, EWEIGHT, EDEGEN, ESINGULAR, ENOMEM, EDEVICE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7, -8
 TILE_SCAN_F16X3 = 1
 TILE_SCAN_F32_FORM = 2
+TILE_TUPLE_LANES = 3
 F32_FORM_VALU, F32_FORM_F16X3, F32_FORM_AUTO = 0, 2, 3
 MAX_BASE = 24
 MAX_POOL = 27

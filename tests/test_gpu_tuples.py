@@ -239,11 +239,12 @@ def test_tuple_errors(ctx):
 
 
 @pytest.mark.parametrize("N,n_tuples,size_lo,size_hi", [(4200, 24, 1, 6), (300, 20000, 2, 2), (1000, 3000, 3, 3)],
-                         ids=["64-lane-groups", "4-lane-groups", "32-lane-groups"])
+                         ids=["few-long-tuples", "many-short-tuples", "mid"])
 def test_lane_group_widths(ctx, N, n_tuples, size_lo, size_hi):
     """The VALU tuple kernels split each tuple's samples over 4..64 lanes
-    depending on how many tuples share a size; every width must agree with
-    the oracle (z and dz/df on a sample of the tuples)."""
+    depending on N and how many tuples share a size (64, 8 and 16 lanes
+    here); every width must agree with the oracle (z and dz/df on a sample
+    of the tuples)."""
     s = synth.random_series(760 + N, N, span=500.0, n_sin=3)
     nrm = O.normalize(s.t, s.x, s.w)
     rng = np.random.default_rng(N)
@@ -263,6 +264,51 @@ def test_lane_group_widths(ctx, N, n_tuples, size_lo, size_hi):
         assert zerr(z[k], zr) <= TOL64, (k, z[k], zr)
         scale = np.maximum(np.abs(gr), 1e-3 * nrm.T_eff * max(zr, 1.0))
         assert np.max(np.abs(g[toff[k]:toff[k + 1]] - gr) / scale) < 1e-8
+
+
+def test_lane_width_setting(ctx):
+    """Lanes per tuple forced through the tile setting (4..64 for every size
+    1..6): z, dz/df and the forward solve made in the Gram kernel agree with
+    the oracle at every width and with each other; bad settings are
+    rejected."""
+    from paper_1309_0100_amd import fredec as F
+    s = synth.random_series(771, 1000, span=500.0, n_sin=3)
+    nrm = O.normalize(s.t, s.x, s.w)
+    rng = np.random.default_rng(771)
+    pool = np.concatenate([s.true_f, rng.uniform(0.05, 0.9, size=5)])
+    sizes = rng.integers(1, 7, size=300)
+    toff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    f = np.concatenate([np.sort(rng.choice(pool, size=k, replace=False)) + rng.uniform(-0.2, 0.2, size=k) / nrm.T_eff
+                        for k in sizes])
+    out = {}
+    try:
+        for L in (4, 8, 16, 32, 64):
+            for n in range(1, 7):
+                ctx.set_tile(F.TILE_TUPLE_LANES, n, L)
+            print(f"case: forced lanes L={L}", flush=True)
+            out[L] = [a.cpu().numpy() for a in ctx.grad(s.t, s.x, s.w, f, toff)]
+    finally:
+        for n in range(1, 7):
+            ctx.set_tile(F.TILE_TUPLE_LANES, n, 0)
+    for k in np.unique(np.linspace(0, sizes.size - 1, 30).astype(int)):
+        fk = f[toff[k]:toff[k + 1]]
+        zr, lr, gr, hr = O.tuple_grad(nrm, fk)
+        for L, (z, l, th, g, h, fl) in out.items():
+            if not np.isfinite(zr):
+                assert fl[k] & 8, (L, k)
+                continue
+            assert zerr(z[k], zr) <= TOL64, (L, k, z[k], zr)
+            scale = np.maximum(np.abs(gr), 1e-3 * nrm.T_eff * max(zr, 1.0))
+            assert np.max(np.abs(g[toff[k]:toff[k + 1]] - gr) / scale) < 1e-8, (L, k)
+    z4 = out[4][0]
+    for L, (z, l, th, g, h, fl) in out.items():
+        assert np.array_equal(fl, out[4][5])
+        good = np.isfinite(z4)
+        assert np.max(zerr(z[good], z4[good])) <= 1e-11, L
+    for key, val in ((0, 8), (7, 8), (3, 12), (3, 128)):
+        with pytest.raises(F.FredecError) as e:
+            ctx.set_tile(F.TILE_TUPLE_LANES, key, val)
+        assert e.value.code == F.EINVAL
 
 
 TOL32 = 1e-6
