@@ -472,17 +472,19 @@ def tuples_leg(ctx, dev, fp32, steps, n_steps=20):
     sec, per = timed(ctx, step, steps, 1)
     nn = np.diff(toff).astype(np.float64)
     C = 2 * nn + 2
-    # per (tuple, sample) and pass: the Gram lower triangle C(C+1)/2 multiply-adds + 12 slots of trig per
-    # member (offset rotation 8 + complex product 4)
-    slots = float(np.sum(C * (C + 1) / 2 + 12 * nn)) * s.N * (n_steps + 1)
+    # per (tuple, sample) and pass: the Gram lower triangle C(C+1)/2 multiply-adds less the n <w sin^2>
+    # that eq. idn gives from <w> - <w cos^2>, + 12 slots of trig per member (offset rotation 8 + complex
+    # product 4)
+    slots = float(np.sum(C * (C + 1) / 2 - nn + 12 * nn)) * s.N * (n_steps + 1)
     t_gram = per["gram"][0]
     fa, zz, ll, ff = res["r"]
     return {"value": nt / sec, "unit": "tuples/s", "tuple_steps_per_s": nt * n_steps / sec,
             "ms_per_call": sec * 1e3, "kernel_ms": {k: v[0] * 1e3 for k, v in per.items()},
             "roofline": {"bound": "alu", "kernel": "tuple_gram_lanes_kernel", "achieved": slots / t_gram / 1e12,
                          "peak": PEAK_VALU_OPS / 1e12, "unit": "Tops/s", "frac": slots / t_gram / PEAK_VALU_OPS,
-                         "algorithmic": "VALU lane-op slots per (tuple, sample) and pass: C(C+1)/2 Gram multiply-adds "
-                                        "(C = 2n+2) + 12 per member for its trig; 21 passes per call"}}, \
+                         "algorithmic": "VALU lane-op slots per (tuple, sample) and pass: C(C+1)/2 - n Gram "
+                                        "multiply-adds (C = 2n+2; the n <w sin^2> follow from eq. idn) + 12 per member "
+                                        "for its trig; 21 passes per call; the kernel also makes the forward solve"}}, \
         (s, f0, toff, fa.cpu().numpy(), zz.cpu().numpy())
 
 

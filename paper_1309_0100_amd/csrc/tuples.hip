@@ -411,9 +411,30 @@ __device__ __forceinline__ void tuple_sincos(double p, const double2* __restrict
   }
 }
 
+// Whether Gram element (a, b) of the lane-group kernels is the <w sin_k^2> of
+// a member, which the float64 form derives as <w> - <w cos_k^2> (eq. idn)
+// instead of summing it.  The float32-trig form sums it: its hardware sin
+// and cos satisfy cos^2 + sin^2 = 1 only to float32 accuracy, and the
+// matrix must stay the Gram of the columns it was built from.
+template <int NF, bool F32>
+__device__ constexpr bool derived_sin2(int a, int b) {
+  return !F32 && a == b && a >= 2 && a <= 2 * NF && a % 2 == 0;
+}
+
+// Whether a lane-group Gram kernel is held to 256 registers, two waves per
+// SIMD: the float64 form at NF = 6, whose 99 summed Gram elements (eq. idn
+// saves six) then fit with the sample loop unspilled (measured 19% faster
+// than one wave per SIMD in 292 registers).  The float32-trig form sums all
+// 105 and measured slower that way.
+template <int NF, bool F32>
+__host__ __device__ constexpr bool lanes_two_waves() {
+  return NF >= 6 && !F32;
+}
+
 // L lanes per tuple; the tuples of one launch all have NF frequencies.
 template <int NF, int L, bool F32>
-__global__ __launch_bounds__(BLOCK) void tuple_gram_lanes_kernel(const TupleDesc* __restrict__ desc,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(lanes_two_waves<NF, F32>() ? 2 : 1)))
+void tuple_gram_lanes_kernel(const TupleDesc* __restrict__ desc,
                                                                  const int32_t* __restrict__ order, int n_order,
                                                                  const TupleCommon* __restrict__ com,
                                                                  const double* __restrict__ tau,
@@ -445,15 +466,32 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_lanes_kernel(const TupleDesc
   for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
   if (live) {
     const int64_t N = com->N;
-    // the next sample's tau, w~, x~ are loaded while this one is processed
-    double nta = r < N ? tau[r] : 0.0, nwi = r < N ? wt[r] : 0.0, nxi = r < N ? xt[r] : 0.0;
+    // the next sample's tau, w~, x~ are loaded while this one is processed,
+    // except in the kernels held to 256 registers for two waves per SIMD
+    // (there the three values would be spilled to scratch)
+    constexpr bool PREFETCH = !lanes_two_waves<NF, F32>();
+    double nta = 0.0, nwi = 0.0, nxi = 0.0;
+    if (PREFETCH && r < N) {
+      nta = tau[r];
+      nwi = wt[r];
+      nxi = xt[r];
+    }
 #pragma unroll 1
     for (int64_t i = r; i < N; i += L) {
-      const double ta = nta, wi = nwi, xi = nxi;
-      if (i + L < N) {
-        nta = tau[i + L];
-        nwi = wt[i + L];
-        nxi = xt[i + L];
+      double ta, wi, xi;
+      if constexpr (PREFETCH) {
+        ta = nta;
+        wi = nwi;
+        xi = nxi;
+        if (i + L < N) {
+          nta = tau[i + L];
+          nwi = wt[i + L];
+          nxi = xt[i + L];
+        }
+      } else {
+        ta = tau[i];
+        wi = wt[i];
+        xi = xt[i];
       }
       double phi[C];
       phi[0] = 1.0;
@@ -465,7 +503,8 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_lanes_kernel(const TupleDesc
         const double wa = wi * phi[a];
         acc[pidx(a, 0)] += wa;
 #pragma unroll
-        for (int b = 1; b <= a; ++b) acc[pidx(a, b)] = __builtin_fma(wa, phi[b], acc[pidx(a, b)]);
+        for (int b = 1; b <= a; ++b)
+          if (!derived_sin2<NF, F32>(a, b)) acc[pidx(a, b)] = __builtin_fma(wa, phi[b], acc[pidx(a, b)]);
       }
     }
   }
@@ -475,6 +514,10 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_lanes_kernel(const TupleDesc
     acc[q] = group_sum<L>(acc[q]);
     asm volatile("" : "+v"(acc[q]));  // complete each sum here: keeps the register count of the loop
   }
+  // <w sin^2> = <w> - <w cos^2> (eq. idn) where it was not summed
+#pragma unroll
+  for (int k = 0; k < NF; ++k)
+    if (derived_sin2<NF, F32>(2 + 2 * k, 2 + 2 * k)) acc[pidx(2 + 2 * k, 2 + 2 * k)] = acc[0] - acc[pidx(1 + 2 * k, 1 + 2 * k)];
   if (!fuse) {
     if (live && r == 0) {
       double* G = gram + desc[ti].goff;
