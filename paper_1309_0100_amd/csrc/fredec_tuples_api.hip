@@ -260,8 +260,16 @@ int run_fit(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev&
             const PoolPass* first = nullptr) {
   const int nt = static_cast<int>(P.desc.size());
   const int mode = refine_steps > 0 ? TUPLE_GN : TUPLE_FWD;
+  // the lane-group kernels solve their tuples in a Gram pass; their groups
+  // are a prefix of `order` (sorted by size), positions 0 .. fused
+  int fused = 0;
+  for (const auto& g : P.groups) {
+    if (!tuple_lanes_supported(g.nf, mode)) break;
+    fused = static_cast<int>(g.begin + g.count);
+  }
   for (int it = 0; it <= refine_steps; ++it) {
     int rc = FREDEC_OK;
+    int sb = 0;  // first position the solve kernel takes
     if (it == 0 && first) {
       ProfScope prof(ctx, st, FREDEC_PROF_GRAM);
       if (launch_tuple_gather(st, D.desc, D.order, nt, D.members, first->pool_gram, first->n_pool, mode, D.gram) !=
@@ -269,11 +277,13 @@ int run_fit(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, const TupleDev&
         return FREDEC_EDEVICE;
     } else {
       rc = gram_pass(ctx, st, P, D, mode);
+      sb = fused;
     }
     if (rc) return rc;
+    if (sb >= nt) continue;
     ProfScope prof(ctx, st, FREDEC_PROF_SOLVE);
-    if (launch_tuple_solve(st, D.desc, D.order, nt, D.com, D.gram, D.scr, D.ftry, D.facc, D.step, D.theta, D.state,
-                           mode, it == refine_steps ? 1 : 0) != hipSuccess)
+    if (launch_tuple_solve(st, D.desc, D.order + sb, nt - sb, D.com, D.gram, D.scr, D.ftry, D.facc, D.step, D.theta,
+                           D.state, mode, it == refine_steps ? 1 : 0) != hipSuccess)
       return FREDEC_EDEVICE;
   }
   return FREDEC_OK;

@@ -424,11 +424,19 @@ __device__ constexpr bool derived_sin2(int a, int b) {
 // Whether a lane-group Gram kernel is held to 256 registers, two waves per
 // SIMD: the float64 form at NF = 6, whose 99 summed Gram elements (eq. idn
 // saves six) then fit with the sample loop unspilled (measured 19% faster
-// than one wave per SIMD in 292 registers).  The float32-trig form sums all
-// 105 and measured slower that way.
+// than one wave per SIMD).  The float32-trig form sums all 105: held to 256
+// registers it spills inside the sample loop.
 template <int NF, bool F32>
 __host__ __device__ constexpr bool lanes_two_waves() {
   return NF >= 6 && !F32;
+}
+
+// Whether packed element q = pidx(a, b) is such a derived <w sin_k^2>.
+template <int NF, bool F32>
+__device__ constexpr bool derived_sin2_at(int q) {
+  for (int k = 0; k < NF; ++k)
+    if (derived_sin2<NF, F32>(2 + 2 * k, 2 + 2 * k) && q == pidx(2 + 2 * k, 2 + 2 * k)) return true;
+  return false;
 }
 
 // L lanes per tuple; the tuples of one launch all have NF frequencies.
@@ -508,37 +516,42 @@ void tuple_gram_lanes_kernel(const TupleDesc* __restrict__ desc,
       }
     }
   }
-  // add the L partial sums of the group (fixed order: deterministic)
-#pragma unroll
-  for (int q = 0; q < NACC; ++q) {
-    acc[q] = group_sum<L>(acc[q]);
-    asm volatile("" : "+v"(acc[q]));  // complete each sum here: keeps the register count of the loop
-  }
-  // <w sin^2> = <w> - <w cos^2> (eq. idn) where it was not summed
-#pragma unroll
-  for (int k = 0; k < NF; ++k)
-    if (derived_sin2<NF, F32>(2 + 2 * k, 2 + 2 * k)) acc[pidx(2 + 2 * k, 2 + 2 * k)] = acc[0] - acc[pidx(1 + 2 * k, 1 + 2 * k)];
-  if (!fuse) {
-    if (live && r == 0) {
-      double* G = gram + desc[ti].goff;
-      const int64_t gs = desc[ti].gs;
-#pragma unroll
-      for (int q = 0; q < NACC; ++q) G[q * gs] = acc[q];
-    }
-    return;
-  }
-  // the solve of the forward mode: the block's Gram matrices go to LDS
-  // ([element][tuple of the block]) and the block solves them, sixteen lanes
-  // a tuple (nothing goes to memory but theta*, the state and the accepted
-  // frequencies)
+  // The L partial sums of the group are added (fixed order: deterministic)
+  // and the block's Gram matrices go to LDS ([element][tuple of the block])
+  // one element at a time, so that each accumulator is free once stored.
   constexpr int TPB = BLOCK / L;
   __shared__ double gsh[NACC * TPB];
   const int tb = threadIdx.x / L;
+#pragma unroll
+  for (int q = 0; q < NACC; ++q) {
+    if (derived_sin2_at<NF, F32>(q)) continue;
+    acc[q] = group_sum<L>(acc[q]);
+    asm volatile("" : "+v"(acc[q]));  // complete each sum here: keeps the register count of the loop
+    if (r == 0) gsh[q * TPB + tb] = acc[q];
+  }
+  // <w sin^2> = <w> - <w cos^2> (eq. idn) where it was not summed
   if (r == 0) {
 #pragma unroll
-    for (int q = 0; q < NACC; ++q) gsh[q * TPB + tb] = acc[q];
+    for (int k = 0; k < NF; ++k)
+      if (derived_sin2<NF, F32>(2 + 2 * k, 2 + 2 * k))
+        gsh[pidx(2 + 2 * k, 2 + 2 * k) * TPB + tb] = acc[0] - acc[pidx(1 + 2 * k, 1 + 2 * k)];
   }
   __syncthreads();
+  if (!fuse) {
+    // the Gram matrices to memory, element-major across the block's tuples
+    for (int e = threadIdx.x; e < NACC * TPB; e += BLOCK) {
+      const int q = e / TPB, j = e % TPB;
+      const int g2 = blockIdx.x * TPB + j;
+      if (g2 >= n_order) continue;
+      const int t2 = order[g2];
+      if (state[t2].done) continue;
+      gram[desc[t2].goff + static_cast<int64_t>(q) * desc[t2].gs] = gsh[e];
+    }
+    return;
+  }
+  // the solve of the forward mode: the block solves its tuples, sixteen
+  // lanes a tuple (nothing goes to memory but theta*, the state and the
+  // accepted frequencies)
   fwd_solve_block<NF, TPB>(gsh, desc, order, n_order, com, ftry, facc, theta, state);
 }
 
