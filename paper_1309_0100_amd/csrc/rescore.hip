@@ -65,43 +65,37 @@ __device__ __forceinline__ int series_of(const int64_t* __restrict__ o, int n, i
   return lo;
 }
 
-// Schur epilogue of one re-scored point from its 2 KP + 3 sums (constant
-// indices only, so the sums stay in registers; the data column is the sum
-// pair of q = KP - 1).
-template <int KPMAX>
-__device__ __forceinline__ void rescore_finish(const double (&acc)[2 * KPMAX + 3], int KP, double f,
-                                               const SeriesIn& si, const SeriesHdr& h, double& z, uint8_t& fl) {
-  const int K = KP - 1;
+// Schur epilogue of one re-scored point from its 2 KP + 3 sums (the data
+// column is the sum pair of column KP - 1).
+template <int KP>
+__device__ __forceinline__ void rescore_finish(const double (&acc)[2 * KP + 3], double f, const SeriesIn& si,
+                                               const SeriesHdr& h, double& z, uint8_t& fl) {
+  constexpr int K = KP - 1;
   const double cc = acc[2], ss = acc[4];
-  double Scc = cc, Scs = acc[3], Sss = ss, hc = 0.0, hs = 0.0;
+  double Scc = cc, Scs = acc[3], Sss = ss;
 #pragma unroll
-  for (int q = 0; q < KPMAX; ++q) {
+  for (int q = 0; q < K; ++q) {
     const double uc = (q == 0) ? acc[0] : acc[3 + 2 * q];
     const double us = (q == 0) ? acc[1] : acc[4 + 2 * q];
-    if (q < K) {
-      Scc = __builtin_fma(-uc, uc, Scc);
-      Scs = __builtin_fma(-uc, us, Scs);
-      Sss = __builtin_fma(-us, us, Sss);
-    } else if (q == K) {
-      hc = uc;
-      hs = us;
-    }
+    Scc = __builtin_fma(-uc, uc, Scc);
+    Scs = __builtin_fma(-uc, us, Scs);
+    Sss = __builtin_fma(-us, us, Sss);
   }
+  const double hc = (K == 0) ? acc[0] : acc[3 + 2 * K];
+  const double hs = (K == 0) ? acc[1] : acc[4 + 2 * K];
   schur_finish(Scc, Scs, Sss, cc, ss, hc, hs, f, si, h, z, fl);
 }
 
 // Sums of one sample for one frequency (phase reduction and sin/cos in
-// float64): the 2 KP + 3 entries of acc.
-template <int KPMAX>
-__device__ __forceinline__ void rescore_sample(const double* __restrict__ q, int KP, double f,
-                                               const double2* __restrict__ tab, double (&acc)[2 * KPMAX + 3]) {
-  // the record's columns are read in groups of four with clamped indices
-  // (always inside the record), so that a group's loads issue together
-  // instead of one guarded load after another
-  constexpr int GR = 4;
-  double g[GR];
+// float64): the 2 KP + 3 entries of acc.  KP is the exact column count of
+// the series, so the record's columns are loads at constant offsets (wide
+// scalar loads where the record is uniform across the wave).
+template <int KP>
+__device__ __forceinline__ void rescore_sample(const double* __restrict__ q, double f,
+                                               const double2* __restrict__ tab, double (&acc)[2 * KP + 3]) {
+  double g[KP];
 #pragma unroll
-  for (int k = 0; k < GR; ++k) g[k] = q[3 + (k < KP ? k : KP - 1)];
+  for (int k = 0; k < KP; ++k) g[k] = q[3 + k];
   double sv, cv;
   sincos_tab(f * q[0], tab, sv, cv);
   const double tc = g[0] * cv, tsn = g[0] * sv;
@@ -111,20 +105,87 @@ __device__ __forceinline__ void rescore_sample(const double* __restrict__ q, int
   acc[3] = __builtin_fma(tc, sv, acc[3]);
   acc[4] = __builtin_fma(tsn, sv, acc[4]);
 #pragma unroll
-  for (int k0 = 0; k0 < KPMAX; k0 += GR) {
-    if (k0 > 0 && k0 < KP) {
-#pragma unroll
-      for (int k = 0; k < GR; ++k) g[k] = q[3 + (k0 + k < KP ? k0 + k : KP - 1)];
-    }
-#pragma unroll
-    for (int k = 0; k < GR; ++k) {
-      if (k0 + k >= 1 && k0 + k < KPMAX && k0 + k < KP) {
-        acc[3 + 2 * (k0 + k)] = __builtin_fma(g[k], cv, acc[3 + 2 * (k0 + k)]);
-        acc[4 + 2 * (k0 + k)] = __builtin_fma(g[k], sv, acc[4 + 2 * (k0 + k)]);
-      }
-    }
+  for (int k = 1; k < KP; ++k) {
+    acc[3 + 2 * k] = __builtin_fma(g[k], cv, acc[3 + 2 * k]);
+    acc[4 + 2 * k] = __builtin_fma(g[k], sv, acc[4 + 2 * k]);
   }
 }
+
+// One wavefront's chunk of up to 64 points of one series (one lane per
+// point; `live` lanes past the series' count compute but store nothing).
+template <int KP>
+__device__ __forceinline__ void rescore_chunk(const SeriesIn& si, const SeriesHdr& h, const double* __restrict__ rec,
+                                              const double2* __restrict__ tab, int64_t j, bool live,
+                                              double* __restrict__ z_out, uint8_t* __restrict__ flags_out) {
+  constexpr int P = rec_stride(KP);
+  const double f = static_cast<double>(j + 1) * si.df;
+  double acc[2 * KP + 3];
+#pragma unroll
+  for (int q = 0; q < 2 * KP + 3; ++q) acc[q] = 0.0;
+  const double* __restrict__ qr = rec + si.rec_off;
+#pragma unroll 2
+  for (int64_t i = 0; i < si.N; ++i) rescore_sample<KP>(qr + i * P, f, tab, acc);
+  if (live) {
+    double z;
+    uint8_t fl;
+    rescore_finish<KP>(acc, f, si, h, z, fl);
+    z_out[si.goff + j] = z;
+    if (flags_out) flags_out[si.goff + j] = fl | FREDEC_FLAG_RESCORED;
+  }
+}
+
+// One point over a workgroup (samples over its lanes; the waves' sums added
+// in wave order through `part`, which holds at least 2 KP + 3 doubles per wave).
+template <int KP>
+__device__ __forceinline__ void rescore_point_block(const SeriesIn& si, const SeriesHdr& h,
+                                                    const double* __restrict__ rec, const double2* __restrict__ tab,
+                                                    int64_t j, double* part, int part_stride,
+                                                    double* __restrict__ z_out, uint8_t* __restrict__ flags_out) {
+  constexpr int P = rec_stride(KP);
+  constexpr int NS = 2 * KP + 3;
+  constexpr int NW = BLOCK / 64;
+  const int lane = threadIdx.x & 63;
+  const int wb = threadIdx.x >> 6;
+  const double f = static_cast<double>(j + 1) * si.df;
+  double acc[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) acc[q] = 0.0;
+  const double* q0 = rec + si.rec_off;
+#pragma unroll 1
+  for (int64_t i = threadIdx.x; i < si.N; i += BLOCK) rescore_sample<KP>(q0 + i * P, f, tab, acc);
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    acc[q] = group_sum<64>(acc[q]);
+    asm volatile("" : "+v"(acc[q]));  // one sum at a time: keeps the register count down
+    if (lane == 0) part[wb * part_stride + q] = acc[q];
+  }
+  __syncthreads();
+  // the waves' sums added in wave order, one thread per sum, into wave 0's slots
+  for (int q = threadIdx.x; q < NS; q += BLOCK) {
+    double v = part[q];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += part[w * part_stride + q];
+    part[q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) acc[q] = part[q];
+    double z;
+    uint8_t fl;
+    rescore_finish<KP>(acc, f, si, h, z, fl);
+    z_out[si.goff + j] = z;
+    if (flags_out) flags_out[si.goff + j] = fl | FREDEC_FLAG_RESCORED;
+  }
+  __syncthreads();  // part is reused by the next point
+}
+
+// Dispatch on the series' column count KP = 2 m + 2 (uniform over the
+// workgroup's current item) to the body compiled for it; KP <= KPMAX.
+#define FREDEC_RESCORE_KP_CASES(X) \
+  X(2) X(4) X(6) X(8) X(10) X(12) X(14) X(16) X(18) X(20) X(22) X(24) X(26) X(28) X(30) X(32) X(34) X(36) \
+  X(38) X(40) X(42) X(44) X(46) X(48) X(50)
+static_assert(MAXKP == 50, "the KP cases cover 2 .. MAXKP");
 
 // float64 re-scoring, many points: series s's points sit at list[goff_s ..
 // goff_s + count[s]) and are taken in chunks of 64, one wavefront per chunk
@@ -140,7 +201,6 @@ __global__ __launch_bounds__(BLOCK) void rescore_lanes_kernel(int n_series, cons
                                                               const int64_t* __restrict__ off,
                                                               double* __restrict__ z_out,
                                                               uint8_t* __restrict__ flags_out) {
-  constexpr int NS = 2 * KPMAX + 3;
   __shared__ double2 tab[TRIG_TAB];
   if (off[2 * n_series + 2] != 1) return;  // uniform over the grid
   trig_table_fill(tab);
@@ -156,20 +216,14 @@ __global__ __launch_bounds__(BLOCK) void rescore_lanes_kernel(int n_series, cons
     const int64_t k = (c - off[s]) * 64 + lane;
     const bool live = k < static_cast<int64_t>(count[s]);
     const int64_t j = live ? list[si.goff + k].j : 0;
-    const int KP = si.KP;
-    const int P = rec_stride(KP);
-    const double f = static_cast<double>(j + 1) * si.df;
-    double acc[NS];
-#pragma unroll
-    for (int q = 0; q < NS; ++q) acc[q] = 0.0;
-    const double* __restrict__ qr = rec + si.rec_off;
-    for (int64_t i = 0; i < si.N; ++i, qr += P) rescore_sample<KPMAX>(qr, KP, f, tab, acc);
-    if (live) {
-      double z;
-      uint8_t fl;
-      rescore_finish<KPMAX>(acc, KP, f, si, h, z, fl);
-      z_out[si.goff + j] = z;
-      if (flags_out) flags_out[si.goff + j] = fl | FREDEC_FLAG_RESCORED;
+    switch (si.KP) {
+#define X(kp)                                                                   \
+  case kp:                                                                      \
+    if constexpr (kp <= KPMAX) rescore_chunk<kp>(si, h, rec, tab, j, live, z_out, flags_out); \
+    break;
+      FREDEC_RESCORE_KP_CASES(X)
+#undef X
+      default: break;
     }
   }
 }
@@ -188,12 +242,10 @@ __global__ __launch_bounds__(BLOCK) void rescore_wave_kernel(int n_series, const
   constexpr int NS = 2 * KPMAX + 3;
   constexpr int NW = BLOCK / 64;
   __shared__ double2 tab[TRIG_TAB];
-  __shared__ double part[NW][NS];  // the waves' sums of the current point
+  __shared__ double part[NW * NS];  // the waves' sums of the current point
   if (off[2 * n_series + 2] != 0) return;  // uniform over the grid
   trig_table_fill(tab);
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int wb = threadIdx.x >> 6;
   const int64_t* poff = off + n_series + 1;
   const int64_t n_pts = poff[n_series];
   // one workgroup per point (few points: the samples over all 256 lanes keep
@@ -203,39 +255,15 @@ __global__ __launch_bounds__(BLOCK) void rescore_wave_kernel(int n_series, const
     const SeriesIn& si = sin_[s];
     const SeriesHdr& h = hdr[s];
     const int64_t j = list[si.goff + (e - poff[s])].j;
-    const int KP = si.KP;
-    const int P = rec_stride(KP);
-    const double f = static_cast<double>(j + 1) * si.df;
-    double acc[NS];
-#pragma unroll
-    for (int q = 0; q < NS; ++q) acc[q] = 0.0;
-    const double* q0 = rec + si.rec_off;
-    for (int64_t i = threadIdx.x; i < si.N; i += BLOCK) rescore_sample<KPMAX>(q0 + i * P, KP, f, tab, acc);
-#pragma unroll
-    for (int q = 0; q < NS; ++q) {
-      if (q < 2 * KP + 3) {
-        acc[q] = group_sum<64>(acc[q]);
-        if (lane == 0) part[wb][q] = acc[q];
-      }
+    switch (si.KP) {
+#define X(kp)                                                                                 \
+  case kp:                                                                                    \
+    if constexpr (kp <= KPMAX) rescore_point_block<kp>(si, h, rec, tab, j, part, NS, z_out, flags_out); \
+    break;
+      FREDEC_RESCORE_KP_CASES(X)
+#undef X
+      default: break;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int q = 0; q < NS; ++q) {
-        if (q < 2 * KP + 3) {
-          double v = part[0][q];
-#pragma unroll
-          for (int w = 1; w < NW; ++w) v += part[w][q];
-          acc[q] = v;
-        }
-      }
-      double z;
-      uint8_t fl;
-      rescore_finish<KPMAX>(acc, KP, f, si, h, z, fl);
-      z_out[si.goff + j] = z;
-      if (flags_out) flags_out[si.goff + j] = fl | FREDEC_FLAG_RESCORED;
-    }
-    __syncthreads();  // part is reused by the next point
   }
 }
 
