@@ -93,7 +93,7 @@ __device__ Peak block_best(Peak p, Peak* sh) {
   sh[threadIdx.x] = p;
   __syncthreads();
   for (int s = BLOCK / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] = better(sh[threadIdx.x], sh[threadIdx.x + s]);
+    if (static_cast<int>(threadIdx.x) < s) sh[threadIdx.x] = better(sh[threadIdx.x], sh[threadIdx.x + s]);
     __syncthreads();
   }
   return sh[0];

@@ -62,7 +62,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // MFMA costs that of 16 float64 multiply-adds.
 template <int NB, int TV>
 __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __restrict__ desc,
-                                                           const int32_t* __restrict__ order, int n_order,
+                                                           const int32_t* __restrict__ order,
+                                                           int /* n_order: one block per tuple */,
                                                            const TupleCommon* __restrict__ com,
                                                            const double* __restrict__ tau, const double* __restrict__ xt,
                                                            const double* __restrict__ wt,
@@ -1236,7 +1237,7 @@ __global__ __launch_bounds__(BLOCK) void tuple_vuong_kernel(int ref, const Tuple
   s2[threadIdx.x] = a2;
   __syncthreads();
   for (int h = BLOCK / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) {
+    if (static_cast<int>(threadIdx.x) < h) {
       s1[threadIdx.x] += s1[threadIdx.x + h];
       s2[threadIdx.x] += s2[threadIdx.x + h];
     }
