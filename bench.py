@@ -737,6 +737,7 @@ def main():
             tl[k], data = tuples_leg(ctx, dev, fp32, args.steps)
             tl[k]["max_err_vs_oracle"] = tuples_error(data)
         res.update({"value": tl["fp32"]["value"], "unit": "tuples/s", "ms_per_step": tl["fp32"]["ms_per_call"],
+                    "speedup_fp32_over_fp64": tl["fp64"]["ms_per_call"] / tl["fp32"]["ms_per_call"],
                     "dtype": "f32", "roofline": tl["fp32"]["roofline"],
                     "config": {"workload": "tuple ascent: N=1000 over 3000 d, 65536 tuples of 1..6 perturbed peaks, "
                                            "20 steps", "form": "fp32"}, "forms": tl})
