@@ -283,17 +283,23 @@ def full_errors(ctx, s, dev, res32, res64):
             err[k] = max(err[k], abs(res.ltab[S] - r.l) / r.l)
     e["refined_l_rel_err_vs_oracle"] = err
     e["refined_subsets_checked"] = len(masks)
-    # the last Phase 1 scan (base = every SLICK frequency of the pass) in both forms
-    base = res64.base
+    # every Phase 1 scan of the pass (scan k has the first k SLICK frequencies as its base) in both
+    # forms, compared at every grid point where neither is flagged
     t, x, w = (torch.as_tensor(a, device=dev) for a in (s.t, s.x, s.w))
-    z32, f32_, _, _ = ctx.scan_series(t, x, w, base, s.df, s.F, precision=fredec.FP32)
-    z64, f64_, _, _ = ctx.scan_series(t, x, w, base, s.df, s.F, precision=fredec.FP64)
-    good = (f32_ == 0) & (f64_ == 0) & torch.isfinite(z64)
-    rel = (z32 - z64).abs() / torch.clamp(z64.abs(), min=1.0)
-    e["last_scan_m"] = int(base.size)
-    e["last_scan_z_rel_err_fp32_vs_fp64"] = float(rel[good].max().item())
-    e["last_scan_points_compared"] = int(good.sum().item())
-    e["last_scan_points_rescored_fp32"] = int(((f32_ & 64) != 0).sum().item())
+    per_scan = []
+    for k in range(res64.n_scans):
+        base = res64.base[:k]
+        z32, f32_, _, _ = ctx.scan_series(t, x, w, base, s.df, s.F, precision=fredec.FP32)
+        z64, f64_, _, _ = ctx.scan_series(t, x, w, base, s.df, s.F, precision=fredec.FP64)
+        good = ((f32_ & ~64) == 0) & (f64_ == 0) & torch.isfinite(z64)
+        rel = (z32 - z64).abs() / torch.clamp(z64.abs(), min=1.0)
+        per_scan.append((float(rel[good].max().item()), int(good.sum().item()), int(((f32_ & 64) != 0).sum().item())))
+    e["scans_z_rel_err_fp32_vs_fp64"] = [v[0] for v in per_scan]
+    e["scans_z_rel_err_fp32_vs_fp64_max"] = max(v[0] for v in per_scan)
+    e["scans_points_compared"] = sum(v[1] for v in per_scan)
+    e["scans_points_rescored_fp32"] = sum(v[2] for v in per_scan)
+    e["last_scan_m"] = int(res64.n_scans - 1)
+    e["last_scan_z_rel_err_fp32_vs_fp64"] = per_scan[-1][0]
     return e
 
 

@@ -184,6 +184,29 @@ def test_full_pipeline_forms_agree(full_runs):
     assert [s.mask for s in a.solutions] == [s.mask for s in b.solutions]
 
 
+def test_full_pass_fp32_scans_within_bound(ctx, full_runs):
+    """Every Phase 1 scan of the full pass (base m = 0 .. 17: the float32
+    VALU kernel, the split-float16 kernel at one, two and three column tiles,
+    float64 re-scoring) in the float32 form against the float64 form at every
+    grid point that neither flags: within the float32 bound 1e-6 (relative to
+    max(1, z)); flags other than the re-scoring mark equal."""
+    import torch
+    from paper_1309_0100_amd import fredec as F
+    s, runs = full_runs
+    res = runs[0]
+    t, x, w = (torch.as_tensor(a, device="cuda") for a in (s.t, s.x, s.w))
+    for k in range(res.n_scans):
+        base = res.base[:k]
+        print(f"case: full pass scan {k} fp32 vs fp64", flush=True)
+        z32, f32, _, st32 = ctx.scan_series(t, x, w, base, s.df, s.F, precision=F.FP32)
+        z64, f64, _, st64 = ctx.scan_series(t, x, w, base, s.df, s.F, precision=F.FP64)
+        assert int(st32.item()) == 0 and int(st64.item()) == 0
+        assert torch.equal(f32 & ~64, f64), k
+        good = (f64 == 0) & torch.isfinite(z64)
+        rel = (z32 - z64).abs() / torch.clamp(z64.abs(), min=1.0)
+        assert float(rel[good].max().item()) <= TOL[1], (k, float(rel[good].max().item()))
+
+
 def test_full_phase1_decisions(ctx, full_runs):
     """Every Phase 1 decision of the full pass checked against the oracle at
     the grid points it rests on: in each scan (base = the SLICK frequencies
