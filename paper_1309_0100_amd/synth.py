@@ -164,9 +164,13 @@ def _resolved_base(rng, injected, m, res):
 
 
 def batched(n_series: int = 4096, F: int = 65536, fmax: float = 2.0,
-            n_lo: int = 50, n_hi: int = 5000, m_max: int = 6) -> Batch:
-    """Workload 3: many independent series of uneven length and base size
-    (base frequencies resolved, see _resolved_base)."""
+            n_lo: int = 50, n_hi: int = 5000, m_max: int = 6, resolved: bool = True) -> Batch:
+    """Workload 3: many independent series of uneven length and base size.
+    resolved=True (the benchmark): base frequencies resolved, see
+    _resolved_base.  resolved=False: the plain draw, the first min(m, n_inj)
+    injected frequencies then log-uniform periods in [2, 1000] d, which can
+    put two base frequencies (or one and zero) closer than the series
+    resolves, i.e. a singular or nearly singular base."""
     root = np.random.SeedSequence(SEED_BASE + 3)
     ts, xs, ws, bfs = [], [], [], []
     soff = [0]
@@ -182,7 +186,11 @@ def batched(n_series: int = 4096, F: int = 65536, fmax: float = 2.0,
         sigma = rng.uniform(1.0, 3.0, size=N)
         x = _signal(rng, t, 1.0 / periods, amps, sigma)
         m = int(rng.integers(0, m_max + 1))
-        base = _resolved_base(rng, 1.0 / periods, m, 1.5 / T)
+        if resolved:
+            base = _resolved_base(rng, 1.0 / periods, m, 1.5 / T)
+        else:
+            base = np.concatenate([1.0 / periods[:min(m, n_inj)],
+                                   1.0 / _log_uniform(rng, 2.0, 1000.0, size=max(0, m - n_inj))])
         ts.append(t)
         xs.append(x)
         ws.append(1.0 / sigma**2)

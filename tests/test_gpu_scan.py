@@ -133,6 +133,69 @@ def test_residual_workload_sampled(ctx):
     assert fl.sum() > 0 and np.all(z[fl == 1] == 0)
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_batched_plain_base_recipe(ctx, prec):
+    """The batched workload with its base frequencies drawn without the
+    resolution rule (the first injected frequencies, then log-uniform periods
+    in [2, 1000] d: some bases are nearly singular, one of the 4096 singular).
+    A series whose base the oracle finds singular gets status ESINGULAR, z
+    NaN and flag 128 at every grid point (where the oracle's smallest
+    relative pivot is within 100x of the 1e-13 threshold either outcome is
+    accepted); every other series has status 0 and z within the bound scaled
+    by the conditioning of the trial columns and of the base (R22), on 16
+    sampled grid points of the 37 worst-conditioned and 64 random series.
+    With an ill-conditioned base (smallest relative pivot rho_b of its normal
+    matrix) the two conditionings compound, in any float64 evaluation, the
+    oracle's included: the Schur block of the trial columns carries a
+    relative error of about eps / (rho_t rho_b), so R22's trial-column term
+    takes rho_t rho_b in place of rho_t; and l carries rounding errors of
+    about eps / rho_b relative, which z = (N - 3m - 4)/2 ln(l_m / l_{m+1})
+    turns into N eps / rho_b, allowed 64 times over."""
+    from paper_1309_0100_amd import fredec as F
+    b = synth.batched(4096, F=2048, resolved=False)
+    print(f"case: batched plain base recipe prec={prec}", flush=True)
+    z, fl, _, st = ctx.scan(b.t, b.x, b.w, b.soff, b.base_f, b.boff, b.df, b.F, precision=prec)
+    z, fl, st = z.cpu().numpy(), fl.cpu().numpy(), st.cpu().numpy()
+    goff = np.concatenate([[0], np.cumsum(b.F)])
+    relmin = np.ones(b.n_series)
+    for s in range(b.n_series):
+        se = b.series(s)
+        if se.base_f.size:
+            nrm = O.normalize(se.t, se.x, se.w)
+            Phi = O.design(nrm.tau, se.base_f)
+            _, _, rel = O.cholesky_checked((Phi * nrm.wt[:, None]).T @ Phi, pivots=True)
+            relmin[s] = rel.min()
+    rng = np.random.default_rng(3)
+    check = set(np.argsort(relmin)[:37].tolist()) | set(rng.choice(b.n_series, 64, replace=False).tolist())
+    tol0 = TOL64 if prec == 0 else 1e-6
+    n_sing, worst = 0, 0.0
+    for s in sorted(check):
+        se = b.series(s)
+        zs, fs = z[goff[s]:goff[s + 1]], fl[goff[s]:goff[s + 1]]
+        borderline = relmin[s] < 1e-11
+        try:
+            idx = np.sort(rng.choice(se.F, 16, replace=False)).astype(np.int64)
+            r = O.scan(se.t, se.x, se.w, se.base_f, se.df, se.F, idx=idx)
+        except ValueError:  # the oracle finds the base singular
+            n_sing += 1
+            assert st[s] == F.ESINGULAR or borderline, (s, st[s], relmin[s])
+            if st[s] == F.ESINGULAR:
+                assert np.all(np.isnan(zs)) and np.all(fs == 128)
+            continue
+        if st[s] != 0:
+            assert borderline and st[s] == F.ESINGULAR, (s, st[s], relmin[s])
+            continue
+        good = (r.flags == 0) & ((fs[idx] & 0xBF) == 0)
+        assert np.array_equal(fs[idx] & 0xBF, r.flags), s
+        bound = np.maximum(tol0 * np.maximum(1.0, 1e-5 / np.maximum(r.rho[good] * relmin[s], 1e-300)),
+                           64.0 * se.t.size * np.finfo(np.float64).eps / relmin[s])
+        e = zerr(zs[idx][good], r.z[good])
+        worst = max(worst, float(np.max(e / bound, initial=0.0)))
+        assert np.all(e <= bound), (s, relmin[s], float(e.max()), float(bound.min()))
+    print(f"largest error / bound: {worst:.3g}; singular bases: {n_sing}", flush=True)
+    assert n_sing == int(np.sum(relmin[sorted(check)] <= 1e-13))
+
+
 def test_per_series_status_and_outputs(ctx):
     """Device-side validation: bad weight, degenerate x, singular base."""
     s = synth.random_series(300, 120, n_sin=1)
