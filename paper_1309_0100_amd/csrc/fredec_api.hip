@@ -83,12 +83,12 @@ namespace {
 
 struct ScanLayout {
   size_t off_sin = 0, off_hdr = 0, off_work = 0, off_tau = 0, off_xt = 0, off_wt = 0, off_rec = 0, off_phi = 0;
-  size_t off_g32 = 0, off_aux = 0, off_b16 = 0, off_list = 0, off_count = 0, off_chunk = 0;
+  size_t off_g32 = 0, off_aux = 0, off_b16 = 0, off_pt16 = 0, off_list = 0, off_count = 0, off_chunk = 0;
   size_t off_ppart = 0, off_pm = 0, off_part = 0;
   size_t total = 0;
   int nsplit = 1;  // sample chunks of a single float64 series with few frequency tiles
-  int64_t Ntot = 0, rec_total = 0, phi_total = 0, g32_total = 0, aux_total = 0, b16_total = 0, n_work = 0,
-          F_total = 0;
+  int64_t Ntot = 0, rec_total = 0, phi_total = 0, g32_total = 0, aux_total = 0, b16_total = 0, pt16_total = 0,
+          n_work = 0, F_total = 0;
   int64_t ptiles = 0, ppart_total = 0, pm_total = 0;  // preparation tiles, Gram partials, basis changes
   int max_nt = 1;
 };
@@ -137,6 +137,7 @@ int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, cons
       L.g32_total += N * 16 * col_tiles(KP);
       L.aux_total += N * AUX_STRIDE;
       L.b16_total += b16_vectors(N, col_tiles(KP));
+      L.pt16_total += pt16_float2(N);
       L.max_nt = std::max(L.max_nt, col_tiles(KP));
     }
   }
@@ -157,6 +158,7 @@ int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, cons
   L.off_g32 = take(sizeof(float) * L.g32_total);
   L.off_aux = take(sizeof(double) * L.aux_total);
   L.off_b16 = take(16 * L.b16_total);
+  L.off_pt16 = take(8 * L.pt16_total);
   L.off_list = take(precision == FREDEC_FP32 ? sizeof(Rescore) * L.F_total : 0);
   L.off_count = take(sizeof(unsigned long long) * n_series);
   L.off_chunk = take(precision == FREDEC_FP32 ? sizeof(int64_t) * (2 * n_series + 3) : 0);
@@ -198,7 +200,7 @@ struct ScanPlan : fredec_plan {
 
 // Running offsets of the per-series arrays of a scan workspace.
 struct SeriesOffsets {
-  int64_t goff = 0, rec = 0, phi = 0, g32 = 0, aux = 0, b16 = 0, ptile = 0, ppart = 0, pm = 0;
+  int64_t goff = 0, rec = 0, phi = 0, g32 = 0, aux = 0, b16 = 0, pt16 = 0, ptile = 0, ppart = 0, pm = 0;
 };
 
 // Descriptor of one series (samples [soff, soff + N) of the caller's arrays,
@@ -227,6 +229,7 @@ int series_desc(SeriesIn& d, int64_t soff, int64_t N, const double* bf, int32_t 
   d.g32_off = o.g32;
   d.aux_off = o.aux;
   d.b16_off = o.b16;
+  d.pt_off = o.pt16;
   o.goff += F;
   o.phi += N * d.KP;
   o.rec += N * rec_stride(d.KP);
@@ -234,6 +237,7 @@ int series_desc(SeriesIn& d, int64_t soff, int64_t N, const double* bf, int32_t 
     o.g32 += N * 16 * d.NT;
     o.aux += N * AUX_STRIDE;
     o.b16 += b16_vectors(N, d.NT);
+    o.pt16 += pt16_float2(N);
   }
   return FREDEC_OK;
 }
@@ -349,6 +353,7 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const ScanPl
   float* d_g32 = at<float>(ws, L.off_g32);
   double* d_aux = at<double>(ws, L.off_aux);
   void* d_b16 = at<char>(ws, L.off_b16);
+  void* d_pt16 = at<char>(ws, L.off_pt16);
   Rescore* d_list = at<Rescore>(ws, L.off_list);
   unsigned long long* d_count = at<unsigned long long>(ws, L.off_count);
   int64_t* d_chunk = at<int64_t>(ws, L.off_chunk);
@@ -362,7 +367,7 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const ScanPl
   {
     ProfScope prof(prof_ctx, st, FREDEC_PROF_PREP);
     if (launch_prep(st, P.n_series, P.kp_max, L.ptiles, d_sin, d_hdr, t, x, w, d_tau - base_off, d_xt - base_off,
-                    d_wt - base_off, d_rec, d_phi, d_g32, d_aux, d_b16, at<double>(ws, L.off_ppart),
+                    d_wt - base_off, d_rec, d_phi, d_g32, d_aux, d_b16, d_pt16, at<double>(ws, L.off_ppart),
                     at<double>(ws, L.off_pm), flags) != hipSuccess)
       return FREDEC_EDEVICE;
   }
@@ -405,8 +410,8 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const ScanPl
       const int n = static_cast<int>(gr.end - gr.begin);
       hipError_t err;
       if (gr.kind == ScanPlan::F16X3)
-        err = launch_scan_f16x3(gs, gr.key, gr.ft, n, d_work + gr.begin, d_sin, d_hdr, d_aux, d_b16, z_out, flags_out,
-                                d_list, d_count);
+        err = launch_scan_f16x3(gs, gr.key, gr.ft, n, d_work + gr.begin, d_sin, d_hdr, d_aux, d_b16, d_pt16, z_out,
+                                flags_out, d_list, d_count);
       else if (gr.kind == ScanPlan::F32)
         err = launch_scan_f32(gs, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_rec, d_g32, z_out, flags_out, d_list,
                               d_count);
@@ -644,7 +649,7 @@ int fredec_normalize(fredec_ctx* ctx, void* stream, int32_t n_series, const int6
   if (rc) return rc;
   // the prep kernel writes the normalised series at the caller's offsets
   if (launch_prep(st, n_series, 0, 0, d_sin, d_hdr, t, x, w, tau_out, xt_out, wt_out, nullptr, nullptr, nullptr,
-                  nullptr, nullptr, nullptr, nullptr, 0) != hipSuccess)
+                  nullptr, nullptr, nullptr, nullptr, nullptr, 0) != hipSuccess)
     return FREDEC_EDEVICE;
   if (launch_copy_stats(st, n_series, d_hdr, d_sin, nullptr, status_out, stats_out) != hipSuccess)
     return FREDEC_EDEVICE;
@@ -823,7 +828,7 @@ int fredec_scan_at(fredec_ctx* ctx, void* stream, const double* t, const double*
   int rc = upload(ctx, st, d_sin, &si, sizeof(si));
   if (rc) return rc;
   if (launch_prep(st, 1, si.KP, ptile, d_sin, d_hdr, t, x, w, d_tau, d_xt, d_wt, d_rec, d_phi, nullptr, nullptr,
-                  nullptr, d_ppart, d_pm, PREP_BASE | PREP_REC64) != hipSuccess)
+                  nullptr, nullptr, d_ppart, d_pm, PREP_BASE | PREP_REC64) != hipSuccess)
     return FREDEC_EDEVICE;
   if (launch_scan_at_f64(st, si.KP, d_sin, d_hdr, d_rec, idx, n_idx, z_out, flags_out) != hipSuccess)
     return FREDEC_EDEVICE;

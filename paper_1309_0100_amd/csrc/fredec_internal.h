@@ -32,6 +32,7 @@ struct SeriesIn {
   int64_t g32_off;  // first float of this series in the float32 operand array
   int64_t aux_off;  // first double of this series in the float32 kernel's aux array
   int64_t b16_off;  // first 8-half vector of this series in the split float16 operand array
+  int64_t pt_off;   // first float2 of this series' phasor rows e^{2 pi i b df tau} (split float16 scan)
   double df;        // grid step: f_j = (j+1) df
   double rot_step;  // frequency step of the float64 kernel's recurrence (BLOCK * df)
   double rot_tile;  // frequency step of the MFMA kernel's recurrence (16 * df)
@@ -273,8 +274,8 @@ inline void prep_assign(SeriesIn& d, int64_t& ptile, int64_t& ppart, int64_t& pm
 // change) are used; kp_max is the largest KP.
 hipError_t launch_prep(hipStream_t st, int n_series, int kp_max, int64_t n_tiles, const SeriesIn* sin,
                        SeriesHdr* hdr, const double* t, const double* x, const double* w, double* tau, double* xt,
-                       double* wt, double* rec, double* phi, float* g32, double* aux, void* b16, double* ppart,
-                       double* pm, int flags);
+                       double* wt, double* rec, double* phi, float* g32, double* aux, void* b16, void* pt16,
+                       double* ppart, double* pm, int flags);
 // float64 re-scoring of the listed points (per-series lists at list[goff_s ..],
 // count[s] entries each; off: 2 n_series + 3 int64 of workspace for the plan)
 hipError_t launch_rescore(hipStream_t st, int NT, int grid, int n_series, const SeriesIn* sin, const SeriesHdr* hdr,
@@ -314,10 +315,17 @@ constexpr bool f16x3_tile_supported(int NT, int FT) {
   return NT >= 1 && NT <= 4 && (FT == 1 || FT == 2 || FT == 4) && NT * FT <= 4;
 }
 hipError_t launch_scan_f16x3(hipStream_t st, int NT, int FT, int n_work, const ScanWork* work, const SeriesIn* sin,
-                             const SeriesHdr* hdr, const double* aux, const void* b16, double* z, uint8_t* flags,
-                             Rescore* list, unsigned long long* count);
+                             const SeriesHdr* hdr, const double* aux, const void* b16, const void* pt16, double* z,
+                             uint8_t* flags, Rescore* list, unsigned long long* count);
 // 8-half vectors of the float16 operand of a series of N samples and NT column tiles:
 // per step of 32 samples and column tile, a high and a low part of 64 lanes.
 __host__ __device__ constexpr int64_t b16_vectors(int64_t N, int NT) { return (N + 31) / 32 * NT * 2 * 64; }
+// Phasor rows of the split-float16 scan, written by the preparation: per tile
+// of PT_TS samples, the 16 rows e^{2 pi i b df tau_s} (b < 16, float64 rounded
+// to float32), each PT_TS consecutive float2, zero beyond N.  They depend on
+// the series and the grid step only, so every workgroup of the scan copies
+// them instead of computing them.
+constexpr int PT_TS = 128;
+__host__ __device__ constexpr int64_t pt16_float2(int64_t N) { return (N + PT_TS - 1) / PT_TS * 16 * PT_TS; }
 
 }  // namespace fredec

@@ -175,7 +175,7 @@ int upload_descriptors(fredec_ctx* ctx, hipStream_t st, const TuplePlan& P, cons
 int normalise(hipStream_t st, const TuplePlan& P, const TupleDev& D, const double* t, const double* x,
               const double* w, int64_t N) {
   if (launch_prep(st, 1, 0, 0, D.sin, D.hdr, t, x, w, D.tau, D.xt, D.wt, nullptr, nullptr, nullptr, nullptr,
-                  nullptr, nullptr, nullptr, 0) !=
+                  nullptr, nullptr, nullptr, nullptr, 0) !=
       hipSuccess)
     return FREDEC_EDEVICE;
   if (launch_tuple_common(st, D.hdr, N, D.com) != hipSuccess) return FREDEC_EDEVICE;

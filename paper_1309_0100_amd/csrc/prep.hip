@@ -419,7 +419,8 @@ __global__ __launch_bounds__(BLOCK) void prep_basis_kernel(int n_series, const S
                                                            const double* __restrict__ phi,
                                                            const double* __restrict__ pm, double* __restrict__ rec,
                                                            float* __restrict__ g32, double* __restrict__ aux,
-                                                           _Float16* __restrict__ b16, int flags) {
+                                                           _Float16* __restrict__ b16, float2* __restrict__ pt16,
+                                                           int flags) {
   extern __shared__ double tile[];  // rows (stride KP | 1), then PREP_PSS scalars per sample
   __shared__ double Msh[MAXKPP];
   __shared__ double wsh[BLOCK];
@@ -576,6 +577,29 @@ __global__ __launch_bounds__(BLOCK) void prep_basis_kernel(int n_series, const S
     }
   }
   if (w_f16) {
+    // phasor rows e^{2 pi i b df tau} (b < 16) of the tile's samples, by
+    // rotation from b = 0 in float64, into their PT_TS-sample tiles; the
+    // series' last tile is zero-filled to its end
+    float2* pts = pt16 + si.pt_off;
+    const int64_t iend = i0 + nts == N ? (N + PT_TS - 1) / PT_TS * PT_TS : i0 + nts;
+    for (int64_t i = i0 + tid; i < iend; i += BLOCK) {
+      const int sl = static_cast<int>(i - i0);
+      float2* dst = pts + (i / PT_TS) * (16 * PT_TS) + (i % PT_TS);
+      if (sl < nts) {
+        const double wc = psc[sl * PREP_PSS + 5], ws = psc[sl * PREP_PSS + 6];
+        double pc = 1.0, ps = 0.0;
+        for (int b = 0; b < 16; ++b) {
+          dst[b * PT_TS] = float2{static_cast<float>(pc), static_cast<float>(ps)};
+          const double nc = __builtin_fma(pc, wc, -ps * ws);
+          ps = __builtin_fma(ps, wc, pc * ws);
+          pc = nc;
+        }
+      } else {
+        for (int b = 0; b < 16; ++b) dst[b * PT_TS] = float2{0.0f, 0.0f};
+      }
+    }
+  }
+  if (w_f16) {
     // B = S sqrt(w~) q_k = hi + lo.  Layout: per step g of 32 samples and column
     // tile nt, the high part then the low part, each 64 lanes x 8 halves;
     // lane L holds column 16 nt + L % 16 at samples 32 g + 8 (L / 16) + e,
@@ -634,8 +658,8 @@ __global__ void copy_stats_kernel(int n_series, const SeriesHdr* __restrict__ hd
 
 hipError_t launch_prep(hipStream_t st, int n_series, int kp_max, int64_t n_tiles, const SeriesIn* sin,
                        SeriesHdr* hdr, const double* t, const double* x, const double* w, double* tau, double* xt,
-                       double* wt, double* rec, double* phi, float* g32, double* aux, void* b16, double* ppart,
-                       double* pm, int flags) {
+                       double* wt, double* rec, double* phi, float* g32, double* aux, void* b16, void* pt16,
+                       double* ppart, double* pm, int flags) {
   if (n_series <= 0) return hipSuccess;
   if ((flags & PREP_BASE) &&
       (kp_max < 2 || kp_max > MAXKP || n_tiles <= 0 || n_tiles > 0x7fffffff || !ppart || !pm))
@@ -656,7 +680,8 @@ hipError_t launch_prep(hipStream_t st, int n_series, int kp_max, int64_t n_tiles
                                                                                     xt, wt, phi, ppart);
   prep_factor_kernel<<<n_series, BLOCK, 0, st>>>(sin, hdr, ppart, pm);
   prep_basis_kernel<<<nb, BLOCK, sizeof(double) * static_cast<size_t>(d_basis), st>>>(
-      n_series, sin, hdr, tau, wt, phi, pm, rec, g32, aux, static_cast<_Float16*>(b16), flags);
+      n_series, sin, hdr, tau, wt, phi, pm, rec, g32, aux, static_cast<_Float16*>(b16), static_cast<float2*>(pt16),
+      flags);
   return hipGetLastError();
 }
 

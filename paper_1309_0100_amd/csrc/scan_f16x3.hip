@@ -18,10 +18,12 @@
 // series; one MFMA step covers 16 frequencies x 32 samples.  The lane
 // (row = lane % 16, kb = lane / 16) generates A for its frequency row at the
 // eight samples 8 kb .. 8 kb + 7 of the step: the float32 complex product
-// eat[a][s] * bt[row][s] of two phasors that the block computes in float64
-// per tile of 128 samples and rounds once (eat = sqrt(w~_s) e^{2 pi i (j0 +
-// 1 + 16 a) df tau_s}, a = the wave's 16-frequency tile; bt = e^{2 pi i row
-// df tau_s}), i.e. c' = sqrt(w~) cos and s' = sqrt(w~) sin.  The same lane
+// eat[a][s] * bt[row][s] of two phasors computed in float64 and rounded once,
+// staged in LDS per tile of 128 samples (eat = sqrt(w~_s) e^{2 pi i (j0 + 1 +
+// 16 a) df tau_s}, a = the wave's 16-frequency tile, computed by the block;
+// bt = e^{2 pi i row df tau_s}, the same for every workgroup of the series,
+// computed once by the preparation and copied), i.e. c' = sqrt(w~) cos and
+// s' = sqrt(w~) sin.  The same lane
 // accumulates, for its row and its samples,
 //   <cos^2> = sum c'^2, <cos sin> = sum c' s'  float32 per tile of 128
 //   samples, then float64,
@@ -83,7 +85,7 @@ __device__ __forceinline__ float row_sum16(float v) {
 
 // The aux-record values of one sample that the tables need.
 struct SampleRec {
-  double tau, sw, gr, wc, ws;  // tau, sqrt(w~), sqrt(w~) r_b, cos and sin of 2 pi df tau
+  double tau, sw, gr, hc, hs;  // tau, sqrt(w~), sqrt(w~) r_b, cos and sin of 2 pi 16 df tau
 };
 
 // Sample `sl` of the tile starting at i0 (neutral values beyond nts).
@@ -92,85 +94,76 @@ __device__ __forceinline__ SampleRec fetch_rec(const double* __restrict__ aser, 
   if (sl < nts) {
     const double* a = aser + (i0 + sl) * AUX_STRIDE;
     r.tau = a[0];
+    r.hc = a[1];
+    r.hs = a[2];
     r.sw = a[3];
     r.gr = a[4];
-    r.wc = a[6];
-    r.ws = a[7];
   }
   return r;
 }
 
 // Tables of one tile of TS samples: eat[a][s] = sqrt(w~_s) e^{2 pi i fb tau_s}
-// w_s^(16 a), bt[b][s] = w_s^b (a, b < 16, w_s = e^{2 pi i df tau_s}),
-// rounded to float32 (the weight folded into eat makes every trial value
-// c' = sqrt(w~) cos, s' = sqrt(w~) sin); grs[s] = sqrt(w~_s) r_b(tau_s).
+// v_s^a (a < AMAX, v_s = e^{2 pi i 16 df tau_s}), computed here in float64
+// and rounded to float32 (the weight folded into eat makes every trial value
+// c' = sqrt(w~) cos, s' = sqrt(w~) sin); bt[b][s] = e^{2 pi i b df tau_s}
+// (b < 16), copied from the preparation's phasor rows of the tile (pts: 16
+// rows of TS float2, zero beyond the series); grs[s] = sqrt(w~_s) r_b(tau_s).
 // Samples nts .. TS - 1 get zero entries, so that they contribute nothing.
-// BLOCK / TS threads per sample, each taking 16 TS / BLOCK values of a and of
-// b; rows a >= AMAX of eat are not used by the kernel and not written.
+// BLOCK / TS threads per sample, each taking AMAX TS / BLOCK consecutive rows
+// of eat (its first row v^(a0) by binary powers of v).
 template <int TS, int AMAX>
-__device__ __forceinline__ void build_tables(const SampleRec& r, int nts, double fb, float2* __restrict__ eat,
-                                             float2* __restrict__ bt,
+__device__ __forceinline__ void build_tables(const SampleRec& r, int nts, double fb, const float4* __restrict__ pts,
+                                             float2* __restrict__ eat, float2* __restrict__ bt,
                                              double* __restrict__ grs) {
-  constexpr int TPS = BLOCK / TS;  // threads per sample
-  constexpr int PER = 16 / TPS;    // values of a and of b per thread
+  constexpr int TPS = BLOCK / TS;   // threads per sample
+  constexpr int ROWS = AMAX / TPS;  // rows of eat per thread
   constexpr int TSP = TS + 2;
-  static_assert(TPS * PER == 16, "tile size must divide the block");
+  constexpr int NV = 16 * TS / 2;   // float4 of bt per tile
+  static_assert(TPS * ROWS == AMAX && NV % BLOCK == 0, "tile size must divide the block");
+  float4 bv[NV / BLOCK];
+#pragma unroll
+  for (int u = 0; u < NV / BLOCK; ++u) bv[u] = pts[u * BLOCK + threadIdx.x];
   const int sl = threadIdx.x / TPS, part = threadIdx.x % TPS;
-  const int eb = PER * part;
-  if (sl >= nts) {
+  const int a0 = ROWS * part;
+  if (sl < nts) {
+    double es, ec;
+    sincos_rev(fb * r.tau, es, ec);
+    double vc = ec * r.sw, vs = es * r.sw;
+    double pc = 1.0, ps = 0.0, xc = r.hc, xs = r.hs;  // v^(a0), v^(2^k)
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      if (eb + k < AMAX) eat[(eb + k) * TSP + sl] = float2{0.0f, 0.0f};
-      bt[(eb + k) * TSP + sl] = float2{0.0f, 0.0f};
+    for (int k = 0; (1 << k) < AMAX; ++k) {
+      if ((a0 >> k) & 1) {
+        const double tc = __builtin_fma(pc, xc, -ps * xs);
+        ps = __builtin_fma(pc, xs, ps * xc);
+        pc = tc;
+      }
+      const double nc = __builtin_fma(xc, xc, -xs * xs);
+      xs = 2.0 * xc * xs;
+      xc = nc;
     }
+    {
+      const double tc = __builtin_fma(vc, pc, -vs * ps);
+      vs = __builtin_fma(vs, pc, vc * ps);
+      vc = tc;
+    }
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k) {
+      eat[(a0 + k) * TSP + sl] = float2{static_cast<float>(vc), static_cast<float>(vs)};
+      const double nc = __builtin_fma(vc, r.hc, -vs * r.hs);
+      vs = __builtin_fma(vs, r.hc, vc * r.hs);
+      vc = nc;
+    }
+    if (part == 0) grs[sl] = r.gr;
+  } else {
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k) eat[(a0 + k) * TSP + sl] = float2{0.0f, 0.0f};
     if (part == 0) grs[sl] = 0.0;
-    return;
-  }
-  const double wc = r.wc, ws = r.ws;
-  const int ea = 16 * eb;  // exponent of w in the first eat entry of this thread
-  double pc = 1.0, ps = 0.0, ac = 1.0, as = 0.0, hc = 1.0, hs = 0.0;
-  double xc = wc, xs = ws;  // w^(2^k)
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    if (k == 4) {
-      hc = xc;
-      hs = xs;
-    }
-    if ((eb >> k) & 1) {
-      const double tc = __builtin_fma(pc, xc, -ps * xs);
-      ps = __builtin_fma(pc, xs, ps * xc);
-      pc = tc;
-    }
-    if ((ea >> k) & 1) {
-      const double tc = __builtin_fma(ac, xc, -as * xs);
-      as = __builtin_fma(ac, xs, as * xc);
-      ac = tc;
-    }
-    const double nc = __builtin_fma(xc, xc, -xs * xs);
-    xs = 2.0 * xc * xs;
-    xc = nc;
   }
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    bt[(eb + k) * TSP + sl] = float2{static_cast<float>(pc), static_cast<float>(ps)};
-    const double nc = __builtin_fma(pc, wc, -ps * ws);
-    ps = __builtin_fma(ps, wc, pc * ws);
-    pc = nc;
-  }
-  if (part == 0) grs[sl] = r.gr;
-  if (eb >= AMAX) return;
-  double es, ec;
-  sincos_rev(fb * r.tau, es, ec);
-  es *= r.sw;
-  ec *= r.sw;
-  double vc = __builtin_fma(ec, ac, -es * as);
-  double vs = __builtin_fma(es, ac, ec * as);
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    if (eb + k < AMAX) eat[(eb + k) * TSP + sl] = float2{static_cast<float>(vc), static_cast<float>(vs)};
-    const double nc = __builtin_fma(vc, hc, -vs * hs);
-    vs = __builtin_fma(vs, hc, vc * hs);
-    vc = nc;
+  for (int u = 0; u < NV / BLOCK; ++u) {
+    const int q = u * BLOCK + threadIdx.x;
+    const int b = q / (TS / 2), c = q % (TS / 2);
+    *reinterpret_cast<float4*>(bt + b * TSP + 2 * c) = bv[u];
   }
 }
 
@@ -180,11 +173,13 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
                                                            const SeriesHdr* __restrict__ hdr,
                                                            const double* __restrict__ aux,
                                                            const v8h* __restrict__ b16,
+                                                           const float4* __restrict__ pt16,
                                                            double* __restrict__ z_out, uint8_t* __restrict__ flags_out,
                                                            Rescore* __restrict__ list,
                                                            unsigned long long* __restrict__ count) {
   static_assert(FT >= 1 && FT <= 4, "the epilogue gives one lane group per frequency tile");
   static_assert(TS % 32 == 0 && BLOCK % TS == 0, "tiles hold whole MFMA steps");
+  static_assert(TS == PT_TS, "tiles of the preparation's phasor rows");
   constexpr int TSP = TS + 2;  // row length (float2) of the transposed tables
   // LDS: the tables during the sample loop; the epilogue reuses the memory
   // for the per-frequency sums (EPF doubles per frequency)
@@ -236,11 +231,12 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
   const double fb = static_cast<double>(wk.j0 + 1) * si.df;
   const double* __restrict__ aser = aux + si.aux_off;
   const v8h* __restrict__ bser = b16 + si.b16_off;
+  const float4* __restrict__ pser = pt16 + si.pt_off / 2;  // float2 offset, a multiple of 16 PT_TS
   const int slb = threadIdx.x / (BLOCK / TS);  // sample of this thread in the table build
   for (int64_t i0 = 0; i0 < N; i0 += TS) {
     const int nts = N - i0 < TS ? static_cast<int>(N - i0) : TS;
     __syncthreads();
-    build_tables<TS, 4 * FT>(fetch_rec(aser, i0, nts, slb), nts, fb, eat, bt, grs);
+    build_tables<TS, 4 * FT>(fetch_rec(aser, i0, nts, slb), nts, fb, pser + (i0 / TS) * (8 * TS), eat, bt, grs);
     __syncthreads();
     const int ng = (nts + 31) >> 5;
     for (int gg = 0; gg < ng; ++gg) {
@@ -376,21 +372,22 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
 
 template <int NT, int FT>
 hipError_t launch_nt(hipStream_t st, int n_work, const ScanWork* work, const SeriesIn* sin, const SeriesHdr* hdr,
-                     const double* aux, const void* b16, double* z, uint8_t* flags, Rescore* list,
+                     const double* aux, const void* b16, const void* pt16, double* z, uint8_t* flags, Rescore* list,
                      unsigned long long* count) {
-  scan_f16x3_kernel<NT, FT, F16X3_TS><<<n_work, BLOCK, 0, st>>>(work, sin, hdr, aux, static_cast<const v8h*>(b16), z,
-                                                               flags, list, count);
+  scan_f16x3_kernel<NT, FT, F16X3_TS><<<n_work, BLOCK, 0, st>>>(work, sin, hdr, aux, static_cast<const v8h*>(b16),
+                                                               static_cast<const float4*>(pt16), z, flags, list,
+                                                               count);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_scan_f16x3(hipStream_t st, int NT, int FT, int n_work, const ScanWork* work, const SeriesIn* sin,
-                             const SeriesHdr* hdr, const double* aux, const void* b16, double* z, uint8_t* flags,
-                             Rescore* list, unsigned long long* count) {
+                             const SeriesHdr* hdr, const double* aux, const void* b16, const void* pt16, double* z,
+                             uint8_t* flags, Rescore* list, unsigned long long* count) {
   if (n_work <= 0) return hipSuccess;
 #define X(nt, ft) \
-  if (NT == nt && FT == ft) return launch_nt<nt, ft>(st, n_work, work, sin, hdr, aux, b16, z, flags, list, count);
+  if (NT == nt && FT == ft) return launch_nt<nt, ft>(st, n_work, work, sin, hdr, aux, b16, pt16, z, flags, list, count);
   X(1, 1) X(1, 2) X(1, 4) X(2, 1) X(2, 2) X(3, 1) X(4, 1)
 #undef X
   return hipErrorInvalidValue;
