@@ -163,9 +163,12 @@ int fredec_normalize(fredec_ctx* ctx, void* stream, int32_t n_series, const int6
  * [n_series], nullable) receives l_m; status_out (device int32 [n_series],
  * nullable).  soff, boff, base_f, df and F are host arrays.
  * A batch's kernel groups (one per kernel instance) run concurrently on the
- * context's side streams.  A single series in FREDEC_FP64 whose grid gives
- * fewer than 128 frequency tiles is split over up to 16 sample chunks (the
- * workspace then holds their partial sums; they are added in chunk order).
+ * context's side streams.  A single series whose grid gives few frequency
+ * tiles (FREDEC_FP64: fewer than 128; FREDEC_FP32: fewer than 512 at the
+ * split-float16 kernel's default tile) is split over up to 16 sample chunks
+ * (the workspace then holds their partial sums; they are added in chunk
+ * order), and in FREDEC_FP32 such a series is given to the split-float16
+ * kernel even where the automatic form would pick the float32 VALU kernel.
  * Errors: EINVAL (null/size/precision), EDOF (N - 3m - 4 <= 0 for a series),
  * ENOTSUP (m > FREDEC_MAX_BASE), ENOMEM (workspace). */
 int fredec_scan_workspace(int32_t n_series, const int64_t* soff_host, const int64_t* boff_host,

@@ -86,7 +86,7 @@ struct ScanLayout {
   size_t off_g32 = 0, off_aux = 0, off_b16 = 0, off_pt16 = 0, off_list = 0, off_count = 0, off_chunk = 0;
   size_t off_ppart = 0, off_pm = 0, off_part = 0;
   size_t total = 0;
-  int nsplit = 1;  // sample chunks of a single float64 series with few frequency tiles
+  int nsplit = 1;  // sample chunks of a single series with few frequency tiles
   int64_t Ntot = 0, rec_total = 0, phi_total = 0, g32_total = 0, aux_total = 0, b16_total = 0, pt16_total = 0,
           n_work = 0, F_total = 0;
   int64_t ptiles = 0, ppart_total = 0, pm_total = 0;  // preparation tiles, Gram partials, basis changes
@@ -121,7 +121,8 @@ int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, cons
     if (N - 3 * m - 4 <= 0) return FREDEC_EDOF;
     const int KP = static_cast<int>(2 * m + 2);
     const int64_t tile = scan_tile(KP, precision);
-    if (n_series == 1 && precision == FREDEC_FP64 && allow_split) L.nsplit = scan_f64_nsplit(N, KP, F[s]);
+    if (n_series == 1 && allow_split)
+      L.nsplit = precision == FREDEC_FP64 ? scan_f64_nsplit(N, KP, F[s]) : scan_f16x3_nsplit(N, col_tiles(KP), F[s]);
     L.n_work += (F[s] + tile - 1) / tile * L.nsplit;
     L.Ntot += N;
     L.phi_total += N * KP;
@@ -164,7 +165,13 @@ int scan_layout(int32_t n_series, const int64_t* soff, const int64_t* boff, cons
   L.off_chunk = take(precision == FREDEC_FP32 ? sizeof(int64_t) * (2 * n_series + 3) : 0);
   L.off_ppart = take(sizeof(double) * L.ppart_total);
   L.off_pm = take(sizeof(double) * L.pm_total);
-  L.off_part = take(L.nsplit > 1 ? sizeof(double) * L.nsplit * (2 * (2 * (boff[1] - boff[0]) + 2) + 3) * F[0] : 0);
+  if (L.nsplit > 1) {
+    const int KP0 = static_cast<int>(2 * (boff[1] - boff[0]) + 2);
+    L.off_part = take(precision == FREDEC_FP64 ? sizeof(double) * L.nsplit * (2 * KP0 + 3) * F[0]
+                                               : static_cast<size_t>(f16x3_part_bytes(L.nsplit, col_tiles(KP0), F[0])));
+  } else {
+    L.off_part = take(0);
+  }
   L.total = off;
   return FREDEC_OK;
 }
@@ -193,7 +200,7 @@ struct ScanPlan : fredec_plan {
     int ft;          // split float16: 16-frequency tiles per wave the work list was cut for
     int64_t begin, end;
     double work = 0.0;  // estimated cost: sum of N F (2 KP + 3) over its series
-    int nsplit = 1;     // float64, one series: sample chunks (work item pad = chunk)
+    int nsplit = 1;     // one series (float64 or split float16): sample chunks (work item pad = chunk)
   };
   std::vector<Group> groups;
 };
@@ -242,12 +249,22 @@ int series_desc(SeriesIn& d, int64_t soff, int64_t N, const double* bf, int32_t 
   return FREDEC_OK;
 }
 
-// Kernel family that scans a series with KP = 2m + 2 columns.
-int scan_kind(const fredec_ctx* ctx, int32_t precision, int KP) {
+// Kernel family that scans a series with KP = 2m + 2 columns.  F_single: the
+// grid of a scan of this one series (0 in a batch).  The automatic form gives
+// a single series to the float32 VALU kernel only where its workgroups (256 R
+// frequencies each) number at least four per CU; on smaller grids most CUs
+// would idle, and the split-float16 kernel (64 FT frequencies per workgroup)
+// is much faster (N = 10^4, F = 65536, m = 0: 0.49 against 5.0 ms, measured).
+int scan_kind(const fredec_ctx* ctx, int32_t precision, int KP, int64_t F_single = 0) {
   const int form = ctx ? ctx->f32_form : FREDEC_F32_FORM_AUTO;
   const int auto_kp = ctx ? ctx->f32_auto_valu_max_kp : F32_AUTO_VALU_MAX_KP;
   if (precision == FREDEC_FP64) return ScanPlan::F64;
   if (form == FREDEC_F32_FORM_F16X3 || (form == FREDEC_F32_FORM_AUTO && KP > auto_kp)) return ScanPlan::F16X3;
+  if (form == FREDEC_F32_FORM_AUTO && F_single > 0) {
+    const int64_t tile = static_cast<int64_t>(BLOCK) * scan_f32_freqs_per_thread(KP);
+    const int64_t n_cu = std::max(ctx ? ctx->n_cu : 0, 1);
+    if ((F_single + tile - 1) / tile < 4 * n_cu) return ScanPlan::F16X3;
+  }
   if (KP <= F32_VALU_MAX_KP) return ScanPlan::F32;
   return ScanPlan::F16X3;
 }
@@ -296,7 +313,7 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
   // Work list: tiles grouped by kernel instance (KP for the float64 and the
   // float32 VALU kernels, column tiles NT for the split-float16 kernel), longest series first
   // inside a group.
-  auto kind = [&](int32_t s) { return scan_kind(ctx, precision, sin[s].KP); };
+  auto kind = [&](int32_t s) { return scan_kind(ctx, precision, sin[s].KP, n_series == 1 ? sin[s].F : 0); };
   auto key = [&](int32_t s) { return kind(s) == ScanPlan::F16X3 ? sin[s].NT : sin[s].KP; };
   std::vector<int32_t> order(n_series);
   for (int32_t s = 0; s < n_series; ++s) order[s] = s;
@@ -315,7 +332,7 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
     const int64_t tile = kind_tile(kd, sin[s].KP, ft, precision);
     if (P.groups.empty() || P.groups.back().kind != kd || P.groups.back().key != key(s))
       P.groups.push_back(ScanPlan::Group{kd, key(s), ft, static_cast<int64_t>(P.work.size()), 0});
-    const int ns = kd == ScanPlan::F64 ? L.nsplit : 1;
+    const int ns = kd == ScanPlan::F64 || kd == ScanPlan::F16X3 ? L.nsplit : 1;
     P.groups.back().nsplit = ns;
     for (int c = 0; c < ns; ++c)
       for (int64_t j0 = 0; j0 < sin[s].F; j0 += tile) P.work.push_back(ScanWork{s, c, j0});
@@ -411,7 +428,8 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const ScanPl
       hipError_t err;
       if (gr.kind == ScanPlan::F16X3)
         err = launch_scan_f16x3(gs, gr.key, gr.ft, n, d_work + gr.begin, d_sin, d_hdr, d_aux, d_b16, d_pt16, z_out,
-                                flags_out, d_list, d_count);
+                                flags_out, d_list, d_count, at<double>(ws, L.off_part), gr.nsplit,
+                                P.n_series == 1 ? P.sin_F0 : 0);
       else if (gr.kind == ScanPlan::F32)
         err = launch_scan_f32(gs, gr.key, n, d_work + gr.begin, d_sin, d_hdr, d_rec, d_g32, z_out, flags_out, d_list,
                               d_count);
@@ -738,7 +756,7 @@ int fredec_scan_static(fredec_ctx* ctx, void* stream, const double* t, const dou
   SeriesOffsets o;
   if ((rc = series_desc(d, 0, N, base_f, m, df, F, precision, o))) return rc;
   if (!ctx || !ctx->static_scratch) return FREDEC_EINVAL;
-  const int kd = scan_kind(ctx, precision, d.KP);
+  const int kd = scan_kind(ctx, precision, d.KP, F);
   d.outputs = kind_outputs(kd);
   const int ft = kd == ScanPlan::F16X3 ? f16x3_ft_for(ctx, d.NT) : 0;
   const int64_t tile = kind_tile(kd, d.KP, ft, precision);

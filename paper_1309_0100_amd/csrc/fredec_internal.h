@@ -64,7 +64,7 @@ struct SeriesHdr {
 
 struct ScanWork {
   int32_t series;
-  int32_t pad;  // sample chunk of a split float64 scan (0 otherwise)
+  int32_t pad;  // sample chunk of a split scan (0 otherwise)
   int64_t j0;  // first grid index of the tile
 };
 
@@ -314,9 +314,21 @@ constexpr int f16x3_freq_tiles(int NT) { return NT <= 1 ? 4 : NT <= 2 ? 2 : 1; }
 constexpr bool f16x3_tile_supported(int NT, int FT) {
   return NT >= 1 && NT <= 4 && (FT == 1 || FT == 2 || FT == 4) && NT * FT <= 4;
 }
+// nsplit > 1 (one series): the work items cover sample chunks (ScanWork::pad)
+// and write raw sums to `part`; a reduction kernel over the F_split grid
+// points adds them in chunk order and finishes the points.
 hipError_t launch_scan_f16x3(hipStream_t st, int NT, int FT, int n_work, const ScanWork* work, const SeriesIn* sin,
                              const SeriesHdr* hdr, const double* aux, const void* b16, const void* pt16, double* z,
-                             uint8_t* flags, Rescore* list, unsigned long long* count);
+                             uint8_t* flags, Rescore* list, unsigned long long* count, double* part = nullptr,
+                             int nsplit = 1, int64_t F_split = 0);
+// Sample chunks of a split-float16 scan of one series: grids that give fewer
+// than two workgroups per CU (512) at the default tile are split over up to 16
+// chunks of at least 1024 samples; 1 = no split.  Partial sums per chunk and
+// grid point: 4 doubles and 2 x 16 NT floats.
+int scan_f16x3_nsplit(int64_t N, int NT, int64_t F);
+__host__ __device__ constexpr int64_t f16x3_part_bytes(int nsplit, int NT, int64_t F) {
+  return static_cast<int64_t>(nsplit) * F * (4 * 8 + 2 * 16 * NT * 4);
+}
 // 8-half vectors of the float16 operand of a series of N samples and NT column tiles:
 // per step of 32 samples and column tile, a high and a low part of 64 lanes.
 __host__ __device__ constexpr int64_t b16_vectors(int64_t N, int NT) { return (N + 31) / 32 * NT * 2 * 64; }

@@ -167,8 +167,40 @@ __device__ __forceinline__ void build_tables(const SampleRec& r, int nts, double
   }
 }
 
+// Samples per chunk when a scan is split over nsplit sample chunks (whole tiles).
+__host__ __device__ inline int64_t f16x3_chunk(int64_t N, int nsplit) {
+  return ((N + nsplit - 1) / nsplit + F16X3_TS - 1) / F16X3_TS * F16X3_TS;
+}
+
+// Grid point j of series `series` from its sums: e[0..2] = U^T U (cos cos,
+// cos sin, sin sin), e[3..6] = <cos^2>, <cos sin>, h_c, h_s.  Writes z and
+// the flags, and lists the point for float64 re-scoring where the reduced
+// precision loses accuracy.
+__device__ __forceinline__ void f16x3_finish(const double* e, int64_t j, int32_t series, const SeriesIn& si,
+                                             const SeriesHdr& h, double* zs, uint8_t* fs, Rescore* list,
+                                             unsigned long long* count) {
+  const double ccr = e[3], csr = e[4], ss = h.W1 - ccr;
+  const double Scc = ccr - e[0], Scs = csr - e[1], Sss = ss - e[2];
+  double z;
+  uint8_t fl;
+  double lratio;
+  schur_finish(Scc, Scs, Sss, ccr, ss, e[5], e[6], static_cast<double>(j + 1) * si.df, si, h, z, fl, &lratio);
+  const double l21 = Scs / sqrt(fmax(Scc, 1e-300));
+  const double rho = fmin(Scc / ccr, (Sss - l21 * l21) / ss);
+  if (!(fl & FREDEC_FLAG_MASKED) && (!(rho >= RHO_MIN) || !(lratio >= LRATIO_MIN))) {
+    const unsigned long long slot = atomicAdd(count + series, 1ull);
+    list[si.goff + slot] = Rescore{series, 0, j};
+  }
+  zs[j] = z;
+  if (fs) fs[j] = fl;
+}
+
+// nsplit > 1: the work item covers the samples of chunk wk.pad and writes its
+// raw sums (the four float64 sums of each grid point, then U per column) to
+// `part` for scan_f16x3_reduce_kernel instead of finishing the points.  Every
+// (NT, FT) is held to 256 registers, i.e. two waves per SIMD.
 template <int NT, int FT, int TS>
-__global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __restrict__ work,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void scan_f16x3_kernel(const ScanWork* __restrict__ work,
                                                            const SeriesIn* __restrict__ sin_,
                                                            const SeriesHdr* __restrict__ hdr,
                                                            const double* __restrict__ aux,
@@ -176,7 +208,8 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
                                                            const float4* __restrict__ pt16,
                                                            double* __restrict__ z_out, uint8_t* __restrict__ flags_out,
                                                            Rescore* __restrict__ list,
-                                                           unsigned long long* __restrict__ count) {
+                                                           unsigned long long* __restrict__ count,
+                                                           double* __restrict__ part, int nsplit) {
   static_assert(FT >= 1 && FT <= 4, "the epilogue gives one lane group per frequency tile");
   static_assert(TS % 32 == 0 && BLOCK % TS == 0, "tiles hold whole MFMA steps");
   static_assert(TS == PT_TS, "tiles of the preparation's phasor rows");
@@ -203,6 +236,13 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
   const int64_t jw = wk.j0 + static_cast<int64_t>(wave) * 16 * FT;
   double* zs = z_out + si.goff;
   uint8_t* fs = flags_out ? flags_out + si.goff : nullptr;
+  int64_t i_lo = 0, i_hi = N;
+  if (nsplit > 1) {
+    const int64_t nc = f16x3_chunk(N, nsplit);
+    i_lo = static_cast<int64_t>(wk.pad) * nc;
+    i_hi = i_lo + nc < N ? i_lo + nc : N;
+    if (h.status != 0) return;  // the reduction writes NaN
+  }
   if (h.status != 0) {
     for (int ft = 0; ft < FT; ++ft) {
       const int64_t j = jw + ft * 16 + row;
@@ -233,8 +273,8 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
   const v8h* __restrict__ bser = b16 + si.b16_off;
   const float4* __restrict__ pser = pt16 + si.pt_off / 2;  // float2 offset, a multiple of 16 PT_TS
   const int slb = threadIdx.x / (BLOCK / TS);  // sample of this thread in the table build
-  for (int64_t i0 = 0; i0 < N; i0 += TS) {
-    const int nts = N - i0 < TS ? static_cast<int>(N - i0) : TS;
+  for (int64_t i0 = i_lo; i0 < i_hi; i0 += TS) {
+    const int nts = i_hi - i0 < TS ? static_cast<int>(i_hi - i0) : TS;
     __syncthreads();
     build_tables<TS, 4 * FT>(fetch_rec(aser, i0, nts, slb), nts, fb, pser + (i0 / TS) * (8 * TS), eat, bt, grs);
     __syncthreads();
@@ -307,6 +347,39 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
   // well below the float32 bound where the point is not re-scored) with DPP
   // row sums.  The seven sums of every frequency go to LDS, and one lane per
   // frequency finishes it.
+  if (nsplit > 1) {
+    // part: [chunk][4][F] doubles, then [chunk][cos, sin][16 NT columns][F]
+    // floats; D[i][col] of a tile sits in lane col + 16 (i / 4), element i % 4
+    const int64_t c = wk.pad;
+    float* pu = reinterpret_cast<float*>(part + static_cast<int64_t>(nsplit) * 4 * F);
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) {
+      double v[4] = {cc[ft], cs[ft], hc[ft], hs[ft]};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        v[q] += __shfl_xor(v[q], 16);
+        v[q] += __shfl_xor(v[q], 32);
+      }
+      const int64_t j = jw + ft * 16 + row;
+      if (kb == 0 && j < F) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) part[(c * 4 + q) * F + j] = v[q];
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int col = 16 * nt + row;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t jf = jw + ft * 16 + 4 * kb + i;
+          if (jf < F) {
+            pu[(c * 32 * NT + col) * F + jf] = uoc[ft][nt][i];
+            pu[(c * 32 * NT + 16 * NT + col) * F + jf] = uos[ft][nt][i];
+          }
+        }
+      }
+    }
+    return;
+  }
   const double inv2 = h.b16_inv * h.b16_inv;  // 1 / S^2
   __syncthreads();  // every wave is done with the tables
   double* ep = lds + wave * 16 * FT * EPF;
@@ -349,34 +422,71 @@ __global__ __launch_bounds__(BLOCK) void scan_f16x3_kernel(const ScanWork* __res
   }
   __builtin_amdgcn_wave_barrier();
   if (lane < 16 * FT) {
-    const double* e = ep + lane * EPF;
     const int64_t j = jw + lane;
-    if (j < F) {
-      const double ccr = e[3], csr = e[4], ss = h.W1 - ccr;
-      const double Scc = ccr - e[0], Scs = csr - e[1], Sss = ss - e[2];
-      double z;
-      uint8_t fl;
-      double lratio;
-      schur_finish(Scc, Scs, Sss, ccr, ss, e[5], e[6], static_cast<double>(j + 1) * si.df, si, h, z, fl, &lratio);
-      const double l21 = Scs / sqrt(fmax(Scc, 1e-300));
-      const double rho = fmin(Scc / ccr, (Sss - l21 * l21) / ss);
-      if (!(fl & FREDEC_FLAG_MASKED) && (!(rho >= RHO_MIN) || !(lratio >= LRATIO_MIN))) {
-        const unsigned long long slot = atomicAdd(count + wk.series, 1ull);
-        list[si.goff + slot] = Rescore{wk.series, 0, j};
-      }
-      zs[j] = z;
-      if (fs) fs[j] = fl;
-    }
+    if (j < F) f16x3_finish(ep + lane * EPF, j, wk.series, si, h, zs, fs, list, count);
   }
+}
+
+// The chunks' sums of a split scan (one series) added in chunk order, U^T U
+// formed in float64, then the finish of scan_f16x3_kernel: one thread per grid
+// point.
+__global__ __launch_bounds__(BLOCK) void scan_f16x3_reduce_kernel(const SeriesIn* __restrict__ sin_,
+                                                                  const SeriesHdr* __restrict__ hdr,
+                                                                  const double* __restrict__ part, int nsplit,
+                                                                  double* __restrict__ z_out,
+                                                                  uint8_t* __restrict__ flags_out,
+                                                                  Rescore* __restrict__ list,
+                                                                  unsigned long long* __restrict__ count) {
+  const SeriesIn& si = sin_[0];
+  const SeriesHdr& h = hdr[0];
+  const int64_t F = si.F;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+  if (j >= F) return;
+  double* zs = z_out + si.goff;
+  uint8_t* fs = flags_out ? flags_out + si.goff : nullptr;
+  if (h.status != 0) {
+    zs[j] = __builtin_nan("");
+    if (fs) fs[j] = FREDEC_FLAG_BADSERIES;
+    return;
+  }
+  double e[7];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double v = 0.0;
+    for (int c = 0; c < nsplit; ++c) v += part[(static_cast<int64_t>(c) * 4 + q) * F + j];
+    e[3 + q] = v;
+  }
+  const float* pu = reinterpret_cast<const float*>(part + static_cast<int64_t>(nsplit) * 4 * F);
+  const int NC = 16 * si.NT;
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+  for (int col = 0; col < NC; ++col) {
+    double uc = 0.0, us = 0.0;
+    for (int c = 0; c < nsplit; ++c) {
+      uc += static_cast<double>(pu[(static_cast<int64_t>(c) * 2 * NC + col) * F + j]);
+      us += static_cast<double>(pu[(static_cast<int64_t>(c) * 2 * NC + NC + col) * F + j]);
+    }
+    p0 = __builtin_fma(uc, uc, p0);
+    p1 = __builtin_fma(uc, us, p1);
+    p2 = __builtin_fma(us, us, p2);
+  }
+  const double inv2 = h.b16_inv * h.b16_inv;  // 1 / S^2
+  e[0] = p0 * inv2;
+  e[1] = p1 * inv2;
+  e[2] = p2 * inv2;
+  f16x3_finish(e, j, 0, si, h, zs, fs, list, count);
 }
 
 template <int NT, int FT>
 hipError_t launch_nt(hipStream_t st, int n_work, const ScanWork* work, const SeriesIn* sin, const SeriesHdr* hdr,
                      const double* aux, const void* b16, const void* pt16, double* z, uint8_t* flags, Rescore* list,
-                     unsigned long long* count) {
+                     unsigned long long* count, double* part, int nsplit, int64_t F_split) {
+  const int ns = nsplit > 1 && part && F_split > 0 ? nsplit : 1;
   scan_f16x3_kernel<NT, FT, F16X3_TS><<<n_work, BLOCK, 0, st>>>(work, sin, hdr, aux, static_cast<const v8h*>(b16),
                                                                static_cast<const float4*>(pt16), z, flags, list,
-                                                               count);
+                                                               count, part, ns);
+  if (ns > 1)
+    scan_f16x3_reduce_kernel<<<static_cast<unsigned>((F_split + BLOCK - 1) / BLOCK), BLOCK, 0, st>>>(
+        sin, hdr, part, ns, z, flags, list, count);
   return hipGetLastError();
 }
 
@@ -384,13 +494,26 @@ hipError_t launch_nt(hipStream_t st, int n_work, const ScanWork* work, const Ser
 
 hipError_t launch_scan_f16x3(hipStream_t st, int NT, int FT, int n_work, const ScanWork* work, const SeriesIn* sin,
                              const SeriesHdr* hdr, const double* aux, const void* b16, const void* pt16, double* z,
-                             uint8_t* flags, Rescore* list, unsigned long long* count) {
+                             uint8_t* flags, Rescore* list, unsigned long long* count, double* part, int nsplit,
+                             int64_t F_split) {
   if (n_work <= 0) return hipSuccess;
-#define X(nt, ft) \
-  if (NT == nt && FT == ft) return launch_nt<nt, ft>(st, n_work, work, sin, hdr, aux, b16, pt16, z, flags, list, count);
+#define X(nt, ft)                                                                                              \
+  if (NT == nt && FT == ft)                                                                                    \
+    return launch_nt<nt, ft>(st, n_work, work, sin, hdr, aux, b16, pt16, z, flags, list, count, part, nsplit, \
+                             F_split);
   X(1, 1) X(1, 2) X(1, 4) X(2, 1) X(2, 2) X(3, 1) X(4, 1)
 #undef X
   return hipErrorInvalidValue;
+}
+
+int scan_f16x3_nsplit(int64_t N, int NT, int64_t F) {
+  const int64_t tile = 64 * static_cast<int64_t>(f16x3_freq_tiles(NT));
+  const int64_t tiles = (F + tile - 1) / tile;
+  if (tiles >= 512) return 1;
+  int64_t ns = (512 + tiles - 1) / tiles;
+  if (ns > 16) ns = 16;
+  if (ns > N / 1024) ns = N / 1024;
+  return ns < 2 ? 1 : static_cast<int>(ns);
 }
 
 }  // namespace fredec

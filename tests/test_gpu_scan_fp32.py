@@ -88,6 +88,26 @@ def test_fp32_base_models(ctx, m, N, F):
     compare(z, fl, ref, label=f"m={m}")
 
 
+@pytest.mark.parametrize("m,N,F", [(0, 3000, 700), (3, 17000, 1500), (9, 9001, 2500), (17, 4100, 600)])
+def test_fp32_split_scan_few_tiles(ctx, m, N, F):
+    """A single scan whose grid gives the split-float16 kernel few
+    workgroups is split over sample chunks (raw sums per chunk, added in chunk
+    order by a reduction that finishes the points): 2 chunks with a ragged
+    last one, 16 chunks of which the last is empty, 8 chunks at two column
+    tiles, 4 chunks at three; every grid point against the oracle."""
+    from paper_1309_0100_amd import fredec as Fr
+    s = synth.random_series(500 + m, N, span=800.0, n_sin=3)
+    rng = np.random.default_rng(50 + m)
+    base = np.concatenate([s.true_f, rng.uniform(0.01, 0.7, size=max(0, m - 3))])[:m]
+    df = 1.5 / F
+    print(f"case: fp32 split scan m={m} N={N} F={F}", flush=True)
+    z, fl, lb, st = ctx.scan_series(s.t, s.x, s.w, base, df, F, precision=Fr.FP32)
+    ref = O.scan(s.t, s.x, s.w, base, df, F)
+    assert int(st.item()) == 0
+    assert abs(float(lb.item()) - ref.l_base) < 1e-13
+    compare(z, fl, ref, label=f"split m={m}")
+
+
 def test_fp32_batched_uneven(ctx):
     from paper_1309_0100_amd import fredec as Fr
     specs = [(80, 0, 100), (300, 3, 4097), (120, 1, 513), (640, 9, 1000), (90, 2, 1), (1000, 0, 3000)]
