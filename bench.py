@@ -62,9 +62,9 @@ COUNTER_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = {
     # float32 Phase 1 scans of the full pass, averaged over its 18 launches (scan_f16x3_kernel x16,
     # scan_f32_kernel x2)
-    "full_fp32_phase1_scans": {"src": {"scan_f16x3.hip": "a546fa38b8ffb7160b3934fefdc5f853d93ec819",
+    "full_fp32_phase1_scans": {"src": {"scan_f16x3.hip": "57f1b384d05695681b3cf4ebf052560541298357",
                                         "scan_f32.hip": "ce2bad490820f493b1da42222c1e35694aabec42"},
-                               "fetch_kib": 8740.1, "write_kib": 35173.7},
+                               "fetch_kib": 20029.4, "write_kib": 35173.7},
 }
 
 
@@ -114,13 +114,17 @@ def scan_model(m, fp32):
 def scan_roofline(ms_list, N, F, t_meas, fp32, traffic=None):
     """Roofline of a list of scans (base sizes ms_list, one launch each) measured at t_meas seconds."""
     P = float(N) * float(F)
-    t_roof, slots, mflops, kerns = 0.0, 0.0, 0.0, {}
+    t_roof, t_serial, slots, mflops, kerns = 0.0, 0.0, 0.0, 0.0, {}
     for m in ms_list:
         kern, v, mf, mpk = scan_model(m, fp32)
         kerns[kern] = kerns.get(kern, 0) + 1
         tv, tm = v * P / PEAK_VALU_OPS, mf * P / mpk
         th = (traffic or 0.0) / PEAK_HBM
         t_roof += max(tv, tm, th)
+        # at two waves per SIMD the VALU and MFMA times of a wave add (timing probe: 16x16x32 float16
+        # MFMAs interleaved with float32 FMAs take the sum of both alone), so the bound of a kernel
+        # that issues both is their sum
+        t_serial += max(tv + tm, th)
         slots += v * P
         mflops += mf * P
     achieved = slots / t_meas
@@ -130,6 +134,7 @@ def scan_roofline(ms_list, N, F, t_meas, fp32, traffic=None):
         # hardware sin and cos at quarter rate (2 x 4), double angle (3) = 14 per pair, every sum on
         # the matrix cores
         extra["frac_fixed_14_slot_model"] = 14.0 * P * len(ms_list) / PEAK_VALU_OPS / t_meas
+        extra["frac_serial_pipes"] = t_serial / t_meas
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12, "unit": "Tops/s",
             "frac": t_roof / t_meas, **extra, "traffic": traffic,
             "kernel": " + ".join(f"{k} x{n}" for k, n in sorted(kerns.items())),
