@@ -210,8 +210,10 @@ int fredec_scan_static(fredec_ctx* ctx, void* stream, const double* t, const dou
                        uint8_t* flags_out, double* l_base_out, int32_t* status_out);
 
 /* The same statistic for one series at an explicit list of grid indices
- * (device int64 idx[n_idx], each in [0, F)), always in float64.  Used to
- * re-score reduced-precision peaks.  z_out/flags_out: device [n_idx]. */
+ * (device int64 idx[n_idx], each in [0, F), n_idx < 2^31), always in float64
+ * (one workgroup per index).  Used to re-score reduced-precision peaks.
+ * z_out/flags_out: device [n_idx].  Errors: EINVAL (null pointer, bad size
+ * or df, n_idx >= 2^31), EDOF, ENOTSUP, ENOMEM (workspace), EDEVICE. */
 int fredec_scan_at_workspace(int64_t N, int32_t m, size_t* bytes);
 int fredec_scan_at(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w,
                    int64_t N, const double* base_f_host, int32_t m, double df,
@@ -430,9 +432,11 @@ int fredec_cascade(fredec_ctx* ctx, void* stream, const double* ltab, int32_t n,
  * zc0 (FAP below fap0); otherwise the phase ends.  The pool is then capped at
  * pool_cap (N/10 if pool_cap <= 0) by dropping the largest-FAP candidates
  * (ties: the higher frequency) and sorted by frequency.  A1: A~_1 of eq. zFAP.
- * With FREDEC_FP32 the scans use the reduced-precision sums and every peak is
- * followed uphill in float64 (fredec_scan_at) before any decision, so that
- * the decisions are taken on float64 values.  Synchronises `stream`.
+ * With FREDEC_FP32 the scans use the reduced-precision sums and every peak
+ * that can still reach z_max / 2 (float32 z within 1e-3 of half the largest
+ * float32 peak, a margin 1000 times the float32 bound) is followed uphill in
+ * float64 (fredec_scan_at) before any decision, so that the decisions are
+ * taken on float64 values.  Synchronises `stream`.
  * Host outputs: pool_out / pool_z_out [pool capacity], *n_pool, base_out
  * [max_scans], *n_base, *n_scans, *truncated (candidates dropped by the cap),
  * *W_out = F df T_eff.  Errors: EINVAL (including fap1 < fap0), a per-series

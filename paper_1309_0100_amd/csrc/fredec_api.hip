@@ -796,7 +796,7 @@ int fredec_scan_at_workspace(int64_t N, int32_t m, size_t* bytes) {
 int fredec_scan_at(fredec_ctx* ctx, void* stream, const double* t, const double* x, const double* w, int64_t N,
                    const double* base_f, int32_t m, double df, const int64_t* idx, int64_t n_idx, void* ws,
                    size_t ws_bytes, double* z_out, uint8_t* flags_out) {
-  if (!t || !x || !w || !z_out || N <= 0 || m < 0 || n_idx < 0) return FREDEC_EINVAL;
+  if (!t || !x || !w || !z_out || N <= 0 || m < 0 || n_idx < 0 || n_idx > 0x7fffffff) return FREDEC_EINVAL;
   if (n_idx > 0 && !idx) return FREDEC_EINVAL;
   if (m > 0 && !base_f) return FREDEC_EINVAL;
   if (!std::isfinite(df) || df == 0.0) return FREDEC_EINVAL;

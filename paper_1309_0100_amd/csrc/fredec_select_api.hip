@@ -393,6 +393,15 @@ int fredec_phase1(fredec_ctx* ctx, void* stream, const double* t, const double* 
     std::vector<Peak> pk(np);
     if ((rc = sync_read(st, pk.data(), d_pk, sizeof(Peak) * np))) return rc;
     if (precision == FREDEC_FP32 && np > 0) {
+      // Only peaks at or above half the largest one enter the decisions
+      // below.  The float32 values are within 1e-6 (relative) of float64, so
+      // a peak more than 1e-3 below half the largest float32 peak cannot
+      // reach half the largest float64 peak after re-scoring: it is dropped
+      // before the float64 hill climb (thousands of peaks per scan otherwise).
+      double zmax32 = 0.0;
+      for (const Peak& p : pk) zmax32 = std::max(zmax32, p.z);
+      const double zkeep = 0.5 * zmax32 * (1.0 - 1e-3);
+      pk.erase(std::remove_if(pk.begin(), pk.end(), [&](const Peak& p) { return p.z < zkeep; }), pk.end());
       ClimbBuffers cb{d_idx, d_zat, d_flat, at<void>(ws, L.off_at), L.at_ws};
       if ((rc = climb_f64(ctx, stream, t, x, w, N, base, df, F, cb, zc1, pk))) return rc;
     }

@@ -210,9 +210,11 @@ __global__ __launch_bounds__(BLOCK) void scan_f64_reduce_kernel(const SeriesIn* 
 }
 
 // Same statistic at an explicit list of grid indices of one series: one
-// wavefront per index, the samples spread over the lanes (float64 phase
+// workgroup per index, its samples spread over the four waves (float64 phase
 // reduction and sin/cos per sample), the 2 KP + 3 partial sums reduced across
-// the wave with DPP and shuffles in a fixed order.
+// each wave with DPP and shuffles and then across the waves in wave order
+// (fixed order: deterministic).  A wave per index left each wave one long
+// dependent chain of record loads (about 300 us for N = 10^4).
 template <int KP>
 __global__ __launch_bounds__(BLOCK) void scan_at_f64_kernel(const SeriesIn* __restrict__ sin_,
                                                             const SeriesHdr* __restrict__ hdr,
@@ -221,13 +223,15 @@ __global__ __launch_bounds__(BLOCK) void scan_at_f64_kernel(const SeriesIn* __re
                                                             double* __restrict__ z_out, uint8_t* __restrict__ flags_out) {
   constexpr int NS = 2 * KP + 3;
   constexpr int P = rec_stride(KP);
+  constexpr int NW = BLOCK / 64;
+  __shared__ double part[NW][NS];
   const SeriesIn& si = sin_[0];
   const SeriesHdr& h = hdr[0];
-  const int lane = threadIdx.x & 63;
-  const int64_t g = static_cast<int64_t>(blockIdx.x) * (BLOCK / 64) + (threadIdx.x >> 6);
-  if (g >= n_idx) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t g = blockIdx.x;
+  if (g >= n_idx) return;  // uniform over the block
   if (h.status != 0) {
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
       z_out[g] = __builtin_nan("");
       if (flags_out) flags_out[g] = FREDEC_FLAG_BADSERIES;
     }
@@ -239,7 +243,7 @@ __global__ __launch_bounds__(BLOCK) void scan_at_f64_kernel(const SeriesIn* __re
 #pragma unroll
   for (int k = 0; k < NS; ++k) acc[k] = 0.0;
   const double* __restrict__ q0 = rec + si.rec_off;
-  for (int64_t i = lane; i < si.N; i += 64) {
+  for (int64_t i = threadIdx.x; i < si.N; i += BLOCK) {
     const double* q = q0 + i * P;
     double s, c;
     sincos_rev(f * q[0], s, c);
@@ -257,8 +261,19 @@ __global__ __launch_bounds__(BLOCK) void scan_at_f64_kernel(const SeriesIn* __re
     }
   }
 #pragma unroll
-  for (int k = 0; k < NS; ++k) acc[k] = group_sum<64>(acc[k]);
-  if (lane == 0) {
+  for (int k = 0; k < NS; ++k) {
+    acc[k] = group_sum<64>(acc[k]);
+    if (lane == 0) part[wave][k] = acc[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      double v = part[0][k];
+#pragma unroll
+      for (int w2 = 1; w2 < NW; ++w2) v += part[w2][k];
+      acc[k] = v;
+    }
     double z;
     uint8_t fl;
     scan_epilogue<KP>(acc, f, si, h, z, fl);
@@ -283,8 +298,8 @@ hipError_t launch_kp(hipStream_t st, int n_work, const ScanWork* work, const Ser
 template <int KP>
 hipError_t launch_at_kp(hipStream_t st, const SeriesIn* sin, const SeriesHdr* hdr, const double* rec,
                         const int64_t* idx, int64_t n_idx, double* z, uint8_t* flags) {
-  const int64_t blocks = (n_idx + BLOCK / 64 - 1) / (BLOCK / 64);  // one wavefront per index
-  scan_at_f64_kernel<KP><<<static_cast<unsigned>(blocks), BLOCK, 0, st>>>(sin, hdr, rec, idx, n_idx, z, flags);
+  // one workgroup per index
+  scan_at_f64_kernel<KP><<<static_cast<unsigned>(n_idx), BLOCK, 0, st>>>(sin, hdr, rec, idx, n_idx, z, flags);
   return hipGetLastError();
 }
 
@@ -324,6 +339,7 @@ hipError_t launch_scan_f64(hipStream_t st, int KP, int n_work, const ScanWork* w
 hipError_t launch_scan_at_f64(hipStream_t st, int KP, const SeriesIn* sin, const SeriesHdr* hdr, const double* rec,
                               const int64_t* idx, int64_t n_idx, double* z, uint8_t* flags) {
   if (n_idx <= 0) return hipSuccess;
+  if (n_idx > 0x7fffffff) return hipErrorInvalidValue;  // one workgroup per index
   switch (KP) {
 #define X(kp) \
   case kp:    \

@@ -96,6 +96,7 @@ def test_scan_at_and_normalize_validation(lib):
     base = np.array([0.1])
     assert lib.fredec_scan_at(None, None, d, d, d, 6, _p(base), 1, 1e-3, d, 10, d, n.value, d, None) == F.EDOF
     assert lib.fredec_scan_at(None, None, d, d, d, 100, _p(base), 1, 0.0, d, 10, d, n.value, d, None) == F.EINVAL
+    assert lib.fredec_scan_at(None, None, d, d, d, 100, _p(base), 1, 1e-3, d, 1 << 31, d, n.value, d, None) == F.EINVAL
     assert lib.fredec_normalize_workspace(0, ctypes.byref(n)) == F.EINVAL
     soff = np.array([0, 0], np.int64)
     assert lib.fredec_normalize(None, None, 1, _p(soff), d, d, d, d, 1 << 20, d, d, d, None, None) == F.EINVAL
