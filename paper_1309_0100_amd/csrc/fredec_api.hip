@@ -193,6 +193,11 @@ struct ScanPlan : fredec_plan {
   int64_t sin_F0 = 0;    // grid size of the first series (a split float64 scan has one series)
   std::vector<SeriesIn> sin;
   std::vector<ScanWork> work;
+  // a single series: the work list is written on the device at launch
+  // (per_chunk tiles of `work_tile` grid points for each sample chunk)
+  // instead of built and uploaded by the host
+  bool device_work = false;
+  int64_t work_tile = 0, work_per_chunk = 0;
   enum Kind { F64 = 0, F32 = 2, F16X3 = 3 };
   struct Group {
     int kind;        // kernel family
@@ -204,6 +209,19 @@ struct ScanPlan : fredec_plan {
   };
   std::vector<Group> groups;
 };
+
+// Work list of a single series: item k covers sample chunk k / per_chunk and
+// the grid points from (k % per_chunk) * tile.
+__global__ void fill_work_kernel(ScanWork* work, int64_t n, int64_t tile, int64_t per_chunk) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k < n) {
+    ScanWork wk;
+    wk.series = 0;
+    wk.pad = static_cast<int32_t>(k / per_chunk);
+    wk.j0 = (k % per_chunk) * tile;
+    work[k] = wk;
+  }
+}
 
 // Running offsets of the per-series arrays of a scan workspace.
 struct SeriesOffsets {
@@ -324,7 +342,8 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
   });
   for (int32_t s = 0; s < n_series; ++s) sin[s].outputs = kind_outputs(kind(s));
   P.work.clear();
-  P.work.reserve(L.n_work);
+  P.device_work = false;
+  if (n_series > 1) P.work.reserve(L.n_work);
   P.groups.clear();
   for (int32_t s : order) {
     const int kd = kind(s);
@@ -334,9 +353,16 @@ int scan_build(const fredec_ctx* ctx, int32_t n_series, const int64_t* soff, con
       P.groups.push_back(ScanPlan::Group{kd, key(s), ft, static_cast<int64_t>(P.work.size()), 0});
     const int ns = kd == ScanPlan::F64 || kd == ScanPlan::F16X3 ? L.nsplit : 1;
     P.groups.back().nsplit = ns;
-    for (int c = 0; c < ns; ++c)
-      for (int64_t j0 = 0; j0 < sin[s].F; j0 += tile) P.work.push_back(ScanWork{s, c, j0});
-    P.groups.back().end = static_cast<int64_t>(P.work.size());
+    if (n_series == 1) {
+      P.device_work = true;
+      P.work_tile = tile;
+      P.work_per_chunk = (sin[s].F + tile - 1) / tile;
+      P.groups.back().end = P.work_per_chunk * ns;
+    } else {
+      for (int c = 0; c < ns; ++c)
+        for (int64_t j0 = 0; j0 < sin[s].F; j0 += tile) P.work.push_back(ScanWork{s, c, j0});
+      P.groups.back().end = static_cast<int64_t>(P.work.size());
+    }
     P.groups.back().work +=
         static_cast<double>(sin[s].N) * static_cast<double>(sin[s].F) * static_cast<double>(2 * sin[s].KP + 3);
   }
@@ -348,6 +374,7 @@ int scan_upload(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P) {
   int rc;
   if ((rc = upload(ctx, st, at<SeriesIn>(P.ws, P.L.off_sin), P.sin.data(), sizeof(SeriesIn) * P.sin.size())))
     return rc;
+  if (P.device_work) return FREDEC_OK;
   return upload(ctx, st, at<ScanWork>(P.ws, P.L.off_work), P.work.data(), sizeof(ScanWork) * P.work.size());
 }
 
@@ -381,6 +408,12 @@ int scan_launch(fredec_ctx* ctx, hipStream_t st, const ScanPlan& P, const ScanPl
   // per series, the prep kernel writes only what its scan kernel reads (SeriesIn::outputs)
   const int flags = PREP_BASE | PREP_REC64 | PREP_G32 | PREP_AUX | PREP_F16;
   if (f32 && launch_zero_u64(st, d_count, P.n_series) != hipSuccess) return FREDEC_EDEVICE;
+  if (P.device_work && n_groups > 0) {
+    const int64_t n = groups[0].end;
+    hipLaunchKernelGGL(fill_work_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, d_work, n,
+                       P.work_tile, P.work_per_chunk);
+    if (hipGetLastError() != hipSuccess) return FREDEC_EDEVICE;
+  }
   {
     ProfScope prof(prof_ctx, st, FREDEC_PROF_PREP);
     if (launch_prep(st, P.n_series, P.kp_max, L.ptiles, d_sin, d_hdr, t, x, w, d_tau - base_off, d_xt - base_off,
@@ -479,18 +512,6 @@ int static_scratch_address(int dev, void** out) {
 // device (kernel argument) instead of a host-to-device copy.
 __global__ void store_series_kernel(SeriesIn d, SeriesIn* dst) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *dst = d;
-}
-
-// Work list of a single series: tile k starts at grid index k * tile.
-__global__ void fill_work_kernel(ScanWork* work, int64_t n, int64_t tile) {
-  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k < n) {
-    ScanWork wk;
-    wk.series = 0;
-    wk.pad = 0;
-    wk.j0 = k * tile;
-    work[k] = wk;
-  }
 }
 
 }  // namespace
@@ -773,7 +794,7 @@ int fredec_scan_static(fredec_ctx* ctx, void* stream, const double* t, const dou
   hipLaunchKernelGGL(store_series_kernel, dim3(1), dim3(64), 0, st, d, at<SeriesIn>(P.ws, P.L.off_sin));
   if (hipGetLastError() != hipSuccess) return FREDEC_EDEVICE;
   hipLaunchKernelGGL(fill_work_kernel, dim3(static_cast<unsigned>((n_work + 255) / 256)), dim3(256), 0, st,
-                     at<ScanWork>(P.ws, P.L.off_work), n_work, tile);
+                     at<ScanWork>(P.ws, P.L.off_work), n_work, tile, n_work);
   if (hipGetLastError() != hipSuccess) return FREDEC_EDEVICE;
   return scan_launch(ctx, st, P, &gr, 1, t, x, w, z_out, flags_out, l_base_out, status_out, /*timed=*/false);
 }
