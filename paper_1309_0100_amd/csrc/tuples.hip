@@ -8,9 +8,9 @@
 //   GN columns       the forward ones, then t' cos 2 pi f_k t, t' sin 2 pi f_k t
 //                    (t' = t / sigma_t): the t-weighted averages from which the
 //                    Fisher matrix Q_f of the frequencies follows (eqs. avrg1, avrg2).
-// Each lane of an MFMA step owns one (column, sample) pair; A = column values,
-// B = w~ * column values, so D accumulates the Gram block by block (lower
-// triangle of 16x16 blocks only).  The sin/cos of each (frequency, sample) is
+// Each lane of an MFMA step owns one (column, sample) pair; A = B = sqrt(w~)
+// * column values, so D accumulates the Gram block by block (lower triangle
+// of 16x16 blocks only).  The sin/cos of each (frequency, sample) is
 // evaluated once per step by one lane and shared through LDS.
 // tuple_solve_kernel: one thread per tuple, float64: Cholesky of the model
 // block, l, theta*, z, and the Gauss-Newton step with the step control shared
@@ -45,9 +45,10 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // idle).  Per step of eight samples, lane (c8, s8) first evaluates cos and
 // sin of the frequencies c8, c8 + 8, ... at sample s8 (one float64 sin/cos
 // pair per frequency and sample) and writes the columns they make (cos, sin,
-// and in the Gauss-Newton mode t' cos, t' sin) into a wave-private LDS table
-// of the eight samples' column values (the columns 1 and x~ by lane c8 = 0,
-// the padding columns zero); then, for each half of four samples, lane
+// and in the Gauss-Newton mode t' cos, t' sin), each times sqrt(w~) of the
+// sample, into a wave-private LDS table of the eight samples' column values
+// (the columns 1 and x~ by lane c8 = 0, the padding columns zero), so that no
+// operand needs a weight multiply; then, for each half of four samples, lane
 // (c16, kq) reads the value of its column 16 b + c16 at sample kq for every
 // 16-column block b, and the wave accumulates the lower-triangle blocks of
 // the Gram on float64 MFMA.
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
       const bool in = k < ns;
       stage[0][k] = in ? tau[t0 + k] : 0.0;
       stage[1][k] = in ? xt[t0 + k] : 0.0;
-      stage[2][k] = in ? wt[t0 + k] : 0.0;
+      stage[2][k] = in ? sqrt(wt[t0 + k]) : 0.0;  // sqrt(w~): folded into every column value
     }
     __syncthreads();
     // the block's waves take every fourth step of eight samples: one sin/cos
@@ -147,6 +148,7 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
       {
         const int il = s0 + s8;  // beyond ns the staged values are 0
         const double ta = stage[0][il];
+        const double sw = stage[2][il];
         const double tt = ta * inv_sig;
 #pragma unroll
         for (int r = 0; r < NRMAX; ++r) {
@@ -154,6 +156,8 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
             const int kk = c8 + 8 * r;
             double sv, cv;
             sincos_tab(fk[r] * ta, tab, sv, cv);
+            cv *= sw;
+            sv *= sw;
             if (kk < n) {
               cw[s8][sl[r]] = cv;
               cw[s8][sl[r] + 1] = sv;
@@ -165,16 +169,15 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
           }
         }
         if (c8 == 0) {
-          cw[s8][slot1] = 1.0;
-          cw[s8][slotx] = stage[1][il];
+          cw[s8][slot1] = sw;
+          cw[s8][slotx] = stage[1][il] * sw;
         }
       }
       __builtin_amdgcn_wave_barrier();
-      double a[2][NB], ax[2], ex[2][TVA], wi[2];
+      double a[2][NB], ax[2], ex[2][TVA];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int row = 4 * u + kq;
-        wi[u] = stage[2][s0 + row];
 #pragma unroll
         for (int b = 0; b < NB; ++b) a[u][b] = cw[row][16 * b + c16];
         if constexpr (TV > 0) {
@@ -188,11 +191,11 @@ __global__ __launch_bounds__(BLOCK) void tuple_gram_kernel(const TupleDesc* __re
       for (int u = 0; u < 2; ++u) {
         double bw[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) bw[b] = wi[u] * a[u][b];
+        for (int b = 0; b < NB; ++b) bw[b] = a[u][b];
         if constexpr (TV > 0) {
 #pragma unroll
           for (int j = 0; j < TV; ++j) {
-            const double ej = wi[u] * ex[u][j];
+            const double ej = ex[u][j];
 #pragma unroll
             for (int b = 0; b < NB; ++b) xacc[j][b] = __builtin_fma(ej, a[u][b], xacc[j][b]);
             xacc[j][NB] = __builtin_fma(ej, ax[u], xacc[j][NB]);
